@@ -1,0 +1,183 @@
+/*
+ * csrad: differentiable CSR sparse-matrix kernels for AMD Instinct MI355X
+ * (gfx950), after "Optimized Sparse Matrix Operations for Reverse Mode
+ * Automatic Differentiation" (arXiv 2212.05159).
+ *
+ * Plain C ABI over hand-written HIP kernels.  Every pointer argument is
+ * device memory owned by the caller unless its name ends in _host.  The
+ * library never allocates or frees memory: calls that need scratch space
+ * take a caller-allocated workspace whose size a *_workspace query gives.
+ * Every call is asynchronous on `stream` (a hipStream_t passed as void*;
+ * NULL is the default stream) except the two that return a count to the
+ * host (csr_spgemm_symbolic and csr_trisolve_analyze), which synchronise
+ * the stream.  No exception or abort crosses the ABI: each call returns a
+ * status code.  Host-side checks are O(1) (null pointers, shapes, dtype);
+ * the pattern invariants below are preconditions that only csr_validate
+ * checks.
+ *
+ * Sparse operands are CSR: rowptr[nrows+1], colind[nnz] with column
+ * indices ascending and unique within each row, vals[nnz].  Indices are
+ * int32.  Values and every dense operand of one call share one type,
+ * float32 or float64 (csrad_csr.dtype).  Dense multi-column operands are
+ * row-major with a leading dimension (elements between rows) >= k.
+ *
+ * Gradients follow the sparse-gradient convention of Section 3.1: the
+ * gradient with respect to a sparse input is a value array on that
+ * input's own pattern (one entry per stored value, stored zeros
+ * included).  Gradient outputs are overwritten, not accumulated.  A NULL
+ * gradient output skips its kernel.
+ */
+#ifndef CSRAD_H
+#define CSRAD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+#define CSRAD_OK 0
+#define CSRAD_EINVAL (-1)     /* null pointer, bad shape, k <= 0, ld < k  */
+#define CSRAD_EDTYPE (-2)     /* unsupported or mismatched value type      */
+#define CSRAD_EPATTERN (-3)   /* malformed CSR (csr_validate only)         */
+#define CSRAD_ESINGULAR (-4)  /* a triangular row has no stored diagonal   */
+#define CSRAD_EWORKSPACE (-5) /* workspace missing or too small            */
+#define CSRAD_EHIP (-6)       /* HIP launch or runtime error               */
+#define CSRAD_EOVERFLOW (-7)  /* a result does not fit int32 indexing      */
+
+/* Value types. */
+#define CSRAD_F32 0
+#define CSRAD_F64 1
+
+/* A CSR matrix: host struct of device pointers.  vals may be NULL where a
+ * call reads only the pattern. */
+typedef struct csrad_csr {
+    int32_t nrows, ncols, nnz;
+    int32_t dtype;
+    const int32_t *rowptr;
+    const int32_t *colind;
+    const void *vals;
+} csrad_csr;
+
+/* Human-readable name of a status code (static storage). */
+const char *csr_status_string(int status);
+
+/* ---------------------------------------------------------------------
+ * SpMV (Section 3.1.1; Table 1, SpMV row).
+ * csr_spmv_fwd: y[nrows] = A x[ncols].
+ * csr_spmv_bwd: VJP with upstream gradient gy[nrows]:
+ *   gx[ncols] = A^T gy, and gvals[nnz] with gvals[e] = gy[row e] x[col e].
+ *   With At (pattern of A^T from csr_transpose, vals ignored) and perm,
+ *   both gradients come from one deterministic gather over A^T; with At
+ *   NULL the A^T product is formed by atomic accumulation (summation
+ *   order then varies between runs).
+ * ------------------------------------------------------------------- */
+int csr_spmv_fwd(const csrad_csr *A, const void *x, void *y, void *stream);
+int csr_spmv_bwd(const csrad_csr *A, const csrad_csr *At, const int32_t *perm,
+                 const void *x, const void *gy, void *gx, void *gvals,
+                 void *stream);
+
+/* ---------------------------------------------------------------------
+ * SpDMM, sparse times dense (Section 3.1.3; Table 1, SpDMM row).
+ * csr_spmm_fwd: C[nrows x k] = A B[ncols x k].
+ * csr_spmm_bwd: VJP with upstream gradient gC[nrows x k]:
+ *   gB[ncols x k] = A^T gC (gather over the transpose At/perm, which the
+ *   paper also uses: sparse transpose, then the forward product), and
+ *   gvals[e] = <gC[row e, :], B[col e, :]> (the masked product (gC B^T)
+ *   on A's pattern).  At/perm are required when gB is requested; with
+ *   both outputs requested one fused pass over A^T produces both.
+ * ------------------------------------------------------------------- */
+int csr_spmm_fwd(const csrad_csr *A, int32_t k, const void *B, int64_t ldb,
+                 void *C, int64_t ldc, void *stream);
+int csr_spmm_bwd(const csrad_csr *A, const csrad_csr *At, const int32_t *perm,
+                 int32_t k, const void *B, int64_t ldb, const void *gC,
+                 int64_t ldgc, void *gB, int64_t ldgb, void *gvals,
+                 void *stream);
+
+/* ---------------------------------------------------------------------
+ * Sparse transpose (Section 3.1.3, used by every A^T product).
+ * Pattern of A^T: rowptrT[ncols+1], colindT[nnz] (source rows ascending
+ * within each column, so the result is canonical CSR), and perm[nnz] with
+ * valsT[t] = vals[perm[t]].  Integer output is bit-exact and identical
+ * between runs.
+ * ------------------------------------------------------------------- */
+int csr_transpose_workspace(const csrad_csr *A, size_t *bytes);
+int csr_transpose(const csrad_csr *A, int32_t *rowptrT, int32_t *colindT,
+                  int32_t *perm, void *work, size_t work_bytes, void *stream);
+
+/* ---------------------------------------------------------------------
+ * SpSpMM, sparse times sparse (Section 3.1.2; Table 1, SpSpMM row).
+ * C = A B with A (m x n), B (n x p).  The pattern of C is structural:
+ * (i,j) is stored when some k has (i,k) in A and (k,j) in B, even if the
+ * sum cancels; column indices ascending.
+ * csr_spgemm_symbolic: C_rowptr[m+1] and *C_nnz_host (synchronises).
+ * csr_spgemm_fwd: C_colind[nnz(C)] and C_vals[nnz(C)] given C_rowptr.
+ *   Each C_ij sums A_ik B_kj over k in A's row order (deterministic).
+ * csr_spgemm_bwd: VJP with upstream gradient gC on pat(C) (Table 1):
+ *   gA = (V B^T) on pat(A), gB = (A^T V) on pat(B).  C carries the
+ *   pattern of C (vals ignored); At/permA (transpose of A) are required
+ *   when gB is requested.
+ * ------------------------------------------------------------------- */
+int csr_spgemm_workspace(const csrad_csr *A, const csrad_csr *B, size_t *bytes);
+int csr_spgemm_symbolic(const csrad_csr *A, const csrad_csr *B,
+                        int32_t *C_rowptr, int64_t *C_nnz_host, void *work,
+                        size_t work_bytes, void *stream);
+int csr_spgemm_fwd(const csrad_csr *A, const csrad_csr *B,
+                   const int32_t *C_rowptr, int32_t *C_colind, void *C_vals,
+                   void *work, size_t work_bytes, void *stream);
+int csr_spgemm_bwd(const csrad_csr *A, const csrad_csr *B,
+                   const csrad_csr *At, const int32_t *permA,
+                   const csrad_csr *C, const void *gC, void *gA, void *gB,
+                   void *stream);
+
+/* ---------------------------------------------------------------------
+ * Sparse triangular solve (Section 3.1.5; Table 1, SpSolve row).
+ * T is square, lower (lower = 1) or upper (lower = 0) triangular with a
+ * stored, non-unit diagonal (a stored entry on the other side of the
+ * diagonal is a precondition violation).
+ * csr_trisolve_analyze: level sets of the solve's dependency graph.  A
+ *   row that reads no other row is on level 0; otherwise it is one above
+ *   the highest level among the rows it reads.  Writes level_of_row[n],
+ *   level_ptr[nlevels+1], level_rows[n] (rows ascending within a level)
+ *   and *nlevels_host (synchronises).  Tt is the pattern of T^T
+ *   (csr_transpose).  Returns CSRAD_ESINGULAR if a diagonal is missing.
+ * csr_trisolve_fwd: x = T^{-1} b, level by level.  level_ptr (device) and
+ *   level_ptr_host (its host copy, nlevels+1 entries) come from
+ *   csr_trisolve_analyze; the host copy schedules the launches (large
+ *   levels as grid launches, runs of small levels in one workgroup).
+ * csr_trisolve_bwd: VJP with upstream gradient gx: gb = T^{-T} gx (the
+ *   solve with T^T runs over Tt/perm and the levels of T in reverse), and
+ *   gvals[(i,j)] = -gb_i x_j on pat(T).  gb is required.
+ * ------------------------------------------------------------------- */
+int csr_trisolve_workspace(const csrad_csr *T, size_t *bytes);
+int csr_trisolve_analyze(const csrad_csr *T, int32_t lower,
+                         const csrad_csr *Tt, int32_t *level_of_row,
+                         int32_t *level_ptr, int32_t *level_rows,
+                         int32_t *nlevels_host, void *work,
+                         size_t work_bytes, void *stream);
+int csr_trisolve_fwd(const csrad_csr *T, int32_t lower, int32_t nlevels,
+                     const int32_t *level_ptr_host, const int32_t *level_ptr,
+                     const int32_t *level_rows, const void *b, void *x,
+                     void *stream);
+int csr_trisolve_bwd(const csrad_csr *T, int32_t lower, const csrad_csr *Tt,
+                     const int32_t *perm, int32_t nlevels,
+                     const int32_t *level_ptr_host, const int32_t *level_ptr,
+                     const int32_t *level_rows, const void *x, const void *gx,
+                     void *gb, void *gvals, void *stream);
+
+/* ---------------------------------------------------------------------
+ * Pattern check: rowptr monotone from 0 to nnz, colind in [0, ncols),
+ * strictly ascending within each row.  *first_bad_row_host receives the
+ * first offending row or -1 (synchronises).  Returns CSRAD_EPATTERN if a
+ * row is malformed.  work needs 8 bytes.
+ * ------------------------------------------------------------------- */
+int csr_validate(const csrad_csr *A, int32_t *first_bad_row_host, void *work,
+                 size_t work_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CSRAD_H */

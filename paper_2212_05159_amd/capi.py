@@ -1,0 +1,214 @@
+"""Thin ctypes binding over libcsrad.so.
+
+The functions here carry the C names of the ABI declared in
+``include/csrad.h`` and only marshal arguments: device tensors become raw
+pointers, PyTorch allocates outputs and workspaces, and the current torch
+stream is passed through.  Every arithmetic step runs in the library's HIP
+kernels.  The library must be built (``paper_2212_05159_amd.build``); a
+missing library is an error, never a fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcsrad.so")
+
+F32, F64 = 0, 1
+_DT = {torch.float32: F32, torch.float64: F64}
+
+
+class csrad_csr(C.Structure):
+    _fields_ = [("nrows", C.c_int32), ("ncols", C.c_int32), ("nnz", C.c_int32),
+                ("dtype", C.c_int32), ("rowptr", C.c_void_p), ("colind", C.c_void_p),
+                ("vals", C.c_void_p)]
+
+
+_lib = None
+
+_SIGS = {
+    "csr_status_string": (C.c_char_p, [C.c_int]),
+    "csr_spmv_fwd": (C.c_int, [C.c_void_p] * 4),
+    "csr_spmv_bwd": (C.c_int, [C.c_void_p] * 8),
+    "csr_spmm_fwd": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int64, C.c_void_p,
+                               C.c_int64, C.c_void_p]),
+    "csr_spmm_bwd": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p,
+                               C.c_int64, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64,
+                               C.c_void_p, C.c_void_p]),
+    "csr_transpose_workspace": (C.c_int, [C.c_void_p, C.POINTER(C.c_size_t)]),
+    "csr_transpose": (C.c_int, [C.c_void_p] * 5 + [C.c_size_t, C.c_void_p]),
+    "csr_spgemm_workspace": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_size_t)]),
+    "csr_spgemm_symbolic": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p,
+                                      C.POINTER(C.c_int64), C.c_void_p, C.c_size_t,
+                                      C.c_void_p]),
+    "csr_spgemm_fwd": (C.c_int, [C.c_void_p] * 6 + [C.c_size_t, C.c_void_p]),
+    "csr_spgemm_bwd": (C.c_int, [C.c_void_p] * 9),
+    "csr_trisolve_workspace": (C.c_int, [C.c_void_p, C.POINTER(C.c_size_t)]),
+    "csr_trisolve_analyze": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
+                                       C.c_void_p, C.c_void_p, C.POINTER(C.c_int32),
+                                       C.c_void_p, C.c_size_t, C.c_void_p]),
+    "csr_trisolve_fwd": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
+                                   C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "csr_trisolve_bwd": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32,
+                                   C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                   C.c_void_p, C.c_void_p, C.c_void_p]),
+    "csr_validate": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.c_void_p, C.c_size_t,
+                               C.c_void_p]),
+}
+
+
+def exported_symbols():
+    return list(_SIGS)
+
+
+def load():
+    """Loads libcsrad.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2212_05159_amd.build`")
+        lib = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+class CsradError(RuntimeError):
+    def __init__(self, fn, status):
+        self.status = status
+        super().__init__(f"{fn}: {load().csr_status_string(status).decode()} (status {status})")
+
+
+def _check(fn, status):
+    if status != 0:
+        raise CsradError(fn, status)
+
+
+def _ptr(t):
+    return None if t is None else t.data_ptr()
+
+
+def _stream():
+    return torch.cuda.current_stream().cuda_stream
+
+
+def desc(nrows, ncols, rowptr, colind, vals=None, dtype=None):
+    """Host descriptor of a device CSR matrix (tensors must stay alive)."""
+    dt = dtype if dtype is not None else vals.dtype
+    if dt not in _DT:
+        raise TypeError(f"unsupported value type {dt}")
+    d = csrad_csr(int(nrows), int(ncols), int(colind.numel()), _DT[dt], rowptr.data_ptr(),
+                  colind.data_ptr() if colind.numel() else None,
+                  _ptr(vals) if vals is not None and vals.numel() else None)
+    return d
+
+
+def _ws(nbytes, device):
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+# ----------------------------------------------------------------------
+# C-named entry points (tensor marshalling only).
+# ----------------------------------------------------------------------
+
+def csr_spmv_fwd(A, x, y):
+    _check("csr_spmv_fwd", load().csr_spmv_fwd(C.byref(A), _ptr(x), _ptr(y), _stream()))
+
+
+def csr_spmv_bwd(A, At, perm, x, gy, gx, gvals):
+    _check("csr_spmv_bwd", load().csr_spmv_bwd(C.byref(A), C.byref(At) if At is not None else None,
+                                               _ptr(perm), _ptr(x), _ptr(gy), _ptr(gx),
+                                               _ptr(gvals), _stream()))
+
+
+def csr_spmm_fwd(A, k, B, ldb, Cout, ldc):
+    _check("csr_spmm_fwd", load().csr_spmm_fwd(C.byref(A), int(k), _ptr(B), int(ldb), _ptr(Cout),
+                                               int(ldc), _stream()))
+
+
+def csr_spmm_bwd(A, At, perm, k, B, ldb, gC, ldgc, gB, ldgb, gvals):
+    _check("csr_spmm_bwd", load().csr_spmm_bwd(C.byref(A), C.byref(At) if At is not None else None,
+                                               _ptr(perm), int(k), _ptr(B), int(ldb), _ptr(gC),
+                                               int(ldgc), _ptr(gB), int(ldgb), _ptr(gvals),
+                                               _stream()))
+
+
+def csr_transpose_workspace(A):
+    n = C.c_size_t(0)
+    _check("csr_transpose_workspace", load().csr_transpose_workspace(C.byref(A), C.byref(n)))
+    return n.value
+
+
+def csr_transpose(A, rowptrT, colindT, perm, work):
+    _check("csr_transpose", load().csr_transpose(C.byref(A), _ptr(rowptrT), _ptr(colindT),
+                                                 _ptr(perm), _ptr(work), work.numel(), _stream()))
+
+
+def csr_spgemm_workspace(A, B):
+    n = C.c_size_t(0)
+    _check("csr_spgemm_workspace", load().csr_spgemm_workspace(C.byref(A), C.byref(B), C.byref(n)))
+    return n.value
+
+
+def csr_spgemm_symbolic(A, B, C_rowptr, work):
+    nnz = C.c_int64(0)
+    _check("csr_spgemm_symbolic", load().csr_spgemm_symbolic(C.byref(A), C.byref(B), _ptr(C_rowptr),
+                                                             C.byref(nnz), _ptr(work), work.numel(),
+                                                             _stream()))
+    return nnz.value
+
+
+def csr_spgemm_fwd(A, B, C_rowptr, C_colind, C_vals, work):
+    _check("csr_spgemm_fwd", load().csr_spgemm_fwd(C.byref(A), C.byref(B), _ptr(C_rowptr),
+                                                   _ptr(C_colind), _ptr(C_vals), _ptr(work),
+                                                   work.numel(), _stream()))
+
+
+def csr_spgemm_bwd(A, B, At, permA, Cpat, gC, gA, gB):
+    _check("csr_spgemm_bwd", load().csr_spgemm_bwd(C.byref(A), C.byref(B),
+                                                   C.byref(At) if At is not None else None,
+                                                   _ptr(permA), C.byref(Cpat), _ptr(gC), _ptr(gA),
+                                                   _ptr(gB), _stream()))
+
+
+def csr_trisolve_workspace(T):
+    n = C.c_size_t(0)
+    _check("csr_trisolve_workspace", load().csr_trisolve_workspace(C.byref(T), C.byref(n)))
+    return n.value
+
+
+def csr_trisolve_analyze(T, lower, Tt, level_of_row, level_ptr, level_rows, work):
+    nl = C.c_int32(0)
+    _check("csr_trisolve_analyze", load().csr_trisolve_analyze(
+        C.byref(T), int(lower), C.byref(Tt), _ptr(level_of_row), _ptr(level_ptr),
+        _ptr(level_rows), C.byref(nl), _ptr(work), work.numel(), _stream()))
+    return nl.value
+
+
+def csr_trisolve_fwd(T, lower, nlevels, level_ptr_host, level_ptr, level_rows, b, x):
+    _check("csr_trisolve_fwd", load().csr_trisolve_fwd(
+        C.byref(T), int(lower), int(nlevels), level_ptr_host.ctypes.data, _ptr(level_ptr),
+        _ptr(level_rows), _ptr(b), _ptr(x), _stream()))
+
+
+def csr_trisolve_bwd(T, lower, Tt, perm, nlevels, level_ptr_host, level_ptr, level_rows, x, gx,
+                     gb, gvals):
+    _check("csr_trisolve_bwd", load().csr_trisolve_bwd(
+        C.byref(T), int(lower), C.byref(Tt), _ptr(perm), int(nlevels),
+        level_ptr_host.ctypes.data, _ptr(level_ptr), _ptr(level_rows), _ptr(x), _ptr(gx),
+        _ptr(gb), _ptr(gvals), _stream()))
+
+
+def csr_validate(A, work):
+    bad = C.c_int32(0)
+    st = load().csr_validate(C.byref(A), C.byref(bad), _ptr(work), work.numel(), _stream())
+    if st not in (0, -3):
+        _check("csr_validate", st)
+    return st, bad.value

@@ -1,0 +1,72 @@
+// Status strings and the CSR pattern validator.
+#include "internal.hpp"
+
+namespace csrad {
+namespace {
+
+// One thread per row.  Reads are clamped to [0, nnz) so a malformed
+// rowptr cannot send the check out of bounds.
+__global__ __launch_bounds__(256) void k_validate(int m, int n, int nnz,
+                                                  const int32_t* __restrict__ rp,
+                                                  const int32_t* __restrict__ ci,
+                                                  int32_t* __restrict__ bad) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const int a = rp[i], b = rp[i + 1];
+  bool ok = a >= 0 && b >= a && b <= nnz;
+  if (i == 0) ok = ok && a == 0;
+  if (i == m - 1) ok = ok && b == nnz;
+  if (ok) {
+    int prev = -1;
+    for (int e = a; e < b; ++e) {
+      const int c = ci[e];
+      if (c <= prev || c >= n) {
+        ok = false;
+        break;
+      }
+      prev = c;
+    }
+  }
+  if (!ok) atomicMin(bad, i);
+}
+
+}  // namespace
+}  // namespace csrad
+
+using namespace csrad;
+
+extern "C" const char* csr_status_string(int status) {
+  switch (status) {
+    case CSRAD_OK: return "ok";
+    case CSRAD_EINVAL: return "invalid argument (null pointer, shape or size)";
+    case CSRAD_EDTYPE: return "unsupported or mismatched value type";
+    case CSRAD_EPATTERN: return "malformed CSR pattern";
+    case CSRAD_ESINGULAR: return "triangular matrix has a row without a stored diagonal";
+    case CSRAD_EWORKSPACE: return "workspace missing or too small";
+    case CSRAD_EHIP: return "HIP launch or runtime error";
+    case CSRAD_EOVERFLOW: return "result exceeds int32 indexing";
+    default: return "unknown status";
+  }
+}
+
+extern "C" int csr_validate(const csrad_csr* A, int32_t* first_bad_row_host, void* work,
+                            size_t work_bytes, void* stream) {
+  if (!A || !first_bad_row_host) return CSRAD_EINVAL;
+  if (A->nrows < 0 || A->ncols < 0 || A->nnz < 0 || !A->rowptr) return CSRAD_EINVAL;
+  if (A->nnz > 0 && !A->colind) return CSRAD_EINVAL;
+  if (!work || work_bytes < sizeof(int32_t)) return CSRAD_EWORKSPACE;
+  hipStream_t s = as_stream(stream);
+  int32_t* bad = static_cast<int32_t*>(work);
+  CSRAD_TRY(fill_i32(bad, 1, INT32_MAX, s));
+  const int m = A->nrows;
+  if (m > 0)
+    hipLaunchKernelGGL(k_validate, dim3((m + 255) / 256), dim3(256), 0, s, m, A->ncols, A->nnz,
+                       A->rowptr, A->colind, bad);
+  CSRAD_TRY(launch_status());
+  int32_t host = INT32_MAX;
+  if (hipMemcpyAsync(&host, bad, sizeof(host), hipMemcpyDeviceToHost, s) != hipSuccess)
+    return CSRAD_EHIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return CSRAD_EHIP;
+  *first_bad_row_host = host == INT32_MAX ? -1 : host;
+  return host == INT32_MAX ? CSRAD_OK : CSRAD_EPATTERN;
+}

@@ -1,0 +1,161 @@
+// Shared device helpers and host-side argument checks for the csrad HIP
+// library (gfx950 / CDNA4: 64-lane wavefronts, 256 CUs in 8 XCDs).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/csrad.h"
+
+namespace csrad {
+
+constexpr int kWave = 64;
+constexpr int kXcds = 8;
+
+// ---------------------------------------------------------------------
+// XCD-aware block order.  The dispatcher hands workgroup b to XCD b % 8.
+// Renumbering so that each XCD receives one contiguous range of logical
+// blocks keeps neighbouring rows (and the dense rows they gather) in the
+// same XCD's L2.  Bijective on [0, nblocks).
+// ---------------------------------------------------------------------
+__device__ __forceinline__ int xcd_block(int b, int nblocks) {
+  const int per = nblocks / kXcds, rem = nblocks % kXcds;
+  const int x = b % kXcds, idx = b / kXcds;
+  return x * per + (x < rem ? x : rem) + idx;
+}
+
+// ---------------------------------------------------------------------
+// Cross-lane reductions over aligned groups of G lanes (G a power of two,
+// G <= 64).  Lanes 1,2 apart combine through DPP quad permutes, 4 and 8
+// apart through the DPP half-row and row mirrors, 16 apart through a
+// ds_swizzle and 32 apart through a bpermute.  Every lane of a group ends
+// with the same, bit-identical sum (each step adds the same two values in
+// both lanes).  All lanes of the wave must execute the call.
+// ---------------------------------------------------------------------
+template <int CTRL>
+__device__ __forceinline__ float dpp_f32(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ float swz16_f32(float v) {
+  // bitmask swizzle: and 0x1f, or 0, xor 0x10 -> lane ^ 16 within 32
+  return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x401F));
+}
+__device__ __forceinline__ double swz16_f64(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_ds_swizzle((int)(b & 0xffffffffll), 0x401F);
+  const int hi = __builtin_amdgcn_ds_swizzle((int)(b >> 32), 0x401F);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+constexpr int kDppXor1 = 0xB1;      // quad_perm [1,0,3,2]
+constexpr int kDppXor2 = 0x4E;      // quad_perm [2,3,0,1]
+constexpr int kDppHalfMirror = 0x141;
+constexpr int kDppMirror = 0x140;
+
+template <int G>
+__device__ __forceinline__ float group_sum(float v) {
+  if constexpr (G >= 2) v += dpp_f32<kDppXor1>(v);
+  if constexpr (G >= 4) v += dpp_f32<kDppXor2>(v);
+  if constexpr (G >= 8) v += dpp_f32<kDppHalfMirror>(v);
+  if constexpr (G >= 16) v += dpp_f32<kDppMirror>(v);
+  if constexpr (G >= 32) v += swz16_f32(v);
+  if constexpr (G >= 64) v += __shfl_xor(v, 32);
+  return v;
+}
+template <int G>
+__device__ __forceinline__ double group_sum(double v) {
+  if constexpr (G >= 2) v += dpp_f64<kDppXor1>(v);
+  if constexpr (G >= 4) v += dpp_f64<kDppXor2>(v);
+  if constexpr (G >= 8) v += dpp_f64<kDppHalfMirror>(v);
+  if constexpr (G >= 16) v += dpp_f64<kDppMirror>(v);
+  if constexpr (G >= 32) v += swz16_f64(v);
+  if constexpr (G >= 64) v += __shfl_xor(v, 32);
+  return v;
+}
+
+// Integer group sum (counts); plain bpermute butterflies.
+template <int G>
+__device__ __forceinline__ int group_sum_int(int v) {
+#pragma unroll
+  for (int o = 1; o < G; o <<= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// ---------------------------------------------------------------------
+// Vector types for 16-byte dense-row accesses.
+// ---------------------------------------------------------------------
+template <typename T, int VW>
+struct alignas(sizeof(T) * VW) Vec {
+  T v[VW];
+};
+
+template <typename T, int VW>
+__device__ __forceinline__ Vec<T, VW> load_vec(const T* p) {
+  return *reinterpret_cast<const Vec<T, VW>*>(p);
+}
+template <typename T, int VW>
+__device__ __forceinline__ void store_vec(T* p, const Vec<T, VW>& x) {
+  *reinterpret_cast<Vec<T, VW>*>(p) = x;
+}
+
+// Streaming loads for data read exactly once (CSR arrays): keep them from
+// evicting reused dense rows.
+template <typename T>
+__device__ __forceinline__ T ld_stream(const T* p) {
+  return __builtin_nontemporal_load(p);
+}
+
+// ---------------------------------------------------------------------
+// Host-side checks.
+// ---------------------------------------------------------------------
+inline int check_csr(const csrad_csr* A, bool need_vals) {
+  if (!A) return CSRAD_EINVAL;
+  if (A->nrows < 0 || A->ncols < 0 || A->nnz < 0) return CSRAD_EINVAL;
+  if (!A->rowptr) return CSRAD_EINVAL;
+  if (A->nnz > 0 && !A->colind) return CSRAD_EINVAL;
+  if (need_vals && A->nnz > 0 && !A->vals) return CSRAD_EINVAL;
+  if (A->dtype != CSRAD_F32 && A->dtype != CSRAD_F64) return CSRAD_EDTYPE;
+  return CSRAD_OK;
+}
+
+inline size_t dtype_size(int dtype) { return dtype == CSRAD_F64 ? 8 : 4; }
+
+inline int launch_status() {
+  return hipGetLastError() == hipSuccess ? CSRAD_OK : CSRAD_EHIP;
+}
+
+inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Carves aligned sub-buffers out of a caller workspace.
+// Constructed with base == nullptr it only measures (off = bytes needed).
+struct Carver {
+  char* base;
+  size_t cap, off = 0;
+  bool ok = true;
+  Carver(void* b, size_t c) : base(static_cast<char*>(b)), cap(c) {}
+  template <typename T>
+  T* take(size_t count) {
+    off = align_up(off, 256);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += sizeof(T) * (count ? count : 1);
+    if (base && off > cap) ok = false;
+    return p;
+  }
+};
+
+#define CSRAD_TRY(expr)            \
+  do {                             \
+    int _st = (expr);              \
+    if (_st != CSRAD_OK) return _st; \
+  } while (0)
+
+}  // namespace csrad

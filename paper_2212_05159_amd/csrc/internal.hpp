@@ -1,0 +1,26 @@
+// Internal host entry points shared between translation units of the
+// csrad library (not part of the C ABI).
+#pragma once
+
+#include "common.hpp"
+
+namespace csrad {
+
+// Exclusive prefix sum of n int32 counts: out[0] = 0, out[i+1] =
+// in[0] + ... + in[i] (n+1 outputs).  The exact 64-bit total goes to
+// *total_dev; out[] is only meaningful when the total fits int32.
+size_t scan_workspace(int n);
+int scan_exclusive(const int32_t* in, int32_t* out, int n, long long* total_dev,
+                   void* work, size_t bytes, hipStream_t s);
+
+// Stable transpose of a CSR pattern (see csr_transpose).
+size_t transpose_workspace(int m, int n, int nnz);
+int transpose_pattern(int m, int n, int nnz, const int32_t* rowptr, const int32_t* colind,
+                      int32_t* rowptrT, int32_t* colindT, int32_t* perm, void* work,
+                      size_t bytes, hipStream_t s);
+
+// Fill a device int32 array with a value (graph-capture safe, no memset node).
+int fill_i32(int32_t* p, long long n, int32_t value, hipStream_t s);
+int fill_bytes_zero(void* p, size_t bytes, hipStream_t s);
+
+}  // namespace csrad

@@ -1,0 +1,601 @@
+// SpSpMM / SpGEMM C = A B, all CSR (Section 3.1.2; Table 1, SpSpMM row;
+// gradient flow of Fig. 2).
+//
+// Rows of C are binned by the product count U_i = sum over A's row of the
+// lengths of the B rows it selects, an upper bound on nnz(C_i):
+//   U <= 16, 64, 512, 4096 : LDS hash table of H = 2U slots per row,
+//                            8 / 16 / 64 / 256 lanes per row;
+//   U > 4096               : a dense per-workgroup marker array in the
+//                            workspace (tagged with the row id).
+// Symbolic: count the distinct columns (hash insert with CAS).
+// Numeric : rebuild the set, sort it (bitonic sort of the whole table in
+//           LDS, empty slots last; for the dense path a block scan of the
+//           marker array), write ascending column indices, then each
+//           output entry C_ij = sum_k A_ik B_kj with k in A's row order and
+//           B_kj found by binary search in B's sorted row k.  No floating
+//           point atomics: values are bit-identical between runs.
+// Backward (both gathers, no atomics):
+//   gA[(i,k)] = sum_{j in pat(C_i) and pat(B_k)} V_ij B_kj   (row-aligned)
+//   gB[(k,j)] = sum_{i in column k of A} A_ik V_ij           (over A^T)
+#include "internal.hpp"
+
+namespace csrad {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kNumBins = 6;  // 0: empty, 1..4: LDS hash, 5: dense marker
+constexpr int kBigU = 4096;
+constexpr size_t kMarkerBudget = size_t(16) << 20;
+
+__host__ __device__ inline int bin_of(long long u) {
+  if (u == 0) return 0;
+  if (u <= 16) return 1;
+  if (u <= 64) return 2;
+  if (u <= 512) return 3;
+  if (u <= kBigU) return 4;
+  return 5;
+}
+
+// Per row: U_i and its bin (count pass) ...
+__global__ __launch_bounds__(kThreads) void k_bin_count(int m, const int32_t* __restrict__ rpA,
+                                                        const int32_t* __restrict__ ciA,
+                                                        const int32_t* __restrict__ rpB,
+                                                        int8_t* __restrict__ binid,
+                                                        int32_t* __restrict__ bin_cnt) {
+  __shared__ int local[kNumBins];
+  if (threadIdx.x < kNumBins) local[threadIdx.x] = 0;
+  __syncthreads();
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) {
+    long long u = 0;
+    for (int a = rpA[i]; a < rpA[i + 1]; ++a) {
+      const int k = ciA[a];
+      u += rpB[k + 1] - rpB[k];
+    }
+    const int b = bin_of(u);
+    binid[i] = (int8_t)b;
+    atomicAdd(&local[b], 1);
+  }
+  __syncthreads();
+  if (threadIdx.x < kNumBins && local[threadIdx.x]) atomicAdd(&bin_cnt[threadIdx.x], local[threadIdx.x]);
+}
+
+// ... offsets (one thread) ...
+__global__ void k_bin_offsets(const int32_t* __restrict__ bin_cnt, int32_t* __restrict__ bin_off,
+                              int32_t* __restrict__ cursor) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    int run = 0;
+    for (int b = 0; b < kNumBins; ++b) {
+      bin_off[b] = run;
+      cursor[b] = run;
+      run += bin_cnt[b];
+    }
+    bin_off[kNumBins] = run;
+  }
+}
+
+// ... and the row lists (order within a bin is irrelevant).
+__global__ __launch_bounds__(kThreads) void k_bin_fill(int m, const int8_t* __restrict__ binid,
+                                                       int32_t* __restrict__ cursor,
+                                                       int32_t* __restrict__ list) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) list[atomicAdd(&cursor[binid[i]], 1)] = i;
+}
+
+__device__ __forceinline__ unsigned hash_slot(int j, int H) {
+  unsigned h = (unsigned)j * 2654435761u;
+  return (h ^ (h >> 15)) & (unsigned)(H - 1);
+}
+
+// Returns 1 if j was newly inserted.  The table (H slots, -1 empty) never
+// fills: every row placed in a bin has at most H/2 products.
+__device__ __forceinline__ int hash_insert(int* tab, int H, int j) {
+  unsigned h = hash_slot(j, H);
+  while (true) {
+    const int prev = atomicCAS(&tab[h], -1, j);
+    if (prev == -1) return 1;
+    if (prev == j) return 0;
+    h = (h + 1) & (unsigned)(H - 1);
+  }
+}
+
+// Visits this lane's share of row i's products: lane l of G takes the
+// flattened product indices congruent to l modulo G.
+template <int G, typename F>
+__device__ __forceinline__ void for_each_product(int i, int l, const int32_t* __restrict__ rpA,
+                                                 const int32_t* __restrict__ ciA,
+                                                 const int32_t* __restrict__ rpB,
+                                                 const int32_t* __restrict__ ciB, F&& f) {
+  int base = 0;
+  const int a1 = rpA[i + 1];
+  for (int a = rpA[i]; a < a1; ++a) {
+    const int k = ciA[a];
+    const int b0 = rpB[k], len = rpB[k + 1] - b0;
+    int off = (l - base) % G;
+    if (off < 0) off += G;
+    for (int o = off; o < len; o += G) f(ciB[b0 + o]);
+    base += len;
+  }
+}
+
+// Index of key in the sorted range ci[lo, hi), or -1.
+__device__ __forceinline__ int find_sorted(const int32_t* __restrict__ ci, int lo, int hi, int key) {
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    const int v = ci[mid];
+    if (v == key) return mid;
+    if (v < key) lo = mid + 1;
+    else hi = mid;
+  }
+  return -1;
+}
+
+// C_ij = sum over A's row i (in order) of A_ik B_kj.
+template <typename T>
+__device__ __forceinline__ T product_entry(int i, int j, const int32_t* __restrict__ rpA,
+                                           const int32_t* __restrict__ ciA,
+                                           const T* __restrict__ vA,
+                                           const int32_t* __restrict__ rpB,
+                                           const int32_t* __restrict__ ciB,
+                                           const T* __restrict__ vB) {
+  T acc = 0;
+  const int a1 = rpA[i + 1];
+  for (int a = rpA[i]; a < a1; ++a) {
+    const int k = ciA[a];
+    const int p = find_sorted(ciB, rpB[k], rpB[k + 1], j);
+    if (p >= 0) acc += vA[a] * vB[p];
+  }
+  return acc;
+}
+
+// ---------------------------------------------------------------------
+// LDS-hash bins.  A block holds RPB = 256/G rows, each with H slots.  The
+// loop over the bin's rows is uniform across the block (barriers inside).
+// ---------------------------------------------------------------------
+template <int G, int H>
+__global__ __launch_bounds__(kThreads) void k_sym_hash(int bin, const int32_t* __restrict__ list,
+                                                       const int32_t* __restrict__ bin_off,
+                                                       const int32_t* __restrict__ rpA,
+                                                       const int32_t* __restrict__ ciA,
+                                                       const int32_t* __restrict__ rpB,
+                                                       const int32_t* __restrict__ ciB,
+                                                       int32_t* __restrict__ counts) {
+  constexpr int RPB = kThreads / G;
+  __shared__ int table[RPB * H];
+  __shared__ int cnt[RPB];
+  const int first = bin_off[bin], nrows = bin_off[bin + 1] - first;
+  const int slot = threadIdx.x / G, l = threadIdx.x % G;
+  int* tab = table + slot * H;
+  for (int base = blockIdx.x * RPB; base < nrows; base += gridDim.x * RPB) {
+    for (int q = l; q < H; q += G) tab[q] = -1;
+    if (l == 0) cnt[slot] = 0;
+    __syncthreads();
+    const int idx = base + slot;
+    int mine = 0;
+    int i = -1;
+    if (idx < nrows) {
+      i = list[first + idx];
+      for_each_product<G>(i, l, rpA, ciA, rpB, ciB, [&](int j) { mine += hash_insert(tab, H, j); });
+    }
+    if (mine) atomicAdd(&cnt[slot], mine);
+    __syncthreads();
+    if (i >= 0 && l == 0) counts[i] = cnt[slot];
+    __syncthreads();
+  }
+}
+
+template <typename T, int G, int H>
+__global__ __launch_bounds__(kThreads) void k_num_hash(
+    int bin, const int32_t* __restrict__ list, const int32_t* __restrict__ bin_off,
+    const int32_t* __restrict__ rpA, const int32_t* __restrict__ ciA, const T* __restrict__ vA,
+    const int32_t* __restrict__ rpB, const int32_t* __restrict__ ciB, const T* __restrict__ vB,
+    const int32_t* __restrict__ rpC, int32_t* __restrict__ ciC, T* __restrict__ vC) {
+  constexpr int RPB = kThreads / G;
+  __shared__ int table[RPB * H];
+  const int first = bin_off[bin], nrows = bin_off[bin + 1] - first;
+  const int slot = threadIdx.x / G, l = threadIdx.x % G;
+  int* tab = table + slot * H;
+  for (int base = blockIdx.x * RPB; base < nrows; base += gridDim.x * RPB) {
+    for (int q = l; q < H; q += G) tab[q] = -1;
+    __syncthreads();
+    const int idx = base + slot;
+    const int i = idx < nrows ? list[first + idx] : -1;
+    if (i >= 0)
+      for_each_product<G>(i, l, rpA, ciA, rpB, ciB, [&](int j) { hash_insert(tab, H, j); });
+    __syncthreads();
+    for (int q = threadIdx.x; q < RPB * H; q += kThreads)
+      if (table[q] == -1) table[q] = INT32_MAX;
+    __syncthreads();
+    // Bitonic sort of every table (independent segments of length H).
+    for (int k = 2; k <= H; k <<= 1) {
+      for (int jj = k >> 1; jj > 0; jj >>= 1) {
+        for (int q = threadIdx.x; q < RPB * H; q += kThreads) {
+          const int e = q % H, ixj = e ^ jj;
+          if (ixj > e) {
+            const int o = q - e;
+            const int a = table[o + e], b = table[o + ixj];
+            if ((a > b) == ((e & k) == 0)) {
+              table[o + e] = b;
+              table[o + ixj] = a;
+            }
+          }
+        }
+        __syncthreads();
+      }
+    }
+    if (i >= 0) {
+      const int c0 = rpC[i], u = rpC[i + 1] - c0;
+      for (int t = l; t < u; t += G) {
+        const int j = tab[t];
+        ciC[c0 + t] = j;
+        vC[c0 + t] = product_entry<T>(i, j, rpA, ciA, vA, rpB, ciB, vB);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------
+// Dense-marker bin (U > 4096): each block owns a marker array of p ints in
+// the workspace, tagged with the row id, and walks the bin's rows.
+// ---------------------------------------------------------------------
+__device__ void block_init_marker(int* marker, int p) {
+  for (int q = threadIdx.x; q < p; q += kThreads) marker[q] = -1;
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(kThreads) void k_sym_dense(int p, const int32_t* __restrict__ list,
+                                                        const int32_t* __restrict__ bin_off,
+                                                        const int32_t* __restrict__ rpA,
+                                                        const int32_t* __restrict__ ciA,
+                                                        const int32_t* __restrict__ rpB,
+                                                        const int32_t* __restrict__ ciB,
+                                                        int32_t* __restrict__ counts,
+                                                        int32_t* __restrict__ markers) {
+  __shared__ int cnt;
+  const int first = bin_off[5], nrows = bin_off[6] - first;
+  if ((int)blockIdx.x >= nrows) return;
+  int* marker = markers + (size_t)blockIdx.x * p;
+  block_init_marker(marker, p);
+  for (int idx = blockIdx.x; idx < nrows; idx += gridDim.x) {
+    const int i = list[first + idx];
+    if (threadIdx.x == 0) cnt = 0;
+    __syncthreads();
+    int mine = 0;
+    for_each_product<kThreads>(i, threadIdx.x, rpA, ciA, rpB, ciB,
+                               [&](int j) { mine += atomicExch(&marker[j], i) != i; });
+    if (mine) atomicAdd(&cnt, mine);
+    __syncthreads();
+    if (threadIdx.x == 0) counts[i] = cnt;
+    __syncthreads();
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_num_dense(
+    int p, const int32_t* __restrict__ list, const int32_t* __restrict__ bin_off,
+    const int32_t* __restrict__ rpA, const int32_t* __restrict__ ciA, const T* __restrict__ vA,
+    const int32_t* __restrict__ rpB, const int32_t* __restrict__ ciB, const T* __restrict__ vB,
+    const int32_t* __restrict__ rpC, int32_t* __restrict__ ciC, T* __restrict__ vC,
+    int32_t* __restrict__ markers) {
+  __shared__ int wsum[kThreads / kWave];
+  const int first = bin_off[5], nrows = bin_off[6] - first;
+  if ((int)blockIdx.x >= nrows) return;
+  int* marker = markers + (size_t)blockIdx.x * p;
+  block_init_marker(marker, p);
+  const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
+  for (int idx = blockIdx.x; idx < nrows; idx += gridDim.x) {
+    const int i = list[first + idx];
+    for_each_product<kThreads>(i, threadIdx.x, rpA, ciA, rpB, ciB,
+                               [&](int j) { atomicExch(&marker[j], i); });
+    __syncthreads();
+    // Ascending compaction of the tagged columns: block scan per chunk.
+    const int c0 = rpC[i];
+    int run = 0;
+    for (int cb = 0; cb < p; cb += kThreads) {
+      const int c = cb + threadIdx.x;
+      const int f = (c < p && marker[c] == i) ? 1 : 0;
+      int v = f;
+#pragma unroll
+      for (int o = 1; o < kWave; o <<= 1) {
+        const int u = __shfl_up(v, o);
+        if (lane >= o) v += u;
+      }
+      if (lane == kWave - 1) wsum[wid] = v;
+      __syncthreads();
+      int off = 0, tot = 0;
+#pragma unroll
+      for (int w = 0; w < kThreads / kWave; ++w) {
+        if (w < wid) off += wsum[w];
+        tot += wsum[w];
+      }
+      if (f) ciC[c0 + run + off + v - 1] = c;
+      run += tot;
+      __syncthreads();
+    }
+    __syncthreads();
+    const int u = rpC[i + 1] - c0;
+    for (int t = threadIdx.x; t < u; t += kThreads)
+      vC[c0 + t] = product_entry<T>(i, ciC[c0 + t], rpA, ciA, vA, rpB, ciB, vB);
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------
+// Backward.
+// ---------------------------------------------------------------------
+// gA: G lanes per row of A, lanes over A's entries.
+template <typename T, int G>
+__global__ __launch_bounds__(kThreads) void k_bwd_a(int m, const int32_t* __restrict__ rpA,
+                                                    const int32_t* __restrict__ ciA,
+                                                    const int32_t* __restrict__ rpB,
+                                                    const int32_t* __restrict__ ciB,
+                                                    const T* __restrict__ vB,
+                                                    const int32_t* __restrict__ rpC,
+                                                    const int32_t* __restrict__ ciC,
+                                                    const T* __restrict__ gC, T* __restrict__ gA) {
+  const int b = xcd_block(blockIdx.x, gridDim.x);
+  const int i = b * (kThreads / G) + threadIdx.x / G;
+  const int l = threadIdx.x % G;
+  if (i >= m) return;
+  const int c0 = rpC[i], c1 = rpC[i + 1];
+  const int a1 = rpA[i + 1];
+  for (int a = rpA[i] + l; a < a1; a += G) {
+    const int k = ciA[a];
+    T s = 0;
+    for (int q = rpB[k]; q < rpB[k + 1]; ++q) {
+      const int p = find_sorted(ciC, c0, c1, ciB[q]);
+      if (p >= 0) s += gC[p] * vB[q];
+    }
+    gA[a] = s;
+  }
+}
+
+// gB: G lanes per row k of B, lanes over B's entries; column k of A from
+// A^T (rows ascending), values through permA.
+template <typename T, int G>
+__global__ __launch_bounds__(kThreads) void k_bwd_b(
+    int n, const int32_t* __restrict__ rpB, const int32_t* __restrict__ ciB,
+    const int32_t* __restrict__ rpAT, const int32_t* __restrict__ ciAT,
+    const int32_t* __restrict__ permA, const T* __restrict__ vA, const int32_t* __restrict__ rpC,
+    const int32_t* __restrict__ ciC, const T* __restrict__ gC, T* __restrict__ gB) {
+  const int b = xcd_block(blockIdx.x, gridDim.x);
+  const int k = b * (kThreads / G) + threadIdx.x / G;
+  const int l = threadIdx.x % G;
+  if (k >= n) return;
+  const int t0 = rpAT[k], t1 = rpAT[k + 1];
+  const int q1 = rpB[k + 1];
+  for (int q = rpB[k] + l; q < q1; q += G) {
+    const int j = ciB[q];
+    T s = 0;
+    for (int t = t0; t < t1; ++t) {
+      const int i = ciAT[t];
+      const int p = find_sorted(ciC, rpC[i], rpC[i + 1], j);
+      if (p >= 0) s += vA[permA[t]] * gC[p];
+    }
+    gB[q] = s;
+  }
+}
+
+// ---------------------------------------------------------------------
+// Host side.
+// ---------------------------------------------------------------------
+struct SpgemmWs {
+  int8_t* binid;
+  int32_t* bin_cnt;
+  int32_t* bin_off;
+  int32_t* cursor;
+  int32_t* list;
+  int32_t* counts;
+  void* scan_ws;
+  size_t scan_bytes;
+  long long* total;
+  int32_t* markers;
+  int nmark;
+};
+
+int marker_slots(int p) {
+  const size_t per = sizeof(int32_t) * (size_t)(p > 0 ? p : 1);
+  size_t s = kMarkerBudget / per;
+  if (s < 1) s = 1;
+  if (s > 64) s = 64;
+  return (int)s;
+}
+
+SpgemmWs carve_spgemm(Carver& cv, int m, int p) {
+  SpgemmWs w;
+  w.binid = cv.take<int8_t>((size_t)m);
+  w.bin_cnt = cv.take<int32_t>(kNumBins);
+  w.bin_off = cv.take<int32_t>(kNumBins + 1);
+  w.cursor = cv.take<int32_t>(kNumBins);
+  w.list = cv.take<int32_t>((size_t)m);
+  w.counts = cv.take<int32_t>((size_t)m);
+  w.scan_bytes = scan_workspace(m);
+  w.scan_ws = cv.take<char>(w.scan_bytes);
+  w.total = cv.take<long long>(1);
+  w.nmark = marker_slots(p);
+  w.markers = cv.take<int32_t>((size_t)w.nmark * (size_t)(p > 0 ? p : 1));
+  return w;
+}
+
+unsigned persistent_grid(int rows_per_block, int m) {
+  long long b = ((long long)m + rows_per_block - 1) / rows_per_block;
+  if (b > 4096) b = 4096;
+  if (b < 1) b = 1;
+  return (unsigned)b;
+}
+
+int classify(const csrad_csr* A, const csrad_csr* B, const SpgemmWs& w, hipStream_t s) {
+  const int m = A->nrows;
+  CSRAD_TRY(fill_i32(w.bin_cnt, kNumBins, 0, s));
+  const unsigned g = (unsigned)((m + kThreads - 1) / kThreads);
+  if (m > 0)
+    hipLaunchKernelGGL(k_bin_count, dim3(g), dim3(kThreads), 0, s, m, A->rowptr, A->colind,
+                       B->rowptr, w.binid, w.bin_cnt);
+  hipLaunchKernelGGL(k_bin_offsets, dim3(1), dim3(64), 0, s, w.bin_cnt, w.bin_off, w.cursor);
+  if (m > 0)
+    hipLaunchKernelGGL(k_bin_fill, dim3(g), dim3(kThreads), 0, s, m, w.binid, w.cursor, w.list);
+  return launch_status();
+}
+
+int check_pair(const csrad_csr* A, const csrad_csr* B, bool vals) {
+  CSRAD_TRY(check_csr(A, vals));
+  CSRAD_TRY(check_csr(B, vals));
+  if (A->ncols != B->nrows) return CSRAD_EINVAL;
+  if (A->dtype != B->dtype) return CSRAD_EDTYPE;
+  return CSRAD_OK;
+}
+
+template <typename T>
+int spgemm_numeric_t(const csrad_csr* A, const csrad_csr* B, const int32_t* rpC, int32_t* ciC,
+                     T* vC, const SpgemmWs& w, hipStream_t s) {
+  const int m = A->nrows, p = B->ncols;
+  const T* vA = static_cast<const T*>(A->vals);
+  const T* vB = static_cast<const T*>(B->vals);
+  hipLaunchKernelGGL((k_num_hash<T, 8, 32>), dim3(persistent_grid(32, m)), dim3(kThreads), 0, s, 1,
+                     w.list, w.bin_off, A->rowptr, A->colind, vA, B->rowptr, B->colind, vB, rpC,
+                     ciC, vC);
+  hipLaunchKernelGGL((k_num_hash<T, 16, 128>), dim3(persistent_grid(16, m)), dim3(kThreads), 0, s,
+                     2, w.list, w.bin_off, A->rowptr, A->colind, vA, B->rowptr, B->colind, vB, rpC,
+                     ciC, vC);
+  hipLaunchKernelGGL((k_num_hash<T, 64, 1024>), dim3(persistent_grid(4, m)), dim3(kThreads), 0, s,
+                     3, w.list, w.bin_off, A->rowptr, A->colind, vA, B->rowptr, B->colind, vB, rpC,
+                     ciC, vC);
+  hipLaunchKernelGGL((k_num_hash<T, 256, 8192>), dim3(persistent_grid(1, m)), dim3(kThreads), 0, s,
+                     4, w.list, w.bin_off, A->rowptr, A->colind, vA, B->rowptr, B->colind, vB, rpC,
+                     ciC, vC);
+  hipLaunchKernelGGL((k_num_dense<T>), dim3(w.nmark), dim3(kThreads), 0, s, p, w.list, w.bin_off,
+                     A->rowptr, A->colind, vA, B->rowptr, B->colind, vB, rpC, ciC, vC, w.markers);
+  return launch_status();
+}
+
+int lanes_for(long long nnz, int rows) {
+  if (rows <= 0) return 1;
+  const double mean = (double)nnz / rows;
+  int g = 1;
+  while (g < 64 && g < mean) g <<= 1;
+  return g;
+}
+
+#define CSRAD_G_SWITCH(g, ...)                            \
+  switch (g) {                                            \
+    case 1: { constexpr int G = 1; __VA_ARGS__; } break;   \
+    case 2: { constexpr int G = 2; __VA_ARGS__; } break;   \
+    case 4: { constexpr int G = 4; __VA_ARGS__; } break;   \
+    case 8: { constexpr int G = 8; __VA_ARGS__; } break;   \
+    case 16: { constexpr int G = 16; __VA_ARGS__; } break; \
+    case 32: { constexpr int G = 32; __VA_ARGS__; } break; \
+    default: { constexpr int G = 64; __VA_ARGS__; } break; \
+  }
+
+template <typename T>
+int spgemm_bwd_t(const csrad_csr* A, const csrad_csr* B, const csrad_csr* At,
+                 const int32_t* permA, const csrad_csr* C, const T* gC, T* gA, T* gB,
+                 hipStream_t s) {
+  if (gA && A->nrows > 0) {
+    const int m = A->nrows;
+    CSRAD_G_SWITCH(lanes_for(A->nnz, m),
+                   hipLaunchKernelGGL((k_bwd_a<T, G>), dim3((m + kThreads / G - 1) / (kThreads / G)),
+                                      dim3(kThreads), 0, s, m, A->rowptr, A->colind, B->rowptr,
+                                      B->colind, static_cast<const T*>(B->vals), C->rowptr,
+                                      C->colind, gC, gA));
+  }
+  if (gB && B->nrows > 0) {
+    const int n = B->nrows;
+    CSRAD_G_SWITCH(lanes_for(B->nnz, n),
+                   hipLaunchKernelGGL((k_bwd_b<T, G>), dim3((n + kThreads / G - 1) / (kThreads / G)),
+                                      dim3(kThreads), 0, s, n, B->rowptr, B->colind, At->rowptr,
+                                      At->colind, permA, static_cast<const T*>(A->vals), C->rowptr,
+                                      C->colind, gC, gB));
+  }
+  return launch_status();
+}
+
+}  // namespace
+}  // namespace csrad
+
+using namespace csrad;
+
+extern "C" int csr_spgemm_workspace(const csrad_csr* A, const csrad_csr* B, size_t* bytes) {
+  if (!A || !B || !bytes) return CSRAD_EINVAL;
+  if (A->nrows < 0 || B->ncols < 0) return CSRAD_EINVAL;
+  Carver cv(nullptr, 0);
+  carve_spgemm(cv, A->nrows, B->ncols);
+  *bytes = cv.off + 256;
+  return CSRAD_OK;
+}
+
+extern "C" int csr_spgemm_symbolic(const csrad_csr* A, const csrad_csr* B, int32_t* C_rowptr,
+                                   int64_t* C_nnz_host, void* work, size_t work_bytes,
+                                   void* stream) {
+  CSRAD_TRY(check_pair(A, B, false));
+  if (!C_rowptr || !C_nnz_host) return CSRAD_EINVAL;
+  hipStream_t s = as_stream(stream);
+  const int m = A->nrows, p = B->ncols;
+  Carver cv(work, work_bytes);
+  SpgemmWs w = carve_spgemm(cv, m, p);
+  if (!work || !cv.ok) return CSRAD_EWORKSPACE;
+  CSRAD_TRY(classify(A, B, w, s));
+  if (m > 0) {
+    CSRAD_TRY(fill_i32(w.counts, m, 0, s));
+    hipLaunchKernelGGL((k_sym_hash<8, 32>), dim3(persistent_grid(32, m)), dim3(kThreads), 0, s, 1,
+                       w.list, w.bin_off, A->rowptr, A->colind, B->rowptr, B->colind, w.counts);
+    hipLaunchKernelGGL((k_sym_hash<16, 128>), dim3(persistent_grid(16, m)), dim3(kThreads), 0, s, 2,
+                       w.list, w.bin_off, A->rowptr, A->colind, B->rowptr, B->colind, w.counts);
+    hipLaunchKernelGGL((k_sym_hash<64, 1024>), dim3(persistent_grid(4, m)), dim3(kThreads), 0, s, 3,
+                       w.list, w.bin_off, A->rowptr, A->colind, B->rowptr, B->colind, w.counts);
+    hipLaunchKernelGGL((k_sym_hash<256, 8192>), dim3(persistent_grid(1, m)), dim3(kThreads), 0, s,
+                       4, w.list, w.bin_off, A->rowptr, A->colind, B->rowptr, B->colind, w.counts);
+    hipLaunchKernelGGL(k_sym_dense, dim3(w.nmark), dim3(kThreads), 0, s, p, w.list, w.bin_off,
+                       A->rowptr, A->colind, B->rowptr, B->colind, w.counts, w.markers);
+  }
+  CSRAD_TRY(scan_exclusive(w.counts, C_rowptr, m, w.total, w.scan_ws, w.scan_bytes, s));
+  long long total = 0;
+  if (hipMemcpyAsync(&total, w.total, sizeof(total), hipMemcpyDeviceToHost, s) != hipSuccess)
+    return CSRAD_EHIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return CSRAD_EHIP;
+  *C_nnz_host = total;
+  if (total > INT32_MAX) return CSRAD_EOVERFLOW;
+  return CSRAD_OK;
+}
+
+extern "C" int csr_spgemm_fwd(const csrad_csr* A, const csrad_csr* B, const int32_t* C_rowptr,
+                              int32_t* C_colind, void* C_vals, void* work, size_t work_bytes,
+                              void* stream) {
+  CSRAD_TRY(check_pair(A, B, true));
+  if (!C_rowptr) return CSRAD_EINVAL;
+  hipStream_t s = as_stream(stream);
+  const int m = A->nrows, p = B->ncols;
+  Carver cv(work, work_bytes);
+  SpgemmWs w = carve_spgemm(cv, m, p);
+  if (!work || !cv.ok) return CSRAD_EWORKSPACE;
+  if (m == 0) return CSRAD_OK;
+  CSRAD_TRY(classify(A, B, w, s));
+  if (A->dtype == CSRAD_F32)
+    return spgemm_numeric_t<float>(A, B, C_rowptr, C_colind, static_cast<float*>(C_vals), w, s);
+  return spgemm_numeric_t<double>(A, B, C_rowptr, C_colind, static_cast<double*>(C_vals), w, s);
+}
+
+extern "C" int csr_spgemm_bwd(const csrad_csr* A, const csrad_csr* B, const csrad_csr* At,
+                              const int32_t* permA, const csrad_csr* C, const void* gC, void* gA,
+                              void* gB, void* stream) {
+  CSRAD_TRY(check_pair(A, B, false));
+  if (!gA && !gB) return CSRAD_OK;
+  if (!C) return CSRAD_EINVAL;
+  CSRAD_TRY(check_csr(C, false));
+  if (C->nrows != A->nrows || C->ncols != B->ncols) return CSRAD_EINVAL;
+  if (C->nnz > 0 && !gC) return CSRAD_EINVAL;
+  if (gA && B->nnz > 0 && !B->vals) return CSRAD_EINVAL;
+  if (gB) {
+    if (!At) return CSRAD_EINVAL;
+    CSRAD_TRY(check_csr(At, false));
+    if (At->nrows != A->ncols || At->ncols != A->nrows || At->nnz != A->nnz) return CSRAD_EINVAL;
+    if (A->nnz > 0 && (!permA || !A->vals)) return CSRAD_EINVAL;
+  }
+  hipStream_t s = as_stream(stream);
+  if (A->dtype == CSRAD_F32)
+    return spgemm_bwd_t<float>(A, B, At, permA, C, static_cast<const float*>(gC),
+                               static_cast<float*>(gA), static_cast<float*>(gB), s);
+  return spgemm_bwd_t<double>(A, B, At, permA, C, static_cast<const double*>(gC),
+                              static_cast<double*>(gA), static_cast<double*>(gB), s);
+}

@@ -1,0 +1,289 @@
+// Stable CSR transpose (the sparse transpose that the SpDMM backward of
+// Section 3.1.3 is built on; every A^T product here gathers over it).
+//
+// count per column -> exclusive scan -> scatter with atomic cursors (order
+// within a column is then arbitrary) -> per-column sort by source row.
+// Source rows are unique within a column, so the sorted order is unique
+// and the result is bit-exact and identical between runs.  Columns are
+// sorted by length class: <= 32 entries one thread (rank sort), <= 4096 one
+// workgroup (bitonic in LDS), longer ones in 4096-entry LDS-sorted chunks
+// merged by a grid-wide rank computation (binary search in every chunk).
+#include "internal.hpp"
+
+namespace csrad {
+namespace {
+
+constexpr int kShort = 32;
+constexpr int kChunk = 4096;
+constexpr int kSortThreads = 256;
+
+__global__ __launch_bounds__(256) void k_count_cols(const int32_t* __restrict__ colind, int nnz,
+                                                    int32_t* __restrict__ cnt) {
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < nnz;
+       e += (long long)gridDim.x * blockDim.x)
+    atomicAdd(&cnt[colind[e]], 1);
+}
+
+__global__ __launch_bounds__(256) void k_copy_i32(const int32_t* __restrict__ src, int n,
+                                                  int32_t* __restrict__ dst) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
+// 8 lanes per row: lanes stride over the row's entries.
+__global__ __launch_bounds__(256) void k_scatter(int m, const int32_t* __restrict__ rowptr,
+                                                 const int32_t* __restrict__ colind,
+                                                 int32_t* __restrict__ cursor,
+                                                 int32_t* __restrict__ tkey,
+                                                 int32_t* __restrict__ tval) {
+  const int row = blockIdx.x * (256 / 8) + threadIdx.x / 8;
+  const int sub = threadIdx.x % 8;
+  if (row >= m) return;
+  const int e1 = rowptr[row + 1];
+  for (int e = rowptr[row] + sub; e < e1; e += 8) {
+    const int slot = atomicAdd(&cursor[colind[e]], 1);
+    tkey[slot] = row;
+    tval[slot] = e;
+  }
+}
+
+// Short columns: one thread, rank sort (keys unique).  Longer columns are
+// appended to a list for the workgroup kernels.
+__global__ __launch_bounds__(256) void k_sort_short(int n, const int32_t* __restrict__ rpT,
+                                                    const int32_t* __restrict__ tkey,
+                                                    const int32_t* __restrict__ tval,
+                                                    int32_t* __restrict__ okey,
+                                                    int32_t* __restrict__ oval,
+                                                    int32_t* __restrict__ long_list,
+                                                    int32_t* __restrict__ long_count) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  const int s = rpT[c], len = rpT[c + 1] - s;
+  if (len <= kShort) {
+    for (int q = 0; q < len; ++q) {
+      const int key = tkey[s + q];
+      int r = 0;
+      for (int u = 0; u < len; ++u) r += tkey[s + u] < key;
+      okey[s + r] = key;
+      oval[s + r] = tval[s + q];
+    }
+  } else {
+    long_list[atomicAdd(long_count, 1)] = c;
+  }
+}
+
+// Bitonic sort of P (power of two) key/value pairs in LDS, ascending keys.
+__device__ void lds_bitonic(int32_t* key, int32_t* val, int P) {
+  for (int k = 2; k <= P; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < P; i += blockDim.x) {
+        const int ixj = i ^ j;
+        if (ixj > i) {
+          const bool up = (i & k) == 0;
+          const int a = key[i], b = key[ixj];
+          if ((a > b) == up) {
+            key[i] = b;
+            key[ixj] = a;
+            const int t = val[i];
+            val[i] = val[ixj];
+            val[ixj] = t;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+__device__ __forceinline__ int pow2_at_least(int x) {
+  int p = 1;
+  while (p < x) p <<= 1;
+  return p;
+}
+
+// Sorts [s, s+len) of (src_key, src_val) into (dst_key, dst_val); len <= kChunk.
+__device__ void sort_range_lds(const int32_t* src_key, const int32_t* src_val, int32_t* dst_key,
+                               int32_t* dst_val, int s, int len, int32_t* kk, int32_t* vv) {
+  const int P = pow2_at_least(len);
+  for (int i = threadIdx.x; i < P; i += blockDim.x) {
+    kk[i] = i < len ? src_key[s + i] : INT32_MAX;
+    vv[i] = i < len ? src_val[s + i] : 0;
+  }
+  __syncthreads();
+  lds_bitonic(kk, vv, P);
+  for (int i = threadIdx.x; i < len; i += blockDim.x) {
+    dst_key[s + i] = kk[i];
+    dst_val[s + i] = vv[i];
+  }
+  __syncthreads();
+}
+
+// Medium columns (kShort < len <= kChunk): one workgroup each.
+__global__ __launch_bounds__(kSortThreads) void k_sort_medium(
+    const int32_t* __restrict__ rpT, const int32_t* __restrict__ tkey,
+    const int32_t* __restrict__ tval, int32_t* __restrict__ okey, int32_t* __restrict__ oval,
+    const int32_t* __restrict__ long_list, const int32_t* __restrict__ long_count) {
+  __shared__ int32_t kk[kChunk];
+  __shared__ int32_t vv[kChunk];
+  const int nl = *long_count;
+  for (int t = blockIdx.x; t < nl; t += gridDim.x) {
+    const int c = long_list[t];
+    const int s = rpT[c], len = rpT[c + 1] - s;
+    if (len > kChunk) continue;  // uniform over the block
+    sort_range_lds(tkey, tval, okey, oval, s, len, kk, vv);
+  }
+}
+
+// Long columns, step 1: sort each kChunk-entry chunk in place in the
+// scratch arrays.  Every block walks the whole long list and takes the
+// chunks whose index matches it modulo the grid size.
+__global__ __launch_bounds__(kSortThreads) void k_sort_long_chunks(
+    const int32_t* __restrict__ rpT, int32_t* __restrict__ tkey, int32_t* __restrict__ tval,
+    const int32_t* __restrict__ long_list, const int32_t* __restrict__ long_count) {
+  __shared__ int32_t kk[kChunk];
+  __shared__ int32_t vv[kChunk];
+  const int nl = *long_count;
+  for (int t = 0; t < nl; ++t) {
+    const int c = long_list[t];
+    const int s = rpT[c], len = rpT[c + 1] - s;
+    if (len <= kChunk) continue;
+    const int nch = (len + kChunk - 1) / kChunk;
+    for (int ch = blockIdx.x; ch < nch; ch += gridDim.x) {
+      const int cs = s + ch * kChunk;
+      const int cl = min(kChunk, s + len - cs);
+      sort_range_lds(tkey, tval, tkey, tval, cs, cl, kk, vv);
+    }
+  }
+}
+
+// Number of keys < key in the sorted range [lo, hi).
+__device__ __forceinline__ int count_less(const int32_t* a, int lo, int hi, int key) {
+  int l = lo, h = hi;
+  while (l < h) {
+    const int mid = (l + h) >> 1;
+    if (a[mid] < key) l = mid + 1;
+    else h = mid;
+  }
+  return l - lo;
+}
+
+// Long columns, step 2: the final position of each entry is its position
+// in its own sorted chunk plus the number of smaller keys in every other
+// chunk.
+__global__ __launch_bounds__(256) void k_rank_long(const int32_t* __restrict__ rpT,
+                                                   const int32_t* __restrict__ tkey,
+                                                   const int32_t* __restrict__ tval,
+                                                   int32_t* __restrict__ okey,
+                                                   int32_t* __restrict__ oval,
+                                                   const int32_t* __restrict__ long_list,
+                                                   const int32_t* __restrict__ long_count) {
+  const int nl = *long_count;
+  const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long gsz = (long long)gridDim.x * blockDim.x;
+  for (int t = 0; t < nl; ++t) {
+    const int c = long_list[t];
+    const int s = rpT[c], len = rpT[c + 1] - s;
+    if (len <= kChunk) continue;
+    const int nch = (len + kChunk - 1) / kChunk;
+    for (long long q = gid; q < len; q += gsz) {
+      const int my = (int)(q / kChunk);
+      const int key = tkey[s + q];
+      int r = (int)(q - (long long)my * kChunk);
+      for (int ch = 0; ch < nch; ++ch) {
+        if (ch == my) continue;
+        const int lo = s + ch * kChunk, hi = min(s + len, lo + kChunk);
+        r += count_less(tkey, lo, hi, key);
+      }
+      okey[s + r] = key;
+      oval[s + r] = tval[s + q];
+    }
+  }
+}
+
+struct TransposeWs {
+  int32_t* cnt;
+  void* scan_ws;
+  size_t scan_bytes;
+  long long* total;
+  int32_t* tkey;
+  int32_t* tval;
+  int32_t* long_list;
+  int32_t* long_count;
+};
+
+TransposeWs carve_transpose(Carver& cv, int n, int nnz) {
+  TransposeWs w;
+  w.cnt = cv.take<int32_t>((size_t)n + 1);
+  w.scan_bytes = scan_workspace(n);
+  w.scan_ws = cv.take<char>(w.scan_bytes);
+  w.total = cv.take<long long>(1);
+  w.tkey = cv.take<int32_t>((size_t)nnz);
+  w.tval = cv.take<int32_t>((size_t)nnz);
+  w.long_list = cv.take<int32_t>((size_t)n + 1);
+  w.long_count = cv.take<int32_t>(1);
+  return w;
+}
+
+unsigned grid_for(long long work, int threads, unsigned cap = 65536) {
+  long long b = (work + threads - 1) / threads;
+  if (b < 1) b = 1;
+  if (b > cap) b = cap;
+  return (unsigned)b;
+}
+
+}  // namespace
+
+size_t transpose_workspace(int m, int n, int nnz) {
+  (void)m;
+  Carver cv(nullptr, 0);
+  carve_transpose(cv, n, nnz);
+  return cv.off + 256;
+}
+
+int transpose_pattern(int m, int n, int nnz, const int32_t* rowptr, const int32_t* colind,
+                      int32_t* rowptrT, int32_t* colindT, int32_t* perm, void* work, size_t bytes,
+                      hipStream_t s) {
+  Carver cv(work, bytes);
+  TransposeWs w = carve_transpose(cv, n, nnz);
+  if (!work || !cv.ok) return CSRAD_EWORKSPACE;
+  CSRAD_TRY(fill_i32(w.cnt, (long long)n + 1, 0, s));
+  CSRAD_TRY(fill_i32(w.long_count, 1, 0, s));
+  if (nnz > 0)
+    hipLaunchKernelGGL(k_count_cols, dim3(grid_for(nnz, 256)), dim3(256), 0, s, colind, nnz, w.cnt);
+  CSRAD_TRY(scan_exclusive(w.cnt, rowptrT, n, w.total, w.scan_ws, w.scan_bytes, s));
+  if (nnz == 0) return launch_status();
+  if (n > 0)
+    hipLaunchKernelGGL(k_copy_i32, dim3(grid_for(n, 256)), dim3(256), 0, s, rowptrT, n, w.cnt);
+  if (m > 0)
+    hipLaunchKernelGGL(k_scatter, dim3((m + 31) / 32), dim3(256), 0, s, m, rowptr, colind, w.cnt,
+                       w.tkey, w.tval);
+  hipLaunchKernelGGL(k_sort_short, dim3(grid_for(n, 256, 1u << 30)), dim3(256), 0, s, n, rowptrT,
+                     w.tkey, w.tval, colindT, perm, w.long_list, w.long_count);
+  hipLaunchKernelGGL(k_sort_medium, dim3(1024), dim3(kSortThreads), 0, s, rowptrT, w.tkey, w.tval,
+                     colindT, perm, w.long_list, w.long_count);
+  hipLaunchKernelGGL(k_sort_long_chunks, dim3(256), dim3(kSortThreads), 0, s, rowptrT, w.tkey,
+                     w.tval, w.long_list, w.long_count);
+  hipLaunchKernelGGL(k_rank_long, dim3(1024), dim3(256), 0, s, rowptrT, w.tkey, w.tval, colindT,
+                     perm, w.long_list, w.long_count);
+  return launch_status();
+}
+
+}  // namespace csrad
+
+using namespace csrad;
+
+extern "C" int csr_transpose_workspace(const csrad_csr* A, size_t* bytes) {
+  if (!A || !bytes) return CSRAD_EINVAL;
+  if (A->nrows < 0 || A->ncols < 0 || A->nnz < 0) return CSRAD_EINVAL;
+  *bytes = transpose_workspace(A->nrows, A->ncols, A->nnz);
+  return CSRAD_OK;
+}
+
+extern "C" int csr_transpose(const csrad_csr* A, int32_t* rowptrT, int32_t* colindT, int32_t* perm,
+                             void* work, size_t work_bytes, void* stream) {
+  CSRAD_TRY(check_csr(A, false));
+  if (!rowptrT || (A->nnz > 0 && (!colindT || !perm))) return CSRAD_EINVAL;
+  return transpose_pattern(A->nrows, A->ncols, A->nnz, A->rowptr, A->colind, rowptrT, colindT,
+                           perm, work, work_bytes, as_stream(stream));
+}

@@ -1,0 +1,384 @@
+// Sparse triangular solve T x = b and its VJP (Section 3.1.5; Table 1,
+// SpSolve row), level-scheduled.
+//
+// Analysis: the dependency graph of the solve (row i reads row j when T_ij
+// is stored on the solve side of the diagonal) is layered by longest path.
+//   1. per row: dependency count, stored diagonal check, level-0 rows;
+//   2. one workgroup runs Kahn's algorithm level by level (dependents of a
+//      row are its column, i.e. a row of T^T): a row joins the next level
+//      when its last dependency is placed;
+//   3. rows are grouped by level with the stable transpose of the
+//      row -> level map, so rows ascend within each level.
+// Level sets are unique, so the integer output is bit-exact.
+//
+// Solve: levels run in order.  A level with many rows is one grid launch;
+// runs of small levels are processed by a single workgroup with a barrier
+// between levels, so deep, narrow level structures do not pay one launch
+// per level.
+//
+// Adjoint: w = T^{-T} gx runs over T^T (rows of T^T are columns of T)
+// visiting T's levels in reverse (every row that column j feeds sits on a
+// higher level).  A second pass over T^T writes gvals[(i,j)] = -w_i x_j.
+// T must be triangular on the side given by `lower`; a stored entry on
+// the other side is a precondition violation.
+#include "internal.hpp"
+
+namespace csrad {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kKahnThreads = 1024;
+constexpr int kOneBlockThreads = 1024;
+constexpr int kBigLevel = 2048;
+
+__device__ __forceinline__ bool dep_side(int lower, int row, int col) {
+  return lower ? col < row : col > row;
+}
+
+// Step 1: dependency counts, diagonal check and the level-0 frontier.
+__global__ __launch_bounds__(kThreads) void k_tri_prep(int n, int lower,
+                                                       const int32_t* __restrict__ rp,
+                                                       const int32_t* __restrict__ ci,
+                                                       int32_t* __restrict__ indeg,
+                                                       int32_t* __restrict__ front,
+                                                       int32_t* __restrict__ front_n,
+                                                       int32_t* __restrict__ bad_row) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int deps = 0;
+  bool diag = false;
+  for (int e = rp[i]; e < rp[i + 1]; ++e) {
+    const int j = ci[e];
+    deps += dep_side(lower, i, j);
+    diag |= (j == i);
+  }
+  indeg[i] = deps;
+  if (!diag) atomicMin(bad_row, i);
+  if (deps == 0) front[atomicAdd(front_n, 1)] = i;
+}
+
+// Step 2: Kahn's algorithm in one workgroup.  Terminates after at most n
+// levels: every level places at least one row, and a row enters a
+// frontier once (when its count reaches zero).
+__global__ __launch_bounds__(kKahnThreads) void k_tri_kahn(
+    int n, int lower, const int32_t* __restrict__ rpT, const int32_t* __restrict__ ciT,
+    int32_t* __restrict__ indeg, int32_t* __restrict__ fa, int32_t* __restrict__ fb,
+    const int32_t* __restrict__ front_n, int32_t* __restrict__ level_of_row,
+    int32_t* __restrict__ nlevels) {
+  __shared__ int next_n;
+  int cur_n = *front_n;
+  int* cur = fa;
+  int* nxt = fb;
+  int level = 0;
+  while (cur_n > 0 && level < n) {
+    if (threadIdx.x == 0) next_n = 0;
+    __syncthreads();
+    for (int q = threadIdx.x; q < cur_n; q += blockDim.x) {
+      const int j = cur[q];
+      level_of_row[j] = level;
+      for (int t = rpT[j]; t < rpT[j + 1]; ++t) {
+        const int i = ciT[t];
+        if (dep_side(lower, i, j) && atomicSub(&indeg[i], 1) == 1) nxt[atomicAdd(&next_n, 1)] = i;
+      }
+    }
+    __syncthreads();
+    cur_n = next_n;
+    int* tmp = cur;
+    cur = nxt;
+    nxt = tmp;
+    ++level;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *nlevels = level;
+}
+
+__global__ void k_iota(int32_t* p, int n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = i;
+}
+
+// Solve one row of T x = b on G lanes (also the adjoint solve over T^T
+// when PERM is set: values then come through perm).
+template <typename T, int G, bool PERM>
+__device__ __forceinline__ void solve_row(int r, int sub, int lower, const int32_t* __restrict__ rp,
+                                          const int32_t* __restrict__ ci,
+                                          const int32_t* __restrict__ perm,
+                                          const T* __restrict__ vals, const T* __restrict__ b,
+                                          T* __restrict__ x, bool valid) {
+  T s = 0, d = 0;
+  if (valid) {
+    const int e1 = rp[r + 1];
+    for (int e = rp[r] + sub; e < e1; e += G) {
+      const int j = ci[e];
+      const T v = PERM ? vals[perm[e]] : vals[e];
+      if (j == r) d = v;
+      else if (dep_side(lower, r, j)) s += v * x[j];
+    }
+  }
+  s = group_sum<G>(s);
+  d = group_sum<G>(d);
+  if (valid && sub == 0) x[r] = (b[r] - s) / d;
+}
+
+template <typename T, int G, bool PERM>
+__global__ __launch_bounds__(kThreads) void k_tri_level(int lo, int hi, int lower,
+                                                       const int32_t* __restrict__ rows,
+                                                       const int32_t* __restrict__ rp,
+                                                       const int32_t* __restrict__ ci,
+                                                       const int32_t* __restrict__ perm,
+                                                       const T* __restrict__ vals,
+                                                       const T* __restrict__ b,
+                                                       T* __restrict__ x) {
+  const int q = lo + blockIdx.x * (kThreads / G) + threadIdx.x / G;
+  const bool valid = q < hi;
+  const int r = valid ? rows[q] : 0;
+  solve_row<T, G, PERM>(r, threadIdx.x % G, lower, rp, ci, perm, vals, b, x, valid);
+}
+
+// A run of consecutive small levels [l0, l1) in one workgroup.  With
+// REVERSE the levels run from l1-1 down to l0.
+template <typename T, int G, bool PERM, bool REVERSE>
+__global__ __launch_bounds__(kOneBlockThreads) void k_tri_levels_block(
+    int l0, int l1, int lower, const int32_t* __restrict__ level_ptr,
+    const int32_t* __restrict__ rows, const int32_t* __restrict__ rp,
+    const int32_t* __restrict__ ci, const int32_t* __restrict__ perm, const T* __restrict__ vals,
+    const T* __restrict__ b, T* __restrict__ x) {
+  constexpr int RPB = kOneBlockThreads / G;
+  for (int t = 0; t < l1 - l0; ++t) {
+    const int l = REVERSE ? l1 - 1 - t : l0 + t;
+    const int lo = level_ptr[l], hi = level_ptr[l + 1];
+    for (int base = lo; base < hi; base += RPB) {
+      const int q = base + threadIdx.x / G;
+      const bool valid = q < hi;
+      const int r = valid ? rows[q] : 0;
+      solve_row<T, G, PERM>(r, threadIdx.x % G, lower, rp, ci, perm, vals, b, x, valid);
+    }
+    __syncthreads();
+  }
+}
+
+// gvals[(i,j)] = -w_i x_j for the entries of T, written from T^T's side:
+// row j of T^T holds column j of T; w there is final once the adjoint
+// solve has passed.
+template <typename T, int G>
+__global__ __launch_bounds__(kThreads) void k_tri_gvals(int n, const int32_t* __restrict__ rpT,
+                                                       const int32_t* __restrict__ ciT,
+                                                       const int32_t* __restrict__ perm,
+                                                       const T* __restrict__ w,
+                                                       const T* __restrict__ x,
+                                                       T* __restrict__ gv) {
+  const int b = xcd_block(blockIdx.x, gridDim.x);
+  const int j = b * (kThreads / G) + threadIdx.x / G;
+  const int sub = threadIdx.x % G;
+  if (j >= n) return;
+  const T xj = x[j];
+  for (int t = rpT[j] + sub; t < rpT[j + 1]; t += G) gv[perm[t]] = -w[ciT[t]] * xj;
+}
+
+int lanes_for(long long nnz, int rows) {
+  if (rows <= 0) return 1;
+  const double mean = (double)nnz / rows;
+  int g = 1;
+  while (g < 64 && g < mean) g <<= 1;
+  return g;
+}
+
+#define CSRAD_G_SWITCH(g, ...)                            \
+  switch (g) {                                            \
+    case 1: { constexpr int G = 1; __VA_ARGS__; } break;   \
+    case 2: { constexpr int G = 2; __VA_ARGS__; } break;   \
+    case 4: { constexpr int G = 4; __VA_ARGS__; } break;   \
+    case 8: { constexpr int G = 8; __VA_ARGS__; } break;   \
+    case 16: { constexpr int G = 16; __VA_ARGS__; } break; \
+    case 32: { constexpr int G = 32; __VA_ARGS__; } break; \
+    default: { constexpr int G = 64; __VA_ARGS__; } break; \
+  }
+
+// Runs the levels: big ones as grid launches, runs of small ones in one
+// workgroup.  REVERSE visits levels from last to first.
+template <typename T, int G, bool PERM, bool REVERSE>
+void run_levels(int nlevels, const int32_t* lp_host, const int32_t* lp_dev, const int32_t* rows,
+                int lower, const int32_t* rp, const int32_t* ci, const int32_t* perm,
+                const T* vals, const T* b, T* x, hipStream_t s) {
+  auto big = [&](int l) { return lp_host[l + 1] - lp_host[l] >= kBigLevel; };
+  int t = 0;
+  while (t < nlevels) {
+    const int l = REVERSE ? nlevels - 1 - t : t;
+    if (big(l)) {
+      const int lo = lp_host[l], hi = lp_host[l + 1];
+      const int rpb = kThreads / G;
+      hipLaunchKernelGGL((k_tri_level<T, G, PERM>), dim3((hi - lo + rpb - 1) / rpb), dim3(kThreads),
+                         0, s, lo, hi, lower, rows, rp, ci, perm, vals, b, x);
+      ++t;
+      continue;
+    }
+    int u = t;
+    while (u < nlevels && !big(REVERSE ? nlevels - 1 - u : u)) ++u;
+    // levels t..u-1 in visiting order
+    const int l0 = REVERSE ? nlevels - u : t;
+    const int l1 = REVERSE ? nlevels - t : u;
+    hipLaunchKernelGGL((k_tri_levels_block<T, G, PERM, REVERSE>), dim3(1), dim3(kOneBlockThreads),
+                       0, s, l0, l1, lower, lp_dev, rows, rp, ci, perm, vals, b, x);
+    t = u;
+  }
+}
+
+template <typename T>
+int trisolve_fwd_t(const csrad_csr* Tm, int lower, int nlevels, const int32_t* lp_host,
+                   const int32_t* lp_dev, const int32_t* rows, const T* b, T* x, hipStream_t s) {
+  const T* v = static_cast<const T*>(Tm->vals);
+  CSRAD_G_SWITCH(lanes_for(Tm->nnz, Tm->nrows),
+                 (run_levels<T, G, false, false>(nlevels, lp_host, lp_dev, rows, lower, Tm->rowptr,
+                                                 Tm->colind, nullptr, v, b, x, s)));
+  return launch_status();
+}
+
+template <typename T>
+int trisolve_bwd_t(const csrad_csr* Tm, int lower, const csrad_csr* Tt, const int32_t* perm,
+                   int nlevels, const int32_t* lp_host, const int32_t* lp_dev, const int32_t* rows,
+                   const T* x, const T* gx, T* gb, T* gv, hipStream_t s) {
+  const T* v = static_cast<const T*>(Tm->vals);
+  const int n = Tm->nrows;
+  // T^T is triangular on the other side: row j of T^T depends on i when
+  // (i, j) is on T's solve side, i.e. the opposite orientation.
+  const int lower_t = lower ? 0 : 1;
+  const int g = lanes_for(Tm->nnz, n);
+  CSRAD_G_SWITCH(g, (run_levels<T, G, true, true>(nlevels, lp_host, lp_dev, rows, lower_t,
+                                                  Tt->rowptr, Tt->colind, perm, v, gx, gb, s)));
+  if (gv) {
+    CSRAD_G_SWITCH(g, hipLaunchKernelGGL((k_tri_gvals<T, G>),
+                                         dim3((n + kThreads / G - 1) / (kThreads / G)),
+                                         dim3(kThreads), 0, s, n, Tt->rowptr, Tt->colind, perm, gb,
+                                         x, gv));
+  }
+  return launch_status();
+}
+
+struct TriWs {
+  int32_t* indeg;
+  int32_t* fa;
+  int32_t* fb;
+  int32_t* counters;  // [0] front_n, [1] bad_row, [2] nlevels
+  int32_t* iota;
+  int32_t* perm;
+  void* tws;
+  size_t tws_bytes;
+};
+
+TriWs carve_tri(Carver& cv, int n) {
+  TriWs w;
+  w.indeg = cv.take<int32_t>((size_t)n);
+  w.fa = cv.take<int32_t>((size_t)n);
+  w.fb = cv.take<int32_t>((size_t)n);
+  w.counters = cv.take<int32_t>(4);
+  w.iota = cv.take<int32_t>((size_t)n + 1);
+  w.perm = cv.take<int32_t>((size_t)n);
+  w.tws_bytes = transpose_workspace(n, n, n);
+  w.tws = cv.take<char>(w.tws_bytes);
+  return w;
+}
+
+int check_levels(const csrad_csr* Tm, int nlevels, const int32_t* lp_host, const int32_t* rows) {
+  if (nlevels < 0 || (Tm->nrows > 0 && (nlevels == 0 || !lp_host || !rows))) return CSRAD_EINVAL;
+  if (Tm->nrows > 0 && (lp_host[0] != 0 || lp_host[nlevels] != Tm->nrows)) return CSRAD_EINVAL;
+  return CSRAD_OK;
+}
+
+}  // namespace
+}  // namespace csrad
+
+using namespace csrad;
+
+extern "C" int csr_trisolve_workspace(const csrad_csr* Tm, size_t* bytes) {
+  if (!Tm || !bytes || Tm->nrows < 0) return CSRAD_EINVAL;
+  Carver cv(nullptr, 0);
+  carve_tri(cv, Tm->nrows);
+  *bytes = cv.off + 256;
+  return CSRAD_OK;
+}
+
+extern "C" int csr_trisolve_analyze(const csrad_csr* Tm, int32_t lower, const csrad_csr* Tt,
+                                    int32_t* level_of_row, int32_t* level_ptr,
+                                    int32_t* level_rows, int32_t* nlevels_host, void* work,
+                                    size_t work_bytes, void* stream) {
+  CSRAD_TRY(check_csr(Tm, false));
+  CSRAD_TRY(check_csr(Tt, false));
+  if (Tm->nrows != Tm->ncols || Tt->nrows != Tm->ncols || Tt->ncols != Tm->nrows ||
+      Tt->nnz != Tm->nnz)
+    return CSRAD_EINVAL;
+  if (!level_ptr || !nlevels_host) return CSRAD_EINVAL;
+  const int n = Tm->nrows;
+  if (n > 0 && (!level_of_row || !level_rows)) return CSRAD_EINVAL;
+  hipStream_t s = as_stream(stream);
+  Carver cv(work, work_bytes);
+  TriWs w = carve_tri(cv, n);
+  if (!work || !cv.ok) return CSRAD_EWORKSPACE;
+  if (n == 0) {
+    *nlevels_host = 0;
+    CSRAD_TRY(fill_i32(level_ptr, 1, 0, s));
+    return hipStreamSynchronize(s) == hipSuccess ? CSRAD_OK : CSRAD_EHIP;
+  }
+  CSRAD_TRY(fill_i32(w.counters, 1, 0, s));
+  CSRAD_TRY(fill_i32(w.counters + 1, 1, INT32_MAX, s));
+  CSRAD_TRY(fill_i32(w.counters + 2, 1, 0, s));
+  hipLaunchKernelGGL(k_tri_prep, dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0, s, n,
+                     lower ? 1 : 0, Tm->rowptr, Tm->colind, w.indeg, w.fa, w.counters,
+                     w.counters + 1);
+  hipLaunchKernelGGL(k_tri_kahn, dim3(1), dim3(kKahnThreads), 0, s, n, lower ? 1 : 0, Tt->rowptr,
+                     Tt->colind, w.indeg, w.fa, w.fb, w.counters, level_of_row, w.counters + 2);
+  CSRAD_TRY(launch_status());
+  int32_t host[4];
+  if (hipMemcpyAsync(host, w.counters, sizeof(host), hipMemcpyDeviceToHost, s) != hipSuccess)
+    return CSRAD_EHIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return CSRAD_EHIP;
+  if (host[1] != INT32_MAX) return CSRAD_ESINGULAR;
+  const int nl = host[2];
+  *nlevels_host = nl;
+  // With a stored diagonal everywhere the graph is acyclic (triangular),
+  // so Kahn places every row.
+  hipLaunchKernelGGL(k_iota, dim3((n + 1 + 255) / 256 < 4096 ? (n + 1 + 255) / 256 : 4096),
+                     dim3(256), 0, s, w.iota, n + 1);
+  CSRAD_TRY(transpose_pattern(n, nl, n, w.iota, level_of_row, level_ptr, level_rows, w.perm,
+                              w.tws, w.tws_bytes, s));
+  return hipStreamSynchronize(s) == hipSuccess ? CSRAD_OK : CSRAD_EHIP;
+}
+
+extern "C" int csr_trisolve_fwd(const csrad_csr* Tm, int32_t lower, int32_t nlevels,
+                                const int32_t* level_ptr_host, const int32_t* level_ptr,
+                                const int32_t* level_rows, const void* b, void* x, void* stream) {
+  CSRAD_TRY(check_csr(Tm, true));
+  if (Tm->nrows != Tm->ncols) return CSRAD_EINVAL;
+  CSRAD_TRY(check_levels(Tm, nlevels, level_ptr_host, level_rows));
+  if (Tm->nrows == 0) return CSRAD_OK;
+  if (!b || !x || !level_ptr) return CSRAD_EINVAL;
+  hipStream_t s = as_stream(stream);
+  if (Tm->dtype == CSRAD_F32)
+    return trisolve_fwd_t<float>(Tm, lower ? 1 : 0, nlevels, level_ptr_host, level_ptr, level_rows,
+                                 static_cast<const float*>(b), static_cast<float*>(x), s);
+  return trisolve_fwd_t<double>(Tm, lower ? 1 : 0, nlevels, level_ptr_host, level_ptr, level_rows,
+                                static_cast<const double*>(b), static_cast<double*>(x), s);
+}
+
+extern "C" int csr_trisolve_bwd(const csrad_csr* Tm, int32_t lower, const csrad_csr* Tt,
+                                const int32_t* perm, int32_t nlevels,
+                                const int32_t* level_ptr_host, const int32_t* level_ptr,
+                                const int32_t* level_rows, const void* x, const void* gx, void* gb,
+                                void* gvals, void* stream) {
+  CSRAD_TRY(check_csr(Tm, true));
+  CSRAD_TRY(check_csr(Tt, false));
+  if (Tm->nrows != Tm->ncols || Tt->nrows != Tm->ncols || Tt->ncols != Tm->nrows ||
+      Tt->nnz != Tm->nnz)
+    return CSRAD_EINVAL;
+  CSRAD_TRY(check_levels(Tm, nlevels, level_ptr_host, level_rows));
+  if (Tm->nrows == 0) return CSRAD_OK;
+  if (!gx || !gb || !level_ptr || (Tm->nnz > 0 && !perm) || (gvals && !x)) return CSRAD_EINVAL;
+  hipStream_t s = as_stream(stream);
+  if (Tm->dtype == CSRAD_F32)
+    return trisolve_bwd_t<float>(Tm, lower ? 1 : 0, Tt, perm, nlevels, level_ptr_host, level_ptr,
+                                 level_rows, static_cast<const float*>(x),
+                                 static_cast<const float*>(gx), static_cast<float*>(gb),
+                                 static_cast<float*>(gvals), s);
+  return trisolve_bwd_t<double>(Tm, lower ? 1 : 0, Tt, perm, nlevels, level_ptr_host, level_ptr,
+                                level_rows, static_cast<const double*>(x),
+                                static_cast<const double*>(gx), static_cast<double*>(gb),
+                                static_cast<double*>(gvals), s);
+}

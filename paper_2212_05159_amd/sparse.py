@@ -1,0 +1,251 @@
+"""CSR tensors on the GPU and their differentiable operations.
+
+``Pattern`` is an immutable device CSR pattern (rowptr, colind) that caches
+what only depends on the pattern: its transpose (pattern + permutation)
+and triangular level sets.  ``CsrTensor`` pairs a pattern with a value
+array that may require grad; ``@`` dispatches to SpMV (vector), SpDMM
+(matrix) or SpSpMM (CsrTensor), and ``solve_triangular`` to the level-
+scheduled solve.  Each op is a ``torch.autograd.Function`` whose forward and
+backward call the HIP library through ``capi``; gradients of sparse inputs
+are value arrays on the input's own pattern (Section 3.1, Table 1).
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import capi
+
+
+class Pattern:
+    def __init__(self, nrows, ncols, rowptr, colind):
+        assert rowptr.dtype == torch.int32 and colind.dtype == torch.int32
+        self.nrows, self.ncols = int(nrows), int(ncols)
+        self.rowptr, self.colind = rowptr, colind
+        self._t = None
+        self._levels = {}
+
+    @property
+    def nnz(self):
+        return int(self.colind.numel())
+
+    @property
+    def device(self):
+        return self.rowptr.device
+
+    def desc(self, vals=None, dtype=torch.float32):
+        return capi.desc(self.nrows, self.ncols, self.rowptr, self.colind, vals,
+                         dtype=vals.dtype if vals is not None else dtype)
+
+    def transpose(self):
+        """(Pattern of A^T, perm) with valsT = vals[perm]; cached."""
+        if self._t is None:
+            d = self.desc()
+            rpT = torch.empty(self.ncols + 1, dtype=torch.int32, device=self.device)
+            ciT = torch.empty(self.nnz, dtype=torch.int32, device=self.device)
+            perm = torch.empty(self.nnz, dtype=torch.int32, device=self.device)
+            ws = capi._ws(capi.csr_transpose_workspace(d), self.device)
+            capi.csr_transpose(d, rpT, ciT, perm, ws)
+            self._t = (Pattern(self.ncols, self.nrows, rpT, ciT), perm)
+        return self._t
+
+    def levels(self, lower=True):
+        """Level sets of the triangular solve; cached per orientation.
+        Returns (nlevels, level_ptr_host ndarray, level_ptr, level_rows,
+        level_of_row)."""
+        key = bool(lower)
+        if key not in self._levels:
+            Tt, _ = self.transpose()
+            n = self.nrows
+            lor = torch.empty(n, dtype=torch.int32, device=self.device)
+            lptr = torch.empty(n + 1, dtype=torch.int32, device=self.device)
+            lrows = torch.empty(n, dtype=torch.int32, device=self.device)
+            d = self.desc()
+            ws = capi._ws(capi.csr_trisolve_workspace(d), self.device)
+            nl = capi.csr_trisolve_analyze(d, int(key), Tt.desc(), lor, lptr, lrows, ws)
+            lptr = lptr[: nl + 1].clone()
+            self._levels[key] = (nl, np.ascontiguousarray(lptr.cpu().numpy()), lptr, lrows, lor)
+        return self._levels[key]
+
+    @classmethod
+    def from_host(cls, m, device="cuda"):
+        return cls(m.nrows, m.ncols, torch.as_tensor(np.asarray(m.rowptr, np.int32), device=device),
+                   torch.as_tensor(np.asarray(m.colind, np.int32), device=device))
+
+
+# ----------------------------------------------------------------------
+# Functional forms (allocate outputs, call the library).
+# ----------------------------------------------------------------------
+
+def spmv(P, vals, x):
+    y = torch.empty(P.nrows, dtype=vals.dtype, device=vals.device)
+    capi.csr_spmv_fwd(P.desc(vals), x, y)
+    return y
+
+
+def spmv_bwd(P, vals, x, gy, need_x=True, need_vals=True, use_transpose=True):
+    gx = torch.empty(P.ncols, dtype=vals.dtype, device=vals.device) if need_x else None
+    gv = torch.empty(P.nnz, dtype=vals.dtype, device=vals.device) if need_vals else None
+    if use_transpose:
+        Pt, perm = P.transpose()
+        capi.csr_spmv_bwd(P.desc(vals), Pt.desc(dtype=vals.dtype), perm, x, gy, gx, gv)
+    else:
+        capi.csr_spmv_bwd(P.desc(vals), None, None, x, gy, gx, gv)
+    return gx, gv
+
+
+def spmm(P, vals, B):
+    k = B.shape[1]
+    out = torch.empty(P.nrows, k, dtype=vals.dtype, device=vals.device)
+    capi.csr_spmm_fwd(P.desc(vals), k, B, B.stride(0), out, out.stride(0))
+    return out
+
+
+def spmm_bwd(P, vals, B, gC, need_B=True, need_vals=True):
+    k = gC.shape[1]
+    gB = torch.empty(P.ncols, k, dtype=vals.dtype, device=vals.device) if need_B else None
+    gv = torch.empty(P.nnz, dtype=vals.dtype, device=vals.device) if need_vals else None
+    Pt, perm = P.transpose() if need_B else (None, None)
+    capi.csr_spmm_bwd(P.desc(vals), Pt.desc(dtype=vals.dtype) if Pt is not None else None, perm, k,
+                      B, B.stride(0) if B is not None else k, gC, gC.stride(0), gB,
+                      gB.stride(0) if gB is not None else k, gv)
+    return gB, gv
+
+
+def spgemm(PA, valsA, PB, valsB):
+    """C = A B.  Returns (Pattern of C, valsC)."""
+    dA, dB = PA.desc(valsA), PB.desc(valsB)
+    ws = capi._ws(capi.csr_spgemm_workspace(dA, dB), valsA.device)
+    rpC = torch.empty(PA.nrows + 1, dtype=torch.int32, device=valsA.device)
+    nnz = capi.csr_spgemm_symbolic(dA, dB, rpC, ws)
+    ciC = torch.empty(nnz, dtype=torch.int32, device=valsA.device)
+    vC = torch.empty(nnz, dtype=valsA.dtype, device=valsA.device)
+    capi.csr_spgemm_fwd(dA, dB, rpC, ciC, vC, ws)
+    return Pattern(PA.nrows, PB.ncols, rpC, ciC), vC
+
+
+def spgemm_bwd(PA, valsA, PB, valsB, PC, gC, need_A=True, need_B=True):
+    gA = torch.empty(PA.nnz, dtype=valsA.dtype, device=valsA.device) if need_A else None
+    gB = torch.empty(PB.nnz, dtype=valsB.dtype, device=valsB.device) if need_B else None
+    At, permA = PA.transpose() if need_B else (None, None)
+    capi.csr_spgemm_bwd(PA.desc(valsA), PB.desc(valsB),
+                        At.desc(dtype=valsA.dtype) if At is not None else None, permA,
+                        PC.desc(dtype=valsA.dtype), gC, gA, gB)
+    return gA, gB
+
+
+def trisolve(P, vals, b, lower=True):
+    nl, lph, lp, lr, _ = P.levels(lower)
+    x = torch.empty_like(b)
+    capi.csr_trisolve_fwd(P.desc(vals), int(lower), nl, lph, lp, lr, b, x)
+    return x
+
+
+def trisolve_bwd(P, vals, x, gx, lower=True, need_vals=True):
+    nl, lph, lp, lr, _ = P.levels(lower)
+    Pt, perm = P.transpose()
+    gb = torch.empty_like(gx)
+    gv = torch.empty(P.nnz, dtype=vals.dtype, device=vals.device) if need_vals else None
+    capi.csr_trisolve_bwd(P.desc(vals), int(lower), Pt.desc(dtype=vals.dtype), perm, nl, lph, lp,
+                          lr, x, gx, gb, gv)
+    return gb, gv
+
+
+# ----------------------------------------------------------------------
+# Autograd functions: differentiable inputs are value arrays and dense
+# operands; patterns are constants.
+# ----------------------------------------------------------------------
+
+class SpMV(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, P, vals, x):
+        ctx.P = P
+        ctx.save_for_backward(vals, x)
+        return spmv(P, vals, x.contiguous())
+
+    @staticmethod
+    def backward(ctx, gy):
+        vals, x = ctx.saved_tensors
+        gx, gv = spmv_bwd(ctx.P, vals, x.contiguous(), gy.contiguous(),
+                          need_x=ctx.needs_input_grad[2], need_vals=ctx.needs_input_grad[1])
+        return None, gv, gx
+
+
+class SpMM(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, P, vals, B):
+        ctx.P = P
+        ctx.save_for_backward(vals, B)
+        return spmm(P, vals, B.contiguous())
+
+    @staticmethod
+    def backward(ctx, gC):
+        vals, B = ctx.saved_tensors
+        gB, gv = spmm_bwd(ctx.P, vals, B.contiguous(), gC.contiguous(),
+                          need_B=ctx.needs_input_grad[2], need_vals=ctx.needs_input_grad[1])
+        return None, gv, gB
+
+
+class SpGEMM(torch.autograd.Function):
+    """Returns the value array of C; its pattern is stored on ``out_pattern``."""
+
+    @staticmethod
+    def forward(ctx, PA, valsA, PB, valsB, out_pattern):
+        PC, vC = spgemm(PA, valsA, PB, valsB)
+        out_pattern.append(PC)
+        ctx.PA, ctx.PB, ctx.PC = PA, PB, PC
+        ctx.save_for_backward(valsA, valsB)
+        return vC
+
+    @staticmethod
+    def backward(ctx, gC):
+        valsA, valsB = ctx.saved_tensors
+        gA, gB = spgemm_bwd(ctx.PA, valsA, ctx.PB, valsB, ctx.PC, gC.contiguous(),
+                            need_A=ctx.needs_input_grad[1], need_B=ctx.needs_input_grad[3])
+        return None, gA, None, gB, None
+
+
+class TriSolve(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, P, vals, b, lower):
+        x = trisolve(P, vals, b.contiguous(), lower)
+        ctx.P, ctx.lower = P, lower
+        ctx.save_for_backward(vals, x)
+        return x
+
+    @staticmethod
+    def backward(ctx, gx):
+        vals, x = ctx.saved_tensors
+        gb, gv = trisolve_bwd(ctx.P, vals, x, gx.contiguous(), ctx.lower,
+                              need_vals=ctx.needs_input_grad[1])
+        return None, gv, gb, None
+
+
+class CsrTensor:
+    """A CSR matrix on the GPU: constant pattern, (possibly trainable) values."""
+
+    def __init__(self, pattern: Pattern, vals: torch.Tensor):
+        assert vals.numel() == pattern.nnz
+        self.pattern, self.vals = pattern, vals
+
+    @property
+    def shape(self):
+        return (self.pattern.nrows, self.pattern.ncols)
+
+    @classmethod
+    def from_host(cls, m, dtype=torch.float32, device="cuda", requires_grad=False):
+        P = Pattern.from_host(m, device)
+        v = torch.as_tensor(np.asarray(m.vals), device=device).to(dtype)
+        return cls(P, v.requires_grad_(requires_grad))
+
+    def __matmul__(self, other):
+        if isinstance(other, CsrTensor):
+            box = []
+            vC = SpGEMM.apply(self.pattern, self.vals, other.pattern, other.vals, box)
+            return CsrTensor(box[0], vC)
+        if other.dim() == 1:
+            return SpMV.apply(self.pattern, self.vals, other)
+        return SpMM.apply(self.pattern, self.vals, other)
+
+    def solve_triangular(self, b, lower=True):
+        return TriSolve.apply(self.pattern, self.vals, b, lower)
