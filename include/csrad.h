@@ -106,6 +106,9 @@ int csr_spmm_bwd(const csrad_csr *A, const csrad_csr *At, const int32_t *perm,
 int csr_transpose_workspace(const csrad_csr *A, size_t *bytes);
 int csr_transpose(const csrad_csr *A, int32_t *rowptrT, int32_t *colindT,
                   int32_t *perm, void *work, size_t work_bytes, void *stream);
+/* Values of A^T in A^T's order: valsT[t] = vals[perm[t]] (nnz entries). */
+int csr_transpose_vals(const csrad_csr *A, const int32_t *perm, void *valsT,
+                       void *stream);
 
 /* ---------------------------------------------------------------------
  * SpSpMM, sparse times sparse (Section 3.1.2; Table 1, SpSpMM row).

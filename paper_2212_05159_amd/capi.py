@@ -40,6 +40,7 @@ _SIGS = {
                                C.c_void_p, C.c_void_p]),
     "csr_transpose_workspace": (C.c_int, [C.c_void_p, C.POINTER(C.c_size_t)]),
     "csr_transpose": (C.c_int, [C.c_void_p] * 5 + [C.c_size_t, C.c_void_p]),
+    "csr_transpose_vals": (C.c_int, [C.c_void_p] * 4),
     "csr_spgemm_workspace": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_size_t)]),
     "csr_spgemm_symbolic": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p,
                                       C.POINTER(C.c_int64), C.c_void_p, C.c_size_t,
@@ -149,6 +150,11 @@ def csr_transpose_workspace(A):
 def csr_transpose(A, rowptrT, colindT, perm, work):
     _check("csr_transpose", load().csr_transpose(C.byref(A), _ptr(rowptrT), _ptr(colindT),
                                                  _ptr(perm), _ptr(work), work.numel(), _stream()))
+
+
+def csr_transpose_vals(A, perm, valsT):
+    _check("csr_transpose_vals", load().csr_transpose_vals(C.byref(A), _ptr(perm), _ptr(valsT),
+                                                           _stream()))
 
 
 def csr_spgemm_workspace(A, B):

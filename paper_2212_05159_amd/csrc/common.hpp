@@ -89,6 +89,40 @@ __device__ __forceinline__ int group_sum_int(int v) {
 }
 
 // ---------------------------------------------------------------------
+// Wave-aggregated atomic increment: lanes holding the same key combine
+// into one atomicAdd on counter[key] (a few rounds of "leader takes all
+// lanes with its key"; lanes left over after kAggRounds add one by one).
+// Returns this lane's slot: the counter's old value plus its rank among
+// the lanes that shared the atomic.  Call with the lanes that have an
+// element active; every active lane must reach the call.
+// ---------------------------------------------------------------------
+constexpr int kAggRounds = 4;
+__device__ __forceinline__ int wave_agg_add(int32_t* counter, int key) {
+  const int lane = __lane_id();
+  const unsigned long long lt = (1ull << lane) - 1ull;
+  unsigned long long todo = __ballot(1);
+  int slot = 0;
+  bool done = false;
+#pragma unroll
+  for (int r = 0; r < kAggRounds; ++r) {
+    if (!todo) break;
+    const int leader = __ffsll((long long)todo) - 1;
+    const int lkey = __shfl(key, leader);
+    const unsigned long long peers = __ballot(!done && key == lkey) & todo;
+    int old = 0;
+    if (lane == leader) old = atomicAdd(&counter[lkey], __popcll(peers));
+    old = __shfl(old, leader);
+    if ((peers >> lane) & 1ull) {
+      slot = old + __popcll(peers & lt);
+      done = true;
+    }
+    todo &= ~peers;
+  }
+  if (!done) slot = atomicAdd(&counter[key], 1);
+  return slot;
+}
+
+// ---------------------------------------------------------------------
 // Vector types for 16-byte dense-row accesses.
 // ---------------------------------------------------------------------
 template <typename T, int VW>

@@ -19,6 +19,12 @@ int transpose_pattern(int m, int n, int nnz, const int32_t* rowptr, const int32_
                       int32_t* rowptrT, int32_t* colindT, int32_t* perm, void* work,
                       size_t bytes, hipStream_t s);
 
+// Stable grouping of n indices by a key in [0, K), K <= 32 (see
+// transpose.hip): ptr[K+1], order[n] (indices ascending within a key).
+size_t group_small_workspace(int n, int K);
+int group_small_keys(const int32_t* keys, int n, int K, int32_t* ptr, int32_t* order, void* work,
+                     size_t bytes, hipStream_t s);
+
 // Fill a device int32 array with a value (graph-capture safe, no memset node).
 int fill_i32(int32_t* p, long long n, int32_t value, hipStream_t s);
 int fill_bytes_zero(void* p, size_t bytes, hipStream_t s);

@@ -74,12 +74,26 @@ __global__ void k_bin_offsets(const int32_t* __restrict__ bin_cnt, int32_t* __re
   }
 }
 
-// ... and the row lists (order within a bin is irrelevant).
+// ... and the row lists (order within a bin is irrelevant).  Each block
+// counts its rows per bin in LDS and reserves one range per bin.
 __global__ __launch_bounds__(kThreads) void k_bin_fill(int m, const int8_t* __restrict__ binid,
                                                        int32_t* __restrict__ cursor,
                                                        int32_t* __restrict__ list) {
+  __shared__ int cnt[kNumBins];
+  __shared__ int base[kNumBins];
+  if (threadIdx.x < kNumBins) cnt[threadIdx.x] = 0;
+  __syncthreads();
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < m) list[atomicAdd(&cursor[binid[i]], 1)] = i;
+  int b = 0, r = 0;
+  if (i < m) {
+    b = binid[i];
+    r = atomicAdd(&cnt[b], 1);
+  }
+  __syncthreads();
+  if (threadIdx.x < kNumBins && cnt[threadIdx.x])
+    base[threadIdx.x] = atomicAdd(&cursor[threadIdx.x], cnt[threadIdx.x]);
+  __syncthreads();
+  if (i < m) list[base[b] + r] = i;
 }
 
 __device__ __forceinline__ unsigned hash_slot(int j, int H) {

@@ -21,7 +21,7 @@ __global__ __launch_bounds__(256) void k_count_cols(const int32_t* __restrict__ 
                                                     int32_t* __restrict__ cnt) {
   for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < nnz;
        e += (long long)gridDim.x * blockDim.x)
-    atomicAdd(&cnt[colind[e]], 1);
+    wave_agg_add(cnt, colind[e]);
 }
 
 __global__ __launch_bounds__(256) void k_copy_i32(const int32_t* __restrict__ src, int n,
@@ -42,7 +42,7 @@ __global__ __launch_bounds__(256) void k_scatter(int m, const int32_t* __restric
   if (row >= m) return;
   const int e1 = rowptr[row + 1];
   for (int e = rowptr[row] + sub; e < e1; e += 8) {
-    const int slot = atomicAdd(&cursor[colind[e]], 1);
+    const int slot = wave_agg_add(cursor, colind[e]);
     tkey[slot] = row;
     tval[slot] = e;
   }
@@ -201,6 +201,83 @@ __global__ __launch_bounds__(256) void k_rank_long(const int32_t* __restrict__ r
   }
 }
 
+// ---------------------------------------------------------------------
+// Stable grouping of n elements by a small key (K <= kSmallKeys): the
+// element indices come out ordered by key, ascending index within a key.
+// Per tile of kMsTile elements: a key histogram, then a scan over
+// (key, tile) gives each tile's base per key; inside a tile the rank of
+// an element among equal keys before it comes from wave ballots and
+// per-wave counts, chunk by chunk.  No global atomics, deterministic.
+// ---------------------------------------------------------------------
+constexpr int kSmallKeys = 32;
+constexpr int kMsChunks = 8;
+constexpr int kMsTile = 256 * kMsChunks;
+
+__global__ __launch_bounds__(256) void k_ms_hist(const int32_t* __restrict__ keys, int n, int K,
+                                                 int ntiles, int32_t* __restrict__ hist) {
+  __shared__ int h[kSmallKeys];
+  if (threadIdx.x < kSmallKeys) h[threadIdx.x] = 0;
+  __syncthreads();
+  const long long base = (long long)blockIdx.x * kMsTile;
+  for (int c = 0; c < kMsChunks; ++c) {
+    const long long i = base + c * 256 + threadIdx.x;
+    if (i < n) atomicAdd(&h[keys[i]], 1);
+  }
+  __syncthreads();
+  if (threadIdx.x < K) hist[(long long)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
+}
+
+__global__ __launch_bounds__(256) void k_ms_scatter(const int32_t* __restrict__ keys, int n,
+                                                    int K, int ntiles,
+                                                    const int32_t* __restrict__ off,
+                                                    int32_t* __restrict__ order) {
+  __shared__ int wcount[4][kSmallKeys];
+  __shared__ int running[kSmallKeys];
+  const int lane = __lane_id(), w = threadIdx.x / kWave;
+  const unsigned long long lt = (1ull << lane) - 1ull;
+  if (threadIdx.x < kSmallKeys) running[threadIdx.x] = 0;
+  for (int q = threadIdx.x; q < 4 * kSmallKeys; q += 256) (&wcount[0][0])[q] = 0;
+  __syncthreads();
+  const long long base = (long long)blockIdx.x * kMsTile;
+  for (int c = 0; c < kMsChunks; ++c) {
+    const long long i = base + c * 256 + threadIdx.x;
+    const bool act = i < n;
+    const int key = act ? keys[i] : -1;
+    // peers: lanes of this wave with the same key (loop over distinct keys)
+    unsigned long long todo = __ballot(act);
+    unsigned long long peers = 0;
+    while (todo) {
+      const int leader = __ffsll((long long)todo) - 1;
+      const int lkey = __shfl(key, leader);
+      const unsigned long long m = __ballot(act && key == lkey);
+      if (act && key == lkey) peers = m;
+      if (lane == leader) wcount[w][lkey] = __popcll(m);
+      todo &= ~m;
+    }
+    __syncthreads();
+    if (act) {
+      int pre = running[key];
+      for (int v = 0; v < w; ++v) pre += wcount[v][key];
+      order[off[(long long)key * ntiles + blockIdx.x] + pre + __popcll(peers & lt)] = (int32_t)i;
+    }
+    __syncthreads();
+    if (threadIdx.x < K) {
+      int t = 0;
+      for (int v = 0; v < 4; ++v) t += wcount[v][threadIdx.x];
+      running[threadIdx.x] += t;
+    }
+    for (int q = threadIdx.x; q < 4 * kSmallKeys; q += 256) (&wcount[0][0])[q] = 0;
+    __syncthreads();
+  }
+}
+
+__global__ void k_ms_ptr(const int32_t* __restrict__ off, int K, int ntiles, int n,
+                         int32_t* __restrict__ ptr) {
+  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l < K) ptr[l] = off[(long long)l * ntiles];
+  if (l == K) ptr[K] = n;
+}
+
 struct TransposeWs {
   int32_t* cnt;
   void* scan_ws;
@@ -230,6 +307,15 @@ unsigned grid_for(long long work, int threads, unsigned cap = 65536) {
   if (b < 1) b = 1;
   if (b > cap) b = cap;
   return (unsigned)b;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_gather_vals(int nnz, const int32_t* __restrict__ perm,
+                                                     const T* __restrict__ vals,
+                                                     T* __restrict__ out) {
+  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < nnz;
+       t += (long long)gridDim.x * blockDim.x)
+    out[t] = vals[perm[t]];
 }
 
 }  // namespace
@@ -269,6 +355,36 @@ int transpose_pattern(int m, int n, int nnz, const int32_t* rowptr, const int32_
   return launch_status();
 }
 
+size_t group_small_workspace(int n, int K) {
+  const size_t ntiles = (size_t)(n + kMsTile - 1) / kMsTile;
+  const size_t cells = ntiles * (size_t)(K > 0 ? K : 1);
+  Carver cv(nullptr, 0);
+  cv.take<int32_t>(cells);
+  cv.take<int32_t>(cells + 1);
+  cv.take<char>(scan_workspace((int)cells));
+  cv.take<long long>(1);
+  return cv.off + 256;
+}
+
+int group_small_keys(const int32_t* keys, int n, int K, int32_t* ptr, int32_t* order, void* work,
+                     size_t bytes, hipStream_t s) {
+  if (K < 1 || K > kSmallKeys || n < 1) return CSRAD_EINVAL;
+  const int ntiles = (n + kMsTile - 1) / kMsTile;
+  const int cells = ntiles * K;
+  Carver cv(work, bytes);
+  int32_t* hist = cv.take<int32_t>(cells);
+  int32_t* off = cv.take<int32_t>((size_t)cells + 1);
+  const size_t sb = scan_workspace(cells);
+  void* sws = cv.take<char>(sb);
+  long long* total = cv.take<long long>(1);
+  if (!work || !cv.ok) return CSRAD_EWORKSPACE;
+  hipLaunchKernelGGL(k_ms_hist, dim3(ntiles), dim3(256), 0, s, keys, n, K, ntiles, hist);
+  CSRAD_TRY(scan_exclusive(hist, off, cells, total, sws, sb, s));
+  hipLaunchKernelGGL(k_ms_scatter, dim3(ntiles), dim3(256), 0, s, keys, n, K, ntiles, off, order);
+  hipLaunchKernelGGL(k_ms_ptr, dim3(1), dim3(64), 0, s, off, K, ntiles, n, ptr);
+  return launch_status();
+}
+
 }  // namespace csrad
 
 using namespace csrad;
@@ -286,4 +402,20 @@ extern "C" int csr_transpose(const csrad_csr* A, int32_t* rowptrT, int32_t* coli
   if (!rowptrT || (A->nnz > 0 && (!colindT || !perm))) return CSRAD_EINVAL;
   return transpose_pattern(A->nrows, A->ncols, A->nnz, A->rowptr, A->colind, rowptrT, colindT,
                            perm, work, work_bytes, as_stream(stream));
+}
+
+extern "C" int csr_transpose_vals(const csrad_csr* A, const int32_t* perm, void* valsT,
+                                  void* stream) {
+  CSRAD_TRY(check_csr(A, true));
+  if (A->nnz == 0) return CSRAD_OK;
+  if (!perm || !valsT) return CSRAD_EINVAL;
+  hipStream_t s = as_stream(stream);
+  const unsigned g = grid_for(A->nnz, 256);
+  if (A->dtype == CSRAD_F32)
+    hipLaunchKernelGGL((k_gather_vals<float>), dim3(g), dim3(256), 0, s, A->nnz, perm,
+                       static_cast<const float*>(A->vals), static_cast<float*>(valsT));
+  else
+    hipLaunchKernelGGL((k_gather_vals<double>), dim3(g), dim3(256), 0, s, A->nnz, perm,
+                       static_cast<const double*>(A->vals), static_cast<double*>(valsT));
+  return launch_status();
 }

@@ -4,11 +4,13 @@
 // Analysis: the dependency graph of the solve (row i reads row j when T_ij
 // is stored on the solve side of the diagonal) is layered by longest path.
 //   1. per row: dependency count, stored diagonal check, level-0 rows;
-//   2. one workgroup runs Kahn's algorithm level by level (dependents of a
-//      row are its column, i.e. a row of T^T): a row joins the next level
-//      when its last dependency is placed;
-//   3. rows are grouped by level with the stable transpose of the
-//      row -> level map, so rows ascend within each level.
+//   2. Kahn's algorithm level by level (dependents of a row are its
+//      column, i.e. a row of T^T): a row joins the next level when its last
+//      dependency is placed; narrow levels run inside one workgroup, wide
+//      ones as grid launches;
+//   3. rows are grouped by level, ascending within each level (a stable
+//      multi-split by level for up to 32 levels, else the stable transpose
+//      of the row -> level map).
 // Level sets are unique, so the integer output is bit-exact.
 //
 // Solve: levels run in order.  A level with many rows is one grid launch;
@@ -57,39 +59,76 @@ __global__ __launch_bounds__(kThreads) void k_tri_prep(int n, int lower,
   if (deps == 0) front[atomicAdd(front_n, 1)] = i;
 }
 
-// Step 2: Kahn's algorithm in one workgroup.  Terminates after at most n
-// levels: every level places at least one row, and a row enters a
-// frontier once (when its count reaches zero).
-__global__ __launch_bounds__(kKahnThreads) void k_tri_kahn(
+// Step 2: Kahn's algorithm, level by level.  Dependents of row j are the
+// rows of column j of T, i.e. row j of T^T; a row joins the next level
+// when its last dependency is placed.  Levels with at most kKahnSmall rows
+// run inside one workgroup (barrier between levels); a wider level is one
+// grid launch.  State lives on the device: [0] rows in the current level,
+// [2] level index, [3] which frontier buffer is current, [4] scratch count.
+constexpr int kKahnSmall = 8192;
+
+__device__ __forceinline__ void kahn_visit(int j, int level, int lower,
+                                           const int32_t* __restrict__ rpT,
+                                           const int32_t* __restrict__ ciT,
+                                           int32_t* __restrict__ indeg, int32_t* __restrict__ nxt,
+                                           int* next_n, int32_t* __restrict__ level_of_row) {
+  level_of_row[j] = level;
+  for (int t = rpT[j]; t < rpT[j + 1]; ++t) {
+    const int i = ciT[t];
+    if (dep_side(lower, i, j) && atomicSub(&indeg[i], 1) == 1) nxt[atomicAdd(next_n, 1)] = i;
+  }
+}
+
+// Runs levels while the frontier is non-empty and small; terminates after
+// at most n levels (each level places at least one row, and a row enters a
+// frontier only once, when its count reaches zero).
+__global__ __launch_bounds__(kKahnThreads) void k_tri_kahn_small(
     int n, int lower, const int32_t* __restrict__ rpT, const int32_t* __restrict__ ciT,
     int32_t* __restrict__ indeg, int32_t* __restrict__ fa, int32_t* __restrict__ fb,
-    const int32_t* __restrict__ front_n, int32_t* __restrict__ level_of_row,
-    int32_t* __restrict__ nlevels) {
+    int32_t* __restrict__ state, int32_t* __restrict__ level_of_row) {
   __shared__ int next_n;
-  int cur_n = *front_n;
-  int* cur = fa;
-  int* nxt = fb;
-  int level = 0;
-  while (cur_n > 0 && level < n) {
+  int cur_n = state[0];
+  int level = state[2];
+  int which = state[3];
+  while (cur_n > 0 && cur_n <= kKahnSmall && level < n) {
+    int* cur = which ? fb : fa;
+    int* nxt = which ? fa : fb;
     if (threadIdx.x == 0) next_n = 0;
     __syncthreads();
-    for (int q = threadIdx.x; q < cur_n; q += blockDim.x) {
-      const int j = cur[q];
-      level_of_row[j] = level;
-      for (int t = rpT[j]; t < rpT[j + 1]; ++t) {
-        const int i = ciT[t];
-        if (dep_side(lower, i, j) && atomicSub(&indeg[i], 1) == 1) nxt[atomicAdd(&next_n, 1)] = i;
-      }
-    }
+    for (int q = threadIdx.x; q < cur_n; q += blockDim.x)
+      kahn_visit(cur[q], level, lower, rpT, ciT, indeg, nxt, &next_n, level_of_row);
     __syncthreads();
     cur_n = next_n;
-    int* tmp = cur;
-    cur = nxt;
-    nxt = tmp;
+    which ^= 1;
     ++level;
     __syncthreads();
   }
-  if (threadIdx.x == 0) *nlevels = level;
+  if (threadIdx.x == 0) {
+    state[0] = cur_n;
+    state[2] = level;
+    state[3] = which;
+  }
+}
+
+// One wide level over the whole grid; the frontier size comes from state.
+__global__ __launch_bounds__(kThreads) void k_tri_kahn_level(
+    int lower, const int32_t* __restrict__ rpT, const int32_t* __restrict__ ciT,
+    int32_t* __restrict__ indeg, int32_t* __restrict__ fa, int32_t* __restrict__ fb,
+    int32_t* __restrict__ state, int32_t* __restrict__ level_of_row) {
+  const int cur_n = state[0], level = state[2], which = state[3];
+  int* cur = which ? fb : fa;
+  int* nxt = which ? fa : fb;
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < cur_n) kahn_visit(cur[q], level, lower, rpT, ciT, indeg, nxt, &state[4], level_of_row);
+}
+
+__global__ void k_tri_kahn_advance(int32_t* __restrict__ state) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    state[0] = state[4];
+    state[4] = 0;
+    state[2] += 1;
+    state[3] ^= 1;
+  }
 }
 
 __global__ void k_iota(int32_t* p, int n) {
@@ -257,11 +296,13 @@ struct TriWs {
   int32_t* indeg;
   int32_t* fa;
   int32_t* fb;
-  int32_t* counters;  // [0] front_n, [1] bad_row, [2] nlevels
+  int32_t* counters;  // [0] frontier size, [1] bad row, [2] level, [3] buffer, [4] scratch
   int32_t* iota;
   int32_t* perm;
   void* tws;
   size_t tws_bytes;
+  void* gws;
+  size_t gws_bytes;
 };
 
 TriWs carve_tri(Carver& cv, int n) {
@@ -269,11 +310,13 @@ TriWs carve_tri(Carver& cv, int n) {
   w.indeg = cv.take<int32_t>((size_t)n);
   w.fa = cv.take<int32_t>((size_t)n);
   w.fb = cv.take<int32_t>((size_t)n);
-  w.counters = cv.take<int32_t>(4);
+  w.counters = cv.take<int32_t>(8);
   w.iota = cv.take<int32_t>((size_t)n + 1);
   w.perm = cv.take<int32_t>((size_t)n);
   w.tws_bytes = transpose_workspace(n, n, n);
   w.tws = cv.take<char>(w.tws_bytes);
+  w.gws_bytes = group_small_workspace(n, 32);
+  w.gws = cv.take<char>(w.gws_bytes);
   return w;
 }
 
@@ -317,28 +360,41 @@ extern "C" int csr_trisolve_analyze(const csrad_csr* Tm, int32_t lower, const cs
     CSRAD_TRY(fill_i32(level_ptr, 1, 0, s));
     return hipStreamSynchronize(s) == hipSuccess ? CSRAD_OK : CSRAD_EHIP;
   }
-  CSRAD_TRY(fill_i32(w.counters, 1, 0, s));
+  CSRAD_TRY(fill_i32(w.counters, 8, 0, s));
   CSRAD_TRY(fill_i32(w.counters + 1, 1, INT32_MAX, s));
-  CSRAD_TRY(fill_i32(w.counters + 2, 1, 0, s));
   hipLaunchKernelGGL(k_tri_prep, dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0, s, n,
                      lower ? 1 : 0, Tm->rowptr, Tm->colind, w.indeg, w.fa, w.counters,
                      w.counters + 1);
-  hipLaunchKernelGGL(k_tri_kahn, dim3(1), dim3(kKahnThreads), 0, s, n, lower ? 1 : 0, Tt->rowptr,
-                     Tt->colind, w.indeg, w.fa, w.fb, w.counters, level_of_row, w.counters + 2);
-  CSRAD_TRY(launch_status());
-  int32_t host[4];
-  if (hipMemcpyAsync(host, w.counters, sizeof(host), hipMemcpyDeviceToHost, s) != hipSuccess)
-    return CSRAD_EHIP;
-  if (hipStreamSynchronize(s) != hipSuccess) return CSRAD_EHIP;
-  if (host[1] != INT32_MAX) return CSRAD_ESINGULAR;
+  int32_t host[8];
+  for (;;) {
+    hipLaunchKernelGGL(k_tri_kahn_small, dim3(1), dim3(kKahnThreads), 0, s, n, lower ? 1 : 0,
+                       Tt->rowptr, Tt->colind, w.indeg, w.fa, w.fb, w.counters, level_of_row);
+    CSRAD_TRY(launch_status());
+    if (hipMemcpyAsync(host, w.counters, sizeof(host), hipMemcpyDeviceToHost, s) != hipSuccess)
+      return CSRAD_EHIP;
+    if (hipStreamSynchronize(s) != hipSuccess) return CSRAD_EHIP;
+    if (host[1] != INT32_MAX) return CSRAD_ESINGULAR;
+    if (host[0] == 0 || host[2] >= n) break;
+    // a wide level: one grid launch, then advance the state
+    hipLaunchKernelGGL(k_tri_kahn_level, dim3((host[0] + kThreads - 1) / kThreads), dim3(kThreads),
+                       0, s, lower ? 1 : 0, Tt->rowptr, Tt->colind, w.indeg, w.fa, w.fb,
+                       w.counters, level_of_row);
+    hipLaunchKernelGGL(k_tri_kahn_advance, dim3(1), dim3(64), 0, s, w.counters);
+  }
   const int nl = host[2];
   *nlevels_host = nl;
   // With a stored diagonal everywhere the graph is acyclic (triangular),
   // so Kahn places every row.
-  hipLaunchKernelGGL(k_iota, dim3((n + 1 + 255) / 256 < 4096 ? (n + 1 + 255) / 256 : 4096),
-                     dim3(256), 0, s, w.iota, n + 1);
-  CSRAD_TRY(transpose_pattern(n, nl, n, w.iota, level_of_row, level_ptr, level_rows, w.perm,
-                              w.tws, w.tws_bytes, s));
+  // Group rows by level, ascending within a level: a stable multi-split for
+  // few levels, otherwise the stable transpose of the row -> level map.
+  if (nl <= 32) {
+    CSRAD_TRY(group_small_keys(level_of_row, n, nl, level_ptr, level_rows, w.gws, w.gws_bytes, s));
+  } else {
+    hipLaunchKernelGGL(k_iota, dim3((n + 1 + 255) / 256 < 4096 ? (n + 1 + 255) / 256 : 4096),
+                       dim3(256), 0, s, w.iota, n + 1);
+    CSRAD_TRY(transpose_pattern(n, nl, n, w.iota, level_of_row, level_ptr, level_rows, w.perm,
+                                w.tws, w.tws_bytes, s));
+  }
   return hipStreamSynchronize(s) == hipSuccess ? CSRAD_OK : CSRAD_EHIP;
 }
 

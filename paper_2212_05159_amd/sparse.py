@@ -112,6 +112,14 @@ def spmm_bwd(P, vals, B, gC, need_B=True, need_vals=True):
     return gB, gv
 
 
+def transpose_vals(P, vals):
+    """Values of A^T in the order of P.transpose()'s pattern."""
+    _, perm = P.transpose()
+    out = torch.empty_like(vals)
+    capi.csr_transpose_vals(P.desc(vals), perm, out)
+    return out
+
+
 def spgemm(PA, valsA, PB, valsB):
     """C = A B.  Returns (Pattern of C, valsC)."""
     dA, dB = PA.desc(valsA), PB.desc(valsB)
@@ -249,3 +257,8 @@ class CsrTensor:
 
     def solve_triangular(self, b, lower=True):
         return TriSolve.apply(self.pattern, self.vals, b, lower)
+
+    def transpose(self):
+        """A^T with its values gathered by the library (not differentiable)."""
+        Pt, _ = self.pattern.transpose()
+        return CsrTensor(Pt, transpose_vals(self.pattern, self.vals.detach()))

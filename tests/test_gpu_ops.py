@@ -154,9 +154,18 @@ def _with_long_columns():
     return gen._from_coo(m, n, key // n, key % n, rng.standard_normal(len(key)))
 
 
+def _few_cols():
+    # 100000 x 3, nearly dense: every wave hits the same few counters
+    rng = np.random.default_rng(33)
+    mask = rng.random((100000, 3)) < 0.9
+    r, c = np.nonzero(mask)
+    return gen._from_coo(100000, 3, r, c, rng.standard_normal(len(r)))
+
+
 @pytest.mark.parametrize("name,A", MATS + [("long_cols", _with_long_columns()),
-                                           ("agg", gen.aggregation(10001, 8))],
-                         ids=[n for n, _ in MATS] + ["long_cols", "agg"])
+                                           ("agg", gen.aggregation(10001, 8)),
+                                           ("few_cols", _few_cols())],
+                         ids=[n for n, _ in MATS] + ["long_cols", "agg", "few_cols"])
 def test_transpose_bit_exact(name, A):
     P = sp.Pattern.from_host(A)
     Pt, perm = P.transpose()
@@ -231,6 +240,8 @@ def _tri_cases():
     yield "q1_four_colour", gen.tril(gen.permute_sym(gen.anisotropic_q1(64, 1e-3, np.pi / 4),
                                                      gen.four_color_2d(64))), True
     yield "q1_natural", gen.tril(gen.anisotropic_q1(48, 1e-2, 0.3)), True
+    yield "rb3d", gen.tril(gen.permute_sym(gen.poisson3d(40), gen.red_black_3d(40))), True
+    yield "rb3d_upper", gen.triu(gen.permute_sym(gen.poisson3d(24), gen.red_black_3d(24))), False
     yield "diag_only", gen._from_coo(3000, 3000, np.arange(3000), np.arange(3000),
                                      np.linspace(1, 2, 3000)), True
     yield "one", gen._from_coo(1, 1, [0], [0], [2.0]), True
