@@ -239,6 +239,25 @@ def cpu_baseline(h, bytes_total):
                       "single thread"}
 
 
+def calibrate(millions):
+    """valsT[t] = vals[perm[t]] with perm = identity: reads 8 bytes and
+    writes 4 bytes per value, once each."""
+    import torch
+    from paper_2212_05159_amd import capi
+
+    n = millions * 1000 * 1000
+    perm = torch.arange(n, dtype=torch.int32, device="cuda")
+    vals = torch.ones(n, dtype=torch.float32, device="cuda")
+    out = torch.empty_like(vals)
+    rp = torch.zeros(2, dtype=torch.int32, device="cuda")
+    d = capi.csrad_csr(1, n, n, capi.F32, rp.data_ptr(), perm.data_ptr(), vals.data_ptr())
+    for _ in range(3):
+        capi.csr_transpose_vals(d, perm, out)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibration": "k_gather_vals", "values": n, "read_bytes": 8 * n,
+                      "write_bytes": 4 * n}), flush=True)
+
+
 # ----------------------------------------------------------------------
 def main():
     ap = argparse.ArgumentParser()
@@ -248,6 +267,10 @@ def main():
     ap.add_argument("--grid", type=int, default=128)
     ap.add_argument("--k", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate", type=int, default=0, metavar="M",
+                    help="only run a copy-like kernel over M million float32 values "
+                         "(identity-permutation gather: 12 bytes per value) to calibrate "
+                         "hardware byte counters, then exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
@@ -258,6 +281,9 @@ def main():
     from paper_2212_05159_amd import capi
 
     capi.load()
+    if args.calibrate:
+        calibrate(args.calibrate)
+        return
     h = make_inputs(args.grid, args.k)
     d = Device(h)
     torch.cuda.synchronize()

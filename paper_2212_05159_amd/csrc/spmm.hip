@@ -18,7 +18,6 @@ namespace csrad {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kUnroll = 4;
 
 template <typename T, int VW>
 __device__ __forceinline__ Vec<T, VW> load_or_zero(const T* p, bool ok) {
@@ -28,6 +27,13 @@ __device__ __forceinline__ Vec<T, VW> load_or_zero(const T* p, bool ok) {
   for (int w = 0; w < VW; ++w) z.v[w] = T(0);
   return z;
 }
+
+// Entries are taken kBatch at a time: all index/value loads of a batch,
+// then all dense-row loads, then the multiply-adds, so each lane keeps
+// kBatch independent 16-byte loads in flight.  Short batches are padded by
+// repeating the last entry of the row with a zero weight (addresses stay
+// valid, no branch), so summation order is the row order.
+constexpr int kBatch = 8;
 
 template <typename T, int VW, int LPR>
 __global__ __launch_bounds__(kThreads) void k_spmm_fwd(int m, int k,
@@ -48,29 +54,22 @@ __global__ __launch_bounds__(kThreads) void k_spmm_fwd(int m, int k,
     T acc[VW];
 #pragma unroll
     for (int w = 0; w < VW; ++w) acc[w] = T(0);
-    int e = e0;
-    for (; e + kUnroll <= e1; e += kUnroll) {
-      int c[kUnroll];
-      T a[kUnroll];
-      Vec<T, VW> bv[kUnroll];
+    for (int eb = e0; eb < e1; eb += kBatch) {
+      int c[kBatch];
+      T a[kBatch];
 #pragma unroll
-      for (int u = 0; u < kUnroll; ++u) {
-        c[u] = ld_stream(&colind[e + u]);
-        a[u] = ld_stream(&vals[e + u]);
+      for (int u = 0; u < kBatch; ++u) {
+        const int e = min(eb + u, e1 - 1);
+        c[u] = ld_stream(&colind[e]);
+        a[u] = eb + u < e1 ? ld_stream(&vals[e]) : T(0);
       }
+      Vec<T, VW> bv[kBatch];
 #pragma unroll
-      for (int u = 0; u < kUnroll; ++u) bv[u] = load_vec<T, VW>(B + (long long)c[u] * ldb + col);
+      for (int u = 0; u < kBatch; ++u) bv[u] = load_vec<T, VW>(B + (long long)c[u] * ldb + col);
 #pragma unroll
-      for (int u = 0; u < kUnroll; ++u)
+      for (int u = 0; u < kBatch; ++u)
 #pragma unroll
         for (int w = 0; w < VW; ++w) acc[w] += a[u] * bv[u].v[w];
-    }
-    for (; e < e1; ++e) {
-      const int c = ld_stream(&colind[e]);
-      const T a = ld_stream(&vals[e]);
-      const Vec<T, VW> bv = load_vec<T, VW>(B + (long long)c * ldb + col);
-#pragma unroll
-      for (int w = 0; w < VW; ++w) acc[w] += a * bv.v[w];
     }
     Vec<T, VW> out;
 #pragma unroll
@@ -80,7 +79,10 @@ __global__ __launch_bounds__(kThreads) void k_spmm_fwd(int m, int k,
 }
 
 // One pass over A^T.  Row j of A^T lists the rows i of column j of A and,
-// through perm, the positions e of those entries in A.
+// through perm, the positions e of those entries in A.  Entries are taken
+// kBwdBatch at a time (loads first, then arithmetic), padded as above.
+constexpr int kBwdBatch = 8;
+
 template <typename T, int VW, int LPR, bool GB, bool GV>
 __global__ __launch_bounds__(kThreads) void k_spmm_bwd_t(
     int n, int k, const int32_t* __restrict__ rpT, const int32_t* __restrict__ ciT,
@@ -101,49 +103,183 @@ __global__ __launch_bounds__(kThreads) void k_spmm_bwd_t(
     T acc[VW];
 #pragma unroll
     for (int w = 0; w < VW; ++w) acc[w] = T(0);
-    int t = t0;
-    for (; t + 2 <= t1; t += 2) {
-      const int i0 = ld_stream(&ciT[t]), i1 = ld_stream(&ciT[t + 1]);
-      const int ea = ld_stream(&perm[t]), eb = ld_stream(&perm[t + 1]);
-      const Vec<T, VW> g0 = load_or_zero<T, VW>(G + (long long)i0 * ldg + col, act);
-      const Vec<T, VW> g1 = load_or_zero<T, VW>(G + (long long)i1 * ldg + col, act);
+    for (int tb = t0; tb < t1; tb += kBwdBatch) {
+      int e[kBwdBatch];
+      T a[kBwdBatch];
+      Vec<T, VW> g[kBwdBatch];
+#pragma unroll
+      for (int u = 0; u < kBwdBatch; ++u) {
+        const int t = min(tb + u, t1 - 1);
+        const int i = ld_stream(&ciT[t]);
+        e[u] = ld_stream(&perm[t]);
+        g[u] = load_or_zero<T, VW>(G + (long long)i * ldg + col, act);
+      }
       if (GB) {
-        const T a0 = vals[ea], a1 = vals[eb];
 #pragma unroll
-        for (int w = 0; w < VW; ++w) acc[w] += a0 * g0.v[w];
+        for (int u = 0; u < kBwdBatch; ++u) a[u] = tb + u < t1 ? vals[e[u]] : T(0);
 #pragma unroll
-        for (int w = 0; w < VW; ++w) acc[w] += a1 * g1.v[w];
+        for (int u = 0; u < kBwdBatch; ++u)
+#pragma unroll
+          for (int w = 0; w < VW; ++w) acc[w] += a[u] * g[u].v[w];
       }
       if (GV) {
-        T d0 = 0, d1 = 0;
 #pragma unroll
-        for (int w = 0; w < VW; ++w) {
-          d0 += g0.v[w] * bj.v[w];
-          d1 += g1.v[w] * bj.v[w];
-        }
-        d0 = group_sum<LPR>(d0);
-        d1 = group_sum<LPR>(d1);
-        if (l == 0) {
-          gv[ea] = c0 == 0 ? d0 : gv[ea] + d0;
-          gv[eb] = c0 == 0 ? d1 : gv[eb] + d1;
+        for (int u = 0; u < kBwdBatch; ++u) {
+          T d = 0;
+#pragma unroll
+          for (int w = 0; w < VW; ++w) d += g[u].v[w] * bj.v[w];
+          d = group_sum<LPR>(d);
+          if (l == 0 && tb + u < t1) gv[e[u]] = c0 == 0 ? d : gv[e[u]] + d;
         }
       }
     }
-    if (t < t1) {
-      const int i0 = ld_stream(&ciT[t]);
-      const int ea = ld_stream(&perm[t]);
-      const Vec<T, VW> g0 = load_or_zero<T, VW>(G + (long long)i0 * ldg + col, act);
-      if (GB) {
-        const T a0 = vals[ea];
+    if (GB && act) {
+      Vec<T, VW> out;
 #pragma unroll
-        for (int w = 0; w < VW; ++w) acc[w] += a0 * g0.v[w];
+      for (int w = 0; w < VW; ++w) out.v[w] = acc[w];
+      store_vec<T, VW>(gB + (long long)j * ldgb + col, out);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------
+// Cooperative variants for groups of >= 16 lanes (k = 64 float32 or
+// wider).  Per batch of 8 entries, lanes 0..7 of each 16-lane DPP row load
+// the batch's indices and values once; DPP row_newbcast hands entry u to
+// every lane of the row; the dense-row loads are predicated on the batch
+// length, so no lane loads padding.  This removes the per-lane index and
+// value loads that otherwise dominate the load pipeline.
+// ---------------------------------------------------------------------
+template <int U>
+__device__ __forceinline__ int bcast16(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, 0x150 + U, 0xF, 0xF, false);
+}
+template <int U>
+__device__ __forceinline__ float bcast16(float v) {
+  return __int_as_float(bcast16<U>(__float_as_int(v)));
+}
+template <int U>
+__device__ __forceinline__ double bcast16(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = bcast16<U>((int)(b & 0xffffffffll));
+  const int hi = bcast16<U>((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+template <typename V, int N, int U = 0>
+__device__ __forceinline__ void bcast_all(V mine, V (&out)[N]) {
+  if constexpr (U < N) {
+    out[U] = bcast16<U>(mine);
+    bcast_all<V, N, U + 1>(mine, out);
+  }
+}
+
+constexpr int kCoop = 8;
+
+template <typename T, int VW, int LPR>
+__global__ __launch_bounds__(kThreads) void k_spmm_fwd_coop(int m, int k,
+                                                           const int32_t* __restrict__ rowptr,
+                                                           const int32_t* __restrict__ colind,
+                                                           const T* __restrict__ vals,
+                                                           const T* __restrict__ B, long long ldb,
+                                                           T* __restrict__ C, long long ldc) {
+  static_assert(LPR >= 16, "cooperative path needs whole DPP rows");
+  constexpr int RPB = kThreads / LPR;
+  const int b = xcd_block(blockIdx.x, gridDim.x);
+  const int row = b * RPB + threadIdx.x / LPR;
+  const int l = threadIdx.x % LPR, lr = threadIdx.x % 16;
+  if (row >= m) return;  // whole group leaves together
+  const int e0 = rowptr[row], e1 = rowptr[row + 1];
+  for (int c0 = 0; c0 < k; c0 += LPR * VW) {
+    const int col = c0 + l * VW;
+    const bool act = col < k;
+    T acc[VW];
+#pragma unroll
+    for (int w = 0; w < VW; ++w) acc[w] = T(0);
+    for (int eb = e0; eb < e1; eb += kCoop) {
+      const int cnt = min(kCoop, e1 - eb);
+      int myc = 0;
+      T myv = 0;
+      if (lr < cnt) {
+        myc = ld_stream(&colind[eb + lr]);
+        myv = ld_stream(&vals[eb + lr]);
+      }
+      int c[kCoop];
+      T a[kCoop];
+      bcast_all<int, kCoop>(myc, c);
+      bcast_all<T, kCoop>(myv, a);
+      Vec<T, VW> bv[kCoop];
+#pragma unroll
+      for (int u = 0; u < kCoop; ++u) bv[u] = load_or_zero<T, VW>(B + (long long)c[u] * ldb + col, act && u < cnt);
+#pragma unroll
+      for (int u = 0; u < kCoop; ++u)
+#pragma unroll
+        for (int w = 0; w < VW; ++w) acc[w] += a[u] * bv[u].v[w];
+    }
+    if (act) {
+      Vec<T, VW> out;
+#pragma unroll
+      for (int w = 0; w < VW; ++w) out.v[w] = acc[w];
+      store_vec<T, VW>(C + (long long)row * ldc + col, out);
+    }
+  }
+}
+
+template <typename T, int VW, int LPR, bool GB, bool GV>
+__global__ __launch_bounds__(kThreads) void k_spmm_bwd_coop(
+    int n, int k, const int32_t* __restrict__ rpT, const int32_t* __restrict__ ciT,
+    const int32_t* __restrict__ perm, const T* __restrict__ vals, const T* __restrict__ B,
+    long long ldb, const T* __restrict__ G, long long ldg, T* __restrict__ gB, long long ldgb,
+    T* __restrict__ gv) {
+  static_assert(LPR >= 16, "cooperative path needs whole DPP rows");
+  constexpr int RPB = kThreads / LPR;
+  const int b = xcd_block(blockIdx.x, gridDim.x);
+  const int j = b * RPB + threadIdx.x / LPR;
+  const int l = threadIdx.x % LPR, lr = threadIdx.x % 16;
+  if (j >= n) return;  // whole group leaves together
+  const int t0 = rpT[j], t1 = rpT[j + 1];
+  for (int c0 = 0; c0 < k; c0 += LPR * VW) {
+    const int col = c0 + l * VW;
+    const bool act = col < k;
+    Vec<T, VW> bj;
+    if (GV) bj = load_or_zero<T, VW>(B + (long long)j * ldb + col, act);
+    T acc[VW];
+#pragma unroll
+    for (int w = 0; w < VW; ++w) acc[w] = T(0);
+    for (int tb = t0; tb < t1; tb += kCoop) {
+      const int cnt = min(kCoop, t1 - tb);
+      int myi = 0, mye = 0;
+      T mya = 0;
+      if (lr < cnt) {
+        myi = ld_stream(&ciT[tb + lr]);
+        mye = ld_stream(&perm[tb + lr]);
+        if (GB) mya = vals[mye];
+      }
+      int i[kCoop];
+      bcast_all<int, kCoop>(myi, i);
+      Vec<T, VW> g[kCoop];
+#pragma unroll
+      for (int u = 0; u < kCoop; ++u) g[u] = load_or_zero<T, VW>(G + (long long)i[u] * ldg + col, act && u < cnt);
+      if (GB) {
+        T a[kCoop];
+        bcast_all<T, kCoop>(mya, a);
+#pragma unroll
+        for (int u = 0; u < kCoop; ++u)
+#pragma unroll
+          for (int w = 0; w < VW; ++w) acc[w] += a[u] * g[u].v[w];
       }
       if (GV) {
-        T d0 = 0;
+        T mine = 0;
 #pragma unroll
-        for (int w = 0; w < VW; ++w) d0 += g0.v[w] * bj.v[w];
-        d0 = group_sum<LPR>(d0);
-        if (l == 0) gv[ea] = c0 == 0 ? d0 : gv[ea] + d0;
+        for (int u = 0; u < kCoop; ++u) {
+          T d = 0;
+#pragma unroll
+          for (int w = 0; w < VW; ++w) d += g[u].v[w] * bj.v[w];
+          d = group_sum<LPR>(d);
+          if (lr == u) mine = d;
+        }
+        // lane u of the group's first DPP row owns entry u of the batch
+        if (l < cnt) gv[mye] = c0 == 0 ? mine : gv[mye] + mine;
       }
     }
     if (GB && act) {
@@ -172,14 +308,21 @@ __global__ __launch_bounds__(kThreads) void k_sddmm_rows(
     const int col = c0 + l * VW;
     const bool act = col < k;
     const Vec<T, VW> gi = load_or_zero<T, VW>(G + (long long)i * ldg + col, act);
-    for (int e = e0; e < e1; ++e) {
-      const int c = ld_stream(&colind[e]);
-      const Vec<T, VW> bv = load_or_zero<T, VW>(B + (long long)c * ldb + col, act);
-      T d = 0;
+    for (int eb = e0; eb < e1; eb += kBatch) {
+      Vec<T, VW> bv[kBatch];
 #pragma unroll
-      for (int w = 0; w < VW; ++w) d += gi.v[w] * bv.v[w];
-      d = group_sum<LPR>(d);
-      if (l == 0) gv[e] = c0 == 0 ? d : gv[e] + d;
+      for (int u = 0; u < kBatch; ++u) {
+        const int c = ld_stream(&colind[min(eb + u, e1 - 1)]);
+        bv[u] = load_or_zero<T, VW>(B + (long long)c * ldb + col, act);
+      }
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) {
+        T d = 0;
+#pragma unroll
+        for (int w = 0; w < VW; ++w) d += gi.v[w] * bv[u].v[w];
+        d = group_sum<LPR>(d);
+        if (l == 0 && eb + u < e1) gv[eb + u] = c0 == 0 ? d : gv[eb + u] + d;
+      }
     }
   }
 }
@@ -234,9 +377,24 @@ int spmm_fwd_t(const csrad_csr* A, int k, const T* B, long long ldb, T* C, long 
                                                 v, B, ldb, C, ldc));
   } else {
     constexpr int VW = 16 / sizeof(T);
-    CSRAD_LPR_SWITCH(sh.lpr, hipLaunchKernelGGL((k_spmm_fwd<T, VW, L>), dim3(blocks_for(m, L)),
-                                                dim3(kThreads), 0, s, m, k, A->rowptr, A->colind,
-                                                v, B, ldb, C, ldc));
+    switch (sh.lpr) {
+      case 16:
+        hipLaunchKernelGGL((k_spmm_fwd_coop<T, VW, 16>), dim3(blocks_for(m, 16)), dim3(kThreads), 0,
+                           s, m, k, A->rowptr, A->colind, v, B, ldb, C, ldc);
+        break;
+      case 32:
+        hipLaunchKernelGGL((k_spmm_fwd_coop<T, VW, 32>), dim3(blocks_for(m, 32)), dim3(kThreads), 0,
+                           s, m, k, A->rowptr, A->colind, v, B, ldb, C, ldc);
+        break;
+      case 64:
+        hipLaunchKernelGGL((k_spmm_fwd_coop<T, VW, 64>), dim3(blocks_for(m, 64)), dim3(kThreads), 0,
+                           s, m, k, A->rowptr, A->colind, v, B, ldb, C, ldc);
+        break;
+      default:
+        CSRAD_LPR_SWITCH(sh.lpr, hipLaunchKernelGGL((k_spmm_fwd<T, VW, L>), dim3(blocks_for(m, L)),
+                                                    dim3(kThreads), 0, s, m, k, A->rowptr,
+                                                    A->colind, v, B, ldb, C, ldc));
+    }
   }
   return launch_status();
 }
@@ -248,12 +406,21 @@ void launch_bwd_t(const csrad_csr* A, const csrad_csr* At, const int32_t* perm, 
   const int n = A->ncols;
   const T* v = static_cast<const T*>(A->vals);
   const dim3 grid(blocks_for(n, L));
-  if (gB && gv)
-    hipLaunchKernelGGL((k_spmm_bwd_t<T, VW, L, true, true>), grid, dim3(kThreads), 0, s, n, k,
-                       At->rowptr, At->colind, perm, v, B, ldb, G, ldg, gB, ldgb, gv);
-  else
-    hipLaunchKernelGGL((k_spmm_bwd_t<T, VW, L, true, false>), grid, dim3(kThreads), 0, s, n, k,
-                       At->rowptr, At->colind, perm, v, B, ldb, G, ldg, gB, ldgb, gv);
+  if constexpr (L >= 16 && VW > 1) {
+    if (gB && gv)
+      hipLaunchKernelGGL((k_spmm_bwd_coop<T, VW, L, true, true>), grid, dim3(kThreads), 0, s, n, k,
+                         At->rowptr, At->colind, perm, v, B, ldb, G, ldg, gB, ldgb, gv);
+    else
+      hipLaunchKernelGGL((k_spmm_bwd_coop<T, VW, L, true, false>), grid, dim3(kThreads), 0, s, n,
+                         k, At->rowptr, At->colind, perm, v, B, ldb, G, ldg, gB, ldgb, gv);
+  } else {
+    if (gB && gv)
+      hipLaunchKernelGGL((k_spmm_bwd_t<T, VW, L, true, true>), grid, dim3(kThreads), 0, s, n, k,
+                         At->rowptr, At->colind, perm, v, B, ldb, G, ldg, gB, ldgb, gv);
+    else
+      hipLaunchKernelGGL((k_spmm_bwd_t<T, VW, L, true, false>), grid, dim3(kThreads), 0, s, n, k,
+                         At->rowptr, At->colind, perm, v, B, ldb, G, ldg, gB, ldgb, gv);
+  }
 }
 
 template <typename T>
