@@ -64,6 +64,26 @@ typedef struct csrad_csr {
 /* Human-readable name of a status code (static storage). */
 const char *csr_status_string(int status);
 
+/* Traversal plan for the row-parallel dense-operand kernels (SpMM forward
+ * and backward).  row_stride = 0 visits rows in natural order.  With
+ * row_stride > 0, rows are visited as tiles of the (p, q) grid
+ * row = p * row_stride + q: a tile is row_tile consecutive q for one p, and the tiles of one q-range are visited for every p
+ * before the next q-range.  For operators whose long-range couplings sit at
+ * a fixed row offset (structured grids) this keeps the dense rows that
+ * neighbouring tiles share in cache.  The plan changes only the order of
+ * work, never a result.  csr_pattern_stats gives the inputs an autotuner
+ * needs to propose plans. */
+typedef struct csrad_plan {
+    int32_t row_stride;
+    int32_t row_tile;
+} csrad_plan;
+
+/* Pattern statistics (synchronises): stats_host[0] = longest row,
+ * [1] = bandwidth max |col - row|, [2] = number of non-empty rows,
+ * [3] = nnz.  work needs 32 bytes. */
+int csr_pattern_stats(const csrad_csr *A, int64_t *stats_host, void *work,
+                      size_t work_bytes, void *stream);
+
 /* ---------------------------------------------------------------------
  * SpMV (Section 3.1.1; Table 1, SpMV row).
  * csr_spmv_fwd: y[nrows] = A x[ncols].
@@ -88,13 +108,16 @@ int csr_spmv_bwd(const csrad_csr *A, const csrad_csr *At, const int32_t *perm,
  *   gvals[e] = <gC[row e, :], B[col e, :]> (the masked product (gC B^T)
  *   on A's pattern).  At/perm are required when gB is requested; with
  *   both outputs requested one fused pass over A^T produces both.
+ *   plan (may be NULL: natural order) orders the rows of A (forward) or of
+ *   A^T (backward); its row_stride must be 0 or in [1, rows] and row_tile
+ *   positive when row_stride is.
  * ------------------------------------------------------------------- */
 int csr_spmm_fwd(const csrad_csr *A, int32_t k, const void *B, int64_t ldb,
-                 void *C, int64_t ldc, void *stream);
+                 void *C, int64_t ldc, const csrad_plan *plan, void *stream);
 int csr_spmm_bwd(const csrad_csr *A, const csrad_csr *At, const int32_t *perm,
                  int32_t k, const void *B, int64_t ldb, const void *gC,
                  int64_t ldgc, void *gB, int64_t ldgb, void *gvals,
-                 void *stream);
+                 const csrad_plan *plan, void *stream);
 
 /* ---------------------------------------------------------------------
  * Sparse transpose (Section 3.1.3, used by every A^T product).

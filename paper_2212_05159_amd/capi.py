@@ -27,6 +27,10 @@ class csrad_csr(C.Structure):
                 ("vals", C.c_void_p)]
 
 
+class csrad_plan(C.Structure):
+    _fields_ = [("row_stride", C.c_int32), ("row_tile", C.c_int32)]
+
+
 _lib = None
 
 _SIGS = {
@@ -34,10 +38,12 @@ _SIGS = {
     "csr_spmv_fwd": (C.c_int, [C.c_void_p] * 4),
     "csr_spmv_bwd": (C.c_int, [C.c_void_p] * 8),
     "csr_spmm_fwd": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int64, C.c_void_p,
-                               C.c_int64, C.c_void_p]),
+                               C.c_int64, C.c_void_p, C.c_void_p]),
     "csr_spmm_bwd": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p,
                                C.c_int64, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64,
-                               C.c_void_p, C.c_void_p]),
+                               C.c_void_p, C.c_void_p, C.c_void_p]),
+    "csr_pattern_stats": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.c_void_p, C.c_size_t,
+                                    C.c_void_p]),
     "csr_transpose_workspace": (C.c_int, [C.c_void_p, C.POINTER(C.c_size_t)]),
     "csr_transpose": (C.c_int, [C.c_void_p] * 5 + [C.c_size_t, C.c_void_p]),
     "csr_transpose_vals": (C.c_int, [C.c_void_p] * 4),
@@ -129,16 +135,27 @@ def csr_spmv_bwd(A, At, perm, x, gy, gx, gvals):
                                                _ptr(gvals), _stream()))
 
 
-def csr_spmm_fwd(A, k, B, ldb, Cout, ldc):
+def _plan(plan):
+    return None if plan is None else C.byref(plan)
+
+
+def csr_spmm_fwd(A, k, B, ldb, Cout, ldc, plan=None):
     _check("csr_spmm_fwd", load().csr_spmm_fwd(C.byref(A), int(k), _ptr(B), int(ldb), _ptr(Cout),
-                                               int(ldc), _stream()))
+                                               int(ldc), _plan(plan), _stream()))
 
 
-def csr_spmm_bwd(A, At, perm, k, B, ldb, gC, ldgc, gB, ldgb, gvals):
+def csr_spmm_bwd(A, At, perm, k, B, ldb, gC, ldgc, gB, ldgb, gvals, plan=None):
     _check("csr_spmm_bwd", load().csr_spmm_bwd(C.byref(A), C.byref(At) if At is not None else None,
                                                _ptr(perm), int(k), _ptr(B), int(ldb), _ptr(gC),
                                                int(ldgc), _ptr(gB), int(ldgb), _ptr(gvals),
-                                               _stream()))
+                                               _plan(plan), _stream()))
+
+
+def csr_pattern_stats(A, work):
+    st = (C.c_int64 * 4)()
+    _check("csr_pattern_stats", load().csr_pattern_stats(C.byref(A), st, _ptr(work), work.numel(),
+                                                         _stream()))
+    return list(st)
 
 
 def csr_transpose_workspace(A):

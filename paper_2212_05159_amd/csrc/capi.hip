@@ -30,10 +30,49 @@ __global__ __launch_bounds__(256) void k_validate(int m, int n, int nnz,
   if (!ok) atomicMin(bad, i);
 }
 
+// stats[0] longest row, [1] max |col - row|, [2] non-empty rows.
+__global__ __launch_bounds__(256) void k_stats(int m, const int32_t* __restrict__ rp,
+                                               const int32_t* __restrict__ ci,
+                                               int32_t* __restrict__ st) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const int a = rp[i], b = rp[i + 1];
+  if (b > a) {
+    const int lo = ci[a], hi = ci[b - 1];
+    const int bw = max(abs(lo - i), abs(hi - i));
+    atomicMax(&st[0], b - a);
+    atomicMax(&st[1], bw);
+    atomicAdd(&st[2], 1);
+  }
+}
+
 }  // namespace
 }  // namespace csrad
 
 using namespace csrad;
+
+extern "C" int csr_pattern_stats(const csrad_csr* A, int64_t* stats_host, void* work,
+                                 size_t work_bytes, void* stream) {
+  if (!A || !stats_host) return CSRAD_EINVAL;
+  if (A->nrows < 0 || A->ncols < 0 || A->nnz < 0 || !A->rowptr) return CSRAD_EINVAL;
+  if (A->nnz > 0 && !A->colind) return CSRAD_EINVAL;
+  if (!work || work_bytes < 4 * sizeof(int32_t)) return CSRAD_EWORKSPACE;
+  hipStream_t s = as_stream(stream);
+  int32_t* st = static_cast<int32_t*>(work);
+  CSRAD_TRY(fill_i32(st, 4, 0, s));
+  if (A->nrows > 0)
+    hipLaunchKernelGGL(k_stats, dim3((A->nrows + 255) / 256), dim3(256), 0, s, A->nrows, A->rowptr,
+                       A->colind, st);
+  CSRAD_TRY(launch_status());
+  int32_t h[4];
+  if (hipMemcpyAsync(h, st, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess) return CSRAD_EHIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return CSRAD_EHIP;
+  stats_host[0] = h[0];
+  stats_host[1] = h[1];
+  stats_host[2] = h[2];
+  stats_host[3] = A->nnz;
+  return CSRAD_OK;
+}
 
 extern "C" const char* csr_status_string(int status) {
   switch (status) {

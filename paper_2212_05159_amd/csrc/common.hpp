@@ -25,6 +25,56 @@ __device__ __forceinline__ int xcd_block(int b, int nblocks) {
 }
 
 // ---------------------------------------------------------------------
+// Row traversal order (see csrad_plan).  Natural: logical block lb owns
+// rows [lb*rpb, lb*rpb + rpb).  Tiled: rows form the grid
+// row = p*stride + q; a tile is `tile` consecutive q for one p and takes
+// ceil(tile/rpb) blocks; tiles are ordered q-range major, p minor.
+// ---------------------------------------------------------------------
+struct RowOrder {
+  int m, stride, tile, planes, qtiles, bpt;  // bpt: blocks per tile
+};
+
+inline RowOrder make_order(int m, int rpb, const csrad_plan* plan) {
+  RowOrder o{m, 0, 0, 0, 0, 0};
+  if (plan && plan->row_stride > 0 && plan->row_tile > 0) {
+    o.stride = plan->row_stride;
+    o.tile = plan->row_tile < o.stride ? plan->row_tile : o.stride;
+    o.planes = (m + o.stride - 1) / o.stride;
+    o.qtiles = (o.stride + o.tile - 1) / o.tile;
+    o.bpt = (o.tile + rpb - 1) / rpb;
+  }
+  return o;
+}
+
+inline long long order_blocks(const RowOrder& o, int rpb) {
+  if (o.stride == 0) return ((long long)o.m + rpb - 1) / rpb;
+  return (long long)o.qtiles * o.planes * o.bpt;
+}
+
+// Row of group g (0 <= g < rpb) in logical block lb, or -1.
+__device__ __forceinline__ int order_row(const RowOrder& o, int lb, int rpb, int g) {
+  if (o.stride == 0) {
+    const int r = lb * rpb + g;
+    return r < o.m ? r : -1;
+  }
+  const int per_q = o.planes * o.bpt;
+  const int qt = lb / per_q, rem = lb - qt * per_q;
+  const int p = rem / o.bpt, t = rem - p * o.bpt;
+  const int off = t * rpb + g;
+  const int q = qt * o.tile + off;
+  if (off >= o.tile || q >= o.stride) return -1;
+  const long long r = (long long)p * o.stride + q;
+  return r < o.m ? (int)r : -1;
+}
+
+inline int check_plan(const csrad_plan* plan, int rows) {
+  if (!plan) return CSRAD_OK;
+  if (plan->row_stride < 0 || plan->row_stride > (rows > 0 ? rows : 0)) return CSRAD_EINVAL;
+  if (plan->row_stride > 0 && plan->row_tile <= 0) return CSRAD_EINVAL;
+  return CSRAD_OK;
+}
+
+// ---------------------------------------------------------------------
 // Cross-lane reductions over aligned groups of G lanes (G a power of two,
 // G <= 64).  Lanes 1,2 apart combine through DPP quad permutes, 4 and 8
 // apart through the DPP half-row and row mirrors, 16 apart through a

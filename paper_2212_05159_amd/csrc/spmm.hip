@@ -36,7 +36,7 @@ __device__ __forceinline__ Vec<T, VW> load_or_zero(const T* p, bool ok) {
 constexpr int kBatch = 8;
 
 template <typename T, int VW, int LPR>
-__global__ __launch_bounds__(kThreads) void k_spmm_fwd(int m, int k,
+__global__ __launch_bounds__(kThreads) void k_spmm_fwd(RowOrder ord, int k,
                                                       const int32_t* __restrict__ rowptr,
                                                       const int32_t* __restrict__ colind,
                                                       const T* __restrict__ vals,
@@ -44,9 +44,9 @@ __global__ __launch_bounds__(kThreads) void k_spmm_fwd(int m, int k,
                                                       T* __restrict__ C, long long ldc) {
   constexpr int RPB = kThreads / LPR;
   const int b = xcd_block(blockIdx.x, gridDim.x);
-  const int row = b * RPB + threadIdx.x / LPR;
+  const int row = order_row(ord, b, RPB, threadIdx.x / LPR);
   const int l = threadIdx.x % LPR;
-  if (row >= m) return;
+  if (row < 0) return;
   const int e0 = rowptr[row], e1 = rowptr[row + 1];
   for (int c0 = 0; c0 < k; c0 += LPR * VW) {
     const int col = c0 + l * VW;
@@ -85,15 +85,15 @@ constexpr int kBwdBatch = 8;
 
 template <typename T, int VW, int LPR, bool GB, bool GV>
 __global__ __launch_bounds__(kThreads) void k_spmm_bwd_t(
-    int n, int k, const int32_t* __restrict__ rpT, const int32_t* __restrict__ ciT,
+    RowOrder ord, int k, const int32_t* __restrict__ rpT, const int32_t* __restrict__ ciT,
     const int32_t* __restrict__ perm, const T* __restrict__ vals, const T* __restrict__ B,
     long long ldb, const T* __restrict__ G, long long ldg, T* __restrict__ gB, long long ldgb,
     T* __restrict__ gv) {
   constexpr int RPB = kThreads / LPR;
   const int b = xcd_block(blockIdx.x, gridDim.x);
-  const int j = b * RPB + threadIdx.x / LPR;
+  const int j = order_row(ord, b, RPB, threadIdx.x / LPR);
   const int l = threadIdx.x % LPR;
-  if (j >= n) return;  // whole group leaves together
+  if (j < 0) return;  // whole group leaves together
   const int t0 = rpT[j], t1 = rpT[j + 1];
   for (int c0 = 0; c0 < k; c0 += LPR * VW) {
     const int col = c0 + l * VW;
@@ -177,7 +177,7 @@ __device__ __forceinline__ void bcast_all(V mine, V (&out)[N]) {
 constexpr int kCoop = 8;
 
 template <typename T, int VW, int LPR>
-__global__ __launch_bounds__(kThreads) void k_spmm_fwd_coop(int m, int k,
+__global__ __launch_bounds__(kThreads) void k_spmm_fwd_coop(RowOrder ord, int k,
                                                            const int32_t* __restrict__ rowptr,
                                                            const int32_t* __restrict__ colind,
                                                            const T* __restrict__ vals,
@@ -186,9 +186,9 @@ __global__ __launch_bounds__(kThreads) void k_spmm_fwd_coop(int m, int k,
   static_assert(LPR >= 16, "cooperative path needs whole DPP rows");
   constexpr int RPB = kThreads / LPR;
   const int b = xcd_block(blockIdx.x, gridDim.x);
-  const int row = b * RPB + threadIdx.x / LPR;
+  const int row = order_row(ord, b, RPB, threadIdx.x / LPR);
   const int l = threadIdx.x % LPR, lr = threadIdx.x % 16;
-  if (row >= m) return;  // whole group leaves together
+  if (row < 0) return;  // whole group leaves together
   const int e0 = rowptr[row], e1 = rowptr[row + 1];
   for (int c0 = 0; c0 < k; c0 += LPR * VW) {
     const int col = c0 + l * VW;
@@ -227,16 +227,16 @@ __global__ __launch_bounds__(kThreads) void k_spmm_fwd_coop(int m, int k,
 
 template <typename T, int VW, int LPR, bool GB, bool GV>
 __global__ __launch_bounds__(kThreads) void k_spmm_bwd_coop(
-    int n, int k, const int32_t* __restrict__ rpT, const int32_t* __restrict__ ciT,
+    RowOrder ord, int k, const int32_t* __restrict__ rpT, const int32_t* __restrict__ ciT,
     const int32_t* __restrict__ perm, const T* __restrict__ vals, const T* __restrict__ B,
     long long ldb, const T* __restrict__ G, long long ldg, T* __restrict__ gB, long long ldgb,
     T* __restrict__ gv) {
   static_assert(LPR >= 16, "cooperative path needs whole DPP rows");
   constexpr int RPB = kThreads / LPR;
   const int b = xcd_block(blockIdx.x, gridDim.x);
-  const int j = b * RPB + threadIdx.x / LPR;
+  const int j = order_row(ord, b, RPB, threadIdx.x / LPR);
   const int l = threadIdx.x % LPR, lr = threadIdx.x % 16;
-  if (j >= n) return;  // whole group leaves together
+  if (j < 0) return;  // whole group leaves together
   const int t0 = rpT[j], t1 = rpT[j + 1];
   for (int c0 = 0; c0 < k; c0 += LPR * VW) {
     const int col = c0 + l * VW;
@@ -295,14 +295,14 @@ __global__ __launch_bounds__(kThreads) void k_spmm_bwd_coop(
 //   gvals[e] = <gC[i,:], B[col e,:]>, gC[i,:] loaded once per row.
 template <typename T, int VW, int LPR>
 __global__ __launch_bounds__(kThreads) void k_sddmm_rows(
-    int m, int k, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colind,
+    RowOrder ord, int k, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colind,
     const T* __restrict__ B, long long ldb, const T* __restrict__ G, long long ldg,
     T* __restrict__ gv) {
   constexpr int RPB = kThreads / LPR;
   const int b = xcd_block(blockIdx.x, gridDim.x);
-  const int i = b * RPB + threadIdx.x / LPR;
+  const int i = order_row(ord, b, RPB, threadIdx.x / LPR);
   const int l = threadIdx.x % LPR;
-  if (i >= m) return;
+  if (i < 0) return;
   const int e0 = rowptr[i], e1 = rowptr[i + 1];
   for (int c0 = 0; c0 < k; c0 += LPR * VW) {
     const int col = c0 + l * VW;
@@ -359,42 +359,34 @@ Shape pick_shape(int k, std::initializer_list<long long> lds,
     default: { constexpr int L = 64; __VA_ARGS__; } break; \
   }
 
-inline unsigned blocks_for(int rows, int lpr) {
-  const int rpb = kThreads / lpr;
-  return (unsigned)((rows + rpb - 1) / rpb);
+inline dim3 grid_for(const RowOrder& o, int lpr) {
+  return dim3((unsigned)order_blocks(o, kThreads / lpr));
 }
 
 template <typename T>
 int spmm_fwd_t(const csrad_csr* A, int k, const T* B, long long ldb, T* C, long long ldc,
-               hipStream_t s) {
+               const csrad_plan* plan, hipStream_t s) {
   const int m = A->nrows;
   if (m == 0) return CSRAD_OK;
   const Shape sh = pick_shape<T>(k, {ldb, ldc}, {B, C});
   const T* v = static_cast<const T*>(A->vals);
   if (sh.vw == 1) {
-    CSRAD_LPR_SWITCH(sh.lpr, hipLaunchKernelGGL((k_spmm_fwd<T, 1, L>), dim3(blocks_for(m, L)),
-                                                dim3(kThreads), 0, s, m, k, A->rowptr, A->colind,
-                                                v, B, ldb, C, ldc));
+    CSRAD_LPR_SWITCH(sh.lpr, {
+      const RowOrder o = make_order(m, kThreads / L, plan);
+      hipLaunchKernelGGL((k_spmm_fwd<T, 1, L>), grid_for(o, L), dim3(kThreads), 0, s, o, k,
+                         A->rowptr, A->colind, v, B, ldb, C, ldc);
+    });
   } else {
     constexpr int VW = 16 / sizeof(T);
-    switch (sh.lpr) {
-      case 16:
-        hipLaunchKernelGGL((k_spmm_fwd_coop<T, VW, 16>), dim3(blocks_for(m, 16)), dim3(kThreads), 0,
-                           s, m, k, A->rowptr, A->colind, v, B, ldb, C, ldc);
-        break;
-      case 32:
-        hipLaunchKernelGGL((k_spmm_fwd_coop<T, VW, 32>), dim3(blocks_for(m, 32)), dim3(kThreads), 0,
-                           s, m, k, A->rowptr, A->colind, v, B, ldb, C, ldc);
-        break;
-      case 64:
-        hipLaunchKernelGGL((k_spmm_fwd_coop<T, VW, 64>), dim3(blocks_for(m, 64)), dim3(kThreads), 0,
-                           s, m, k, A->rowptr, A->colind, v, B, ldb, C, ldc);
-        break;
-      default:
-        CSRAD_LPR_SWITCH(sh.lpr, hipLaunchKernelGGL((k_spmm_fwd<T, VW, L>), dim3(blocks_for(m, L)),
-                                                    dim3(kThreads), 0, s, m, k, A->rowptr,
-                                                    A->colind, v, B, ldb, C, ldc));
-    }
+    CSRAD_LPR_SWITCH(sh.lpr, {
+      const RowOrder o = make_order(m, kThreads / L, plan);
+      if constexpr (L >= 16)
+        hipLaunchKernelGGL((k_spmm_fwd_coop<T, VW, L>), grid_for(o, L), dim3(kThreads), 0, s, o,
+                           k, A->rowptr, A->colind, v, B, ldb, C, ldc);
+      else
+        hipLaunchKernelGGL((k_spmm_fwd<T, VW, L>), grid_for(o, L), dim3(kThreads), 0, s, o, k,
+                           A->rowptr, A->colind, v, B, ldb, C, ldc);
+    });
   }
   return launch_status();
 }
@@ -402,23 +394,23 @@ int spmm_fwd_t(const csrad_csr* A, int k, const T* B, long long ldb, T* C, long 
 template <typename T, int VW, int L>
 void launch_bwd_t(const csrad_csr* A, const csrad_csr* At, const int32_t* perm, int k,
                   const T* B, long long ldb, const T* G, long long ldg, T* gB, long long ldgb,
-                  T* gv, hipStream_t s) {
-  const int n = A->ncols;
+                  T* gv, const csrad_plan* plan, hipStream_t s) {
   const T* v = static_cast<const T*>(A->vals);
-  const dim3 grid(blocks_for(n, L));
+  const RowOrder o = make_order(A->ncols, kThreads / L, plan);
+  const dim3 grid = grid_for(o, L);
   if constexpr (L >= 16 && VW > 1) {
     if (gB && gv)
-      hipLaunchKernelGGL((k_spmm_bwd_coop<T, VW, L, true, true>), grid, dim3(kThreads), 0, s, n, k,
+      hipLaunchKernelGGL((k_spmm_bwd_coop<T, VW, L, true, true>), grid, dim3(kThreads), 0, s, o, k,
                          At->rowptr, At->colind, perm, v, B, ldb, G, ldg, gB, ldgb, gv);
     else
-      hipLaunchKernelGGL((k_spmm_bwd_coop<T, VW, L, true, false>), grid, dim3(kThreads), 0, s, n,
+      hipLaunchKernelGGL((k_spmm_bwd_coop<T, VW, L, true, false>), grid, dim3(kThreads), 0, s, o,
                          k, At->rowptr, At->colind, perm, v, B, ldb, G, ldg, gB, ldgb, gv);
   } else {
     if (gB && gv)
-      hipLaunchKernelGGL((k_spmm_bwd_t<T, VW, L, true, true>), grid, dim3(kThreads), 0, s, n, k,
+      hipLaunchKernelGGL((k_spmm_bwd_t<T, VW, L, true, true>), grid, dim3(kThreads), 0, s, o, k,
                          At->rowptr, At->colind, perm, v, B, ldb, G, ldg, gB, ldgb, gv);
     else
-      hipLaunchKernelGGL((k_spmm_bwd_t<T, VW, L, true, false>), grid, dim3(kThreads), 0, s, n, k,
+      hipLaunchKernelGGL((k_spmm_bwd_t<T, VW, L, true, false>), grid, dim3(kThreads), 0, s, o, k,
                          At->rowptr, At->colind, perm, v, B, ldb, G, ldg, gB, ldgb, gv);
   }
 }
@@ -426,33 +418,37 @@ void launch_bwd_t(const csrad_csr* A, const csrad_csr* At, const int32_t* perm, 
 template <typename T>
 int spmm_bwd_t(const csrad_csr* A, const csrad_csr* At, const int32_t* perm, int k, const T* B,
                long long ldb, const T* G, long long ldg, T* gB, long long ldgb, T* gv,
-               hipStream_t s) {
+               const csrad_plan* plan, hipStream_t s) {
   if (gB) {
     if (A->ncols == 0) return CSRAD_OK;
     const Shape sh = pick_shape<T>(k, {ldb, ldg, ldgb}, {B, G, gB});
     if (sh.vw == 1) {
       CSRAD_LPR_SWITCH(sh.lpr, (launch_bwd_t<T, 1, L>(A, At, perm, k, B, ldb, G, ldg, gB, ldgb,
-                                                      gv, s)));
+                                                      gv, plan, s)));
     } else {
       constexpr int VW = 16 / sizeof(T);
       CSRAD_LPR_SWITCH(sh.lpr, (launch_bwd_t<T, VW, L>(A, At, perm, k, B, ldb, G, ldg, gB, ldgb,
-                                                       gv, s)));
+                                                       gv, plan, s)));
     }
     return launch_status();
   }
-  // gvals only: row-wise masked product, no transpose.
+  // gvals only: row-wise masked product over A, no transpose.
   const int m = A->nrows;
   if (m == 0) return CSRAD_OK;
   const Shape sh = pick_shape<T>(k, {ldb, ldg}, {B, G});
   if (sh.vw == 1) {
-    CSRAD_LPR_SWITCH(sh.lpr, hipLaunchKernelGGL((k_sddmm_rows<T, 1, L>), dim3(blocks_for(m, L)),
-                                                dim3(kThreads), 0, s, m, k, A->rowptr, A->colind,
-                                                B, ldb, G, ldg, gv));
+    CSRAD_LPR_SWITCH(sh.lpr, {
+      const RowOrder o = make_order(m, kThreads / L, plan);
+      hipLaunchKernelGGL((k_sddmm_rows<T, 1, L>), grid_for(o, L), dim3(kThreads), 0, s, o, k,
+                         A->rowptr, A->colind, B, ldb, G, ldg, gv);
+    });
   } else {
     constexpr int VW = 16 / sizeof(T);
-    CSRAD_LPR_SWITCH(sh.lpr, hipLaunchKernelGGL((k_sddmm_rows<T, VW, L>), dim3(blocks_for(m, L)),
-                                                dim3(kThreads), 0, s, m, k, A->rowptr, A->colind,
-                                                B, ldb, G, ldg, gv));
+    CSRAD_LPR_SWITCH(sh.lpr, {
+      const RowOrder o = make_order(m, kThreads / L, plan);
+      hipLaunchKernelGGL((k_sddmm_rows<T, VW, L>), grid_for(o, L), dim3(kThreads), 0, s, o, k,
+                         A->rowptr, A->colind, B, ldb, G, ldg, gv);
+    });
   }
   return launch_status();
 }
@@ -463,21 +459,25 @@ int spmm_bwd_t(const csrad_csr* A, const csrad_csr* At, const int32_t* perm, int
 using namespace csrad;
 
 extern "C" int csr_spmm_fwd(const csrad_csr* A, int32_t k, const void* B, int64_t ldb, void* C,
-                            int64_t ldc, void* stream) {
+                            int64_t ldc, const csrad_plan* plan, void* stream) {
   CSRAD_TRY(check_csr(A, true));
+  CSRAD_TRY(check_plan(plan, A->nrows));
   if (k <= 0 || ldb < k || ldc < k) return CSRAD_EINVAL;
   if ((A->ncols > 0 && !B) || (A->nrows > 0 && !C)) return CSRAD_EINVAL;
   hipStream_t s = as_stream(stream);
   if (A->dtype == CSRAD_F32)
-    return spmm_fwd_t<float>(A, k, static_cast<const float*>(B), ldb, static_cast<float*>(C), ldc, s);
+    return spmm_fwd_t<float>(A, k, static_cast<const float*>(B), ldb, static_cast<float*>(C), ldc,
+                             plan, s);
   return spmm_fwd_t<double>(A, k, static_cast<const double*>(B), ldb, static_cast<double*>(C), ldc,
-                            s);
+                            plan, s);
 }
 
 extern "C" int csr_spmm_bwd(const csrad_csr* A, const csrad_csr* At, const int32_t* perm,
                             int32_t k, const void* B, int64_t ldb, const void* gC, int64_t ldgc,
-                            void* gB, int64_t ldgb, void* gvals, void* stream) {
+                            void* gB, int64_t ldgb, void* gvals, const csrad_plan* plan,
+                            void* stream) {
   CSRAD_TRY(check_csr(A, gB != nullptr));
+  CSRAD_TRY(check_plan(plan, gB ? A->ncols : A->nrows));
   if (!gB && !gvals) return CSRAD_OK;
   if (k <= 0 || ldgc < k) return CSRAD_EINVAL;
   if (A->nrows > 0 && !gC) return CSRAD_EINVAL;
@@ -492,8 +492,8 @@ extern "C" int csr_spmm_bwd(const csrad_csr* A, const csrad_csr* At, const int32
   if (A->dtype == CSRAD_F32)
     return spmm_bwd_t<float>(A, At, perm, k, static_cast<const float*>(B), ldb,
                              static_cast<const float*>(gC), ldgc, static_cast<float*>(gB), ldgb,
-                             static_cast<float*>(gvals), s);
+                             static_cast<float*>(gvals), plan, s);
   return spmm_bwd_t<double>(A, At, perm, k, static_cast<const double*>(B), ldb,
                             static_cast<const double*>(gC), ldgc, static_cast<double*>(gB), ldgb,
-                            static_cast<double*>(gvals), s);
+                            static_cast<double*>(gvals), plan, s);
 }

@@ -24,6 +24,8 @@ class Pattern:
         self.rowptr, self.colind = rowptr, colind
         self._t = None
         self._levels = {}
+        self._plans = {}
+        self._stats = None
 
     @property
     def nnz(self):
@@ -48,6 +50,20 @@ class Pattern:
             capi.csr_transpose(d, rpT, ciT, perm, ws)
             self._t = (Pattern(self.ncols, self.nrows, rpT, ciT), perm)
         return self._t
+
+    def stats(self):
+        """(longest row, bandwidth, non-empty rows, nnz); cached."""
+        if self._stats is None:
+            ws = torch.empty(64, dtype=torch.uint8, device=self.device)
+            self._stats = capi.csr_pattern_stats(self.desc(), ws)
+        return self._stats
+
+    def plan(self, op):
+        """Traversal plan chosen for ``op`` (set by the autotuner), or None."""
+        return self._plans.get(op)
+
+    def set_plan(self, op, plan):
+        self._plans[op] = plan
 
     def levels(self, lower=True):
         """Level sets of the triangular solve; cached per orientation.
@@ -94,21 +110,23 @@ def spmv_bwd(P, vals, x, gy, need_x=True, need_vals=True, use_transpose=True):
     return gx, gv
 
 
-def spmm(P, vals, B):
+def spmm(P, vals, B, plan=None):
     k = B.shape[1]
     out = torch.empty(P.nrows, k, dtype=vals.dtype, device=vals.device)
-    capi.csr_spmm_fwd(P.desc(vals), k, B, B.stride(0), out, out.stride(0))
+    capi.csr_spmm_fwd(P.desc(vals), k, B, B.stride(0), out, out.stride(0),
+                      plan if plan is not None else P.plan("spmm_fwd"))
     return out
 
 
-def spmm_bwd(P, vals, B, gC, need_B=True, need_vals=True):
+def spmm_bwd(P, vals, B, gC, need_B=True, need_vals=True, plan=None):
     k = gC.shape[1]
     gB = torch.empty(P.ncols, k, dtype=vals.dtype, device=vals.device) if need_B else None
     gv = torch.empty(P.nnz, dtype=vals.dtype, device=vals.device) if need_vals else None
     Pt, perm = P.transpose() if need_B else (None, None)
     capi.csr_spmm_bwd(P.desc(vals), Pt.desc(dtype=vals.dtype) if Pt is not None else None, perm, k,
                       B, B.stride(0) if B is not None else k, gC, gC.stride(0), gB,
-                      gB.stride(0) if gB is not None else k, gv)
+                      gB.stride(0) if gB is not None else k, gv,
+                      plan if plan is not None else P.plan("spmm_bwd" if need_B else "sddmm"))
     return gB, gv
 
 

@@ -49,8 +49,12 @@ def test_argument_errors_return_codes(lib):
     d = capi.csrad_csr(-1, 4, 0, 0, 1, None, None)
     assert lib.csr_spmv_fwd(C.byref(d), 1, 1, None) == -1
     d = capi.csrad_csr(4, 4, 4, 0, 1, 1, 1)
-    assert lib.csr_spmm_fwd(C.byref(d), 0, 1, 1, 1, 1, None) == -1      # k <= 0
-    assert lib.csr_spmm_fwd(C.byref(d), 8, 1, 4, 1, 8, None) == -1      # ldb < k
+    assert lib.csr_spmm_fwd(C.byref(d), 0, 1, 1, 1, 1, None, None) == -1      # k <= 0
+    assert lib.csr_spmm_fwd(C.byref(d), 8, 1, 4, 1, 8, None, None) == -1      # ldb < k
+    bad_plan = capi.csrad_plan(5, 0)  # stride without a tile
+    assert lib.csr_spmm_fwd(C.byref(d), 8, 1, 8, 1, 8, C.byref(bad_plan), None) == -1
+    big_plan = capi.csrad_plan(99, 16)  # stride beyond the row count
+    assert lib.csr_spmm_fwd(C.byref(d), 8, 1, 8, 1, 8, C.byref(big_plan), None) == -1
     sz = C.c_size_t(0)
     assert lib.csr_transpose_workspace(C.byref(d), C.byref(sz)) == 0 and sz.value > 0
     # too-small workspace is reported, not overrun

@@ -136,6 +136,53 @@ def test_spmm_strided_operands(dtype):
     assert_close(gv, gvo, dtype, "gvals")
 
 
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("case", ["grid", "random"])
+def test_spmm_plans_do_not_change_results(dtype, case):
+    # A traversal plan only reorders rows: results must be bit-identical.
+    from paper_2212_05159_amd import capi
+    if case == "grid":
+        A = gen.poisson3d(16)
+        plans = [(256, 64), (256, 100), (256, 300), (4096, 16), (1, 1)]
+    else:
+        A = gen.random_csr(1000, 900, 0.01, seed=81, empty_rows=0.1)
+        plans = [(37, 5), (1000, 64), (333, 1000), (1, 7)]
+    k = 64
+    Ad = _dev(A, dtype)
+    Bd = to_dev(gen.normal((A.ncols, k), 82), dtype)
+    Gd = to_dev(gen.normal((A.nrows, k), 83), dtype)
+    nat = capi.csrad_plan(0, 0)
+    C0 = sp.spmm(Ad.pattern, Ad.vals, Bd, plan=nat)
+    gB0, gv0 = sp.spmm_bwd(Ad.pattern, Ad.vals, Bd, Gd, plan=nat)
+    _, sv0 = sp.spmm_bwd(Ad.pattern, Ad.vals, Bd, Gd, need_B=False, plan=nat)
+    for st, tl in plans:
+        pl = capi.csrad_plan(min(st, A.nrows), tl)
+        C1 = sp.spmm(Ad.pattern, Ad.vals, Bd, plan=pl)
+        assert torch.equal(C0, C1), (st, tl)
+        pl_t = capi.csrad_plan(min(st, A.ncols), tl)
+        gB1, gv1 = sp.spmm_bwd(Ad.pattern, Ad.vals, Bd, Gd, plan=pl_t)
+        assert torch.equal(gB0, gB1) and torch.equal(gv0, gv1), (st, tl)
+        _, sv1 = sp.spmm_bwd(Ad.pattern, Ad.vals, Bd, Gd, need_B=False, plan=pl)
+        assert torch.equal(sv0, sv1)
+    Ao = upcast(A, dtype)
+    assert_close(C0, oracle.spmm(Ao, Bd.double().cpu().numpy()), dtype, "C")
+
+
+def test_autotuner_picks_a_valid_plan():
+    from paper_2212_05159_amd import autotune
+    A = gen.poisson3d(24)
+    Ad = _dev(A, torch.float32)
+    Bd = to_dev(gen.normal((A.ncols, 64), 84), torch.float32)
+    Gd = to_dev(gen.normal((A.nrows, 64), 85), torch.float32)
+    maxrow, bw, nonempty, nnz = Ad.pattern.stats()
+    assert (maxrow, bw, nonempty, nnz) == (7, 24 * 24, A.nrows, A.nnz)
+    res = autotune.tune_spmm(Ad.pattern, Ad.vals, Bd, Gd, reps=1, use_cache=False)
+    assert set(res) == {"spmm_fwd", "spmm_bwd"}
+    C1 = sp.spmm(Ad.pattern, Ad.vals, Bd)  # uses the tuned plan
+    assert_close(C1, oracle.spmm(upcast(A, torch.float32), Bd.double().cpu().numpy()),
+                 torch.float32, "C tuned")
+
+
 # ---------------------------------------------------------------- transpose
 def _with_long_columns():
     # columns of length ~50 (workgroup sort) and 9000 (chunked sort)
