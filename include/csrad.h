@@ -194,6 +194,43 @@ int csr_trisolve_bwd(const csrad_csr *T, int32_t lower, const csrad_csr *Tt,
                      void *gb, void *gvals, void *stream);
 
 /* ---------------------------------------------------------------------
+ * Conjugate gradients as device-resident steps (the Krylov iteration of
+ * Section 4.3) and the reverse mode of each step.  A is square; vectors
+ * have A's value type; dot products accumulate in float64 with a fixed
+ * reduction order, so steps are bit-reproducible.  scal (8 float64 on the
+ * device) carries the solver scalars, step (1 int32 on the device) the
+ * step index, hist (hist_cap x 5 float64, may be NULL) receives per step
+ * (rho_t, sigma_t, alpha_t, rho_{t+1}, beta_t).  No call synchronises.
+ * csr_cg_init: x = 0, r = p = b, rho = b.b, step = 0.
+ * csr_cg_step: q = A p; alpha = rho/(p.q); x += alpha p; r -= alpha q;
+ *   beta = (r.r)/rho; p = r + beta p (alpha = beta = 0 once rho is 0).
+ *   p_save (p before the step) and r_save (r after it) may be NULL.
+ * csr_cg_step_bwd: undoes one step in reverse given that step's p_t, q_t,
+ *   r_{t+1} and hist record, the upstream gradient gR of r_{t+1} (may be
+ *   NULL) and the running adjoints xb, rb, pb, qb (vectors) and scal
+ *   (reverse slots); accumulates the value gradient into gvals (q = A p
+ *   contributes qb_i p_j at (i,j)).  At/perm: transpose of A.
+ * csr_cg_finish_bwd: gb = rb + pb + 2 rhob b after the first step is undone.
+ * The workspace (csr_cg_workspace) holds block partial sums.
+ * ------------------------------------------------------------------- */
+int csr_cg_workspace(const csrad_csr *A, size_t *bytes);
+int csr_cg_init(const csrad_csr *A, const void *b, void *x, void *r, void *p,
+                double *scal, int32_t *step, void *work, size_t work_bytes,
+                void *stream);
+int csr_cg_step(const csrad_csr *A, void *x, void *r, void *p, void *q,
+                void *p_save, void *r_save, double *scal, int32_t *step,
+                double *hist, int32_t hist_cap, void *work, size_t work_bytes,
+                void *stream);
+int csr_cg_step_bwd(const csrad_csr *A, const csrad_csr *At,
+                    const int32_t *perm, const void *p, const void *q,
+                    const void *r1, const double *step_hist, const void *gR,
+                    void *xb, void *rb, void *pb, void *qb, double *scal,
+                    void *gvals, void *work, size_t work_bytes, void *stream);
+int csr_cg_finish_bwd(const csrad_csr *A, const void *b, const void *rb,
+                      const void *pb, const double *scal, void *gb,
+                      void *stream);
+
+/* ---------------------------------------------------------------------
  * Pattern check: rowptr monotone from 0 to nnz, colind in [0, ncols),
  * strictly ascending within each row.  *first_bad_row_host receives the
  * first offending row or -1 (synchronises).  Returns CSRAD_EPATTERN if a

@@ -62,6 +62,11 @@ _SIGS = {
     "csr_trisolve_bwd": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32,
                                    C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                    C.c_void_p, C.c_void_p, C.c_void_p]),
+    "csr_cg_workspace": (C.c_int, [C.c_void_p, C.POINTER(C.c_size_t)]),
+    "csr_cg_init": (C.c_int, [C.c_void_p] * 8 + [C.c_size_t, C.c_void_p]),
+    "csr_cg_step": (C.c_int, [C.c_void_p] * 10 + [C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p]),
+    "csr_cg_step_bwd": (C.c_int, [C.c_void_p] * 15 + [C.c_size_t, C.c_void_p]),
+    "csr_cg_finish_bwd": (C.c_int, [C.c_void_p] * 7),
     "csr_validate": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.c_void_p, C.c_size_t,
                                C.c_void_p]),
 }
@@ -227,6 +232,37 @@ def csr_trisolve_bwd(T, lower, Tt, perm, nlevels, level_ptr_host, level_ptr, lev
         C.byref(T), int(lower), C.byref(Tt), _ptr(perm), int(nlevels),
         level_ptr_host.ctypes.data, _ptr(level_ptr), _ptr(level_rows), _ptr(x), _ptr(gx),
         _ptr(gb), _ptr(gvals), _stream()))
+
+
+def csr_cg_workspace(A):
+    n = C.c_size_t(0)
+    _check("csr_cg_workspace", load().csr_cg_workspace(C.byref(A), C.byref(n)))
+    return n.value
+
+
+def csr_cg_init(A, b, x, r, p, scal, step, work):
+    _check("csr_cg_init", load().csr_cg_init(C.byref(A), _ptr(b), _ptr(x), _ptr(r), _ptr(p),
+                                             _ptr(scal), _ptr(step), _ptr(work), work.numel(),
+                                             _stream()))
+
+
+def csr_cg_step(A, x, r, p, q, p_save, r_save, scal, step, hist, work):
+    _check("csr_cg_step", load().csr_cg_step(
+        C.byref(A), _ptr(x), _ptr(r), _ptr(p), _ptr(q), _ptr(p_save), _ptr(r_save), _ptr(scal),
+        _ptr(step), _ptr(hist), 0 if hist is None else hist.shape[0], _ptr(work), work.numel(),
+        _stream()))
+
+
+def csr_cg_step_bwd(A, At, perm, p, q, r1, step_hist, gR, xb, rb, pb, qb, scal, gvals, work):
+    _check("csr_cg_step_bwd", load().csr_cg_step_bwd(
+        C.byref(A), C.byref(At), _ptr(perm), _ptr(p), _ptr(q), _ptr(r1), _ptr(step_hist),
+        _ptr(gR), _ptr(xb), _ptr(rb), _ptr(pb), _ptr(qb), _ptr(scal), _ptr(gvals), _ptr(work),
+        work.numel(), _stream()))
+
+
+def csr_cg_finish_bwd(A, b, rb, pb, scal, gb):
+    _check("csr_cg_finish_bwd", load().csr_cg_finish_bwd(C.byref(A), _ptr(b), _ptr(rb), _ptr(pb),
+                                                         _ptr(scal), _ptr(gb), _stream()))
 
 
 def csr_validate(A, work):

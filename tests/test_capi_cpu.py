@@ -34,6 +34,23 @@ def test_every_declared_symbol_is_exported_and_bound(lib):
     assert sorted(capi.exported_symbols()) == names
 
 
+def _param_counts():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    out = {}
+    for m in re.finditer(r"\b(csr_[a-z0-9_]+)\s*\(([^)]*)\)\s*;", txt):
+        params = [p for p in m.group(2).split(",") if p.strip() and p.strip() != "void"]
+        out[m.group(1)] = len(params)
+    return out
+
+
+def test_binding_argument_counts_match_header():
+    # A ctypes signature with the wrong arity shifts every later argument.
+    counts = _param_counts()
+    for name, (_, args) in capi._SIGS.items():
+        assert len(args) == counts[name], f"{name}: binding has {len(args)} args, header {counts[name]}"
+
+
 def test_status_strings(lib):
     for st in range(-7, 1):
         s = lib.csr_status_string(st).decode()

@@ -1,0 +1,139 @@
+"""GPU parity of differentiated CG against the FP64 oracle.
+
+Float64 runs must match the oracle's CG and its reverse mode to 1e-9
+(infinity-norm relative; the reverse sweep divides by rho and sigma, so
+rounding grows a little over the steps).  Float32 runs (float32 values and
+vectors, float64 dot products) are held to the bound stated per test.
+Checkpointed and fully stored gradients must agree bit for bit, and graph
+replays must reproduce the eager steps exactly."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2212_05159_amd import cg as cgmod
+from paper_2212_05159_amd import gen
+from paper_2212_05159_amd import sparse as sp
+
+from _util import rel_err, rounded, to_dev, upcast
+
+pytestmark = pytest.mark.gpu
+
+
+def _spd(n, seed):
+    rng = np.random.default_rng(seed)
+    M = (rng.random((n, n)) < 0.03) * rng.standard_normal((n, n))
+    S = np.triu(M, 1)
+    S = S + S.T
+    S += np.diag(np.abs(S).sum(1) + 0.5 + rng.random(n))
+    r, c = np.nonzero(S)
+    return gen._from_coo(n, n, r, c, S[r, c])
+
+
+CASES = [("spd300", lambda: _spd(300, 1), 40),
+         ("poisson32", lambda: gen.poisson2d(32, 32), 25),
+         ("q1_aniso48", lambda: gen.anisotropic_q1(48, 1e-3, np.pi / 4), 60)]
+
+
+@pytest.mark.parametrize("name,mk,K", CASES, ids=[c[0] for c in CASES])
+def test_cg_fp64_matches_oracle(name, mk, K):
+    A = mk()
+    b = gen.normal(A.nrows, 4)
+    t = gen.normal(A.nrows, 5)
+    Ad = sp.CsrTensor.from_host(A, dtype=torch.float64, requires_grad=True)
+    bd = to_dev(b).requires_grad_(True)
+    x = cgmod.cg_solve(Ad, bd, K)
+    (0.5 * ((x - to_dev(t)) ** 2).sum()).backward()
+    xo = oracle.cg(A, b, K)
+    gvo, gbo = oracle.cg_bwd(A, b, K, gx=x.detach().cpu().numpy() - t)
+    assert rel_err(x, xo) < 1e-11
+    assert rel_err(Ad.vals.grad, gvo) < 1e-9, rel_err(Ad.vals.grad, gvo)
+    assert rel_err(bd.grad, gbo) < 1e-9, rel_err(bd.grad, gbo)
+
+
+def test_cg_fp32_matches_oracle_small():
+    # float32 vectors over 25 steps on the 32x32 Poisson matrix (condition
+    # number ~ 440): the float32 iteration tracks the float64 one to ~1e-5.
+    A = gen.poisson2d(32, 32)
+    b = gen.normal(A.nrows, 6)
+    K = 25
+    Ad = sp.CsrTensor.from_host(A, dtype=torch.float32, requires_grad=True)
+    bd = to_dev(b, torch.float32).requires_grad_(True)
+    x = cgmod.cg_solve(Ad, bd, K)
+    x.sum().backward()
+    Ao, bo = upcast(A, torch.float32), rounded(b, torch.float32)
+    xo = oracle.cg(Ao, bo, K)
+    gvo, gbo = oracle.cg_bwd(Ao, bo, K, gx=np.ones(A.nrows))
+    assert rel_err(x, xo) < 1e-4
+    assert rel_err(Ad.vals.grad, gvo) < 2e-3, rel_err(Ad.vals.grad, gvo)
+    assert rel_err(bd.grad, gbo) < 2e-3, rel_err(bd.grad, gbo)
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_checkpointed_gradient_equals_fully_stored(dtype):
+    A = gen.anisotropic_q1(40, 1e-2, 0.7)
+    b = gen.normal(A.nrows, 7)
+    g = gen.normal(A.nrows, 8)
+    K = 37
+    outs = []
+    for kw in (dict(store_all=True), dict(), dict(ckpt_every=5), dict(ckpt_every=1)):
+        Ad = sp.CsrTensor.from_host(A, dtype=dtype, requires_grad=True)
+        bd = to_dev(b, dtype).requires_grad_(True)
+        x = cgmod.cg_solve(Ad, bd, K, **kw)
+        (x * to_dev(g, dtype)).sum().backward()
+        outs.append((x.detach().cpu(), Ad.vals.grad.cpu(), bd.grad.cpu()))
+    for o in outs[1:]:
+        for a, b_ in zip(outs[0], o):
+            assert torch.equal(a, b_)
+
+
+def test_graph_replays_match_eager():
+    A = gen.poisson2d(40, 40)
+    b = gen.normal(A.nrows, 9)
+    K = 30
+    Ad = sp.CsrTensor.from_host(A, dtype=torch.float32)
+    bd = to_dev(b, torch.float32)
+    sol_e = cgmod._Solver(Ad.pattern, Ad.vals, bd)
+    x_e, sv_e = sol_e.forward(K)
+    torch.cuda.synchronize()
+    sol_g = cgmod._Solver(Ad.pattern, Ad.vals, bd)
+    x_g, sv_g = sol_g.forward(K, graph=True)
+    torch.cuda.synchronize()
+    assert torch.equal(sv_e["hist"], sv_g["hist"])  # every replay's scalars
+    assert torch.equal(x_e, x_g)
+    for (r1, p1, s1), (r2, p2, s2) in zip(sv_e["ckpts"], sv_g["ckpts"]):
+        assert torch.equal(r1, r2) and torch.equal(p1, p2) and torch.equal(s1, s2)
+    gv_e, gb_e = sol_e.backward(sv_e, gx=torch.ones_like(bd))
+    gv_g, gb_g = sol_g.backward(sv_g, gx=torch.ones_like(bd))
+    assert torch.equal(gv_e, gv_g) and torch.equal(gb_e, gb_g)
+
+
+def test_residual_history_gradient_matches_oracle():
+    A = _spd(120, 10)
+    b = gen.normal(A.nrows, 11)
+    K = 6
+    Ad = sp.CsrTensor.from_host(A, dtype=torch.float64)
+    bd = to_dev(b)
+    x, R, handle = cgmod.cg_with_residuals(Ad, bd, K)
+    w = gen.normal(K, 12)
+    Rn = R.cpu().numpy()
+    gR = w[:, None] * Rn / np.linalg.norm(Rn, axis=1)[:, None]
+    gv, gb = cgmod.residual_grads(handle, gR=to_dev(gR))
+    xo, Ro = oracle.cg(A, b, K, want_history=True)
+    assert rel_err(R, Ro) < 1e-11
+    gvo, gbo = oracle.cg_bwd(A, b, K, gR=gR)
+    assert rel_err(gv, gvo) < 1e-9 and rel_err(gb, gbo) < 1e-9
+
+
+def test_cg_converged_steps_are_identity():
+    # 1D Poisson with n = 8: CG converges in 8 steps; later steps keep
+    # alpha = beta = 0 and the gradient stays finite.
+    A = gen.poisson1d(8)
+    b = gen.normal(8, 13)
+    Ad = sp.CsrTensor.from_host(A, dtype=torch.float64, requires_grad=True)
+    bd = to_dev(b).requires_grad_(True)
+    x = cgmod.cg_solve(Ad, bd, 12)
+    x.sum().backward()
+    assert torch.isfinite(Ad.vals.grad).all() and torch.isfinite(bd.grad).all()
+    np.testing.assert_allclose(x.detach().cpu().numpy(), np.linalg.solve(A.todense(), b),
+                               rtol=1e-10, atol=1e-12)
