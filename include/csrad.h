@@ -231,6 +231,37 @@ int csr_cg_finish_bwd(const csrad_csr *A, const void *b, const void *rb,
                       void *stream);
 
 /* ---------------------------------------------------------------------
+ * Preconditioned CG (Section 4.3) with float64 vectors and dot products
+ * over float32 or float64 matrix values, device-resident like csr_cg_*.
+ * kind: 0 Jacobi (dinv = 1/diag(A) from csr_diag_inv), 1 factor
+ * (z = L^{-T} L^{-1} r with L lower triangular, its transpose Lt/perm and
+ * its level sets from csr_trisolve_analyze), 2 none.  scal (16 float64 on
+ * the device): [0] r.z, [1] p.q, [2] alpha, [3] beta, [4] ||b||,
+ * [5] ||r||/||b||, [6] done flag, [7] breakdown flag, [8] steps taken,
+ * [9] tolerance.  A step that finds ||r||/||b|| <= tol sets done; p.q not
+ * positive and finite, or a non-finite r.z, sets breakdown and done.
+ * Steps after done change nothing, so the host may run steps in chunks
+ * and read scal in between.  hist (hist_cap float64, may be NULL)
+ * receives ||r||/||b|| per step.
+ * ------------------------------------------------------------------- */
+int csr_pcg_workspace(const csrad_csr *A, size_t *bytes);
+int csr_diag_inv(const csrad_csr *A, double *dinv, void *stream);
+int csr_pcg_init(const csrad_csr *A, int32_t kind, const double *dinv,
+                 const csrad_csr *L, const csrad_csr *Lt, const int32_t *perm,
+                 int32_t nlevels, const int32_t *level_ptr_host,
+                 const int32_t *level_ptr, const int32_t *level_rows,
+                 const double *b, double *x, double *r, double *z, double *p,
+                 double tol, double *scal, void *work, size_t work_bytes,
+                 void *stream);
+int csr_pcg_step(const csrad_csr *A, int32_t kind, const double *dinv,
+                 const csrad_csr *L, const csrad_csr *Lt, const int32_t *perm,
+                 int32_t nlevels, const int32_t *level_ptr_host,
+                 const int32_t *level_ptr, const int32_t *level_rows,
+                 double *x, double *r, double *z, double *p, double *q,
+                 double *scal, double *hist, int32_t hist_cap, void *work,
+                 size_t work_bytes, void *stream);
+
+/* ---------------------------------------------------------------------
  * Pattern check: rowptr monotone from 0 to nnz, colind in [0, ncols),
  * strictly ascending within each row.  *first_bad_row_host receives the
  * first offending row or -1 (synchronises).  Returns CSRAD_EPATTERN if a

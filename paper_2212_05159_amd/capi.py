@@ -67,6 +67,14 @@ _SIGS = {
     "csr_cg_step": (C.c_int, [C.c_void_p] * 10 + [C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p]),
     "csr_cg_step_bwd": (C.c_int, [C.c_void_p] * 15 + [C.c_size_t, C.c_void_p]),
     "csr_cg_finish_bwd": (C.c_int, [C.c_void_p] * 7),
+    "csr_pcg_workspace": (C.c_int, [C.c_void_p, C.POINTER(C.c_size_t)]),
+    "csr_diag_inv": (C.c_int, [C.c_void_p] * 3),
+    "csr_pcg_init": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                               C.c_void_p, C.c_int32] + [C.c_void_p] * 8
+                     + [C.c_double, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
+    "csr_pcg_step": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                               C.c_void_p, C.c_int32] + [C.c_void_p] * 10
+                     + [C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p]),
     "csr_validate": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.c_void_p, C.c_size_t,
                                C.c_void_p]),
 }
@@ -263,6 +271,36 @@ def csr_cg_step_bwd(A, At, perm, p, q, r1, step_hist, gR, xb, rb, pb, qb, scal, 
 def csr_cg_finish_bwd(A, b, rb, pb, scal, gb):
     _check("csr_cg_finish_bwd", load().csr_cg_finish_bwd(C.byref(A), _ptr(b), _ptr(rb), _ptr(pb),
                                                          _ptr(scal), _ptr(gb), _stream()))
+
+
+def csr_pcg_workspace(A):
+    n = C.c_size_t(0)
+    _check("csr_pcg_workspace", load().csr_pcg_workspace(C.byref(A), C.byref(n)))
+    return n.value
+
+
+def csr_diag_inv(A, dinv):
+    _check("csr_diag_inv", load().csr_diag_inv(C.byref(A), _ptr(dinv), _stream()))
+
+
+def _pc_args(pc):
+    """(kind, dinv, L, Lt, perm, nlevels, lp_host, lp, rows) -> ctypes values."""
+    kind, dinv, L, Lt, perm, nl, lph, lp, rows = pc
+    return (int(kind), _ptr(dinv), None if L is None else C.byref(L),
+            None if Lt is None else C.byref(Lt), _ptr(perm), int(nl),
+            None if lph is None else lph.ctypes.data, _ptr(lp), _ptr(rows))
+
+
+def csr_pcg_init(A, pc, b, x, r, z, p, tol, scal, work):
+    _check("csr_pcg_init", load().csr_pcg_init(C.byref(A), *_pc_args(pc), _ptr(b), _ptr(x),
+                                               _ptr(r), _ptr(z), _ptr(p), float(tol), _ptr(scal),
+                                               _ptr(work), work.numel(), _stream()))
+
+
+def csr_pcg_step(A, pc, x, r, z, p, q, scal, hist, work):
+    _check("csr_pcg_step", load().csr_pcg_step(
+        C.byref(A), *_pc_args(pc), _ptr(x), _ptr(r), _ptr(z), _ptr(p), _ptr(q), _ptr(scal),
+        _ptr(hist), 0 if hist is None else hist.numel(), _ptr(work), work.numel(), _stream()))
 
 
 def csr_validate(A, work):

@@ -25,6 +25,12 @@ size_t group_small_workspace(int n, int K);
 int group_small_keys(const int32_t* keys, int n, int K, int32_t* ptr, int32_t* order, void* work,
                      size_t bytes, hipStream_t s);
 
+// Level-scheduled solve with float64 vectors over T's value type (see
+// trisolve.hip); transpose selects T^{-T} over Tt/perm with reversed levels.
+int trisolve_vec64(const csrad_csr* Tm, int lower, const csrad_csr* Tt, const int32_t* perm,
+                   bool transpose, int nlevels, const int32_t* lp_host, const int32_t* lp_dev,
+                   const int32_t* rows, const double* b, double* x, hipStream_t s);
+
 // Fill a device int32 array with a value (graph-capture safe, no memset node).
 int fill_i32(int32_t* p, long long n, int32_t value, hipStream_t s);
 int fill_bytes_zero(void* p, size_t bytes, hipStream_t s);

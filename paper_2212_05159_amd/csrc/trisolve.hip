@@ -137,18 +137,18 @@ __global__ void k_iota(int32_t* p, int n) {
 
 // Solve one row of T x = b on G lanes (also the adjoint solve over T^T
 // when PERM is set: values then come through perm).
-template <typename T, int G, bool PERM>
+template <typename TV, typename TX, int G, bool PERM>
 __device__ __forceinline__ void solve_row(int r, int sub, int lower, const int32_t* __restrict__ rp,
                                           const int32_t* __restrict__ ci,
                                           const int32_t* __restrict__ perm,
-                                          const T* __restrict__ vals, const T* __restrict__ b,
-                                          T* __restrict__ x, bool valid) {
-  T s = 0, d = 0;
+                                          const TV* __restrict__ vals, const TX* __restrict__ b,
+                                          TX* __restrict__ x, bool valid) {
+  TX s = 0, d = 0;
   if (valid) {
     const int e1 = rp[r + 1];
     for (int e = rp[r] + sub; e < e1; e += G) {
       const int j = ci[e];
-      const T v = PERM ? vals[perm[e]] : vals[e];
+      const TX v = (TX)(PERM ? vals[perm[e]] : vals[e]);
       if (j == r) d = v;
       else if (dep_side(lower, r, j)) s += v * x[j];
     }
@@ -158,29 +158,29 @@ __device__ __forceinline__ void solve_row(int r, int sub, int lower, const int32
   if (valid && sub == 0) x[r] = (b[r] - s) / d;
 }
 
-template <typename T, int G, bool PERM>
+template <typename TV, typename TX, int G, bool PERM>
 __global__ __launch_bounds__(kThreads) void k_tri_level(int lo, int hi, int lower,
                                                        const int32_t* __restrict__ rows,
                                                        const int32_t* __restrict__ rp,
                                                        const int32_t* __restrict__ ci,
                                                        const int32_t* __restrict__ perm,
-                                                       const T* __restrict__ vals,
-                                                       const T* __restrict__ b,
-                                                       T* __restrict__ x) {
+                                                       const TV* __restrict__ vals,
+                                                       const TX* __restrict__ b,
+                                                       TX* __restrict__ x) {
   const int q = lo + blockIdx.x * (kThreads / G) + threadIdx.x / G;
   const bool valid = q < hi;
   const int r = valid ? rows[q] : 0;
-  solve_row<T, G, PERM>(r, threadIdx.x % G, lower, rp, ci, perm, vals, b, x, valid);
+  solve_row<TV, TX, G, PERM>(r, threadIdx.x % G, lower, rp, ci, perm, vals, b, x, valid);
 }
 
 // A run of consecutive small levels [l0, l1) in one workgroup.  With
 // REVERSE the levels run from l1-1 down to l0.
-template <typename T, int G, bool PERM, bool REVERSE>
+template <typename TV, typename TX, int G, bool PERM, bool REVERSE>
 __global__ __launch_bounds__(kOneBlockThreads) void k_tri_levels_block(
     int l0, int l1, int lower, const int32_t* __restrict__ level_ptr,
     const int32_t* __restrict__ rows, const int32_t* __restrict__ rp,
-    const int32_t* __restrict__ ci, const int32_t* __restrict__ perm, const T* __restrict__ vals,
-    const T* __restrict__ b, T* __restrict__ x) {
+    const int32_t* __restrict__ ci, const int32_t* __restrict__ perm, const TV* __restrict__ vals,
+    const TX* __restrict__ b, TX* __restrict__ x) {
   constexpr int RPB = kOneBlockThreads / G;
   for (int t = 0; t < l1 - l0; ++t) {
     const int l = REVERSE ? l1 - 1 - t : l0 + t;
@@ -189,7 +189,7 @@ __global__ __launch_bounds__(kOneBlockThreads) void k_tri_levels_block(
       const int q = base + threadIdx.x / G;
       const bool valid = q < hi;
       const int r = valid ? rows[q] : 0;
-      solve_row<T, G, PERM>(r, threadIdx.x % G, lower, rp, ci, perm, vals, b, x, valid);
+      solve_row<TV, TX, G, PERM>(r, threadIdx.x % G, lower, rp, ci, perm, vals, b, x, valid);
     }
     __syncthreads();
   }
@@ -234,10 +234,10 @@ int lanes_for(long long nnz, int rows) {
 
 // Runs the levels: big ones as grid launches, runs of small ones in one
 // workgroup.  REVERSE visits levels from last to first.
-template <typename T, int G, bool PERM, bool REVERSE>
+template <typename TV, typename TX, int G, bool PERM, bool REVERSE>
 void run_levels(int nlevels, const int32_t* lp_host, const int32_t* lp_dev, const int32_t* rows,
                 int lower, const int32_t* rp, const int32_t* ci, const int32_t* perm,
-                const T* vals, const T* b, T* x, hipStream_t s) {
+                const TV* vals, const TX* b, TX* x, hipStream_t s) {
   auto big = [&](int l) { return lp_host[l + 1] - lp_host[l] >= kBigLevel; };
   int t = 0;
   while (t < nlevels) {
@@ -245,8 +245,8 @@ void run_levels(int nlevels, const int32_t* lp_host, const int32_t* lp_dev, cons
     if (big(l)) {
       const int lo = lp_host[l], hi = lp_host[l + 1];
       const int rpb = kThreads / G;
-      hipLaunchKernelGGL((k_tri_level<T, G, PERM>), dim3((hi - lo + rpb - 1) / rpb), dim3(kThreads),
-                         0, s, lo, hi, lower, rows, rp, ci, perm, vals, b, x);
+      hipLaunchKernelGGL((k_tri_level<TV, TX, G, PERM>), dim3((hi - lo + rpb - 1) / rpb),
+                         dim3(kThreads), 0, s, lo, hi, lower, rows, rp, ci, perm, vals, b, x);
       ++t;
       continue;
     }
@@ -255,8 +255,9 @@ void run_levels(int nlevels, const int32_t* lp_host, const int32_t* lp_dev, cons
     // levels t..u-1 in visiting order
     const int l0 = REVERSE ? nlevels - u : t;
     const int l1 = REVERSE ? nlevels - t : u;
-    hipLaunchKernelGGL((k_tri_levels_block<T, G, PERM, REVERSE>), dim3(1), dim3(kOneBlockThreads),
-                       0, s, l0, l1, lower, lp_dev, rows, rp, ci, perm, vals, b, x);
+    hipLaunchKernelGGL((k_tri_levels_block<TV, TX, G, PERM, REVERSE>), dim3(1),
+                       dim3(kOneBlockThreads), 0, s, l0, l1, lower, lp_dev, rows, rp, ci, perm,
+                       vals, b, x);
     t = u;
   }
 }
@@ -266,7 +267,7 @@ int trisolve_fwd_t(const csrad_csr* Tm, int lower, int nlevels, const int32_t* l
                    const int32_t* lp_dev, const int32_t* rows, const T* b, T* x, hipStream_t s) {
   const T* v = static_cast<const T*>(Tm->vals);
   CSRAD_G_SWITCH(lanes_for(Tm->nnz, Tm->nrows),
-                 (run_levels<T, G, false, false>(nlevels, lp_host, lp_dev, rows, lower, Tm->rowptr,
+                 (run_levels<T, T, G, false, false>(nlevels, lp_host, lp_dev, rows, lower, Tm->rowptr,
                                                  Tm->colind, nullptr, v, b, x, s)));
   return launch_status();
 }
@@ -281,7 +282,7 @@ int trisolve_bwd_t(const csrad_csr* Tm, int lower, const csrad_csr* Tt, const in
   // (i, j) is on T's solve side, i.e. the opposite orientation.
   const int lower_t = lower ? 0 : 1;
   const int g = lanes_for(Tm->nnz, n);
-  CSRAD_G_SWITCH(g, (run_levels<T, G, true, true>(nlevels, lp_host, lp_dev, rows, lower_t,
+  CSRAD_G_SWITCH(g, (run_levels<T, T, G, true, true>(nlevels, lp_host, lp_dev, rows, lower_t,
                                                   Tt->rowptr, Tt->colind, perm, v, gx, gb, s)));
   if (gv) {
     CSRAD_G_SWITCH(g, hipLaunchKernelGGL((k_tri_gvals<T, G>),
@@ -289,6 +290,25 @@ int trisolve_bwd_t(const csrad_csr* Tm, int lower, const csrad_csr* Tt, const in
                                          dim3(kThreads), 0, s, n, Tt->rowptr, Tt->colind, perm, gb,
                                          x, gv));
   }
+  return launch_status();
+}
+
+// Float64-vector solves over T's value type, for preconditioners: with
+// transpose = false x = T^{-1} b over T's levels; with transpose = true
+// x = T^{-T} b over T^T (Tt, perm) with T's levels reversed.
+template <typename TV>
+int trisolve_vec64_t(const csrad_csr* Tm, int lower, const csrad_csr* Tt, const int32_t* perm,
+                     bool transpose, int nlevels, const int32_t* lp_host, const int32_t* lp_dev,
+                     const int32_t* rows, const double* b, double* x, hipStream_t s) {
+  const TV* v = static_cast<const TV*>(Tm->vals);
+  CSRAD_G_SWITCH(lanes_for(Tm->nnz, Tm->nrows), {
+    if (transpose)
+      run_levels<TV, double, G, true, true>(nlevels, lp_host, lp_dev, rows, lower ? 0 : 1,
+                                            Tt->rowptr, Tt->colind, perm, v, b, x, s);
+    else
+      run_levels<TV, double, G, false, false>(nlevels, lp_host, lp_dev, rows, lower, Tm->rowptr,
+                                              Tm->colind, nullptr, v, b, x, s);
+  });
   return launch_status();
 }
 
@@ -327,6 +347,17 @@ int check_levels(const csrad_csr* Tm, int nlevels, const int32_t* lp_host, const
 }
 
 }  // namespace
+
+int trisolve_vec64(const csrad_csr* Tm, int lower, const csrad_csr* Tt, const int32_t* perm,
+                   bool transpose, int nlevels, const int32_t* lp_host, const int32_t* lp_dev,
+                   const int32_t* rows, const double* b, double* x, hipStream_t s) {
+  if (Tm->dtype == CSRAD_F32)
+    return trisolve_vec64_t<float>(Tm, lower, Tt, perm, transpose, nlevels, lp_host, lp_dev, rows,
+                                   b, x, s);
+  return trisolve_vec64_t<double>(Tm, lower, Tt, perm, transpose, nlevels, lp_host, lp_dev, rows,
+                                  b, x, s);
+}
+
 }  // namespace csrad
 
 using namespace csrad;

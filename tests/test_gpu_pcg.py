@@ -1,0 +1,108 @@
+"""GPU parity of PCG (Section 4.3) against the FP64 oracle.
+
+Float64 runs reproduce the oracle's residual history to 1e-8 relative and
+stop within one step of it; exact factors converge in one step; float32
+values with float64 vectors reach ||b - A x||/||b|| <= 1e-6 (checked on the
+host in float64); breakdowns are reported and fall back to Jacobi."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2212_05159_amd import gen
+from paper_2212_05159_amd import pcg as pcgmod
+from paper_2212_05159_amd import sparse as sp
+
+from _util import rel_err, to_dev, upcast
+
+pytestmark = pytest.mark.gpu
+
+
+def _spd(n, seed):
+    rng = np.random.default_rng(seed)
+    M = (rng.random((n, n)) < 0.03) * rng.standard_normal((n, n))
+    S = np.triu(M, 1)
+    S = S + S.T
+    S += np.diag(np.abs(S).sum(1) * 0.6 + 0.05 + rng.random(n))
+    r, c = np.nonzero(S)
+    return gen._from_coo(n, n, r, c, S[r, c])
+
+
+@pytest.mark.parametrize("precond", ["jacobi", "none"])
+@pytest.mark.parametrize("name,mk", [("spd400", lambda: _spd(400, 1)),
+                                     ("q1_aniso40", lambda: gen.anisotropic_q1(40, 1e-2, 0.4))],
+                         ids=["spd400", "q1_aniso40"])
+def test_pcg_fp64_matches_oracle(precond, name, mk):
+    A = mk()
+    b = gen.normal(A.nrows, 2)
+    Ad = sp.CsrTensor.from_host(A, dtype=torch.float64)
+    x, info = pcgmod.pcg(Ad, to_dev(b), precond=precond, tol=1e-8, record=True)
+    xo, ito, ho = oracle.pcg(A, b, precond, tol=1e-8)
+    assert info["converged"] and ito > 0
+    assert abs(info["iters"] - ito) <= 1
+    m = min(info["iters"], ito)
+    # rounding differences grow over hundreds of steps: absolute floor 1e-9
+    # on the relative residual (the initial one is 1)
+    np.testing.assert_allclose(info["hist"][:m], ho[1:m + 1], rtol=1e-6, atol=1e-9)
+    assert rel_err(x, xo) < 1e-6
+    assert pcgmod.true_residual(A, x, b) < 2e-8
+
+
+def test_pcg_exact_factor_converges_in_one_step():
+    A = gen.poisson1d(500)
+    Lp = gen.tril(A)
+    L = gen.Csr(500, 500, Lp.rowptr, Lp.colind, oracle.ic0(A, Lp))
+    b = gen.normal(500, 3)
+    Ad = sp.CsrTensor.from_host(A, dtype=torch.float64)
+    Ld = sp.CsrTensor.from_host(L, dtype=torch.float64)
+    x, info = pcgmod.pcg(Ad, to_dev(b), precond="factor", L=Ld, tol=1e-10)
+    assert info["converged"] and info["iters"] == 1
+    assert pcgmod.true_residual(A, x, b) < 1e-10
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_pcg_fp32_values_reach_1e6(graph):
+    A = gen.anisotropic_q1(96, 1e-3, np.pi / 4)
+    b = gen.normal(A.nrows, 4)
+    Ad = sp.CsrTensor.from_host(A, dtype=torch.float32)
+    x, info = pcgmod.pcg(Ad, to_dev(b), precond="jacobi", tol=1e-6, graph=graph)
+    assert info["converged"]
+    # the system solved is the float32-rounded matrix
+    assert pcgmod.true_residual(upcast(A, torch.float32), x, b) <= 1.05e-6
+    _, ito, _ = oracle.pcg(upcast(A, torch.float32), b, "jacobi", tol=1e-6)
+    assert abs(info["iters"] - ito) <= 2
+
+
+def test_pcg_factor_matches_oracle_factor():
+    # a non-exact factor: L = (D + tril) D^{-1/2} (symmetric Gauss-Seidel)
+    A = gen.anisotropic_q1(48, 1e-2, 1.1)
+    T = gen.tril(A)
+    rows = T.row_of_entry()
+    d = np.zeros(A.nrows)
+    d[rows[T.colind == rows]] = T.vals[T.colind == rows]
+    L = gen.Csr(A.nrows, A.ncols, T.rowptr, T.colind, T.vals / np.sqrt(d[T.colind]))
+    b = gen.normal(A.nrows, 5)
+    Ad = sp.CsrTensor.from_host(A, dtype=torch.float64)
+    Ld = sp.CsrTensor.from_host(L, dtype=torch.float64)
+    x, info = pcgmod.pcg(Ad, to_dev(b), precond="factor", L=Ld, tol=1e-8, record=True)
+    xo, ito, ho = oracle.pcg(A, b, "factor", L=L, tol=1e-8)
+    assert info["converged"] and abs(info["iters"] - ito) <= 1
+    m = min(info["iters"], ito)
+    np.testing.assert_allclose(info["hist"][:m], ho[1:m + 1], rtol=1e-6, atol=1e-9)
+    _, itj, _ = oracle.pcg(A, b, "jacobi", tol=1e-8)
+    assert ito < itj  # the factor helps
+
+
+def test_pcg_breakdown_falls_back_to_jacobi():
+    A = gen.poisson2d(20, 20)
+    T = gen.tril(A)
+    bad = gen.Csr(A.nrows, A.ncols, T.rowptr, T.colind,
+                  np.where(T.colind == T.row_of_entry(), 0.0, T.vals))  # zero diagonal
+    b = gen.normal(A.nrows, 6)
+    Ad = sp.CsrTensor.from_host(A, dtype=torch.float64)
+    Ld = sp.CsrTensor.from_host(bad, dtype=torch.float64)
+    x, info = pcgmod.pcg(Ad, to_dev(b), precond="factor", L=Ld, tol=1e-8, fallback=False)
+    assert info["breakdown"] and not info["converged"]
+    x, info = pcgmod.pcg(Ad, to_dev(b), precond="factor", L=Ld, tol=1e-8, fallback=True)
+    assert info["fallback"] and info["converged"]
+    assert pcgmod.true_residual(A, x, b) < 2e-8
