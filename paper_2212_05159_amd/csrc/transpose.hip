@@ -266,6 +266,8 @@ __global__ __launch_bounds__(256) void k_ms_scatter(const int32_t* __restrict__ 
       for (int v = 0; v < 4; ++v) t += wcount[v][threadIdx.x];
       running[threadIdx.x] += t;
     }
+    // every wave's counts must be summed before any of them is cleared
+    __syncthreads();
     for (int q = threadIdx.x; q < 4 * kSmallKeys; q += 256) (&wcount[0][0])[q] = 0;
     __syncthreads();
   }

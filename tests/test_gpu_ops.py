@@ -295,9 +295,17 @@ def _tri_cases():
 
 
 TRI = list(_tri_cases())
+# Few levels over many rows: the grouping by level runs as a multi-split
+# over many tiles and chunks (regression cover for its per-chunk counts).
+LEVELS_WIDE = [
+    ("q1_four_colour_400", gen.tril(gen.permute_sym(gen.anisotropic_q1(400, 1e-2, 0.7),
+                                                    gen.four_color_2d(400))), True),
+    ("geometric_29", gen.tril(gen.block_diag([gen.geometric_graph_laplacian(
+        b, n_range=(300, 5000), k_range=(6, 14)) for b in range(12)])[0]), True),
+]
 
 
-@pytest.mark.parametrize("name,T,lower", TRI, ids=[c[0] for c in TRI])
+@pytest.mark.parametrize("name,T,lower", TRI + LEVELS_WIDE, ids=[c[0] for c in TRI + LEVELS_WIDE])
 def test_levels_bit_exact(name, T, lower):
     P = sp.Pattern.from_host(T)
     nl, lph, lp, lr, lor = P.levels(lower)
