@@ -19,6 +19,15 @@ algorithmic bytes count every array it must touch once.  The dominant
 kernel (the fused SpMM backward) is also timed on its own with HIP events
 on the launch stream for the roofline entry.
 
+Second part (the "pcg" entry): preconditioned CG to ||r||/||b|| <= 1e-6 on
+held-out 2D anisotropic Q1 diffusion systems of 1024^2 (2x2 four-coloured
+order, float32 values, float64 vectors), wall time per system with HIP
+events, for the learned factor L L^T (the network briefly trained here on
+256^2 systems), the untrained network (the Gauss-Seidel factor), Jacobi
+and plain CG.  Each timed solve includes building its preconditioner
+(network inference, values of L^T, 1/diag); the level sets of L's pattern
+are shared by all systems and analysed once beforehand.
+
 Prints one JSON line on stdout; progress goes to stderr.
 """
 from __future__ import annotations
@@ -41,6 +50,82 @@ I4 = 4
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+# ----------------------------------------------------------------------
+# PCG time to 1e-6: learned factor vs Jacobi
+# ----------------------------------------------------------------------
+def pcg_section(n_eval, n_train, train_steps, systems):
+    import torch
+    from paper_2212_05159_amd import learned
+    from paper_2212_05159_amd import pcg as pcgmod
+    from paper_2212_05159_amd import sparse as sp
+
+    t0 = time.perf_counter()
+    model = learned.MPNN(seed=1)
+    untrained = learned.MPNN(seed=1)
+    hist = learned.train(model, N=n_train, steps=train_steps, lr=3e-3, nit=6, seed=5)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    log(f"trained the network: {train_steps} systems of {n_train}^2 in {train_s:.1f} s "
+        f"(loss {np.mean(hist[:20]):.4f} -> {np.mean(hist[-20:]):.4f})")
+    fam = learned.Q1Family(n_eval)
+    t0 = time.perf_counter()
+    nl = fam.Lpat.levels(True)[0]
+    fam.Lpat.transpose()
+    torch.cuda.synchronize()
+    analysis_ms = (time.perf_counter() - t0) * 1e3
+    methods = ("learned", "untrained", "jacobi", "cg")
+    maxit = 40000
+
+    def solve(key, A, b, cap=maxit):
+        if key in ("learned", "untrained"):
+            net = model if key == "learned" else untrained
+            with torch.no_grad():
+                L = sp.CsrTensor(fam.Lpat, net(A, fam.Lpat))
+            return pcgmod.pcg(A, b, "factor", L=L, tol=1e-6, maxit=cap, chunk=50, graph=True)
+        return pcgmod.pcg(A, b, "jacobi" if key == "jacobi" else "none", tol=1e-6, maxit=cap,
+                          chunk=50, graph=True)
+
+    times = {k: [] for k in methods}
+    iters = {k: [] for k in methods}
+    fallbacks = 0
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for j in range(systems):
+        rng = np.random.default_rng([5, 1, j])
+        eps, theta = learned.Q1Family.sample(rng)
+        A, _ = fam.system(eps, theta)
+        b = torch.as_tensor(rng.standard_normal(fam.P.nrows), device="cuda")
+        if j == 0:
+            for key in methods:  # warm-up: allocator, graph capture paths
+                solve(key, A, b, cap=100)
+        for key in methods:
+            torch.cuda.synchronize()
+            e0.record()
+            x, info = solve(key, A, b)
+            e1.record()
+            torch.cuda.synchronize()
+            if not info["converged"]:
+                raise RuntimeError(f"{key} PCG did not reach 1e-6 on system {j}: {info}")
+            fallbacks += int(info.get("fallback", False))
+            times[key].append(e0.elapsed_time(e1))
+            iters[key].append(info["iters"])
+        log(f"pcg system {j}: eps {eps:.2e} theta {theta:.2f} " +
+            " ".join(f"{k} {times[k][-1]:.1f} ms/{iters[k][-1]} it" for k in methods))
+    med = {k: round(float(np.median(v)), 3) for k, v in times.items()}
+    return {
+        "workload": f"2D anisotropic Q1 diffusion {n_eval}^2 (n={fam.P.nrows}, nnz={fam.P.nnz}), "
+                    f"2x2 four-coloured order, float32 values, float64 vectors; L on tril(A) "
+                    f"(nnz={fam.Lpat.nnz}, {nl} levels)",
+        "systems": systems, "tol": 1e-6,
+        "median_ms": med,
+        "median_iterations": {k: float(np.median(v)) for k, v in iters.items()},
+        "learned_speedup_vs_jacobi": round(med["jacobi"] / med["learned"], 3),
+        "fallbacks": fallbacks,
+        "level_analysis_ms": round(analysis_ms, 3),
+        "train": {"systems": train_steps, "grid": n_train, "seconds": round(train_s, 2),
+                  "lr": 3e-3, "pcg_steps_in_loss": 6},
+    }
 
 
 # ----------------------------------------------------------------------
@@ -267,6 +352,11 @@ def main():
     ap.add_argument("--grid", type=int, default=128)
     ap.add_argument("--k", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-pcg", action="store_true", help="skip the PCG time-to-1e-6 part")
+    ap.add_argument("--pcg-grid", type=int, default=1024)
+    ap.add_argument("--pcg-systems", type=int, default=4)
+    ap.add_argument("--train-grid", type=int, default=256)
+    ap.add_argument("--train-steps", type=int, default=300)
     ap.add_argument("--calibrate", type=int, default=0, metavar="M",
                     help="only run a copy-like kernel over M million float32 values "
                          "(identity-permutation gather: 12 bytes per value) to calibrate "
@@ -345,6 +435,11 @@ def main():
         cpu = cpu_baseline(h, total_bytes)
         log(f"oracle: {cpu['seconds']} s for one step")
 
+    pcg = None
+    if not args.no_pcg:
+        log("PCG time-to-1e-6 part ...")
+        pcg = pcg_section(args.pcg_grid, args.train_grid, args.train_steps, args.pcg_systems)
+
     out = {
         "metric": "fwd+bwd sparse-op GB/s (% HBM peak); PCG time-to-1e-6: learned vs Jacobi",
         "value": round(value, 2),
@@ -368,6 +463,7 @@ def main():
         "frac_hbm_peak": round(value / HBM_PEAK_GBS, 4),
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "pcg": pcg,
         "breakdown": breakdown,
         "step_bytes": total_bytes,
     }

@@ -235,7 +235,9 @@ int csr_cg_finish_bwd(const csrad_csr *A, const void *b, const void *rb,
  * over float32 or float64 matrix values, device-resident like csr_cg_*.
  * kind: 0 Jacobi (dinv = 1/diag(A) from csr_diag_inv), 1 factor
  * (z = L^{-T} L^{-1} r with L lower triangular, its transpose Lt/perm and
- * its level sets from csr_trisolve_analyze), 2 none.  scal (16 float64 on
+ * its level sets from csr_trisolve_analyze; when Lt->vals is non-NULL it
+ * holds L^T's values (csr_transpose_vals, same dtype as L) and perm is not
+ * read), 2 none.  scal (16 float64 on
  * the device): [0] r.z, [1] p.q, [2] alpha, [3] beta, [4] ||b||,
  * [5] ||r||/||b||, [6] done flag, [7] breakdown flag, [8] steps taken,
  * [9] tolerance.  A step that finds ||r||/||b|| <= tol sets done; p.q not
@@ -260,6 +262,44 @@ int csr_pcg_step(const csrad_csr *A, int32_t kind, const double *dinv,
                  double *x, double *r, double *z, double *p, double *q,
                  double *scal, double *hist, int32_t hist_cap, void *work,
                  size_t work_bytes, void *stream);
+
+/* ---------------------------------------------------------------------
+ * Learned preconditioner network (float32 tensors, hidden width 32).
+ * csr_dense_fwd: Y (n x 32) = act([X1 X2] W + b) on bf16 matrix cores with
+ *   float32 accumulation; X1 (n x K1, leading dim ld1), X2 (n x K2, may be
+ *   absent with K2 = 0), W ((K1+K2) x 32 row-major, float32, rounded to
+ *   bf16 for the products), b (32, may be NULL), relu = 1 or identity;
+ *   K1 + K2 <= 64.
+ * csr_dense_bwd: with G = dY * act'(Y): dX1, dX2 = G W^T (may be NULL),
+ *   dW = [X1 X2]^T G, db = column sums of G (may be NULL; need the
+ *   workspace of csr_dense_workspace; deterministic).
+ * csr_mpnn_prep: for A (float32, square) and Lpat = tril(A)'s pattern:
+ *   ahat = D^{-1/2} A D^{-1/2} on A's pattern, ahatL the same on Lpat,
+ *   dsqrt = sqrt(diag A), X0 (n x 16) node inputs [1, sum |ahat_offdiag|,
+ *   sum ahat_offdiag, (row length - 1)/8, then for the neighbours j < i
+ *   and j > i in turn: sum ahat_ij, sum |ahat_ij|, count/8; 0...].
+ * csr_mpnn_readout: L on Lpat from the per-entry network output t:
+ *   L_ij = sqrt(A_ii) ahat_ij (1 + t_ij) for j < i and
+ *   L_ii = sqrt(A_ii) (softplus(t_ii + c) + delta), so diag(L) > 0.
+ * csr_mpnn_readout_bwd: gt = dL/dt given gL.
+ * ------------------------------------------------------------------- */
+int csr_dense_workspace(int32_t n, size_t *bytes);
+int csr_dense_fwd(int32_t n, int32_t K1, const float *X1, int64_t ld1,
+                  int32_t K2, const float *X2, int64_t ld2, const float *W,
+                  const float *b, int32_t relu, float *Y, void *stream);
+int csr_dense_bwd(int32_t n, int32_t K1, const float *X1, int64_t ld1,
+                  int32_t K2, const float *X2, int64_t ld2, const float *W,
+                  const float *Y, const float *dY, int32_t relu, float *dX1,
+                  float *dX2, float *dW, float *db, void *work,
+                  size_t work_bytes, void *stream);
+int csr_mpnn_prep(const csrad_csr *A, const csrad_csr *Lpat, float *ahat,
+                  float *ahatL, float *dsqrt, float *X0, void *stream);
+int csr_mpnn_readout(const csrad_csr *Lpat, const float *ahatL,
+                     const float *dsqrt, const float *t, float c, float delta,
+                     float *Lv, void *stream);
+int csr_mpnn_readout_bwd(const csrad_csr *Lpat, const float *ahatL,
+                         const float *dsqrt, const float *t, float c,
+                         const float *gL, float *gt, void *stream);
 
 /* ---------------------------------------------------------------------
  * Pattern check: rowptr monotone from 0 to nnz, colind in [0, ncols),

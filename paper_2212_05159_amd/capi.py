@@ -75,6 +75,17 @@ _SIGS = {
     "csr_pcg_step": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
                                C.c_void_p, C.c_int32] + [C.c_void_p] * 10
                      + [C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p]),
+    "csr_dense_workspace": (C.c_int, [C.c_int32, C.POINTER(C.c_size_t)]),
+    "csr_dense_fwd": (C.c_int, [C.c_int32, C.c_int32, C.c_void_p, C.c_int64, C.c_int32, C.c_void_p,
+                                C.c_int64, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p,
+                                C.c_void_p]),
+    "csr_dense_bwd": (C.c_int, [C.c_int32, C.c_int32, C.c_void_p, C.c_int64, C.c_int32, C.c_void_p,
+                                C.c_int64] + [C.c_void_p] * 3 + [C.c_int32] + [C.c_void_p] * 5
+                      + [C.c_size_t, C.c_void_p]),
+    "csr_mpnn_prep": (C.c_int, [C.c_void_p] * 7),
+    "csr_mpnn_readout": (C.c_int, [C.c_void_p] * 4 + [C.c_float, C.c_float, C.c_void_p,
+                                                      C.c_void_p]),
+    "csr_mpnn_readout_bwd": (C.c_int, [C.c_void_p] * 4 + [C.c_float] + [C.c_void_p] * 3),
     "csr_validate": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.c_void_p, C.c_size_t,
                                C.c_void_p]),
 }
@@ -301,6 +312,42 @@ def csr_pcg_step(A, pc, x, r, z, p, q, scal, hist, work):
     _check("csr_pcg_step", load().csr_pcg_step(
         C.byref(A), *_pc_args(pc), _ptr(x), _ptr(r), _ptr(z), _ptr(p), _ptr(q), _ptr(scal),
         _ptr(hist), 0 if hist is None else hist.numel(), _ptr(work), work.numel(), _stream()))
+
+
+def csr_dense_workspace(n):
+    nb = C.c_size_t(0)
+    _check("csr_dense_workspace", load().csr_dense_workspace(int(n), C.byref(nb)))
+    return nb.value
+
+
+def csr_dense_fwd(n, K1, X1, ld1, K2, X2, ld2, W, b, relu, Y):
+    _check("csr_dense_fwd", load().csr_dense_fwd(int(n), int(K1), _ptr(X1), int(ld1), int(K2),
+                                                 _ptr(X2), int(ld2), _ptr(W), _ptr(b), int(relu),
+                                                 _ptr(Y), _stream()))
+
+
+def csr_dense_bwd(n, K1, X1, ld1, K2, X2, ld2, W, Y, dY, relu, dX1, dX2, dW, db, work):
+    _check("csr_dense_bwd", load().csr_dense_bwd(
+        int(n), int(K1), _ptr(X1), int(ld1), int(K2), _ptr(X2), int(ld2), _ptr(W), _ptr(Y),
+        _ptr(dY), int(relu), _ptr(dX1), _ptr(dX2), _ptr(dW), _ptr(db), _ptr(work),
+        0 if work is None else work.numel(), _stream()))
+
+
+def csr_mpnn_prep(A, Lpat, ahat, ahatL, dsqrt, X0):
+    _check("csr_mpnn_prep", load().csr_mpnn_prep(C.byref(A), C.byref(Lpat), _ptr(ahat),
+                                                 _ptr(ahatL), _ptr(dsqrt), _ptr(X0), _stream()))
+
+
+def csr_mpnn_readout(Lpat, ahatL, dsqrt, t, c, delta, Lv):
+    _check("csr_mpnn_readout", load().csr_mpnn_readout(C.byref(Lpat), _ptr(ahatL), _ptr(dsqrt),
+                                                       _ptr(t), float(c), float(delta), _ptr(Lv),
+                                                       _stream()))
+
+
+def csr_mpnn_readout_bwd(Lpat, ahatL, dsqrt, t, c, gL, gt):
+    _check("csr_mpnn_readout_bwd", load().csr_mpnn_readout_bwd(
+        C.byref(Lpat), _ptr(ahatL), _ptr(dsqrt), _ptr(t), float(c), _ptr(gL), _ptr(gt),
+        _stream()))
 
 
 def csr_validate(A, work):

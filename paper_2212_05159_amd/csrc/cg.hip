@@ -98,20 +98,24 @@ __global__ __launch_bounds__(kThreads) void k_cg_spmv_dot(int n, const int32_t* 
                                                           T* __restrict__ p_save,
                                                           double* __restrict__ part) {
   __shared__ double sm[kThreads / kWave];
-  const int row = blockIdx.x * (kThreads / G) + threadIdx.x / G;
+  // G lanes per row; the block strides over row groups (grid capped).
+  constexpr int RPB = kThreads / G;
   const int sub = threadIdx.x % G;
-  T s = 0;
-  if (row < n) {
-    const int e1 = rp[row + 1];
-    for (int e = rp[row] + sub; e < e1; e += G) s += v[e] * p[ci[e]];
-  }
-  s = group_sum<G>(s);
   double d = 0;
-  if (row < n && sub == 0) {
-    const T pr = p[row];
-    q[row] = s;
-    if (p_save) p_save[row] = pr;
-    d = (double)pr * (double)s;
+  for (int base = blockIdx.x * RPB; base < n; base += gridDim.x * RPB) {
+    const int row = base + threadIdx.x / G;
+    T s = 0;
+    if (row < n) {
+      const int e1 = rp[row + 1];
+      for (int e = rp[row] + sub; e < e1; e += G) s += v[e] * p[ci[e]];
+    }
+    s = group_sum<G>(s);
+    if (row < n && sub == 0) {
+      const T pr = p[row];
+      q[row] = s;
+      if (p_save) p_save[row] = pr;
+      d += (double)pr * (double)s;
+    }
   }
   d = block_sum_double(d, sm);
   if (threadIdx.x == 0) part[blockIdx.x] = d;
@@ -321,7 +325,8 @@ int vec_blocks(int n) {
 
 int spmv_blocks(int n, int g) {
   const int rpb = kThreads / g;
-  return (n + rpb - 1) / rpb;
+  const int b = (n + rpb - 1) / rpb;
+  return b < 1 ? 1 : (b > kVecBlocksMax ? kVecBlocksMax : b);
 }
 
 // Workspace: block partials (float64) sized for the larger of the two grids.
@@ -368,7 +373,9 @@ int cg_step_bwd_t(const csrad_csr* A, const csrad_csr* At, const int32_t* perm, 
   hipLaunchKernelGGL(k_cgb_r2, dim3(1), dim3(kThreads), 0, s, part, nbv, h, scal);
   hipLaunchKernelGGL((k_cgb_3<T>), dim3(nbv), dim3(kThreads), 0, s, n, p, qb, scal);
   const int g = lanes_for(At->nnz, n);
-  CSRAD_G_SWITCH(g, hipLaunchKernelGGL((k_cgb_4<T, G>), dim3(spmv_blocks(n, g)), dim3(kThreads),
+  // one row group per block (no grid stride here)
+  const int rpb = kThreads / g;
+  CSRAD_G_SWITCH(g, hipLaunchKernelGGL((k_cgb_4<T, G>), dim3((n + rpb - 1) / rpb), dim3(kThreads),
                                        0, s, n, At->rowptr, At->colind, perm, v, p, q, qb, pb, gv,
                                        scal));
   return launch_status();

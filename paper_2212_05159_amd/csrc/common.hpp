@@ -172,6 +172,28 @@ __device__ __forceinline__ int wave_agg_add(int32_t* counter, int key) {
   return slot;
 }
 
+// Wave-aggregated append to one counter: the lanes with pred set take
+// consecutive slots (in lane order) from a single atomicAdd by the first
+// of them.  Every lane of the wave must reach the call.  Returns the slot
+// (meaningful where pred is set).
+__device__ __forceinline__ int wave_append(int32_t* counter, bool pred) {
+  const unsigned long long mask = __ballot(pred);
+  if (!mask) return 0;
+  const int lane = __lane_id();
+  const int leader = __ffsll((long long)mask) - 1;
+  int base = 0;
+  if (lane == leader) base = atomicAdd(counter, __popcll(mask));
+  base = __shfl(base, leader);
+  return base + __popcll(mask & ((1ull << lane) - 1ull));
+}
+
+// Maximum of v over the wave (every lane must reach the call).
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+  return v;
+}
+
 // ---------------------------------------------------------------------
 // Vector types for 16-byte dense-row accesses.
 // ---------------------------------------------------------------------

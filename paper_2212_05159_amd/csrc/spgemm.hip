@@ -3,12 +3,16 @@
 //
 // Rows of C are binned by the product count U_i = sum over A's row of the
 // lengths of the B rows it selects, an upper bound on nnz(C_i):
-//   U <= 16, 64, 512, 4096 : LDS hash table of H = 2U slots per row,
-//                            8 / 16 / 64 / 256 lanes per row;
+//   U <= 16, 64            : 16 / 64 lanes per row, one product per lane,
+//                            sorted across the lanes in registers;
+//   U <= 512, 4096         : LDS hash table of H = 2U slots per row,
+//                            64 / 256 lanes per row;
 //   U > 4096               : a dense per-workgroup marker array in the
 //                            workspace (tagged with the row id).
-// Symbolic: count the distinct columns (hash insert with CAS).
-// Numeric : rebuild the set, sort it (bitonic sort of the whole table in
+// Symbolic: count the distinct columns (run heads after the lane sort;
+//           hash insert with CAS; marker tags).
+// Numeric : small bins sum each run of equal columns in k order; the
+//           others rebuild the set, sort it (bitonic sort of the table in
 //           LDS, empty slots last; for the dense path a block scan of the
 //           marker array), write ascending column indices, then each
 //           output entry C_ij = sum_k A_ik B_kj with k in A's row order and
@@ -250,6 +254,136 @@ __global__ __launch_bounds__(kThreads) void k_num_hash(
 }
 
 // ---------------------------------------------------------------------
+// Small bins (U <= G, G = 16 or 64): G lanes per row, no LDS.  Lane l holds
+// the row's l-th product in k order (A's row order, then B's row order);
+// the G keys (column, product index) are sorted across the lanes by a
+// register bitonic network, so equal columns form runs ordered by k.  A
+// run's first lane ("head") stands for one output entry: the heads count
+// the row (symbolic), give each entry its rank, and sum their run's
+// products in lane order, i.e. k ascending (numeric).
+// ---------------------------------------------------------------------
+__device__ __forceinline__ unsigned long long shfl_xor_u64(unsigned long long v, int m) {
+  const unsigned lo = (unsigned)__shfl_xor((int)(unsigned)v, m);
+  const unsigned hi = (unsigned)__shfl_xor((int)(unsigned)(v >> 32), m);
+  return ((unsigned long long)hi << 32) | lo;
+}
+
+// Ascending sort of one key per lane over aligned groups of G lanes.
+template <int G>
+__device__ __forceinline__ unsigned long long group_sort(unsigned long long key, int l) {
+#pragma unroll
+  for (int k = 2; k <= G; k <<= 1) {
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      const unsigned long long other = shfl_xor_u64(key, j);
+      const bool keep_min = ((l & j) == 0) == ((l & k) == 0);
+      key = keep_min ? (other < key ? other : key) : (other > key ? other : key);
+    }
+  }
+  return key;
+}
+
+// The l-th product of row i: its column, and its A and B entry positions
+// (col = INT32_MAX when the row has at most l products).
+__device__ __forceinline__ void lane_product(int i, int l, const int32_t* __restrict__ rpA,
+                                             const int32_t* __restrict__ ciA,
+                                             const int32_t* __restrict__ rpB,
+                                             const int32_t* __restrict__ ciB, int& col, int& ea,
+                                             int& eb) {
+  col = INT32_MAX;
+  ea = eb = -1;
+  int base = 0;
+  const int a1 = rpA[i + 1];
+  for (int a = rpA[i]; a < a1 && base <= l; ++a) {
+    const int k = ciA[a];
+    const int b0 = rpB[k], len = rpB[k + 1] - b0;
+    if (l < base + len) {
+      ea = a;
+      eb = b0 + (l - base);
+      col = ciB[eb];
+    }
+    base += len;
+  }
+}
+
+// Mask of the lanes of this lane's group, and of the group's lanes below it.
+template <int G>
+__device__ __forceinline__ unsigned long long group_mask(int lane) {
+  return G == 64 ? ~0ull : (((1ull << G) - 1ull) << (lane & ~(G - 1)));
+}
+
+template <int G>
+__global__ __launch_bounds__(kThreads) void k_sym_lanes(int bin, const int32_t* __restrict__ list,
+                                                        const int32_t* __restrict__ bin_off,
+                                                        const int32_t* __restrict__ rpA,
+                                                        const int32_t* __restrict__ ciA,
+                                                        const int32_t* __restrict__ rpB,
+                                                        const int32_t* __restrict__ ciB,
+                                                        int32_t* __restrict__ counts) {
+  constexpr int RPB = kThreads / G;
+  const int first = bin_off[bin], nrows = bin_off[bin + 1] - first;
+  const int lane = __lane_id(), l = threadIdx.x % G;
+  const unsigned long long gm = group_mask<G>(lane);
+  for (int base = blockIdx.x * RPB; base < nrows; base += gridDim.x * RPB) {
+    const int idx = base + threadIdx.x / G;
+    const bool valid = idx < nrows;
+    const int i = valid ? list[first + idx] : 0;
+    int col = INT32_MAX, ea, eb;
+    if (valid) lane_product(i, l, rpA, ciA, rpB, ciB, col, ea, eb);
+    const unsigned long long key =
+        group_sort<G>(((unsigned long long)(unsigned)col << 32) | (unsigned)l, l);
+    const int sc = (int)(key >> 32);
+    const int prev = __shfl(sc, lane > 0 ? lane - 1 : 0);
+    const bool head = sc != INT32_MAX && (l == 0 || prev != sc);
+    const int cnt = __popcll(__ballot(head) & gm);
+    if (valid && l == 0) counts[i] = cnt;
+  }
+}
+
+template <typename T, int G>
+__global__ __launch_bounds__(kThreads) void k_num_lanes(
+    int bin, const int32_t* __restrict__ list, const int32_t* __restrict__ bin_off,
+    const int32_t* __restrict__ rpA, const int32_t* __restrict__ ciA, const T* __restrict__ vA,
+    const int32_t* __restrict__ rpB, const int32_t* __restrict__ ciB, const T* __restrict__ vB,
+    const int32_t* __restrict__ rpC, int32_t* __restrict__ ciC, T* __restrict__ vC) {
+  constexpr int RPB = kThreads / G;
+  const int first = bin_off[bin], nrows = bin_off[bin + 1] - first;
+  const int lane = __lane_id(), l = threadIdx.x % G;
+  const int gbase = lane & ~(G - 1);
+  const unsigned long long gm = group_mask<G>(lane);
+  const unsigned long long below = gm & ((1ull << lane) - 1ull);
+  for (int base = blockIdx.x * RPB; base < nrows; base += gridDim.x * RPB) {
+    const int idx = base + threadIdx.x / G;
+    const bool valid = idx < nrows;
+    const int i = valid ? list[first + idx] : 0;
+    int col = INT32_MAX, ea = -1, eb = -1;
+    if (valid) lane_product(i, l, rpA, ciA, rpB, ciB, col, ea, eb);
+    const T prod = ea >= 0 ? vA[ea] * vB[eb] : T(0);
+    const unsigned long long key =
+        group_sort<G>(((unsigned long long)(unsigned)col << 32) | (unsigned)l, l);
+    const int sc = (int)(key >> 32);
+    const int src = (int)(key & 0xffffffffull);  // product index of this sorted slot
+    const T v = __shfl(prod, gbase + src);
+    const int prev = __shfl(sc, lane > 0 ? lane - 1 : 0);
+    const bool head = sc != INT32_MAX && (l == 0 || prev != sc);
+    const unsigned long long heads = __ballot(head);
+    // run sums in lane order (k ascending)
+    T acc = v;
+#pragma unroll
+    for (int d = 1; d < G; ++d) {
+      const int c = __shfl(sc, lane + d < 64 ? lane + d : lane);
+      const T w = __shfl(v, lane + d < 64 ? lane + d : lane);
+      if (l + d < G && c == sc) acc += w;
+    }
+    if (valid && head) {
+      const int pos = rpC[i] + __popcll(heads & below);
+      ciC[pos] = sc;
+      vC[pos] = acc;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------
 // Dense-marker bin (U > 4096): each block owns a marker array of p ints in
 // the workspace, tagged with the row id, and walks the bin's rows.
 // ---------------------------------------------------------------------
@@ -466,12 +600,12 @@ int spgemm_numeric_t(const csrad_csr* A, const csrad_csr* B, const int32_t* rpC,
   const int m = A->nrows, p = B->ncols;
   const T* vA = static_cast<const T*>(A->vals);
   const T* vB = static_cast<const T*>(B->vals);
-  hipLaunchKernelGGL((k_num_hash<T, 8, 32>), dim3(persistent_grid(32, m)), dim3(kThreads), 0, s, 1,
-                     w.list, w.bin_off, A->rowptr, A->colind, vA, B->rowptr, B->colind, vB, rpC,
-                     ciC, vC);
-  hipLaunchKernelGGL((k_num_hash<T, 16, 128>), dim3(persistent_grid(16, m)), dim3(kThreads), 0, s,
-                     2, w.list, w.bin_off, A->rowptr, A->colind, vA, B->rowptr, B->colind, vB, rpC,
-                     ciC, vC);
+  hipLaunchKernelGGL((k_num_lanes<T, 16>), dim3(persistent_grid(kThreads / 16, m)),
+                     dim3(kThreads), 0, s, 1, w.list, w.bin_off, A->rowptr, A->colind, vA,
+                     B->rowptr, B->colind, vB, rpC, ciC, vC);
+  hipLaunchKernelGGL((k_num_lanes<T, 64>), dim3(persistent_grid(kThreads / 64, m)),
+                     dim3(kThreads), 0, s, 2, w.list, w.bin_off, A->rowptr, A->colind, vA,
+                     B->rowptr, B->colind, vB, rpC, ciC, vC);
   hipLaunchKernelGGL((k_num_hash<T, 64, 1024>), dim3(persistent_grid(4, m)), dim3(kThreads), 0, s,
                      3, w.list, w.bin_off, A->rowptr, A->colind, vA, B->rowptr, B->colind, vB, rpC,
                      ciC, vC);
@@ -552,10 +686,12 @@ extern "C" int csr_spgemm_symbolic(const csrad_csr* A, const csrad_csr* B, int32
   CSRAD_TRY(classify(A, B, w, s));
   if (m > 0) {
     CSRAD_TRY(fill_i32(w.counts, m, 0, s));
-    hipLaunchKernelGGL((k_sym_hash<8, 32>), dim3(persistent_grid(32, m)), dim3(kThreads), 0, s, 1,
-                       w.list, w.bin_off, A->rowptr, A->colind, B->rowptr, B->colind, w.counts);
-    hipLaunchKernelGGL((k_sym_hash<16, 128>), dim3(persistent_grid(16, m)), dim3(kThreads), 0, s, 2,
-                       w.list, w.bin_off, A->rowptr, A->colind, B->rowptr, B->colind, w.counts);
+    hipLaunchKernelGGL((k_sym_lanes<16>), dim3(persistent_grid(kThreads / 16, m)), dim3(kThreads),
+                       0, s, 1, w.list, w.bin_off, A->rowptr, A->colind, B->rowptr, B->colind,
+                       w.counts);
+    hipLaunchKernelGGL((k_sym_lanes<64>), dim3(persistent_grid(kThreads / 64, m)), dim3(kThreads),
+                       0, s, 2, w.list, w.bin_off, A->rowptr, A->colind, B->rowptr, B->colind,
+                       w.counts);
     hipLaunchKernelGGL((k_sym_hash<64, 1024>), dim3(persistent_grid(4, m)), dim3(kThreads), 0, s, 3,
                        w.list, w.bin_off, A->rowptr, A->colind, B->rowptr, B->colind, w.counts);
     hipLaunchKernelGGL((k_sym_hash<256, 8192>), dim3(persistent_grid(1, m)), dim3(kThreads), 0, s,

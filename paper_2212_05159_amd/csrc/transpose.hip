@@ -5,7 +5,7 @@
 // within a column is then arbitrary) -> per-column sort by source row.
 // Source rows are unique within a column, so the sorted order is unique
 // and the result is bit-exact and identical between runs.  Columns are
-// sorted by length class: <= 32 entries one thread (rank sort), <= 4096 one
+// sorted by length class: <= 32 entries by a few lanes (rank sort), <= 4096 one
 // workgroup (bitonic in LDS), longer ones in 4096-entry LDS-sorted chunks
 // merged by a grid-wide rank computation (binary search in every chunk).
 #include "internal.hpp"
@@ -48,8 +48,11 @@ __global__ __launch_bounds__(256) void k_scatter(int m, const int32_t* __restric
   }
 }
 
-// Short columns: one thread, rank sort (keys unique).  Longer columns are
+// Short columns (<= kShort entries): G lanes per column, rank sort (keys
+// unique).  Lane l ranks entries l, l+G, ... against the whole column; the
+// lanes of a group read the same addresses in step.  Longer columns are
 // appended to a list for the workgroup kernels.
+template <int G>
 __global__ __launch_bounds__(256) void k_sort_short(int n, const int32_t* __restrict__ rpT,
                                                     const int32_t* __restrict__ tkey,
                                                     const int32_t* __restrict__ tval,
@@ -57,18 +60,19 @@ __global__ __launch_bounds__(256) void k_sort_short(int n, const int32_t* __rest
                                                     int32_t* __restrict__ oval,
                                                     int32_t* __restrict__ long_list,
                                                     int32_t* __restrict__ long_count) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = blockIdx.x * (256 / G) + threadIdx.x / G;
+  const int l = threadIdx.x % G;
   if (c >= n) return;
   const int s = rpT[c], len = rpT[c + 1] - s;
   if (len <= kShort) {
-    for (int q = 0; q < len; ++q) {
+    for (int q = l; q < len; q += G) {
       const int key = tkey[s + q];
       int r = 0;
       for (int u = 0; u < len; ++u) r += tkey[s + u] < key;
       okey[s + r] = key;
       oval[s + r] = tval[s + q];
     }
-  } else {
+  } else if (l == 0) {
     long_list[atomicAdd(long_count, 1)] = c;
   }
 }
@@ -346,8 +350,27 @@ int transpose_pattern(int m, int n, int nnz, const int32_t* rowptr, const int32_
   if (m > 0)
     hipLaunchKernelGGL(k_scatter, dim3((m + 31) / 32), dim3(256), 0, s, m, rowptr, colind, w.cnt,
                        w.tkey, w.tval);
-  hipLaunchKernelGGL(k_sort_short, dim3(grid_for(n, 256, 1u << 30)), dim3(256), 0, s, n, rowptrT,
-                     w.tkey, w.tval, colindT, perm, w.long_list, w.long_count);
+  {
+    // lanes per column from the mean column length (at most kShort)
+    int g = 1;
+    while (g < kShort && (long long)g * n < nnz) g <<= 1;
+    const long long cpb = 256 / g;
+    const unsigned grid = (unsigned)((n + cpb - 1) / cpb);
+    switch (g) {
+      case 1: hipLaunchKernelGGL((k_sort_short<1>), dim3(grid), dim3(256), 0, s, n, rowptrT, w.tkey,
+                                 w.tval, colindT, perm, w.long_list, w.long_count); break;
+      case 2: hipLaunchKernelGGL((k_sort_short<2>), dim3(grid), dim3(256), 0, s, n, rowptrT, w.tkey,
+                                 w.tval, colindT, perm, w.long_list, w.long_count); break;
+      case 4: hipLaunchKernelGGL((k_sort_short<4>), dim3(grid), dim3(256), 0, s, n, rowptrT, w.tkey,
+                                 w.tval, colindT, perm, w.long_list, w.long_count); break;
+      case 8: hipLaunchKernelGGL((k_sort_short<8>), dim3(grid), dim3(256), 0, s, n, rowptrT, w.tkey,
+                                 w.tval, colindT, perm, w.long_list, w.long_count); break;
+      case 16: hipLaunchKernelGGL((k_sort_short<16>), dim3(grid), dim3(256), 0, s, n, rowptrT,
+                                  w.tkey, w.tval, colindT, perm, w.long_list, w.long_count); break;
+      default: hipLaunchKernelGGL((k_sort_short<32>), dim3(grid), dim3(256), 0, s, n, rowptrT,
+                                  w.tkey, w.tval, colindT, perm, w.long_list, w.long_count); break;
+    }
+  }
   hipLaunchKernelGGL(k_sort_medium, dim3(1024), dim3(kSortThreads), 0, s, rowptrT, w.tkey, w.tval,
                      colindT, perm, w.long_list, w.long_count);
   hipLaunchKernelGGL(k_sort_long_chunks, dim3(256), dim3(kSortThreads), 0, s, rowptrT, w.tkey,

@@ -37,7 +37,8 @@ __device__ __forceinline__ bool dep_side(int lower, int row, int col) {
   return lower ? col < row : col > row;
 }
 
-// Step 1: dependency counts, diagonal check and the level-0 frontier.
+// Step 1: dependency counts, diagonal check and the level-0 frontier
+// (appended a wave at a time).
 __global__ __launch_bounds__(kThreads) void k_tri_prep(int n, int lower,
                                                        const int32_t* __restrict__ rp,
                                                        const int32_t* __restrict__ ci,
@@ -46,17 +47,21 @@ __global__ __launch_bounds__(kThreads) void k_tri_prep(int n, int lower,
                                                        int32_t* __restrict__ front_n,
                                                        int32_t* __restrict__ bad_row) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+  const bool valid = i < n;
   int deps = 0;
-  bool diag = false;
-  for (int e = rp[i]; e < rp[i + 1]; ++e) {
-    const int j = ci[e];
-    deps += dep_side(lower, i, j);
-    diag |= (j == i);
+  if (valid) {
+    bool diag = false;
+    for (int e = rp[i]; e < rp[i + 1]; ++e) {
+      const int j = ci[e];
+      deps += dep_side(lower, i, j);
+      diag |= (j == i);
+    }
+    indeg[i] = deps;
+    if (!diag) atomicMin(bad_row, i);
   }
-  indeg[i] = deps;
-  if (!diag) atomicMin(bad_row, i);
-  if (deps == 0) front[atomicAdd(front_n, 1)] = i;
+  const bool ready = valid && deps == 0;
+  const int slot = wave_append(front_n, ready);
+  if (ready) front[slot] = i;
 }
 
 // Step 2: Kahn's algorithm, level by level.  Dependents of row j are the
@@ -67,15 +72,31 @@ __global__ __launch_bounds__(kThreads) void k_tri_prep(int n, int lower,
 // [2] level index, [3] which frontier buffer is current, [4] scratch count.
 constexpr int kKahnSmall = 8192;
 
-__device__ __forceinline__ void kahn_visit(int j, int level, int lower,
+// Places row j (when valid) on `level` and releases its dependents.  The
+// lanes of a wave walk their rows' dependents in step, so that rows made
+// ready in the same step are appended with one atomic per wave.  Every
+// lane of the wave must reach the call.
+__device__ __forceinline__ void kahn_visit(int j, bool valid, int level, int lower,
                                            const int32_t* __restrict__ rpT,
                                            const int32_t* __restrict__ ciT,
                                            int32_t* __restrict__ indeg, int32_t* __restrict__ nxt,
                                            int* next_n, int32_t* __restrict__ level_of_row) {
-  level_of_row[j] = level;
-  for (int t = rpT[j]; t < rpT[j + 1]; ++t) {
-    const int i = ciT[t];
-    if (dep_side(lower, i, j) && atomicSub(&indeg[i], 1) == 1) nxt[atomicAdd(next_n, 1)] = i;
+  int t0 = 0, len = 0;
+  if (valid) {
+    level_of_row[j] = level;
+    t0 = rpT[j];
+    len = rpT[j + 1] - t0;
+  }
+  const int steps = wave_max(len);
+  for (int u = 0; u < steps; ++u) {
+    bool ready = false;
+    int i = 0;
+    if (u < len) {
+      i = ciT[t0 + u];
+      ready = dep_side(lower, i, j) && atomicSub(&indeg[i], 1) == 1;
+    }
+    const int slot = wave_append(next_n, ready);
+    if (ready) nxt[slot] = i;
   }
 }
 
@@ -95,8 +116,12 @@ __global__ __launch_bounds__(kKahnThreads) void k_tri_kahn_small(
     int* nxt = which ? fa : fb;
     if (threadIdx.x == 0) next_n = 0;
     __syncthreads();
-    for (int q = threadIdx.x; q < cur_n; q += blockDim.x)
-      kahn_visit(cur[q], level, lower, rpT, ciT, indeg, nxt, &next_n, level_of_row);
+    for (int base = 0; base < cur_n; base += blockDim.x) {
+      const int q = base + threadIdx.x;
+      const bool valid = q < cur_n;
+      kahn_visit(valid ? cur[q] : 0, valid, level, lower, rpT, ciT, indeg, nxt, &next_n,
+                 level_of_row);
+    }
     __syncthreads();
     cur_n = next_n;
     which ^= 1;
@@ -119,7 +144,9 @@ __global__ __launch_bounds__(kThreads) void k_tri_kahn_level(
   int* cur = which ? fb : fa;
   int* nxt = which ? fa : fb;
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q < cur_n) kahn_visit(cur[q], level, lower, rpT, ciT, indeg, nxt, &state[4], level_of_row);
+  const bool valid = q < cur_n;
+  kahn_visit(valid ? cur[q] : 0, valid, level, lower, rpT, ciT, indeg, nxt, &state[4],
+             level_of_row);
 }
 
 __global__ void k_tri_kahn_advance(int32_t* __restrict__ state) {
@@ -295,14 +322,19 @@ int trisolve_bwd_t(const csrad_csr* Tm, int lower, const csrad_csr* Tt, const in
 
 // Float64-vector solves over T's value type, for preconditioners: with
 // transpose = false x = T^{-1} b over T's levels; with transpose = true
-// x = T^{-T} b over T^T (Tt, perm) with T's levels reversed.
+// x = T^{-T} b over T^T with T's levels reversed, reading T^T's own values
+// when Tt carries them and T's values through perm otherwise.
 template <typename TV>
 int trisolve_vec64_t(const csrad_csr* Tm, int lower, const csrad_csr* Tt, const int32_t* perm,
                      bool transpose, int nlevels, const int32_t* lp_host, const int32_t* lp_dev,
                      const int32_t* rows, const double* b, double* x, hipStream_t s) {
   const TV* v = static_cast<const TV*>(Tm->vals);
+  const TV* vt = static_cast<const TV*>(Tt ? Tt->vals : nullptr);
   CSRAD_G_SWITCH(lanes_for(Tm->nnz, Tm->nrows), {
-    if (transpose)
+    if (transpose && vt)
+      run_levels<TV, double, G, false, true>(nlevels, lp_host, lp_dev, rows, lower ? 0 : 1,
+                                             Tt->rowptr, Tt->colind, nullptr, vt, b, x, s);
+    else if (transpose)
       run_levels<TV, double, G, true, true>(nlevels, lp_host, lp_dev, rows, lower ? 0 : 1,
                                             Tt->rowptr, Tt->colind, perm, v, b, x, s);
     else

@@ -15,6 +15,7 @@ import numpy as np
 import torch
 
 from . import capi
+from . import sparse as sp
 
 _KIND = {"jacobi": 0, "factor": 1, "none": 2}
 
@@ -40,8 +41,10 @@ class PCG:
                 raise ValueError("factor preconditioner needs L")
             nl, lph, lp, lr, _ = L.pattern.levels(True)
             Lt, perm = L.pattern.transpose()
-            Ld, Ltd = L.pattern.desc(L.vals), Lt.desc(dtype=L.vals.dtype)
-            self.Lkeep = (L, Lt, Ld, Ltd, lph, lp, lr, perm)
+            # L^T's values once, so the adjoint solve reads them directly
+            Ltv = sp.transpose_vals(L.pattern, L.vals)
+            Ld, Ltd = L.pattern.desc(L.vals), Lt.desc(Ltv)
+            self.Lkeep = (L, Lt, Ltv, Ld, Ltd, lph, lp, lr, perm)
             self.pc = (1, None, Ld, Ltd, perm, nl, lph, lp, lr)
         else:
             self.pc = (2, None, None, None, None, 0, None, None, None)
@@ -64,20 +67,22 @@ class PCG:
                           self.ws)
         g = None
         if self.graph and not record:
-            if self._g is None:
-                # capture one step (recorded, not executed); every replay
-                # reads the same state buffers
-                self._g = torch.cuda.CUDAGraph()
-                with torch.cuda.graph(self._g):
-                    self._step(None)
-            g = self._g
+            if self._g is None or self._g[0] != chunk:
+                # capture `chunk` steps as one graph (recorded, not
+                # executed); every replay reads the same state buffers
+                cg = torch.cuda.CUDAGraph()
+                with torch.cuda.graph(cg):
+                    for _ in range(chunk):
+                        self._step(None)
+                self._g = (chunk, cg)
+            g = self._g[1]
         it = 0
         while it < maxit:
             n = min(chunk, maxit - it)
-            for _ in range(n):
-                if g is not None:
-                    g.replay()
-                else:
+            if g is not None and n == chunk:
+                g.replay()
+            else:
+                for _ in range(n):
                     self._step(hist)
             it += n
             st = self.scal.cpu().numpy()
