@@ -245,8 +245,16 @@ int csr_cg_finish_bwd(const csrad_csr *A, const void *b, const void *rb,
  * Steps after done change nothing, so the host may run steps in chunks
  * and read scal in between.  hist (hist_cap float64, may be NULL)
  * receives ||r||/||b|| per step.
+ * csr_pcg_workspace sizes the workspace shared by init and the steps; for
+ * the factor kind pass L and its levels (else NULL, 0, NULL).  init copies
+ * A into an ELL layout inside the workspace and, when every level of L
+ * has at least 1024 rows, L and L^T by level as well (values included:
+ * call init again after A's or L's values change); the steps read those
+ * copies.  A segment whose ELL copy would exceed twice the matrix's nnz is
+ * read from the CSR arrays instead.
  * ------------------------------------------------------------------- */
-int csr_pcg_workspace(const csrad_csr *A, size_t *bytes);
+int csr_pcg_workspace(const csrad_csr *A, const csrad_csr *L, int32_t nlevels,
+                      const int32_t *level_ptr_host, size_t *bytes);
 int csr_diag_inv(const csrad_csr *A, double *dinv, void *stream);
 int csr_pcg_init(const csrad_csr *A, int32_t kind, const double *dinv,
                  const csrad_csr *L, const csrad_csr *Lt, const int32_t *perm,

@@ -67,7 +67,8 @@ _SIGS = {
     "csr_cg_step": (C.c_int, [C.c_void_p] * 10 + [C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p]),
     "csr_cg_step_bwd": (C.c_int, [C.c_void_p] * 15 + [C.c_size_t, C.c_void_p]),
     "csr_cg_finish_bwd": (C.c_int, [C.c_void_p] * 7),
-    "csr_pcg_workspace": (C.c_int, [C.c_void_p, C.POINTER(C.c_size_t)]),
+    "csr_pcg_workspace": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p,
+                                    C.POINTER(C.c_size_t)]),
     "csr_diag_inv": (C.c_int, [C.c_void_p] * 3),
     "csr_pcg_init": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
                                C.c_void_p, C.c_int32] + [C.c_void_p] * 8
@@ -284,9 +285,11 @@ def csr_cg_finish_bwd(A, b, rb, pb, scal, gb):
                                                          _ptr(scal), _ptr(gb), _stream()))
 
 
-def csr_pcg_workspace(A):
+def csr_pcg_workspace(A, L=None, nlevels=0, level_ptr_host=None):
     n = C.c_size_t(0)
-    _check("csr_pcg_workspace", load().csr_pcg_workspace(C.byref(A), C.byref(n)))
+    _check("csr_pcg_workspace", load().csr_pcg_workspace(
+        C.byref(A), C.byref(L) if L is not None else None, int(nlevels),
+        level_ptr_host.ctypes.data if level_ptr_host is not None else None, C.byref(n)))
     return n.value
 
 

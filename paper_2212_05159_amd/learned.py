@@ -259,14 +259,50 @@ class Q1Family:
         return 10.0 ** rng.uniform(-4.0, 0.0), rng.uniform(0.0, np.pi)
 
 
-def train(model, N=256, steps=200, lr=1e-3, nit=4, gamma=0.6, seed=5, log_every=0, t_budget=None):
+def held_out(fam, count, seed):
+    """`count` systems of the family with their right-hand sides, drawn from
+    default_rng([seed, j]) (float32 values, float64 b)."""
+    out = []
+    for j in range(count):
+        rng = np.random.default_rng([seed, j])
+        eps, theta = Q1Family.sample(rng)
+        A, _ = fam.system(eps, theta)
+        out.append((A, torch.as_tensor(rng.standard_normal(fam.P.nrows), device=fam.device)))
+    return out
+
+
+def mean_iterations(model, fam, systems, tol=1e-6):
+    """Mean PCG iterations to tol with the network's factor."""
+    from . import pcg as pcgmod
+
+    its = []
+    with torch.no_grad():
+        for A, b in systems:
+            L = sp.CsrTensor(fam.Lpat, model(A, fam.Lpat))
+            _, info = pcgmod.pcg(A, b, "factor", L=L, tol=tol, fallback=False)
+            its.append(info["iters"] if info["converged"] else float("inf"))
+    return float(np.mean(its))
+
+
+def train(model, N=256, steps=200, lr=1e-3, nit=4, gamma=0.6, seed=5, log_every=0, t_budget=None,
+          val_systems=None, eval_every=50):
     """Adam on the residual-history loss over freshly drawn systems
-    (eps log-uniform in [1e-4, 1], theta uniform in [0, pi], b ~ N(0,1))."""
+    (eps log-uniform in [1e-4, 1], theta uniform in [0, pi], b ~ N(0,1)).
+
+    With val_systems (a list of (A, b) of the same grid), the parameters
+    are scored every eval_every steps (and before the first) by the mean
+    PCG iterations to 1e-6 on those systems, and the best-scoring ones are
+    kept (model selection on held-out systems; the untrained network is a
+    candidate).  Returns the loss history."""
     import time
 
     fam = Q1Family(N, model.W0.device)
     opt = torch.optim.Adam(model.parameters(), lr=lr)
     history = []
+    best = None
+    if val_systems is not None:
+        best = (mean_iterations(model, fam, val_systems),
+                {k: v.detach().clone() for k, v in model.state_dict().items()})
     t0 = time.time()
     for step in range(steps):
         rng = np.random.default_rng([seed, 0, step])
@@ -278,9 +314,17 @@ def train(model, N=256, steps=200, lr=1e-3, nit=4, gamma=0.6, seed=5, log_every=
         loss = pcg_residual_loss(A, fam.Lpat, Lv, b, nit, gamma)
         loss.backward()
         opt.step()
-        history.append(float(loss))
+        history.append(float(loss.detach()))
         if log_every and step % log_every == 0:
             print(f"[train] step {step} loss {history[-1]:.4f}", flush=True)
-        if t_budget is not None and time.time() - t0 > t_budget:
+        last = step + 1 == steps or (t_budget is not None and time.time() - t0 > t_budget)
+        if val_systems is not None and ((step + 1) % eval_every == 0 or last):
+            score = mean_iterations(model, fam, val_systems)
+            if score < best[0]:
+                best = (score, {k: v.detach().clone() for k, v in model.state_dict().items()})
+        if last:
             break
+    if best is not None:
+        model.load_state_dict(best[1])
+        model.selected_score = best[0]
     return history

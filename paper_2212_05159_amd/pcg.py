@@ -48,7 +48,11 @@ class PCG:
             self.pc = (1, None, Ld, Ltd, perm, nl, lph, lp, lr)
         else:
             self.pc = (2, None, None, None, None, 0, None, None, None)
-        self.ws = capi._ws(capi.csr_pcg_workspace(self.Ad), dev)
+        if self.kind == 1:
+            bytes_ = capi.csr_pcg_workspace(self.Ad, self.pc[2], self.pc[5], self.pc[6])
+        else:
+            bytes_ = capi.csr_pcg_workspace(self.Ad)
+        self.ws = capi._ws(bytes_, dev)
         f = lambda: torch.empty(self.n, dtype=torch.float64, device=dev)
         self.x, self.r, self.z, self.p, self.q = f(), f(), f(), f(), f()
         self.scal = torch.zeros(16, dtype=torch.float64, device=dev)

@@ -48,6 +48,26 @@ def test_pcg_fp64_matches_oracle(precond, name, mk):
     assert pcgmod.true_residual(A, x, b) < 2e-8
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+def test_pcg_arrow_matrix_reads_csr_rows(dtype):
+    # one dense row and column: A's ELL copy would need n slots per row, far
+    # beyond twice nnz(A), so the product reads A's CSR rows instead
+    n = 3000
+    r = np.concatenate([np.arange(n), np.zeros(n - 1, int), np.arange(1, n)])
+    c = np.concatenate([np.arange(n), np.arange(1, n), np.zeros(n - 1, int)])
+    v = np.concatenate([[float(n)], np.full(n - 1, 2.0), np.full(2 * (n - 1), -0.5)])
+    A = gen._from_coo(n, n, r, c, v)
+    b = gen.normal(n, 8)
+    Ad = sp.CsrTensor.from_host(A, dtype=dtype)
+    x, info = pcgmod.pcg(Ad, to_dev(b), precond="jacobi", tol=1e-8, record=True)
+    Ao = upcast(A, dtype)
+    xo, ito, ho = oracle.pcg(Ao, b, "jacobi", tol=1e-8)
+    assert info["converged"] and abs(info["iters"] - ito) <= 1
+    m = min(info["iters"], ito)
+    np.testing.assert_allclose(info["hist"][:m], ho[1:m + 1], rtol=1e-6, atol=1e-9)
+    assert pcgmod.true_residual(Ao, x, b) < 2e-8
+
+
 def test_pcg_exact_factor_converges_in_one_step():
     A = gen.poisson1d(500)
     Lp = gen.tril(A)
@@ -91,6 +111,69 @@ def test_pcg_factor_matches_oracle_factor():
     np.testing.assert_allclose(info["hist"][:m], ho[1:m + 1], rtol=1e-6, atol=1e-9)
     _, itj, _ = oracle.pcg(A, b, "jacobi", tol=1e-8)
     assert ito < itj  # the factor helps
+
+
+def _sgs_factor(A):
+    T = gen.tril(A)
+    rows = T.row_of_entry()
+    d = np.zeros(A.nrows)
+    d[rows[T.colind == rows]] = T.vals[T.colind == rows]
+    return gen.Csr(A.nrows, A.ncols, T.rowptr, T.colind, T.vals / np.sqrt(d[T.colind]))
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+@pytest.mark.parametrize("graph", [False, True])
+def test_pcg_level_ordered_factor_matches_oracle(dtype, graph):
+    # four-coloured Q1 on 96^2: 4 levels of 2304 rows, so the steps solve
+    # over the level-ordered copies of L and L^T
+    N = 96
+    A = gen.permute_sym(gen.anisotropic_q1(N, 3e-3, 0.7), gen.four_color_2d(N))
+    L = _sgs_factor(A)
+    Ad = sp.CsrTensor.from_host(A, dtype=dtype)
+    Ld = sp.CsrTensor.from_host(L, dtype=dtype)
+    nl, lph, _, _, _ = Ld.pattern.levels(True)
+    assert nl == 4 and np.diff(lph).min() >= 1024
+    Lh = Ld.pattern.desc(Ld.vals)
+    from paper_2212_05159_amd import capi
+    assert capi.csr_pcg_workspace(Ad.pattern.desc(Ad.vals), Lh, nl, lph) > \
+        capi.csr_pcg_workspace(Ad.pattern.desc(Ad.vals))
+    b = gen.normal(A.nrows, 7)
+    Ao, Lo = upcast(A, dtype), upcast(L, dtype)
+    x, info = pcgmod.pcg(Ad, to_dev(b), precond="factor", L=Ld, tol=1e-8, graph=graph,
+                         record=not graph)
+    xo, ito, ho = oracle.pcg(Ao, b, "factor", L=Lo, tol=1e-8)
+    assert info["converged"] and abs(info["iters"] - ito) <= 1
+    if not graph:
+        m = min(info["iters"], ito)
+        np.testing.assert_allclose(info["hist"][:m], ho[1:m + 1], rtol=1e-6, atol=1e-9)
+    assert rel_err(x, xo) < 1e-6
+    assert pcgmod.true_residual(Ao, x, b) < 2e-8
+
+
+def test_pcg_ell_factor_interleaved_levels():
+    # L with even rows on level 0 and odd rows on level 1 (levels interleave
+    # in the row order, each with 2048 rows): the solves go through the
+    # level-row lists
+    A = gen.poisson2d(64, 64)
+    n = A.nrows
+    r, c, v = list(range(n)), list(range(n)), [2.0] * n
+    for i in range(1, n, 2):
+        for d, w in ((1, -0.5), (3, -0.25)):
+            if i - d >= 0:
+                r.append(i), c.append(i - d), v.append(w)
+    L = gen._from_coo(n, n, np.array(r), np.array(c), np.array(v))
+    Ad = sp.CsrTensor.from_host(A, dtype=torch.float64)
+    Ld = sp.CsrTensor.from_host(L, dtype=torch.float64)
+    nl, lph, _, lr, _ = Ld.pattern.levels(True)
+    assert nl == 2 and np.diff(lph).min() >= 1024
+    assert not np.array_equal(lr.cpu().numpy(), np.arange(n))
+    b = gen.normal(n, 9)
+    x, info = pcgmod.pcg(Ad, to_dev(b), precond="factor", L=Ld, tol=1e-8, record=True)
+    xo, ito, ho = oracle.pcg(A, b, "factor", L=L, tol=1e-8)
+    assert info["converged"] and abs(info["iters"] - ito) <= 1
+    m = min(info["iters"], ito)
+    np.testing.assert_allclose(info["hist"][:m], ho[1:m + 1], rtol=1e-6, atol=1e-9)
+    assert pcgmod.true_residual(A, x, b) < 2e-8
 
 
 def test_pcg_breakdown_falls_back_to_jacobi():
