@@ -53,6 +53,33 @@ def log(msg):
 
 
 # ----------------------------------------------------------------------
+# Measured HBM traffic of the dominant kernel (committed counter summary)
+# ----------------------------------------------------------------------
+COUNTERS = os.path.join(ROOT, "profiles", "spmm_poisson128_counters.md")
+SPMM_SRC = os.path.join(ROOT, "paper_2212_05159_amd", "csrc", "spmm.hip")
+
+
+def measured_traffic(kernel, plan):
+    """Bytes per launch of `kernel` under traversal `plan` from the counter
+    summary, or None when the summary is missing, lists no such plan, or
+    was taken on a different version of the kernel source."""
+    import hashlib
+
+    try:
+        text = open(COUNTERS).read().splitlines()
+        src = hashlib.sha256(open(SPMM_SRC, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    if f"spmm_source_sha256: {src}" not in text:
+        return None
+    key = f"traffic {kernel} {'natural' if plan is None else '(%d, %d)' % tuple(plan)}:"
+    for line in text:
+        if line.startswith(key):
+            return int(float(line.split(":")[1]))
+    return None
+
+
+# ----------------------------------------------------------------------
 # PCG time to 1e-6: learned factor vs Jacobi
 # ----------------------------------------------------------------------
 def pcg_section(n_eval, n_train, train_steps, systems):
@@ -429,10 +456,13 @@ def main():
     dom = "spmm bwd"
     dom_ms = op_ms[dom]
     achieved = bm[dom] / (dom_ms * 1e-3) / 1e9
+    bwd_plan = tuned["spmm_bwd"][0]
     roofline = {"bound": "hbm", "kernel": "k_spmm_bwd_coop (fused A^T G and G B^T on pat(A))",
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "bytes_per_launch": bm[dom], "avg_ms": round(dom_ms, 4)}
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": measured_traffic("k_spmm_bwd_coop", bwd_plan),
+                "bytes_per_launch": bm[dom], "avg_ms": round(dom_ms, 4),
+                "plan": "natural" if bwd_plan is None else list(bwd_plan)}
 
     cpu = None
     if not args.no_cpu_baseline:

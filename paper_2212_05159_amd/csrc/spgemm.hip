@@ -3,8 +3,8 @@
 //
 // Rows of C are binned by the product count U_i = sum over A's row of the
 // lengths of the B rows it selects, an upper bound on nnz(C_i):
-//   U <= 16, 64            : 16 / 64 lanes per row, one product per lane,
-//                            sorted across the lanes in registers;
+//   U <= 8, 16, 32, 64     : 8 / 16 / 32 / 64 lanes per row, one product
+//                            per lane, sorted across the lanes in registers;
 //   U <= 512, 4096         : LDS hash table of H = 2U slots per row,
 //                            64 / 256 lanes per row;
 //   U > 4096               : a dense per-workgroup marker array in the
@@ -27,77 +27,37 @@ namespace csrad {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kNumBins = 6;  // 0: empty, 1..4: LDS hash, 5: dense marker
+// 0: empty, 1..4: lanes (U <= 8, 16, 32, 64), 5..6: LDS hash, 7: dense marker
+constexpr int kNumBins = 8;
+constexpr int kDenseBin = 7;
 constexpr int kBigU = 4096;
 constexpr size_t kMarkerBudget = size_t(16) << 20;
 
 __host__ __device__ inline int bin_of(long long u) {
   if (u == 0) return 0;
-  if (u <= 16) return 1;
-  if (u <= 64) return 2;
-  if (u <= 512) return 3;
-  if (u <= kBigU) return 4;
-  return 5;
+  if (u <= 8) return 1;
+  if (u <= 16) return 2;
+  if (u <= 32) return 3;
+  if (u <= 64) return 4;
+  if (u <= 512) return 5;
+  if (u <= kBigU) return 6;
+  return kDenseBin;
 }
 
-// Per row: U_i and its bin (count pass) ...
-__global__ __launch_bounds__(kThreads) void k_bin_count(int m, const int32_t* __restrict__ rpA,
-                                                        const int32_t* __restrict__ ciA,
-                                                        const int32_t* __restrict__ rpB,
-                                                        int8_t* __restrict__ binid,
-                                                        int32_t* __restrict__ bin_cnt) {
-  __shared__ int local[kNumBins];
-  if (threadIdx.x < kNumBins) local[threadIdx.x] = 0;
-  __syncthreads();
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < m) {
+// Per row: U_i and its bin.  The rows are then grouped by bin with the
+// stable multi-split (ascending row order within a bin, no atomics).
+__global__ __launch_bounds__(kThreads) void k_bin_of(int m, const int32_t* __restrict__ rpA,
+                                                     const int32_t* __restrict__ ciA,
+                                                     const int32_t* __restrict__ rpB,
+                                                     int32_t* __restrict__ binid) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x) {
     long long u = 0;
     for (int a = rpA[i]; a < rpA[i + 1]; ++a) {
       const int k = ciA[a];
       u += rpB[k + 1] - rpB[k];
     }
-    const int b = bin_of(u);
-    binid[i] = (int8_t)b;
-    atomicAdd(&local[b], 1);
+    binid[i] = bin_of(u);
   }
-  __syncthreads();
-  if (threadIdx.x < kNumBins && local[threadIdx.x]) atomicAdd(&bin_cnt[threadIdx.x], local[threadIdx.x]);
-}
-
-// ... offsets (one thread) ...
-__global__ void k_bin_offsets(const int32_t* __restrict__ bin_cnt, int32_t* __restrict__ bin_off,
-                              int32_t* __restrict__ cursor) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    int run = 0;
-    for (int b = 0; b < kNumBins; ++b) {
-      bin_off[b] = run;
-      cursor[b] = run;
-      run += bin_cnt[b];
-    }
-    bin_off[kNumBins] = run;
-  }
-}
-
-// ... and the row lists (order within a bin is irrelevant).  Each block
-// counts its rows per bin in LDS and reserves one range per bin.
-__global__ __launch_bounds__(kThreads) void k_bin_fill(int m, const int8_t* __restrict__ binid,
-                                                       int32_t* __restrict__ cursor,
-                                                       int32_t* __restrict__ list) {
-  __shared__ int cnt[kNumBins];
-  __shared__ int base[kNumBins];
-  if (threadIdx.x < kNumBins) cnt[threadIdx.x] = 0;
-  __syncthreads();
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  int b = 0, r = 0;
-  if (i < m) {
-    b = binid[i];
-    r = atomicAdd(&cnt[b], 1);
-  }
-  __syncthreads();
-  if (threadIdx.x < kNumBins && cnt[threadIdx.x])
-    base[threadIdx.x] = atomicAdd(&cursor[threadIdx.x], cnt[threadIdx.x]);
-  __syncthreads();
-  if (i < m) list[base[b] + r] = i;
 }
 
 __device__ __forceinline__ unsigned hash_slot(int j, int H) {
@@ -262,20 +222,23 @@ __global__ __launch_bounds__(kThreads) void k_num_hash(
 // the row (symbolic), give each entry its rank, and sum their run's
 // products in lane order, i.e. k ascending (numeric).
 // ---------------------------------------------------------------------
-__device__ __forceinline__ unsigned long long shfl_xor_u64(unsigned long long v, int m) {
+__device__ __forceinline__ unsigned long long shfl_xor_key(unsigned long long v, int m) {
   const unsigned lo = (unsigned)__shfl_xor((int)(unsigned)v, m);
   const unsigned hi = (unsigned)__shfl_xor((int)(unsigned)(v >> 32), m);
   return ((unsigned long long)hi << 32) | lo;
 }
+__device__ __forceinline__ unsigned shfl_xor_key(unsigned v, int m) {
+  return (unsigned)__shfl_xor((int)v, m);
+}
 
 // Ascending sort of one key per lane over aligned groups of G lanes.
-template <int G>
-__device__ __forceinline__ unsigned long long group_sort(unsigned long long key, int l) {
+template <int G, typename K>
+__device__ __forceinline__ K group_sort(K key, int l) {
 #pragma unroll
   for (int k = 2; k <= G; k <<= 1) {
 #pragma unroll
     for (int j = k >> 1; j > 0; j >>= 1) {
-      const unsigned long long other = shfl_xor_u64(key, j);
+      const K other = shfl_xor_key(key, j);
       const bool keep_min = ((l & j) == 0) == ((l & k) == 0);
       key = keep_min ? (other < key ? other : key) : (other > key ? other : key);
     }
@@ -283,36 +246,99 @@ __device__ __forceinline__ unsigned long long group_sort(unsigned long long key,
   return key;
 }
 
-// The l-th product of row i: its column, and its A and B entry positions
-// (col = INT32_MAX when the row has at most l products).
-__device__ __forceinline__ void lane_product(int i, int l, const int32_t* __restrict__ rpA,
+// The l-th product of row i, found by the G lanes of the row together: A's
+// row is taken G entries at a time, each lane loads one entry and the
+// length of the B row it selects, a scan over the group gives every
+// entry's first product, and each lane finds the entry holding its product
+// by binary search over the scan.  col = INT32_MAX when the row has at most
+// l products.  Every lane of the wave must reach the call.
+template <int G>
+__device__ __forceinline__ void lane_product(int i, bool valid, int l,
+                                             const int32_t* __restrict__ rpA,
                                              const int32_t* __restrict__ ciA,
                                              const int32_t* __restrict__ rpB,
                                              const int32_t* __restrict__ ciB, int& col, int& ea,
                                              int& eb) {
   col = INT32_MAX;
   ea = eb = -1;
-  int base = 0;
-  const int a1 = rpA[i + 1];
-  for (int a = rpA[i]; a < a1 && base <= l; ++a) {
-    const int k = ciA[a];
-    const int b0 = rpB[k], len = rpB[k + 1] - b0;
-    if (l < base + len) {
-      ea = a;
-      eb = b0 + (l - base);
+  const int gbase = __lane_id() & ~(G - 1);
+  int a0 = 0, a1 = 0;
+  if (valid) {
+    a0 = rpA[i];
+    a1 = rpA[i + 1];
+  }
+  const int chunks = wave_max((a1 - a0 + G - 1) / G);
+  int before = 0;  // products of the row's earlier chunks
+  for (int c = 0; c < chunks; ++c) {
+    const int a = a0 + c * G + l;
+    int b0 = 0, len = 0;
+    if (a < a1) {
+      const int k = ciA[a];
+      b0 = rpB[k];
+      len = rpB[k + 1] - b0;
+    }
+    int inc = len;
+#pragma unroll
+    for (int o = 1; o < G; o <<= 1) {
+      const int t = __shfl_up(inc, o, G);
+      if (l >= o) inc += t;
+    }
+    const int total = __shfl(inc, gbase + G - 1);
+    const int pidx = l - before;  // this lane's product within the chunk
+    // first t with inc[t] > pidx (lanes without a product search too)
+    int lo = 0, hi = G - 1;
+#pragma unroll
+    for (int st = G; st > 1; st >>= 1) {
+      const int mid = (lo + hi) >> 1;
+      const int v = __shfl(inc, gbase + mid);
+      if (v > pidx) hi = mid;
+      else lo = mid + 1;
+    }
+    const int t = lo;
+    const int st_b0 = __shfl(b0, gbase + t);
+    const int st_ex = __shfl(inc - len, gbase + t);
+    if (pidx >= 0 && pidx < total) {
+      ea = a0 + c * G + t;
+      eb = st_b0 + (pidx - st_ex);
       col = ciB[eb];
     }
-    base += len;
+    before += total;
   }
 }
 
-// Mask of the lanes of this lane's group, and of the group's lanes below it.
+// Mask of the lanes of this lane's group.
 template <int G>
 __device__ __forceinline__ unsigned long long group_mask(int lane) {
   return G == 64 ? ~0ull : (((1ull << G) - 1ull) << (lane & ~(G - 1)));
 }
 
+// Sort key of (column, product index): 32 bits when the column fits in
+// 32 - log2(G) bits, else 64.
 template <int G>
+constexpr int log2_of() {
+  return G == 8 ? 3 : G == 16 ? 4 : G == 32 ? 5 : 6;
+}
+
+template <int G, typename K>
+__device__ __forceinline__ K make_key(int col, int l) {
+  constexpr int LG = log2_of<G>();
+  if (sizeof(K) == 4)
+    return col == INT32_MAX ? (K)0xffffffffu : (K)(((unsigned)col << LG) | (unsigned)l);
+  return (K)(((unsigned long long)(unsigned)col << 32) | (unsigned)l);
+}
+template <int G, typename K>
+__device__ __forceinline__ int key_col(K key) {
+  constexpr int LG = log2_of<G>();
+  if (sizeof(K) == 4) return key == (K)0xffffffffu ? INT32_MAX : (int)((unsigned)key >> LG);
+  return (int)((unsigned long long)key >> 32);
+}
+template <int G, typename K>
+__device__ __forceinline__ int key_idx(K key) {
+  if (sizeof(K) == 4) return (int)((unsigned)key & (G - 1));
+  return (int)((unsigned long long)key & 0xffffffffull);
+}
+
+template <int G, typename K>
 __global__ __launch_bounds__(kThreads) void k_sym_lanes(int bin, const int32_t* __restrict__ list,
                                                         const int32_t* __restrict__ bin_off,
                                                         const int32_t* __restrict__ rpA,
@@ -328,11 +354,10 @@ __global__ __launch_bounds__(kThreads) void k_sym_lanes(int bin, const int32_t* 
     const int idx = base + threadIdx.x / G;
     const bool valid = idx < nrows;
     const int i = valid ? list[first + idx] : 0;
-    int col = INT32_MAX, ea, eb;
-    if (valid) lane_product(i, l, rpA, ciA, rpB, ciB, col, ea, eb);
-    const unsigned long long key =
-        group_sort<G>(((unsigned long long)(unsigned)col << 32) | (unsigned)l, l);
-    const int sc = (int)(key >> 32);
+    int col, ea, eb;
+    lane_product<G>(i, valid, l, rpA, ciA, rpB, ciB, col, ea, eb);
+    const K key = group_sort<G, K>(make_key<G, K>(col, l), l);
+    const int sc = key_col<G, K>(key);
     const int prev = __shfl(sc, lane > 0 ? lane - 1 : 0);
     const bool head = sc != INT32_MAX && (l == 0 || prev != sc);
     const int cnt = __popcll(__ballot(head) & gm);
@@ -340,7 +365,7 @@ __global__ __launch_bounds__(kThreads) void k_sym_lanes(int bin, const int32_t* 
   }
 }
 
-template <typename T, int G>
+template <typename T, int G, typename K>
 __global__ __launch_bounds__(kThreads) void k_num_lanes(
     int bin, const int32_t* __restrict__ list, const int32_t* __restrict__ bin_off,
     const int32_t* __restrict__ rpA, const int32_t* __restrict__ ciA, const T* __restrict__ vA,
@@ -352,28 +377,34 @@ __global__ __launch_bounds__(kThreads) void k_num_lanes(
   const int gbase = lane & ~(G - 1);
   const unsigned long long gm = group_mask<G>(lane);
   const unsigned long long below = gm & ((1ull << lane) - 1ull);
+  const unsigned long long above = gm & ~((2ull << lane) - 1ull);
   for (int base = blockIdx.x * RPB; base < nrows; base += gridDim.x * RPB) {
     const int idx = base + threadIdx.x / G;
     const bool valid = idx < nrows;
     const int i = valid ? list[first + idx] : 0;
-    int col = INT32_MAX, ea = -1, eb = -1;
-    if (valid) lane_product(i, l, rpA, ciA, rpB, ciB, col, ea, eb);
+    int col, ea, eb;
+    lane_product<G>(i, valid, l, rpA, ciA, rpB, ciB, col, ea, eb);
     const T prod = ea >= 0 ? vA[ea] * vB[eb] : T(0);
-    const unsigned long long key =
-        group_sort<G>(((unsigned long long)(unsigned)col << 32) | (unsigned)l, l);
-    const int sc = (int)(key >> 32);
-    const int src = (int)(key & 0xffffffffull);  // product index of this sorted slot
-    const T v = __shfl(prod, gbase + src);
+    const K key = group_sort<G, K>(make_key<G, K>(col, l), l);
+    const int sc = key_col<G, K>(key);
+    const T v = __shfl(prod, gbase + key_idx<G, K>(key));
     const int prev = __shfl(sc, lane > 0 ? lane - 1 : 0);
     const bool head = sc != INT32_MAX && (l == 0 || prev != sc);
     const unsigned long long heads = __ballot(head);
+    const unsigned long long used = __ballot(sc != INT32_MAX) & gm;
+    // run length of a head: up to the next head, else to the last product
+    int run = 0;
+    if (head) {
+      const unsigned long long nxt = heads & above;
+      const int end = nxt ? __ffsll((long long)nxt) - 1 : gbase + __popcll(used);
+      run = end - lane;
+    }
+    const int steps = wave_max(run);
     // run sums in lane order (k ascending)
     T acc = v;
-#pragma unroll
-    for (int d = 1; d < G; ++d) {
-      const int c = __shfl(sc, lane + d < 64 ? lane + d : lane);
+    for (int d = 1; d < steps; ++d) {
       const T w = __shfl(v, lane + d < 64 ? lane + d : lane);
-      if (l + d < G && c == sc) acc += w;
+      if (d < run) acc += w;
     }
     if (valid && head) {
       const int pos = rpC[i] + __popcll(heads & below);
@@ -401,7 +432,7 @@ __global__ __launch_bounds__(kThreads) void k_sym_dense(int p, const int32_t* __
                                                         int32_t* __restrict__ counts,
                                                         int32_t* __restrict__ markers) {
   __shared__ int cnt;
-  const int first = bin_off[5], nrows = bin_off[6] - first;
+  const int first = bin_off[kDenseBin], nrows = bin_off[kDenseBin + 1] - first;
   if ((int)blockIdx.x >= nrows) return;
   int* marker = markers + (size_t)blockIdx.x * p;
   block_init_marker(marker, p);
@@ -427,7 +458,7 @@ __global__ __launch_bounds__(kThreads) void k_num_dense(
     const int32_t* __restrict__ rpC, int32_t* __restrict__ ciC, T* __restrict__ vC,
     int32_t* __restrict__ markers) {
   __shared__ int wsum[kThreads / kWave];
-  const int first = bin_off[5], nrows = bin_off[6] - first;
+  const int first = bin_off[kDenseBin], nrows = bin_off[kDenseBin + 1] - first;
   if ((int)blockIdx.x >= nrows) return;
   int* marker = markers + (size_t)blockIdx.x * p;
   block_init_marker(marker, p);
@@ -499,8 +530,10 @@ __global__ __launch_bounds__(kThreads) void k_bwd_a(int m, const int32_t* __rest
   }
 }
 
-// gB: G lanes per row k of B, lanes over B's entries; column k of A from
-// A^T (rows ascending), values through permA.
+// gB: G lanes per row k of B; the entries of the row in turn, the lanes
+// splitting column k of A (A^T's row k, rows ascending, values through
+// permA) and summing with a group reduction.  The entry loop runs the
+// same number of times across the wave (the reduction needs whole groups).
 template <typename T, int G>
 __global__ __launch_bounds__(kThreads) void k_bwd_b(
     int n, const int32_t* __restrict__ rpB, const int32_t* __restrict__ ciB,
@@ -510,18 +543,28 @@ __global__ __launch_bounds__(kThreads) void k_bwd_b(
   const int b = xcd_block(blockIdx.x, gridDim.x);
   const int k = b * (kThreads / G) + threadIdx.x / G;
   const int l = threadIdx.x % G;
-  if (k >= n) return;
-  const int t0 = rpAT[k], t1 = rpAT[k + 1];
-  const int q1 = rpB[k + 1];
-  for (int q = rpB[k] + l; q < q1; q += G) {
-    const int j = ciB[q];
+  const bool valid = k < n;
+  int t0 = 0, t1 = 0, q0 = 0, q1 = 0;
+  if (valid) {
+    t0 = rpAT[k];
+    t1 = rpAT[k + 1];
+    q0 = rpB[k];
+    q1 = rpB[k + 1];
+  }
+  const int steps = wave_max(q1 - q0);
+  for (int u = 0; u < steps; ++u) {
+    const int q = q0 + u;
     T s = 0;
-    for (int t = t0; t < t1; ++t) {
-      const int i = ciAT[t];
-      const int p = find_sorted(ciC, rpC[i], rpC[i + 1], j);
-      if (p >= 0) s += vA[permA[t]] * gC[p];
+    if (q < q1) {
+      const int j = ciB[q];
+      for (int t = t0 + l; t < t1; t += G) {
+        const int i = ciAT[t];
+        const int p = find_sorted(ciC, rpC[i], rpC[i + 1], j);
+        if (p >= 0) s += vA[permA[t]] * gC[p];
+      }
     }
-    gB[q] = s;
+    s = group_sum<G>(s);
+    if (q < q1 && l == 0) gB[q] = s;
   }
 }
 
@@ -529,15 +572,15 @@ __global__ __launch_bounds__(kThreads) void k_bwd_b(
 // Host side.
 // ---------------------------------------------------------------------
 struct SpgemmWs {
-  int8_t* binid;
-  int32_t* bin_cnt;
+  int32_t* binid;
   int32_t* bin_off;
-  int32_t* cursor;
   int32_t* list;
   int32_t* counts;
   void* scan_ws;
   size_t scan_bytes;
   long long* total;
+  void* group_ws;
+  size_t group_bytes;
   int32_t* markers;
   int nmark;
 };
@@ -552,15 +595,15 @@ int marker_slots(int p) {
 
 SpgemmWs carve_spgemm(Carver& cv, int m, int p) {
   SpgemmWs w;
-  w.binid = cv.take<int8_t>((size_t)m);
-  w.bin_cnt = cv.take<int32_t>(kNumBins);
+  w.binid = cv.take<int32_t>((size_t)m);
   w.bin_off = cv.take<int32_t>(kNumBins + 1);
-  w.cursor = cv.take<int32_t>(kNumBins);
   w.list = cv.take<int32_t>((size_t)m);
   w.counts = cv.take<int32_t>((size_t)m);
   w.scan_bytes = scan_workspace(m);
   w.scan_ws = cv.take<char>(w.scan_bytes);
   w.total = cv.take<long long>(1);
+  w.group_bytes = group_small_workspace(m > 0 ? m : 1, kNumBins);
+  w.group_ws = cv.take<char>(w.group_bytes);
   w.nmark = marker_slots(p);
   w.markers = cv.take<int32_t>((size_t)w.nmark * (size_t)(p > 0 ? p : 1));
   return w;
@@ -575,15 +618,12 @@ unsigned persistent_grid(int rows_per_block, int m) {
 
 int classify(const csrad_csr* A, const csrad_csr* B, const SpgemmWs& w, hipStream_t s) {
   const int m = A->nrows;
-  CSRAD_TRY(fill_i32(w.bin_cnt, kNumBins, 0, s));
-  const unsigned g = (unsigned)((m + kThreads - 1) / kThreads);
-  if (m > 0)
-    hipLaunchKernelGGL(k_bin_count, dim3(g), dim3(kThreads), 0, s, m, A->rowptr, A->colind,
-                       B->rowptr, w.binid, w.bin_cnt);
-  hipLaunchKernelGGL(k_bin_offsets, dim3(1), dim3(64), 0, s, w.bin_cnt, w.bin_off, w.cursor);
-  if (m > 0)
-    hipLaunchKernelGGL(k_bin_fill, dim3(g), dim3(kThreads), 0, s, m, w.binid, w.cursor, w.list);
-  return launch_status();
+  if (m == 0) return fill_i32(w.bin_off, kNumBins + 1, 0, s);
+  unsigned g = (unsigned)((m + kThreads - 1) / kThreads);
+  if (g > 8192) g = 8192;
+  hipLaunchKernelGGL(k_bin_of, dim3(g), dim3(kThreads), 0, s, m, A->rowptr, A->colind, B->rowptr,
+                     w.binid);
+  return group_small_keys(w.binid, m, kNumBins, w.bin_off, w.list, w.group_ws, w.group_bytes, s);
 }
 
 int check_pair(const csrad_csr* A, const csrad_csr* B, bool vals) {
@@ -594,23 +634,54 @@ int check_pair(const csrad_csr* A, const csrad_csr* B, bool vals) {
   return CSRAD_OK;
 }
 
+// Launches of the lane bins; 32-bit sort keys while (column, product
+// index) fits in 32 bits.
+template <int G>
+bool keys32(int ncols) {
+  return (long long)ncols < (1ll << (32 - log2_of<G>())) - 1;
+}
+
+template <int G>
+void sym_lanes(int bin, const csrad_csr* A, const csrad_csr* B, const SpgemmWs& w,
+               hipStream_t s) {
+  const unsigned g = persistent_grid(kThreads / G, A->nrows);
+  if (keys32<G>(B->ncols))
+    hipLaunchKernelGGL((k_sym_lanes<G, unsigned>), dim3(g), dim3(kThreads), 0, s, bin, w.list,
+                       w.bin_off, A->rowptr, A->colind, B->rowptr, B->colind, w.counts);
+  else
+    hipLaunchKernelGGL((k_sym_lanes<G, unsigned long long>), dim3(g), dim3(kThreads), 0, s, bin,
+                       w.list, w.bin_off, A->rowptr, A->colind, B->rowptr, B->colind, w.counts);
+}
+
+template <typename T, int G>
+void num_lanes(int bin, const csrad_csr* A, const csrad_csr* B, const T* vA, const T* vB,
+               const int32_t* rpC, int32_t* ciC, T* vC, const SpgemmWs& w, hipStream_t s) {
+  const unsigned g = persistent_grid(kThreads / G, A->nrows);
+  if (keys32<G>(B->ncols))
+    hipLaunchKernelGGL((k_num_lanes<T, G, unsigned>), dim3(g), dim3(kThreads), 0, s, bin, w.list,
+                       w.bin_off, A->rowptr, A->colind, vA, B->rowptr, B->colind, vB, rpC, ciC,
+                       vC);
+  else
+    hipLaunchKernelGGL((k_num_lanes<T, G, unsigned long long>), dim3(g), dim3(kThreads), 0, s,
+                       bin, w.list, w.bin_off, A->rowptr, A->colind, vA, B->rowptr, B->colind, vB,
+                       rpC, ciC, vC);
+}
+
 template <typename T>
 int spgemm_numeric_t(const csrad_csr* A, const csrad_csr* B, const int32_t* rpC, int32_t* ciC,
                      T* vC, const SpgemmWs& w, hipStream_t s) {
   const int m = A->nrows, p = B->ncols;
   const T* vA = static_cast<const T*>(A->vals);
   const T* vB = static_cast<const T*>(B->vals);
-  hipLaunchKernelGGL((k_num_lanes<T, 16>), dim3(persistent_grid(kThreads / 16, m)),
-                     dim3(kThreads), 0, s, 1, w.list, w.bin_off, A->rowptr, A->colind, vA,
-                     B->rowptr, B->colind, vB, rpC, ciC, vC);
-  hipLaunchKernelGGL((k_num_lanes<T, 64>), dim3(persistent_grid(kThreads / 64, m)),
-                     dim3(kThreads), 0, s, 2, w.list, w.bin_off, A->rowptr, A->colind, vA,
-                     B->rowptr, B->colind, vB, rpC, ciC, vC);
+  num_lanes<T, 8>(1, A, B, vA, vB, rpC, ciC, vC, w, s);
+  num_lanes<T, 16>(2, A, B, vA, vB, rpC, ciC, vC, w, s);
+  num_lanes<T, 32>(3, A, B, vA, vB, rpC, ciC, vC, w, s);
+  num_lanes<T, 64>(4, A, B, vA, vB, rpC, ciC, vC, w, s);
   hipLaunchKernelGGL((k_num_hash<T, 64, 1024>), dim3(persistent_grid(4, m)), dim3(kThreads), 0, s,
-                     3, w.list, w.bin_off, A->rowptr, A->colind, vA, B->rowptr, B->colind, vB, rpC,
+                     5, w.list, w.bin_off, A->rowptr, A->colind, vA, B->rowptr, B->colind, vB, rpC,
                      ciC, vC);
   hipLaunchKernelGGL((k_num_hash<T, 256, 8192>), dim3(persistent_grid(1, m)), dim3(kThreads), 0, s,
-                     4, w.list, w.bin_off, A->rowptr, A->colind, vA, B->rowptr, B->colind, vB, rpC,
+                     6, w.list, w.bin_off, A->rowptr, A->colind, vA, B->rowptr, B->colind, vB, rpC,
                      ciC, vC);
   hipLaunchKernelGGL((k_num_dense<T>), dim3(w.nmark), dim3(kThreads), 0, s, p, w.list, w.bin_off,
                      A->rowptr, A->colind, vA, B->rowptr, B->colind, vB, rpC, ciC, vC, w.markers);
@@ -650,7 +721,8 @@ int spgemm_bwd_t(const csrad_csr* A, const csrad_csr* B, const csrad_csr* At,
   }
   if (gB && B->nrows > 0) {
     const int n = B->nrows;
-    CSRAD_G_SWITCH(lanes_for(B->nnz, n),
+    // lanes from the mean column length of A (the inner loop)
+    CSRAD_G_SWITCH(lanes_for(A->nnz, A->ncols),
                    hipLaunchKernelGGL((k_bwd_b<T, G>), dim3((n + kThreads / G - 1) / (kThreads / G)),
                                       dim3(kThreads), 0, s, n, B->rowptr, B->colind, At->rowptr,
                                       At->colind, permA, static_cast<const T*>(A->vals), C->rowptr,
@@ -686,16 +758,14 @@ extern "C" int csr_spgemm_symbolic(const csrad_csr* A, const csrad_csr* B, int32
   CSRAD_TRY(classify(A, B, w, s));
   if (m > 0) {
     CSRAD_TRY(fill_i32(w.counts, m, 0, s));
-    hipLaunchKernelGGL((k_sym_lanes<16>), dim3(persistent_grid(kThreads / 16, m)), dim3(kThreads),
-                       0, s, 1, w.list, w.bin_off, A->rowptr, A->colind, B->rowptr, B->colind,
-                       w.counts);
-    hipLaunchKernelGGL((k_sym_lanes<64>), dim3(persistent_grid(kThreads / 64, m)), dim3(kThreads),
-                       0, s, 2, w.list, w.bin_off, A->rowptr, A->colind, B->rowptr, B->colind,
-                       w.counts);
-    hipLaunchKernelGGL((k_sym_hash<64, 1024>), dim3(persistent_grid(4, m)), dim3(kThreads), 0, s, 3,
+    sym_lanes<8>(1, A, B, w, s);
+    sym_lanes<16>(2, A, B, w, s);
+    sym_lanes<32>(3, A, B, w, s);
+    sym_lanes<64>(4, A, B, w, s);
+    hipLaunchKernelGGL((k_sym_hash<64, 1024>), dim3(persistent_grid(4, m)), dim3(kThreads), 0, s, 5,
                        w.list, w.bin_off, A->rowptr, A->colind, B->rowptr, B->colind, w.counts);
     hipLaunchKernelGGL((k_sym_hash<256, 8192>), dim3(persistent_grid(1, m)), dim3(kThreads), 0, s,
-                       4, w.list, w.bin_off, A->rowptr, A->colind, B->rowptr, B->colind, w.counts);
+                       6, w.list, w.bin_off, A->rowptr, A->colind, B->rowptr, B->colind, w.counts);
     hipLaunchKernelGGL(k_sym_dense, dim3(w.nmark), dim3(kThreads), 0, s, p, w.list, w.bin_off,
                        A->rowptr, A->colind, B->rowptr, B->colind, w.counts, w.markers);
   }

@@ -1,8 +1,14 @@
 // Stable CSR transpose (the sparse transpose that the SpDMM backward of
 // Section 3.1.3 is built on; every A^T product here gathers over it).
 //
-// count per column -> exclusive scan -> scatter with atomic cursors (order
-// within a column is then arbitrary) -> per-column sort by source row.
+// A square pattern is first tried as structurally symmetric: entry (i, j)
+// looks up (j, i) in row j by binary search; when every entry finds its
+// mirror, the transpose pattern is the pattern itself and perm maps the
+// mirror positions (a device flag records the outcome, and the general
+// kernels below skip or copy accordingly, so the call stays asynchronous).
+// General case: count per column -> exclusive scan -> scatter with atomic
+// cursors (order within a column is then arbitrary) -> per-column sort by
+// source row.
 // Source rows are unique within a column, so the sorted order is unique
 // and the result is bit-exact and identical between runs.  Columns are
 // sorted by length class: <= 32 entries by a few lanes (rank sort), <= 4096 one
@@ -17,10 +23,62 @@ constexpr int kShort = 32;
 constexpr int kChunk = 4096;
 constexpr int kSortThreads = 256;
 
-__global__ __launch_bounds__(256) void k_count_cols(const int32_t* __restrict__ colind, int nnz,
+// Position of column i in row j (rows sorted), or -1.
+__device__ __forceinline__ int mirror_pos(const int32_t* __restrict__ rowptr,
+                                          const int32_t* __restrict__ colind, int j, int i) {
+  const int hi = rowptr[j + 1];
+  int a = rowptr[j], b = hi;
+  while (a < b) {
+    const int mid = (a + b) >> 1;
+    if (colind[mid] < i) a = mid + 1;
+    else b = mid;
+  }
+  return a < hi && colind[a] == i ? a : -1;
+}
+
+// Cheap first look: one block checks 256 rows spread over the pattern and
+// clears *sym on a missing mirror, so that clearly unsymmetric patterns
+// (e.g. triangular ones) skip the full pass.
+__global__ __launch_bounds__(256) void k_sym_probe(int n, const int32_t* __restrict__ rowptr,
+                                                   const int32_t* __restrict__ colind,
+                                                   int32_t* __restrict__ sym) {
+  const int i = (int)(((long long)threadIdx.x * n) / 256 + (n > 256 ? 128 % (n / 256) : 0));
+  if (i >= n || (n <= 256 && (int)threadIdx.x >= n)) return;
+  for (int e = rowptr[i]; e < rowptr[i + 1]; ++e)
+    if (mirror_pos(rowptr, colind, colind[e], i) < 0) *sym = 0;
+}
+
+// Symmetric try: perm[position of (j, i) in row j] = position of (i, j);
+// clears *sym when some entry has no mirror.  8 lanes per row.
+__global__ __launch_bounds__(256) void k_sym_perm(int n, const int32_t* __restrict__ rowptr,
+                                                  const int32_t* __restrict__ colind,
+                                                  int32_t* __restrict__ perm,
+                                                  int32_t* __restrict__ sym) {
+  const int i = blockIdx.x * (256 / 8) + threadIdx.x / 8;
+  if (i >= n || *sym == 0) return;
+  for (int e = rowptr[i] + threadIdx.x % 8; e < rowptr[i + 1]; e += 8) {
+    const int pos = mirror_pos(rowptr, colind, colind[e], i);
+    if (pos < 0) {
+      *sym = 0;
+      return;
+    }
+    perm[pos] = e;
+  }
+}
+
+// Column counts: the row lengths when the pattern is symmetric, else one
+// (wave-aggregated) atomic per entry.
+__global__ __launch_bounds__(256) void k_count_cols(const int32_t* __restrict__ rowptr, int n,
+                                                    const int32_t* __restrict__ colind, int nnz,
+                                                    const int32_t* __restrict__ sym,
                                                     int32_t* __restrict__ cnt) {
-  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < nnz;
-       e += (long long)gridDim.x * blockDim.x)
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  if (*sym) {
+    for (long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += stride)
+      cnt[j] = rowptr[j + 1] - rowptr[j];
+    return;
+  }
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += stride)
     wave_agg_add(cnt, colind[e]);
 }
 
@@ -36,10 +94,11 @@ __global__ __launch_bounds__(256) void k_scatter(int m, const int32_t* __restric
                                                  const int32_t* __restrict__ colind,
                                                  int32_t* __restrict__ cursor,
                                                  int32_t* __restrict__ tkey,
-                                                 int32_t* __restrict__ tval) {
+                                                 int32_t* __restrict__ tval,
+                                                 const int32_t* __restrict__ sym) {
   const int row = blockIdx.x * (256 / 8) + threadIdx.x / 8;
   const int sub = threadIdx.x % 8;
-  if (row >= m) return;
+  if (row >= m || *sym) return;
   const int e1 = rowptr[row + 1];
   for (int e = rowptr[row] + sub; e < e1; e += 8) {
     const int slot = wave_agg_add(cursor, colind[e]);
@@ -59,11 +118,17 @@ __global__ __launch_bounds__(256) void k_sort_short(int n, const int32_t* __rest
                                                     int32_t* __restrict__ okey,
                                                     int32_t* __restrict__ oval,
                                                     int32_t* __restrict__ long_list,
-                                                    int32_t* __restrict__ long_count) {
+                                                    int32_t* __restrict__ long_count,
+                                                    const int32_t* __restrict__ colind,
+                                                    const int32_t* __restrict__ sym) {
   const int c = blockIdx.x * (256 / G) + threadIdx.x / G;
   const int l = threadIdx.x % G;
   if (c >= n) return;
   const int s = rpT[c], len = rpT[c + 1] - s;
+  if (*sym) {  // the transpose pattern is the pattern; perm is written
+    for (int q = l; q < len; q += G) okey[s + q] = colind[s + q];
+    return;
+  }
   if (len <= kShort) {
     for (int q = l; q < len; q += G) {
       const int key = tkey[s + q];
@@ -293,6 +358,7 @@ struct TransposeWs {
   int32_t* tval;
   int32_t* long_list;
   int32_t* long_count;
+  int32_t* sym;
 };
 
 TransposeWs carve_transpose(Carver& cv, int n, int nnz) {
@@ -305,6 +371,7 @@ TransposeWs carve_transpose(Carver& cv, int n, int nnz) {
   w.tval = cv.take<int32_t>((size_t)nnz);
   w.long_list = cv.take<int32_t>((size_t)n + 1);
   w.long_count = cv.take<int32_t>(1);
+  w.sym = cv.take<int32_t>(1);
   return w;
 }
 
@@ -341,15 +408,22 @@ int transpose_pattern(int m, int n, int nnz, const int32_t* rowptr, const int32_
   if (!work || !cv.ok) return CSRAD_EWORKSPACE;
   CSRAD_TRY(fill_i32(w.cnt, (long long)n + 1, 0, s));
   CSRAD_TRY(fill_i32(w.long_count, 1, 0, s));
+  CSRAD_TRY(fill_i32(w.sym, 1, (m == n && nnz > 0) ? 1 : 0, s));
+  if (m == n && nnz > 0) {
+    hipLaunchKernelGGL(k_sym_probe, dim3(1), dim3(256), 0, s, m, rowptr, colind, w.sym);
+    hipLaunchKernelGGL(k_sym_perm, dim3((m + 31) / 32), dim3(256), 0, s, m, rowptr, colind, perm,
+                       w.sym);
+  }
   if (nnz > 0)
-    hipLaunchKernelGGL(k_count_cols, dim3(grid_for(nnz, 256)), dim3(256), 0, s, colind, nnz, w.cnt);
+    hipLaunchKernelGGL(k_count_cols, dim3(grid_for(nnz, 256)), dim3(256), 0, s, rowptr, n,
+                       colind, nnz, w.sym, w.cnt);
   CSRAD_TRY(scan_exclusive(w.cnt, rowptrT, n, w.total, w.scan_ws, w.scan_bytes, s));
   if (nnz == 0) return launch_status();
   if (n > 0)
     hipLaunchKernelGGL(k_copy_i32, dim3(grid_for(n, 256)), dim3(256), 0, s, rowptrT, n, w.cnt);
   if (m > 0)
     hipLaunchKernelGGL(k_scatter, dim3((m + 31) / 32), dim3(256), 0, s, m, rowptr, colind, w.cnt,
-                       w.tkey, w.tval);
+                       w.tkey, w.tval, w.sym);
   {
     // lanes per column from the mean column length (at most kShort)
     int g = 1;
@@ -357,18 +431,16 @@ int transpose_pattern(int m, int n, int nnz, const int32_t* rowptr, const int32_
     const long long cpb = 256 / g;
     const unsigned grid = (unsigned)((n + cpb - 1) / cpb);
     switch (g) {
-      case 1: hipLaunchKernelGGL((k_sort_short<1>), dim3(grid), dim3(256), 0, s, n, rowptrT, w.tkey,
-                                 w.tval, colindT, perm, w.long_list, w.long_count); break;
-      case 2: hipLaunchKernelGGL((k_sort_short<2>), dim3(grid), dim3(256), 0, s, n, rowptrT, w.tkey,
-                                 w.tval, colindT, perm, w.long_list, w.long_count); break;
-      case 4: hipLaunchKernelGGL((k_sort_short<4>), dim3(grid), dim3(256), 0, s, n, rowptrT, w.tkey,
-                                 w.tval, colindT, perm, w.long_list, w.long_count); break;
-      case 8: hipLaunchKernelGGL((k_sort_short<8>), dim3(grid), dim3(256), 0, s, n, rowptrT, w.tkey,
-                                 w.tval, colindT, perm, w.long_list, w.long_count); break;
-      case 16: hipLaunchKernelGGL((k_sort_short<16>), dim3(grid), dim3(256), 0, s, n, rowptrT,
-                                  w.tkey, w.tval, colindT, perm, w.long_list, w.long_count); break;
-      default: hipLaunchKernelGGL((k_sort_short<32>), dim3(grid), dim3(256), 0, s, n, rowptrT,
-                                  w.tkey, w.tval, colindT, perm, w.long_list, w.long_count); break;
+#define CSRAD_SORT_SHORT(G)                                                                  \
+  hipLaunchKernelGGL((k_sort_short<G>), dim3(grid), dim3(256), 0, s, n, rowptrT, w.tkey, w.tval, \
+                     colindT, perm, w.long_list, w.long_count, colind, w.sym)
+      case 1: CSRAD_SORT_SHORT(1); break;
+      case 2: CSRAD_SORT_SHORT(2); break;
+      case 4: CSRAD_SORT_SHORT(4); break;
+      case 8: CSRAD_SORT_SHORT(8); break;
+      case 16: CSRAD_SORT_SHORT(16); break;
+      default: CSRAD_SORT_SHORT(32); break;
+#undef CSRAD_SORT_SHORT
     }
   }
   hipLaunchKernelGGL(k_sort_medium, dim3(1024), dim3(kSortThreads), 0, s, rowptrT, w.tkey, w.tval,

@@ -37,19 +37,19 @@ __device__ __forceinline__ bool dep_side(int lower, int row, int col) {
   return lower ? col < row : col > row;
 }
 
-// Step 1: dependency counts, diagonal check and the level-0 frontier
-// (appended a wave at a time).
+constexpr int kUnset = INT32_MAX;
+
+// Step 1: dependency counts, the diagonal check, and level 0 (rows without
+// dependencies); flag[i] marks the level-0 rows for compaction.
 __global__ __launch_bounds__(kThreads) void k_tri_prep(int n, int lower,
                                                        const int32_t* __restrict__ rp,
                                                        const int32_t* __restrict__ ci,
                                                        int32_t* __restrict__ indeg,
-                                                       int32_t* __restrict__ front,
-                                                       int32_t* __restrict__ front_n,
+                                                       int32_t* __restrict__ flag,
+                                                       int32_t* __restrict__ level_of_row,
                                                        int32_t* __restrict__ bad_row) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const bool valid = i < n;
-  int deps = 0;
-  if (valid) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    int deps = 0;
     bool diag = false;
     for (int e = rp[i]; e < rp[i + 1]; ++e) {
       const int j = ci[e];
@@ -57,25 +57,32 @@ __global__ __launch_bounds__(kThreads) void k_tri_prep(int n, int lower,
       diag |= (j == i);
     }
     indeg[i] = deps;
+    level_of_row[i] = deps == 0 ? 0 : kUnset;
+    flag[i] = deps == 0;
     if (!diag) atomicMin(bad_row, i);
   }
-  const bool ready = valid && deps == 0;
-  const int slot = wave_append(front_n, ready);
-  if (ready) front[slot] = i;
 }
 
-// Step 2: Kahn's algorithm, level by level.  Dependents of row j are the
-// rows of column j of T, i.e. row j of T^T; a row joins the next level
-// when its last dependency is placed.  Levels with at most kKahnSmall rows
-// run inside one workgroup (barrier between levels); a wider level is one
-// grid launch.  State lives on the device: [0] rows in the current level,
-// [2] level index, [3] which frontier buffer is current, [4] scratch count.
+// front[pos[i]] = i for the flagged rows (pos = exclusive scan of flag).
+__global__ void k_tri_compact(int n, const int32_t* __restrict__ flag,
+                              const int32_t* __restrict__ pos, int32_t* __restrict__ front) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    if (flag[i]) front[pos[i]] = i;
+}
+
+// Step 2, narrow levels: Kahn's algorithm by levels inside one workgroup.
+// Dependents of row j are the rows of column j of T, i.e. row j of T^T; a
+// row joins the next level (and gets its level) when its last dependency
+// is placed.  Runs while the frontier is non-empty and at most kKahnSmall
+// rows; terminates after at most n levels (each level places at least one
+// row, and a row enters a frontier only once).  State on the device: [0]
+// rows in the current frontier, [2] its level, [3] which buffer holds it.
 constexpr int kKahnSmall = 8192;
 
-// Places row j (when valid) on `level` and releases its dependents.  The
-// lanes of a wave walk their rows' dependents in step, so that rows made
-// ready in the same step are appended with one atomic per wave.  Every
-// lane of the wave must reach the call.
+// Releases the dependents of row j (when valid).  The lanes of a wave walk
+// their rows' dependents in step so that rows made ready together are
+// appended with one atomic per wave.  Every lane of the wave must reach
+// the call.
 __device__ __forceinline__ void kahn_visit(int j, bool valid, int level, int lower,
                                            const int32_t* __restrict__ rpT,
                                            const int32_t* __restrict__ ciT,
@@ -83,7 +90,6 @@ __device__ __forceinline__ void kahn_visit(int j, bool valid, int level, int low
                                            int* next_n, int32_t* __restrict__ level_of_row) {
   int t0 = 0, len = 0;
   if (valid) {
-    level_of_row[j] = level;
     t0 = rpT[j];
     len = rpT[j + 1] - t0;
   }
@@ -96,13 +102,13 @@ __device__ __forceinline__ void kahn_visit(int j, bool valid, int level, int low
       ready = dep_side(lower, i, j) && atomicSub(&indeg[i], 1) == 1;
     }
     const int slot = wave_append(next_n, ready);
-    if (ready) nxt[slot] = i;
+    if (ready) {
+      level_of_row[i] = level + 1;
+      nxt[slot] = i;
+    }
   }
 }
 
-// Runs levels while the frontier is non-empty and small; terminates after
-// at most n levels (each level places at least one row, and a row enters a
-// frontier only once, when its count reaches zero).
 __global__ __launch_bounds__(kKahnThreads) void k_tri_kahn_small(
     int n, int lower, const int32_t* __restrict__ rpT, const int32_t* __restrict__ ciT,
     int32_t* __restrict__ indeg, int32_t* __restrict__ fa, int32_t* __restrict__ fb,
@@ -135,26 +141,52 @@ __global__ __launch_bounds__(kKahnThreads) void k_tri_kahn_small(
   }
 }
 
-// One wide level over the whole grid; the frontier size comes from state.
-__global__ __launch_bounds__(kThreads) void k_tri_kahn_level(
-    int lower, const int32_t* __restrict__ rpT, const int32_t* __restrict__ ciT,
-    int32_t* __restrict__ indeg, int32_t* __restrict__ fa, int32_t* __restrict__ fb,
-    int32_t* __restrict__ state, int32_t* __restrict__ level_of_row) {
-  const int cur_n = state[0], level = state[2], which = state[3];
-  int* cur = which ? fb : fa;
-  int* nxt = which ? fa : fb;
-  const int q = blockIdx.x * blockDim.x + threadIdx.x;
-  const bool valid = q < cur_n;
-  kahn_visit(valid ? cur[q] : 0, valid, level, lower, rpT, ciT, indeg, nxt, &state[4],
-             level_of_row);
+// Step 2, wide levels: one pass over the rows not yet placed.  With the
+// frontier on level L placed, a row is ready (level L + 1) when all its
+// dependencies sit on levels <= L; otherwise indeg gets the number of
+// dependencies still above L (unplaced, or on level L + 1 from this same
+// pass: either way above L), which is what Kahn's algorithm needs next.
+__global__ __launch_bounds__(kThreads) void k_tri_pull(int n, int lower, int L,
+                                                       const int32_t* __restrict__ rp,
+                                                       const int32_t* __restrict__ ci,
+                                                       int32_t* __restrict__ level_of_row,
+                                                       int32_t* __restrict__ indeg,
+                                                       int32_t* __restrict__ flag) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    int f = 0;
+    if (level_of_row[i] == kUnset) {
+      int cnt = 0;
+      for (int e = rp[i]; e < rp[i + 1]; ++e) {
+        const int j = ci[e];
+        if (dep_side(lower, i, j) && level_of_row[j] > L) ++cnt;
+      }
+      if (cnt == 0) {
+        level_of_row[i] = L + 1;
+        f = 1;
+      } else {
+        indeg[i] = cnt;
+      }
+    }
+    flag[i] = f;
+  }
 }
 
-__global__ void k_tri_kahn_advance(int32_t* __restrict__ state) {
+// state[0] = the compacted frontier size, [2] += 1, [3] ^= 1.
+__global__ void k_tri_next_level(const long long* __restrict__ total, int32_t* __restrict__ state) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
-    state[0] = state[4];
-    state[4] = 0;
+    state[0] = (int32_t)*total;
     state[2] += 1;
     state[3] ^= 1;
+  }
+}
+
+// state[0] = the level-0 frontier size, [2] = 0, [3] = 0.
+__global__ void k_tri_first_level(const long long* __restrict__ total,
+                                  int32_t* __restrict__ state) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    state[0] = (int32_t)*total;
+    state[2] = 0;
+    state[3] = 0;
   }
 }
 
@@ -348,7 +380,12 @@ struct TriWs {
   int32_t* indeg;
   int32_t* fa;
   int32_t* fb;
-  int32_t* counters;  // [0] frontier size, [1] bad row, [2] level, [3] buffer, [4] scratch
+  int32_t* counters;  // [0] frontier size, [1] bad row, [2] level, [3] buffer
+  int32_t* flag;
+  int32_t* pos;
+  void* sws;
+  size_t sws_bytes;
+  long long* total;
   int32_t* iota;
   int32_t* perm;
   void* tws;
@@ -363,6 +400,11 @@ TriWs carve_tri(Carver& cv, int n) {
   w.fa = cv.take<int32_t>((size_t)n);
   w.fb = cv.take<int32_t>((size_t)n);
   w.counters = cv.take<int32_t>(8);
+  w.flag = cv.take<int32_t>((size_t)n + 1);
+  w.pos = cv.take<int32_t>((size_t)n + 1);
+  w.sws_bytes = scan_workspace(n);
+  w.sws = cv.take<char>(w.sws_bytes);
+  w.total = cv.take<long long>(1);
   w.iota = cv.take<int32_t>((size_t)n + 1);
   w.perm = cv.take<int32_t>((size_t)n);
   w.tws_bytes = transpose_workspace(n, n, n);
@@ -425,24 +467,39 @@ extern "C" int csr_trisolve_analyze(const csrad_csr* Tm, int32_t lower, const cs
   }
   CSRAD_TRY(fill_i32(w.counters, 8, 0, s));
   CSRAD_TRY(fill_i32(w.counters + 1, 1, INT32_MAX, s));
-  hipLaunchKernelGGL(k_tri_prep, dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0, s, n,
-                     lower ? 1 : 0, Tm->rowptr, Tm->colind, w.indeg, w.fa, w.counters,
-                     w.counters + 1);
+  const unsigned gn = (unsigned)((n + kThreads - 1) / kThreads < 4096 ? (n + kThreads - 1) / kThreads
+                                                                     : 4096);
+  const int lw = lower ? 1 : 0;
+  hipLaunchKernelGGL(k_tri_prep, dim3(gn), dim3(kThreads), 0, s, n, lw, Tm->rowptr, Tm->colind,
+                     w.indeg, w.flag, level_of_row, w.counters + 1);
+  CSRAD_TRY(scan_exclusive(w.flag, w.pos, n, w.total, w.sws, w.sws_bytes, s));
+  hipLaunchKernelGGL(k_tri_compact, dim3(gn), dim3(kThreads), 0, s, n, w.flag, w.pos, w.fa);
+  hipLaunchKernelGGL(k_tri_first_level, dim3(1), dim3(64), 0, s, w.total, w.counters);
   int32_t host[8];
-  for (;;) {
-    hipLaunchKernelGGL(k_tri_kahn_small, dim3(1), dim3(kKahnThreads), 0, s, n, lower ? 1 : 0,
-                       Tt->rowptr, Tt->colind, w.indeg, w.fa, w.fb, w.counters, level_of_row);
-    CSRAD_TRY(launch_status());
+  auto read_state = [&]() -> int {
     if (hipMemcpyAsync(host, w.counters, sizeof(host), hipMemcpyDeviceToHost, s) != hipSuccess)
       return CSRAD_EHIP;
-    if (hipStreamSynchronize(s) != hipSuccess) return CSRAD_EHIP;
-    if (host[1] != INT32_MAX) return CSRAD_ESINGULAR;
-    if (host[0] == 0 || host[2] >= n) break;
-    // a wide level: one grid launch, then advance the state
-    hipLaunchKernelGGL(k_tri_kahn_level, dim3((host[0] + kThreads - 1) / kThreads), dim3(kThreads),
-                       0, s, lower ? 1 : 0, Tt->rowptr, Tt->colind, w.indeg, w.fa, w.fb,
-                       w.counters, level_of_row);
-    hipLaunchKernelGGL(k_tri_kahn_advance, dim3(1), dim3(64), 0, s, w.counters);
+    return hipStreamSynchronize(s) == hipSuccess ? CSRAD_OK : CSRAD_EHIP;
+  };
+  CSRAD_TRY(read_state());
+  if (host[1] != INT32_MAX) return CSRAD_ESINGULAR;
+  while (host[0] > 0 && host[2] < n) {
+    if (host[0] <= kKahnSmall) {
+      // narrow levels inside one workgroup, until the frontier is empty or wide
+      hipLaunchKernelGGL(k_tri_kahn_small, dim3(1), dim3(kKahnThreads), 0, s, n, lw, Tt->rowptr,
+                         Tt->colind, w.indeg, w.fa, w.fb, w.counters, level_of_row);
+      CSRAD_TRY(launch_status());
+    } else {
+      // a wide level: one pass over the unplaced rows, then compaction into
+      // the other frontier buffer
+      int32_t* nxt = host[3] ? w.fa : w.fb;
+      hipLaunchKernelGGL(k_tri_pull, dim3(gn), dim3(kThreads), 0, s, n, lw, host[2], Tm->rowptr,
+                         Tm->colind, level_of_row, w.indeg, w.flag);
+      CSRAD_TRY(scan_exclusive(w.flag, w.pos, n, w.total, w.sws, w.sws_bytes, s));
+      hipLaunchKernelGGL(k_tri_compact, dim3(gn), dim3(kThreads), 0, s, n, w.flag, w.pos, nxt);
+      hipLaunchKernelGGL(k_tri_next_level, dim3(1), dim3(64), 0, s, w.total, w.counters);
+    }
+    CSRAD_TRY(read_state());
   }
   const int nl = host[2];
   *nlevels_host = nl;
