@@ -53,6 +53,120 @@ def log(msg):
 
 
 # ----------------------------------------------------------------------
+# Batched uneven blocks: one launch per op over a block-diagonal CSR
+# ----------------------------------------------------------------------
+def _geometric_block(b):
+    from paper_2212_05159_amd import gen
+    return gen.geometric_graph_laplacian(b)
+
+
+def geometric_blocks(nblocks):
+    """The first `nblocks` host blocks of the batched workload, built by a
+    pool of worker processes (before this process touches the GPU)."""
+    import multiprocessing as mp
+
+    t0 = time.perf_counter()
+    with mp.get_context("spawn").Pool(min(16, os.cpu_count() or 1)) as pool:
+        blocks = pool.map(_geometric_block, range(nblocks))
+    return blocks, time.perf_counter() - t0
+
+
+def batched_section(blocks, gen_s, reps=5):
+    """SpMV / SpMM (64 columns) fwd+bwd and the tri-solve fwd+adjoint over
+    random geometric-graph Laplacians (+1e-2 I; n from 1k to 64k, kNN with
+    k from 6 to 14), float32, concatenated block-diagonally: each op is one
+    launch over the whole batch.  Also timed: the same ops launched block
+    by block."""
+    import torch
+    from paper_2212_05159_amd import autotune, batch as bt, gen
+    from paper_2212_05159_amd import sparse as sp
+
+    nblocks = len(blocks)
+    B = bt.Batch(blocks)
+    L = bt.Batch([gen.tril(b) for b in blocks])
+    n, nnz, nnzL = B.host.nrows, B.host.nnz, L.host.nnz
+    k = 64
+    rng = np.random.default_rng(7)
+    dev = lambda a: torch.as_tensor(np.asarray(a, np.float32), device="cuda")
+    x, gy = dev(rng.standard_normal(n)), dev(rng.standard_normal(n))
+    X, G = dev(rng.standard_normal((n, k))), dev(rng.standard_normal((n, k)))
+    bL, gL = dev(rng.standard_normal(n)), dev(rng.standard_normal(n))
+    P, v, PL, vL = B.pattern, B.A.vals, L.pattern, L.A.vals
+    P.transpose()
+    PL.transpose()
+    nl = PL.levels(True)[0]
+    tuned = autotune.tune_spmm(P, v, X, G, reps=3, use_cache=False)
+    ops = {
+        "spmv fwd": lambda: sp.spmv(P, v, x),
+        "spmv bwd": lambda: sp.spmv_bwd(P, v, x, gy),
+        "spmm fwd": lambda: sp.spmm(P, v, X),
+        "spmm bwd": lambda: sp.spmm_bwd(P, v, X, G),
+        "trisolve fwd": lambda: sp.trisolve(PL, vL, bL, True),
+        "trisolve bwd": lambda: sp.trisolve_bwd(PL, vL, bL, gL, True),
+    }
+    V, I = 4, I4
+    pat = lambda rows, z: (rows + 1) * I + z * I
+    model = {"spmv fwd": pat(n, nnz) + nnz * V + 2 * n * V,
+             "spmv bwd": pat(n, nnz) + nnz * (I + 2 * V) + 3 * n * V,
+             "spmm fwd": pat(n, nnz) + nnz * V + 2 * n * k * V,
+             "spmm bwd": pat(n, nnz) + nnz * (I + 2 * V) + 3 * n * k * V,
+             "trisolve fwd": pat(n, nnzL) + nnzL * V + 2 * n * V + n * I,
+             "trisolve bwd": (pat(n, nnzL) + nnzL * (I + V) + 2 * n * V + n * I)
+             + (pat(n, nnzL) + nnzL * I + 2 * n * V + nnzL * V)}
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    res = {}
+    for name, fn in ops.items():
+        ms = timed(fn)
+        res[name] = {"ms": round(ms, 4), "GB/s": round(model[name] / (ms * 1e-3) / 1e9, 1)}
+    total_ms = sum(r["ms"] for r in res.values())
+    # the same six ops launched block by block
+    per = []
+    for blk, lblk in zip(blocks, [gen.tril(b) for b in blocks]):
+        Ab = sp.CsrTensor.from_host(blk, dtype=torch.float32)
+        Lb = sp.CsrTensor.from_host(lblk, dtype=torch.float32)
+        m = blk.nrows
+        xb, Xb = x[:m].contiguous(), X[:m].contiguous()
+        Gb, gb = G[:m].contiguous(), gy[:m].contiguous()
+        Ab.pattern.transpose()
+        Lb.pattern.levels(True)
+        per.append((Ab, Lb, xb, Xb, Gb, gb))
+
+    def per_block():
+        for Ab, Lb, xb, Xb, Gb, gb in per:
+            sp.spmv(Ab.pattern, Ab.vals, xb)
+            sp.spmv_bwd(Ab.pattern, Ab.vals, xb, gb)
+            sp.spmm(Ab.pattern, Ab.vals, Xb)
+            sp.spmm_bwd(Ab.pattern, Ab.vals, Xb, Gb)
+            sp.trisolve(Lb.pattern, Lb.vals, xb, True)
+            sp.trisolve_bwd(Lb.pattern, Lb.vals, xb, gb, True)
+
+    per_ms = timed(per_block)
+    return {
+        "workload": f"{nblocks} random geometric-graph Laplacians + 1e-2 I (of the 512-block recipe: "
+                    f"blocks 0..{nblocks - 1}), n in [1024, 65536], kNN k in [6, 14], float32, "
+                    f"block-diagonal: n={n}, nnz={nnz}; L = tril (nnz={nnzL}, {nl} levels); k={k}",
+        "ops": res,
+        "batched_ms": round(total_ms, 4),
+        "batched_GB/s": round(sum(model.values()) / (total_ms * 1e-3) / 1e9, 1),
+        "per_block_ms": round(per_ms, 4),
+        "batching_speedup": round(per_ms / total_ms, 2),
+        "spmm_plans": {op: (list(c) if c else "natural") for op, (c, _) in tuned.items()},
+        "generation_s": round(gen_s, 1),
+    }
+
+
+# ----------------------------------------------------------------------
 # Measured HBM traffic of the dominant kernel (committed counter summary)
 # ----------------------------------------------------------------------
 COUNTERS = os.path.join(ROOT, "profiles", "spmm_poisson128_counters.md")
@@ -389,6 +503,9 @@ def main():
     ap.add_argument("--pcg-systems", type=int, default=4)
     ap.add_argument("--train-grid", type=int, default=256)
     ap.add_argument("--train-steps", type=int, default=300)
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-blocks part")
+    ap.add_argument("--batched-blocks", type=int, default=64,
+                    help="number of the 512 geometric-graph blocks in the batched part")
     ap.add_argument("--calibrate", type=int, default=0, metavar="M",
                     help="only run a copy-like kernel over M million float32 values "
                          "(identity-permutation gather: 12 bytes per value) to calibrate "
@@ -398,6 +515,13 @@ def main():
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
               "(the multi-GPU sharding is a design note, not built)", file=sys.stderr)
         sys.exit(2)
+
+    host_blocks = None
+    if not args.no_batched and not args.calibrate:
+        # host inputs of the batched part first: worker processes are
+        # started before this process uses the GPU
+        host_blocks = geometric_blocks(args.batched_blocks)
+        log(f"built {args.batched_blocks} geometric-graph blocks in {host_blocks[1]:.1f} s")
 
     import torch
     from paper_2212_05159_amd import capi
@@ -475,6 +599,13 @@ def main():
         log("PCG time-to-1e-6 part ...")
         pcg = pcg_section(args.pcg_grid, args.train_grid, args.train_steps, args.pcg_systems)
 
+    batched = None
+    if not args.no_batched:
+        log(f"batched part ({args.batched_blocks} blocks) ...")
+        batched = batched_section(*host_blocks)
+        log(f"batched: {batched['batched_ms']} ms for the six ops over the batch, "
+            f"{batched['per_block_ms']} ms block by block")
+
     out = {
         "metric": "fwd+bwd sparse-op GB/s (% HBM peak); PCG time-to-1e-6: learned vs Jacobi",
         "value": round(value, 2),
@@ -499,6 +630,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "pcg": pcg,
+        "batched": batched,
         "breakdown": breakdown,
         "step_bytes": total_bytes,
     }
