@@ -167,6 +167,66 @@ def batched_section(blocks, gen_s, reps=5):
 
 
 # ----------------------------------------------------------------------
+# Differentiated CG: K steps forward, hand-written reverse, sqrt(K) checkpoints
+# ----------------------------------------------------------------------
+def cg_section(N=512, K=100, reps=5):
+    """x_K of K CG steps on 2D anisotropic Q1 diffusion (eps 1e-3, angle
+    pi/4, N^2 unknowns, float32 values, float64 dots), loss 0.5 ||x_K - t||^2
+    backpropagated to the matrix values and b with checkpoints every
+    ceil(sqrt(K)) steps; one forward step captured in a graph."""
+    import torch
+    from paper_2212_05159_amd import cg as cgmod, gen
+    from paper_2212_05159_amd import sparse as sp
+
+    A = gen.anisotropic_q1(N, 1e-3, np.pi / 4)
+    rng = np.random.default_rng(4)
+    Ad = sp.CsrTensor.from_host(A, dtype=torch.float32)
+    b = torch.as_tensor(rng.standard_normal(A.nrows), dtype=torch.float32, device="cuda")
+    t = torch.as_tensor(rng.standard_normal(A.nrows), dtype=torch.float32, device="cuda")
+    vals = Ad.vals.detach().clone().requires_grad_(True)
+    bb = b.clone().requires_grad_(True)
+    Av = sp.CsrTensor(Ad.pattern, vals)
+    Ad.pattern.transpose()
+    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+
+    def run():
+        vals.grad = None
+        bb.grad = None
+        x = cgmod.cg_solve(Av, bb, K, graph=True)
+        e1.record()
+        (0.5 * (x - t).pow(2).sum()).backward()
+        return x
+
+    run()
+    torch.cuda.synchronize()
+    fwd, tot = [], []
+    for _ in range(reps):
+        e0.record()
+        run()
+        e2.record()
+        torch.cuda.synchronize()
+        fwd.append(e0.elapsed_time(e1))
+        tot.append(e0.elapsed_time(e2))
+    n, nnz = A.nrows, A.nnz
+    V, I = 4, I4
+    # per step: product with p.q (pattern, values, p gathered, q), update of
+    # x and r, r.r, p = r + beta p (vectors read or written once each)
+    fwd_step = (n + 1) * I + nnz * (I + V) + 2 * n * V + 6 * n * V + n * V + 3 * n * V
+    f_ms, t_ms = float(np.median(fwd)), float(np.median(tot))
+    return {
+        "workload": f"2D anisotropic Q1 diffusion {N}^2 (n={n}, nnz={nnz}), eps 1e-3, angle pi/4, "
+                    f"float32 values, float64 dots; {K} CG steps, loss 0.5||x_K - t||^2, gradients "
+                    f"to the values and b, checkpoints every {int(np.ceil(np.sqrt(K)))} steps",
+        "K": K,
+        "forward_ms": round(f_ms, 4),
+        "forward_backward_ms": round(t_ms, 4),
+        "forward_us_per_step": round(1e3 * f_ms / K, 2),
+        "backward_us_per_step": round(1e3 * (t_ms - f_ms) / K, 2),
+        "forward_GB/s": round(fwd_step * K / (f_ms * 1e-3) / 1e9, 1),
+    }
+
+
+# ----------------------------------------------------------------------
 # Measured HBM traffic of the dominant kernel (committed counter summary)
 # ----------------------------------------------------------------------
 COUNTERS = os.path.join(ROOT, "profiles", "spmm_poisson128_counters.md")
@@ -504,6 +564,7 @@ def main():
     ap.add_argument("--train-grid", type=int, default=256)
     ap.add_argument("--train-steps", type=int, default=300)
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-blocks part")
+    ap.add_argument("--no-cg", action="store_true", help="skip the differentiated-CG part")
     ap.add_argument("--batched-blocks", type=int, default=64,
                     help="number of the 512 geometric-graph blocks in the batched part")
     ap.add_argument("--calibrate", type=int, default=0, metavar="M",
@@ -606,6 +667,12 @@ def main():
         log(f"batched: {batched['batched_ms']} ms for the six ops over the batch, "
             f"{batched['per_block_ms']} ms block by block")
 
+    cgres = None
+    if not args.no_cg:
+        log("differentiated-CG part ...")
+        cgres = cg_section()
+        log(f"CG: {cgres['forward_ms']} ms forward, {cgres['forward_backward_ms']} ms forward+backward")
+
     out = {
         "metric": "fwd+bwd sparse-op GB/s (% HBM peak); PCG time-to-1e-6: learned vs Jacobi",
         "value": round(value, 2),
@@ -631,6 +698,7 @@ def main():
         "cpu_baseline": cpu,
         "pcg": pcg,
         "batched": batched,
+        "cg": cgres,
         "breakdown": breakdown,
         "step_bytes": total_bytes,
     }
