@@ -211,6 +211,25 @@ __device__ __forceinline__ void store_vec(T* p, const Vec<T, VW>& x) {
   *reinterpret_cast<Vec<T, VW>*>(p) = x;
 }
 
+// Streaming store of a whole output row slice that nothing in the kernel
+// reads again: kept out of the caches' way of the reused rows.
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+template <typename T, int VW>
+__device__ __forceinline__ void store_vec_stream(T* p, const Vec<T, VW>& x) {
+  if constexpr (sizeof(T) * VW == 16) {
+    u32x4 u;
+    __builtin_memcpy(&u, &x, 16);
+    __builtin_nontemporal_store(u, reinterpret_cast<u32x4*>(p));
+  } else if constexpr (sizeof(T) * VW == 8) {
+    u32x2 u;
+    __builtin_memcpy(&u, &x, 8);
+    __builtin_nontemporal_store(u, reinterpret_cast<u32x2*>(p));
+  } else {
+    store_vec<T, VW>(p, x);
+  }
+}
+
 // Streaming loads for data read exactly once (CSR arrays): keep them from
 // evicting reused dense rows.
 template <typename T>

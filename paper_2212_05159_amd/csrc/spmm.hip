@@ -74,7 +74,7 @@ __global__ __launch_bounds__(kThreads) void k_spmm_fwd(RowOrder ord, int k,
     Vec<T, VW> out;
 #pragma unroll
     for (int w = 0; w < VW; ++w) out.v[w] = acc[w];
-    store_vec<T, VW>(C + (long long)row * ldc + col, out);
+    store_vec_stream<T, VW>(C + (long long)row * ldc + col, out);
   }
 }
 
@@ -137,7 +137,7 @@ __global__ __launch_bounds__(kThreads) void k_spmm_bwd_t(
       Vec<T, VW> out;
 #pragma unroll
       for (int w = 0; w < VW; ++w) out.v[w] = acc[w];
-      store_vec<T, VW>(gB + (long long)j * ldgb + col, out);
+      store_vec_stream<T, VW>(gB + (long long)j * ldgb + col, out);
     }
   }
 }
@@ -220,7 +220,7 @@ __global__ __launch_bounds__(kThreads) void k_spmm_fwd_coop(RowOrder ord, int k,
       Vec<T, VW> out;
 #pragma unroll
       for (int w = 0; w < VW; ++w) out.v[w] = acc[w];
-      store_vec<T, VW>(C + (long long)row * ldc + col, out);
+      store_vec_stream<T, VW>(C + (long long)row * ldc + col, out);
     }
   }
 }
@@ -286,7 +286,7 @@ __global__ __launch_bounds__(kThreads) void k_spmm_bwd_coop(
       Vec<T, VW> out;
 #pragma unroll
       for (int w = 0; w < VW; ++w) out.v[w] = acc[w];
-      store_vec<T, VW>(gB + (long long)j * ldgb + col, out);
+      store_vec_stream<T, VW>(gB + (long long)j * ldgb + col, out);
     }
   }
 }
