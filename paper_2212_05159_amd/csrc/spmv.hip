@@ -1,7 +1,10 @@
 // SpMV forward and backward (Section 3.1.1; Table 1, SpMV row).
 //
-// Forward: row split, G lanes per row (G a power of two picked from the
-// mean row length), lanes stride over the row's entries, DPP group sum.
+// Forward: short rows (mean length <= 9) by row blocks staged in LDS: a
+// block loads the entries of ROWS consecutive rows with coalesced loads
+// (several in flight per thread), keeps the products in LDS, and each
+// thread sums one row in entry order; longer rows by G lanes per row (G a
+// power of two picked from the mean row length), DPP group sum.
 // Backward: one pass over A^T (transpose pattern + perm) yields both
 //   gx[j] = sum over column j of vals[e] * gy[row e]    (A^T gy)
 //   gvals[e] = gy[row e] * x[j]                         (masked outer product)
@@ -29,6 +32,50 @@ __global__ __launch_bounds__(kThreads) void k_spmv(int m, const int32_t* __restr
   }
   s = group_sum<G>(s);
   if (row < m && sub == 0) y[row] = s;
+}
+
+// Row blocks of ROWS rows (one per thread), at most CAP entries staged; a
+// block with more entries takes its rows one wave each.
+template <typename T, int ROWS, int CAP>
+__global__ __launch_bounds__(ROWS) void k_spmv_stream(int m, const int32_t* __restrict__ rowptr,
+                                                      const int32_t* __restrict__ colind,
+                                                      const T* __restrict__ vals,
+                                                      const T* __restrict__ x, T* __restrict__ y) {
+  __shared__ T prod[CAP];
+  const int r0 = xcd_block(blockIdx.x, gridDim.x) * ROWS;
+  if (r0 >= m) return;
+  const int r1 = min(r0 + ROWS, m);
+  const int e0 = rowptr[r0], cnt = rowptr[r1] - e0;
+  if (cnt <= CAP) {
+    for (int t = threadIdx.x; t < cnt; t += 4 * ROWS) {
+      T pr[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int tt = t + u * ROWS;
+        pr[u] = tt < cnt ? ld_stream(&vals[e0 + tt]) * x[ld_stream(&colind[e0 + tt])] : T(0);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (t + u * ROWS < cnt) prod[t + u * ROWS] = pr[u];
+    }
+    __syncthreads();
+    const int r = r0 + threadIdx.x;
+    if (r < r1) {
+      const int a = rowptr[r] - e0, b = rowptr[r + 1] - e0;
+      T acc = 0;
+      for (int t = a; t < b; ++t) acc += prod[t];
+      y[r] = acc;
+    }
+  } else {
+    const int lane = threadIdx.x % kWave;
+    for (int r = r0 + threadIdx.x / kWave; r < r1; r += ROWS / kWave) {
+      T acc = 0;
+      for (int e = rowptr[r] + lane; e < rowptr[r + 1]; e += kWave)
+        acc += ld_stream(&vals[e]) * x[ld_stream(&colind[e])];
+      acc = group_sum<kWave>(acc);
+      if (lane == 0) y[r] = acc;
+    }
+  }
 }
 
 // Gather over A^T: output row j of A^T is column j of A.
@@ -108,6 +155,12 @@ int spmv_fwd_t(const csrad_csr* A, const void* x, void* y, hipStream_t s) {
   if (m == 0) return CSRAD_OK;
   const T* xx = static_cast<const T*>(x);
   T* yy = static_cast<T*>(y);
+  const double mean = (double)A->nnz / m;
+  if (mean <= 9.0) {
+    hipLaunchKernelGGL((k_spmv_stream<T, 128, 1280>), dim3((m + 127) / 128), dim3(128), 0, s, m,
+                       A->rowptr, A->colind, static_cast<const T*>(A->vals), xx, yy);
+    return launch_status();
+  }
   switch (lanes_for(A->nnz, m)) {
     case 1: launch_fwd<T, 1>(m, A, xx, yy, s); break;
     case 2: launch_fwd<T, 2>(m, A, xx, yy, s); break;
