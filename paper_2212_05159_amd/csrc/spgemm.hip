@@ -9,8 +9,8 @@
 //                            64 / 256 lanes per row;
 //   U > 4096               : a dense per-workgroup marker array in the
 //                            workspace (tagged with the row id).
-// Symbolic: count the distinct columns (run heads after the lane sort;
-//           hash insert with CAS; marker tags).
+// Symbolic: count the distinct columns (run heads after the lane sort for
+//           U <= 32; hash insert with CAS up to 4096; marker tags beyond).
 // Numeric : small bins sum each run of equal columns in k order; the
 //           others rebuild the set, sort it (bitonic sort of the table in
 //           LDS, empty slots last; for the dense path a block scan of the
@@ -761,7 +761,11 @@ extern "C" int csr_spgemm_symbolic(const csrad_csr* A, const csrad_csr* B, int32
     sym_lanes<8>(1, A, B, w, s);
     sym_lanes<16>(2, A, B, w, s);
     sym_lanes<32>(3, A, B, w, s);
-    sym_lanes<64>(4, A, B, w, s);
+    // counting alone: for U <= 64 an LDS hash with 16 lanes per row beats
+    // sorting across a whole wave per row
+    hipLaunchKernelGGL((k_sym_hash<16, 128>), dim3(persistent_grid(16, m)), dim3(kThreads), 0, s,
+                       4, w.list, w.bin_off, A->rowptr, A->colind, B->rowptr, B->colind,
+                       w.counts);
     hipLaunchKernelGGL((k_sym_hash<64, 1024>), dim3(persistent_grid(4, m)), dim3(kThreads), 0, s, 5,
                        w.list, w.bin_off, A->rowptr, A->colind, B->rowptr, B->colind, w.counts);
     hipLaunchKernelGGL((k_sym_hash<256, 8192>), dim3(persistent_grid(1, m)), dim3(kThreads), 0, s,

@@ -48,8 +48,11 @@ __global__ __launch_bounds__(256) void k_sym_probe(int n, const int32_t* __restr
     if (mirror_pos(rowptr, colind, colind[e], i) < 0) *sym = 0;
 }
 
-// Symmetric try: perm[position of (j, i) in row j] = position of (i, j);
-// clears *sym when some entry has no mirror.  8 lanes per row.
+// Symmetric try: entry e = (i, j) finds the position of its mirror (j, i)
+// in row j; the transpose's entry at that position is e.  The mirror map is
+// an involution, so perm[e] = mirror position is the same permutation,
+// written in order.  Clears *sym when some entry has no mirror.  8 lanes
+// per row.
 __global__ __launch_bounds__(256) void k_sym_perm(int n, const int32_t* __restrict__ rowptr,
                                                   const int32_t* __restrict__ colind,
                                                   int32_t* __restrict__ perm,
@@ -62,7 +65,7 @@ __global__ __launch_bounds__(256) void k_sym_perm(int n, const int32_t* __restri
       *sym = 0;
       return;
     }
-    perm[pos] = e;
+    perm[e] = pos;
   }
 }
 
