@@ -169,11 +169,13 @@ def batched_section(blocks, gen_s, reps=5):
 # ----------------------------------------------------------------------
 # Differentiated CG: K steps forward, hand-written reverse, sqrt(K) checkpoints
 # ----------------------------------------------------------------------
-def cg_section(N=512, K=100, reps=5):
+def cg_section(N=512, K=100, reps=5, graph=False):
     """x_K of K CG steps on 2D anisotropic Q1 diffusion (eps 1e-3, angle
     pi/4, N^2 unknowns, float32 values, float64 dots), loss 0.5 ||x_K - t||^2
     backpropagated to the matrix values and b with checkpoints every
-    ceil(sqrt(K)) steps; one forward step captured in a graph."""
+    ceil(sqrt(K)) steps.  Steps are launched eagerly (one library call per
+    step launches its three kernels, faster than the GPU runs them); a
+    captured graph would add its capture to every solve."""
     import torch
     from paper_2212_05159_amd import cg as cgmod, gen
     from paper_2212_05159_amd import sparse as sp
@@ -192,7 +194,7 @@ def cg_section(N=512, K=100, reps=5):
     def run():
         vals.grad = None
         bb.grad = None
-        x = cgmod.cg_solve(Av, bb, K, graph=True)
+        x = cgmod.cg_solve(Av, bb, K, graph=graph)
         e1.record()
         (0.5 * (x - t).pow(2).sum()).backward()
         return x

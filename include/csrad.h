@@ -209,7 +209,8 @@ int csr_trisolve_bwd(const csrad_csr *T, int32_t lower, const csrad_csr *Tt,
  *   r_{t+1} and hist record, the upstream gradient gR of r_{t+1} (may be
  *   NULL) and the running adjoints xb, rb, pb, qb (vectors) and scal
  *   (reverse slots); accumulates the value gradient into gvals (q = A p
- *   contributes qb_i p_j at (i,j)).  At/perm: transpose of A.
+ *   contributes qb_i p_j at (i,j)).  At: the transpose of A with its
+ *   values (csr_transpose / csr_transpose_vals, same dtype as A).
  * csr_cg_finish_bwd: gb = rb + pb + 2 rhob b after the first step is undone.
  * The workspace (csr_cg_workspace) holds block partial sums.
  * ------------------------------------------------------------------- */
@@ -221,11 +222,11 @@ int csr_cg_step(const csrad_csr *A, void *x, void *r, void *p, void *q,
                 void *p_save, void *r_save, double *scal, int32_t *step,
                 double *hist, int32_t hist_cap, void *work, size_t work_bytes,
                 void *stream);
-int csr_cg_step_bwd(const csrad_csr *A, const csrad_csr *At,
-                    const int32_t *perm, const void *p, const void *q,
-                    const void *r1, const double *step_hist, const void *gR,
-                    void *xb, void *rb, void *pb, void *qb, double *scal,
-                    void *gvals, void *work, size_t work_bytes, void *stream);
+int csr_cg_step_bwd(const csrad_csr *A, const csrad_csr *At, const void *p,
+                    const void *q, const void *r1, const double *step_hist,
+                    const void *gR, void *xb, void *rb, void *pb, void *qb,
+                    double *scal, void *gvals, void *work, size_t work_bytes,
+                    void *stream);
 int csr_cg_finish_bwd(const csrad_csr *A, const void *b, const void *rb,
                       const void *pb, const double *scal, void *gb,
                       void *stream);

@@ -65,7 +65,7 @@ _SIGS = {
     "csr_cg_workspace": (C.c_int, [C.c_void_p, C.POINTER(C.c_size_t)]),
     "csr_cg_init": (C.c_int, [C.c_void_p] * 8 + [C.c_size_t, C.c_void_p]),
     "csr_cg_step": (C.c_int, [C.c_void_p] * 10 + [C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p]),
-    "csr_cg_step_bwd": (C.c_int, [C.c_void_p] * 15 + [C.c_size_t, C.c_void_p]),
+    "csr_cg_step_bwd": (C.c_int, [C.c_void_p] * 14 + [C.c_size_t, C.c_void_p]),
     "csr_cg_finish_bwd": (C.c_int, [C.c_void_p] * 7),
     "csr_pcg_workspace": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p,
                                     C.POINTER(C.c_size_t)]),
@@ -273,9 +273,9 @@ def csr_cg_step(A, x, r, p, q, p_save, r_save, scal, step, hist, work):
         _stream()))
 
 
-def csr_cg_step_bwd(A, At, perm, p, q, r1, step_hist, gR, xb, rb, pb, qb, scal, gvals, work):
+def csr_cg_step_bwd(A, At, p, q, r1, step_hist, gR, xb, rb, pb, qb, scal, gvals, work):
     _check("csr_cg_step_bwd", load().csr_cg_step_bwd(
-        C.byref(A), C.byref(At), _ptr(perm), _ptr(p), _ptr(q), _ptr(r1), _ptr(step_hist),
+        C.byref(A), C.byref(At), _ptr(p), _ptr(q), _ptr(r1), _ptr(step_hist),
         _ptr(gR), _ptr(xb), _ptr(rb), _ptr(pb), _ptr(qb), _ptr(scal), _ptr(gvals), _ptr(work),
         work.numel(), _stream()))
 

@@ -8,8 +8,9 @@ steps; the backward recomputes one segment at a time from its checkpoint,
 storing that segment's (p_t, q_t, r_{t+1}) through the step kernels' save
 outputs, then undoes its steps in reverse.  Forward steps are
 bit-reproducible, so the checkpointed gradient equals the fully stored one
-exactly.  With ``graph=True`` one forward step is captured in a HIP graph
-and replayed K times (scalars stay on the device; no host synchronisation).
+exactly.  With ``graph=True`` one checkpoint segment (c forward steps) is
+captured in a HIP graph and replayed per segment (scalars stay on the
+device; no host synchronisation); a shorter last segment runs eagerly.
 """
 from __future__ import annotations
 
@@ -50,8 +51,9 @@ class _Solver:
             full = [torch.empty(K, self.n, dtype=self.b.dtype, device=self.b.device) for _ in range(3)]
         ckpts = []
         g = None
-        if graph and not store_all and not keep_residuals and K > 0:
-            # capture one step; each replay advances the device step counter
+        if graph and not store_all and not keep_residuals and K >= c:
+            # capture one checkpoint segment (c steps); each replay advances
+            # the device step counter c times
             g = torch.cuda.CUDAGraph()
             probe = {k: v.clone() for k, v in st.items()}
             hist_probe = torch.zeros_like(hist)
@@ -61,16 +63,21 @@ class _Solver:
                 self._step(probe, hist_probe)  # warm-up outside the capture
             torch.cuda.current_stream().wait_stream(s)
             with torch.cuda.graph(g):
-                self._step(st, hist)
-        for t in range(K):
+                for _ in range(c):
+                    self._step(st, hist)
+        t = 0
+        while t < K:
             if t % c == 0 and not store_all:
                 ckpts.append((st["r"].clone(), st["p"].clone(), st["scal"].clone()))
-            if g is not None:
+            if g is not None and t + c <= K:
                 g.replay()
-            elif store_all:
+                t += c
+                continue
+            if store_all:
                 self._step(st, hist, p_save=full[0][t], r_save=full[2][t], q=full[1][t])
             else:
                 self._step(st, hist, r_save=None if R is None else R[t])
+            t += 1
         return st["x"], dict(c=c, hist=hist, ckpts=ckpts, full=full, R=R, K=K)
 
     def backward(self, saved, gx=None, gR=None):
@@ -78,7 +85,9 @@ class _Solver:
         K, c, hist = saved["K"], saved["c"], saved["hist"]
         dev, dt = self.b.device, self.b.dtype
         Pt, perm = self.P.transpose()
-        At = Pt.desc(dtype=dt)
+        vT = torch.empty_like(self.vals)  # A^T's values, gathered once per sweep
+        capi.csr_transpose_vals(self.A, perm, vT)
+        At = Pt.desc(vT)
         z = lambda: torch.zeros(self.n, dtype=dt, device=dev)
         xb = gx.clone().to(dt) if gx is not None else z()
         rb, pb, qb = z(), z(), z()
@@ -86,7 +95,7 @@ class _Solver:
         gv = torch.zeros(self.P.nnz, dtype=dt, device=dev)
 
         def undo(t, p_t, q_t, r_t1):
-            capi.csr_cg_step_bwd(self.A, At, perm, p_t, q_t, r_t1, hist[t],
+            capi.csr_cg_step_bwd(self.A, At, p_t, q_t, r_t1, hist[t],
                                  None if gR is None else gR[t], xb, rb, pb, qb, scal_b, gv, self.ws)
 
         if saved["full"] is not None:

@@ -30,7 +30,21 @@ def _spd(n, seed):
     return gen._from_coo(n, n, r, c, S[r, c])
 
 
+def _arrow(n):
+    # tridiagonal plus a full first row and column: mean row length ~5, but
+    # the first 256-row block holds more entries than the product kernel
+    # stages, so it takes the wave-per-row branch
+    r = np.concatenate([np.arange(n), np.arange(1, n), np.arange(n - 1), np.zeros(n - 2, int),
+                        np.arange(2, n)])
+    c = np.concatenate([np.arange(n), np.arange(n - 1), np.arange(1, n), np.arange(2, n),
+                        np.zeros(n - 2, int)])
+    v = np.concatenate([np.full(n, 4.0), np.full(2 * (n - 1), -1.0), np.full(2 * (n - 2), 1e-3)])
+    v[0] = 8.0
+    return gen._from_coo(n, n, r, c, v)
+
+
 CASES = [("spd300", lambda: _spd(300, 1), 40),
+         ("arrow3000", lambda: _arrow(3000), 12),  # K short of convergence to rounding
          ("poisson32", lambda: gen.poisson2d(32, 32), 25),
          ("q1_aniso48", lambda: gen.anisotropic_q1(48, 1e-3, np.pi / 4), 60)]
 
@@ -90,7 +104,7 @@ def test_checkpointed_gradient_equals_fully_stored(dtype):
 def test_graph_replays_match_eager():
     A = gen.poisson2d(40, 40)
     b = gen.normal(A.nrows, 9)
-    K = 30
+    K = 31  # five captured 6-step segments and one eager step
     Ad = sp.CsrTensor.from_host(A, dtype=torch.float32)
     bd = to_dev(b, torch.float32)
     sol_e = cgmod._Solver(Ad.pattern, Ad.vals, bd)
