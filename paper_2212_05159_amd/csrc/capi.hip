@@ -30,19 +30,43 @@ __global__ __launch_bounds__(256) void k_validate(int m, int n, int nnz,
   if (!ok) atomicMin(bad, i);
 }
 
-// stats[0] longest row, [1] max |col - row|, [2] non-empty rows.
+// stats[0] longest row, [1] max |col - row|, [2] non-empty rows.  Each
+// block strides over rows, reduces its wave results in LDS and applies
+// three atomics, so few atomics meet on the same three addresses.
+constexpr int kStatsBlocksMax = 1024;
+
 __global__ __launch_bounds__(256) void k_stats(int m, const int32_t* __restrict__ rp,
                                                const int32_t* __restrict__ ci,
                                                int32_t* __restrict__ st) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= m) return;
-  const int a = rp[i], b = rp[i + 1];
-  if (b > a) {
-    const int lo = ci[a], hi = ci[b - 1];
-    const int bw = max(abs(lo - i), abs(hi - i));
-    atomicMax(&st[0], b - a);
+  __shared__ int sm[3][256 / kWave];
+  int longest = 0, bw = 0, nonempty = 0;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < m; i += gridDim.x * 256) {
+    const int a = rp[i], b = rp[i + 1];
+    if (b > a) {
+      longest = max(longest, b - a);
+      bw = max(bw, max(abs(ci[a] - i), abs(ci[b - 1] - i)));
+      ++nonempty;
+    }
+  }
+  longest = wave_max(longest);
+  bw = wave_max(bw);
+  nonempty = group_sum_int<kWave>(nonempty);
+  const int w = threadIdx.x / kWave;
+  if (threadIdx.x % kWave == 0) {
+    sm[0][w] = longest;
+    sm[1][w] = bw;
+    sm[2][w] = nonempty;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 1; k < 256 / kWave; ++k) {
+      longest = max(longest, sm[0][k]);
+      bw = max(bw, sm[1][k]);
+      nonempty += sm[2][k];
+    }
+    atomicMax(&st[0], longest);
     atomicMax(&st[1], bw);
-    atomicAdd(&st[2], 1);
+    atomicAdd(&st[2], nonempty);
   }
 }
 
@@ -61,8 +85,8 @@ extern "C" int csr_pattern_stats(const csrad_csr* A, int64_t* stats_host, void* 
   int32_t* st = static_cast<int32_t*>(work);
   CSRAD_TRY(fill_i32(st, 4, 0, s));
   if (A->nrows > 0)
-    hipLaunchKernelGGL(k_stats, dim3((A->nrows + 255) / 256), dim3(256), 0, s, A->nrows, A->rowptr,
-                       A->colind, st);
+    hipLaunchKernelGGL(k_stats, dim3(std::min((A->nrows + 255) / 256, kStatsBlocksMax)), dim3(256),
+                       0, s, A->nrows, A->rowptr, A->colind, st);
   CSRAD_TRY(launch_status());
   int32_t h[4];
   if (hipMemcpyAsync(h, st, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess) return CSRAD_EHIP;

@@ -16,7 +16,11 @@ constexpr int kXcds = 8;
 // XCD-aware block order.  The dispatcher hands workgroup b to XCD b % 8.
 // Renumbering so that each XCD receives one contiguous range of logical
 // blocks keeps neighbouring rows (and the dense rows they gather) in the
-// same XCD's L2.  Bijective on [0, nblocks).
+// same XCD's L2.  Bijective on [0, nblocks).  The SpMV and SpMM kernels do
+// not use it: in dispatch order the eight XCDs sweep one window of rows
+// together, so HBM sees one sweep instead of eight and the shared Infinity
+// Cache serves the dense rows that several XCDs gather (measured 7-11%
+// faster on the 3D Poisson workload).
 // ---------------------------------------------------------------------
 __device__ __forceinline__ int xcd_block(int b, int nblocks) {
   const int per = nblocks / kXcds, rem = nblocks % kXcds;

@@ -43,7 +43,7 @@ __global__ __launch_bounds__(kThreads) void k_spmm_fwd(RowOrder ord, int k,
                                                       const T* __restrict__ B, long long ldb,
                                                       T* __restrict__ C, long long ldc) {
   constexpr int RPB = kThreads / LPR;
-  const int b = xcd_block(blockIdx.x, gridDim.x);
+  const int b = blockIdx.x;
   const int row = order_row(ord, b, RPB, threadIdx.x / LPR);
   const int l = threadIdx.x % LPR;
   if (row < 0) return;
@@ -90,7 +90,7 @@ __global__ __launch_bounds__(kThreads) void k_spmm_bwd_t(
     long long ldb, const T* __restrict__ G, long long ldg, T* __restrict__ gB, long long ldgb,
     T* __restrict__ gv) {
   constexpr int RPB = kThreads / LPR;
-  const int b = xcd_block(blockIdx.x, gridDim.x);
+  const int b = blockIdx.x;
   const int j = order_row(ord, b, RPB, threadIdx.x / LPR);
   const int l = threadIdx.x % LPR;
   if (j < 0) return;  // whole group leaves together
@@ -185,7 +185,7 @@ __global__ __launch_bounds__(kThreads) void k_spmm_fwd_coop(RowOrder ord, int k,
                                                            T* __restrict__ C, long long ldc) {
   static_assert(LPR >= 16, "cooperative path needs whole DPP rows");
   constexpr int RPB = kThreads / LPR;
-  const int b = xcd_block(blockIdx.x, gridDim.x);
+  const int b = blockIdx.x;
   const int row = order_row(ord, b, RPB, threadIdx.x / LPR);
   const int l = threadIdx.x % LPR, lr = threadIdx.x % 16;
   if (row < 0) return;  // whole group leaves together
@@ -233,7 +233,7 @@ __global__ __launch_bounds__(kThreads) void k_spmm_bwd_coop(
     T* __restrict__ gv) {
   static_assert(LPR >= 16, "cooperative path needs whole DPP rows");
   constexpr int RPB = kThreads / LPR;
-  const int b = xcd_block(blockIdx.x, gridDim.x);
+  const int b = blockIdx.x;
   const int j = order_row(ord, b, RPB, threadIdx.x / LPR);
   const int l = threadIdx.x % LPR, lr = threadIdx.x % 16;
   if (j < 0) return;  // whole group leaves together
@@ -299,7 +299,7 @@ __global__ __launch_bounds__(kThreads) void k_sddmm_rows(
     const T* __restrict__ B, long long ldb, const T* __restrict__ G, long long ldg,
     T* __restrict__ gv) {
   constexpr int RPB = kThreads / LPR;
-  const int b = xcd_block(blockIdx.x, gridDim.x);
+  const int b = blockIdx.x;
   const int i = order_row(ord, b, RPB, threadIdx.x / LPR);
   const int l = threadIdx.x % LPR;
   if (i < 0) return;

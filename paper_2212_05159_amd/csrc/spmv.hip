@@ -22,7 +22,7 @@ __global__ __launch_bounds__(kThreads) void k_spmv(int m, const int32_t* __restr
                                                   const int32_t* __restrict__ colind,
                                                   const T* __restrict__ vals,
                                                   const T* __restrict__ x, T* __restrict__ y) {
-  const int b = xcd_block(blockIdx.x, gridDim.x);
+  const int b = blockIdx.x;
   const int row = b * (kThreads / G) + threadIdx.x / G;
   const int sub = threadIdx.x % G;
   T s = 0;
@@ -42,7 +42,7 @@ __global__ __launch_bounds__(ROWS) void k_spmv_stream(int m, const int32_t* __re
                                                       const T* __restrict__ vals,
                                                       const T* __restrict__ x, T* __restrict__ y) {
   __shared__ T prod[CAP];
-  const int r0 = xcd_block(blockIdx.x, gridDim.x) * ROWS;
+  const int r0 = blockIdx.x * ROWS;
   if (r0 >= m) return;
   const int r1 = min(r0 + ROWS, m);
   const int e0 = rowptr[r0], cnt = rowptr[r1] - e0;
@@ -84,7 +84,7 @@ __global__ __launch_bounds__(kThreads) void k_spmv_bwd_gather(
     int n, const int32_t* __restrict__ rpT, const int32_t* __restrict__ ciT,
     const int32_t* __restrict__ perm, const T* __restrict__ vals, const T* __restrict__ x,
     const T* __restrict__ gy, T* __restrict__ gx, T* __restrict__ gv) {
-  const int b = xcd_block(blockIdx.x, gridDim.x);
+  const int b = blockIdx.x;
   const int j = b * (kThreads / G) + threadIdx.x / G;
   const int sub = threadIdx.x % G;
   T s = 0;
@@ -112,7 +112,7 @@ __global__ __launch_bounds__(kThreads) void k_spmv_bwd_rows(
     int m, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colind,
     const T* __restrict__ vals, const T* __restrict__ x, const T* __restrict__ gy,
     T* __restrict__ gx, T* __restrict__ gv) {
-  const int b = xcd_block(blockIdx.x, gridDim.x);
+  const int b = blockIdx.x;
   const int row = b * (kThreads / G) + threadIdx.x / G;
   const int sub = threadIdx.x % G;
   if (row >= m) return;

@@ -183,6 +183,21 @@ def test_autotuner_picks_a_valid_plan():
                  torch.float32, "C tuned")
 
 
+@pytest.mark.parametrize("m", [1, 1000, 300_001])
+def test_pattern_stats_match_host(m):
+    # 300_001 rows: more rows than the stats kernel's capped grid covers in
+    # one sweep, so blocks stride; a fifth of the rows are empty
+    rng = np.random.default_rng(91)
+    k = np.where(rng.random(m) < 0.2, 0, rng.integers(1, 10, m))
+    r = np.repeat(np.arange(m), k)
+    A = gen._from_coo(m, m, r, rng.integers(0, m, r.size), np.ones(r.size))
+    lens = np.diff(A.rowptr)
+    rows = A.row_of_entry()
+    want = (int(lens.max(initial=0)), int(np.abs(A.colind - rows).max(initial=0)),
+            int((lens > 0).sum()), A.nnz)
+    assert tuple(sp.Pattern.from_host(A).stats()) == want
+
+
 # ---------------------------------------------------------------- transpose
 def _with_long_columns():
     # columns of length ~50 (workgroup sort) and 9000 (chunked sort)
