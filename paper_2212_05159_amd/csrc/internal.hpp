@@ -8,10 +8,11 @@ namespace csrad {
 
 // Exclusive prefix sum of n int32 counts: out[0] = 0, out[i+1] =
 // in[0] + ... + in[i] (n+1 outputs).  The exact 64-bit total goes to
-// *total_dev; out[] is only meaningful when the total fits int32.
+// *total_dev; out[] is only meaningful when the total fits int32.  With
+// skip non-null, the kernels do nothing when *skip (device) is non-zero.
 size_t scan_workspace(int n);
 int scan_exclusive(const int32_t* in, int32_t* out, int n, long long* total_dev,
-                   void* work, size_t bytes, hipStream_t s);
+                   void* work, size_t bytes, hipStream_t s, const int32_t* skip = nullptr);
 
 // Stable transpose of a CSR pattern (see csr_transpose).
 size_t transpose_workspace(int m, int n, int nnz);

@@ -1,6 +1,7 @@
-// Device-wide exclusive prefix sum of int32 counts (three passes: tile
-// sums, a single-block scan of the tile sums, tile-local scans with the
-// tile offset) and small fill helpers.  Used for transpose row pointers,
+// Device-wide exclusive prefix sum of int32 counts (tile sums, then
+// tile-local scans with the tile offset; with up to kFusedTiles tiles every
+// tile adds up the sums before it itself, otherwise one block scans the tile
+// sums in between) and small fill helpers.  Used for transpose row pointers,
 // SpGEMM row pointers and level pointers.
 #include "internal.hpp"
 
@@ -10,6 +11,7 @@ namespace {
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 8;
 constexpr int kScanTile = kScanThreads * kScanItems;
+constexpr int kFusedTiles = 2048;
 
 // Inclusive block scan of one value per thread (256 threads = 4 waves).
 template <typename T>
@@ -34,8 +36,10 @@ __device__ T block_inclusive_scan(T v, T* smem /* >= 4 */, T* total) {
 }
 
 __global__ __launch_bounds__(kScanThreads) void k_tile_sums(const int32_t* __restrict__ in, int n,
-                                                            long long* __restrict__ part) {
+                                                            long long* __restrict__ part,
+                                                            const int32_t* __restrict__ skip) {
   __shared__ long long sm[4];
+  if (skip && *skip) return;
   const long long base = (long long)blockIdx.x * kScanTile;
   long long s = 0;
 #pragma unroll
@@ -50,8 +54,10 @@ __global__ __launch_bounds__(kScanThreads) void k_tile_sums(const int32_t* __res
 
 // One block scans the tile sums in place (exclusive) and writes the total.
 __global__ __launch_bounds__(kScanThreads) void k_scan_tiles(long long* __restrict__ part, int ntiles,
-                                                             long long* __restrict__ total) {
+                                                             long long* __restrict__ total,
+                                                             const int32_t* __restrict__ skip) {
   __shared__ long long sm[4];
+  if (skip && *skip) return;
   long long carry = 0;
   for (int base = 0; base < ntiles; base += kScanThreads) {
     const int i = base + threadIdx.x;
@@ -67,8 +73,10 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_tiles(long long* __restri
 __global__ __launch_bounds__(kScanThreads) void k_tile_scan(const int32_t* __restrict__ in, int n,
                                                             const long long* __restrict__ part,
                                                             const long long* __restrict__ total,
-                                                            int32_t* __restrict__ out) {
+                                                            int32_t* __restrict__ out,
+                                                            const int32_t* __restrict__ skip) {
   __shared__ long long sm[4];
+  if (skip && *skip) return;
   const long long base = (long long)blockIdx.x * kScanTile + (long long)threadIdx.x * kScanItems;
   long long v[kScanItems];
   long long s = 0;
@@ -88,6 +96,47 @@ __global__ __launch_bounds__(kScanThreads) void k_tile_scan(const int32_t* __res
     run += v[t];
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = (int32_t)*total;
+}
+
+// Tile-local scan whose offset this block forms itself from the sums of the
+// tiles before it (fixed order, exact in 64 bits); the last tile writes the
+// total and out[n].
+__global__ __launch_bounds__(kScanThreads) void k_tile_scan_fused(const int32_t* __restrict__ in,
+                                                                  int n,
+                                                                  const long long* __restrict__ part,
+                                                                  int ntiles,
+                                                                  long long* __restrict__ total,
+                                                                  int32_t* __restrict__ out,
+                                                                  const int32_t* __restrict__ skip) {
+  __shared__ long long sm[4];
+  if (skip && *skip) return;
+  long long before = 0;
+  for (int t = threadIdx.x; t < (int)blockIdx.x; t += kScanThreads) before += part[t];
+  long long pre_tot;
+  block_inclusive_scan<long long>(before, sm, &pre_tot);  // pre_tot: sum of earlier tiles
+  __syncthreads();  // sm is reused below
+  const long long base = (long long)blockIdx.x * kScanTile + (long long)threadIdx.x * kScanItems;
+  long long v[kScanItems];
+  long long s = 0;
+#pragma unroll
+  for (int t = 0; t < kScanItems; ++t) {
+    long long i = base + t;
+    v[t] = i < n ? in[i] : 0;
+    s += v[t];
+  }
+  long long tot;
+  long long inc = block_inclusive_scan<long long>(s, sm, &tot);
+  long long run = pre_tot + inc - s;
+#pragma unroll
+  for (int t = 0; t < kScanItems; ++t) {
+    long long i = base + t;
+    if (i < n) out[i] = (int32_t)run;
+    run += v[t];
+  }
+  if ((int)blockIdx.x == ntiles - 1 && threadIdx.x == 0) {
+    *total = pre_tot + tot;
+    out[n] = (int32_t)(pre_tot + tot);
+  }
 }
 
 __global__ void k_fill_i32(int32_t* p, long long n, int32_t value) {
@@ -110,17 +159,23 @@ size_t scan_workspace(int n) {
 }
 
 int scan_exclusive(const int32_t* in, int32_t* out, int n, long long* total_dev, void* work,
-                   size_t bytes, hipStream_t s) {
+                   size_t bytes, hipStream_t s, const int32_t* skip) {
   if (n < 0) return CSRAD_EINVAL;
   const int ntiles = (n + kScanTile - 1) / kScanTile;
   if (bytes < scan_workspace(n) || !work) return CSRAD_EWORKSPACE;
   long long* part = reinterpret_cast<long long*>(work);
   if (ntiles > 0) {
-    hipLaunchKernelGGL(k_tile_sums, dim3(ntiles), dim3(kScanThreads), 0, s, in, n, part);
+    hipLaunchKernelGGL(k_tile_sums, dim3(ntiles), dim3(kScanThreads), 0, s, in, n, part, skip);
   }
-  hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(kScanThreads), 0, s, part, ntiles, total_dev);
+  if (ntiles > 0 && ntiles <= kFusedTiles) {
+    hipLaunchKernelGGL(k_tile_scan_fused, dim3(ntiles), dim3(kScanThreads), 0, s, in, n, part,
+                       ntiles, total_dev, out, skip);
+    return launch_status();
+  }
+  hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(kScanThreads), 0, s, part, ntiles, total_dev,
+                     skip);
   hipLaunchKernelGGL(k_tile_scan, dim3(ntiles > 0 ? ntiles : 1), dim3(kScanThreads), 0, s, in, n,
-                     part, total_dev, out);
+                     part, total_dev, out, skip);
   return launch_status();
 }
 

@@ -36,12 +36,76 @@ __device__ __forceinline__ int mirror_pos(const int32_t* __restrict__ rowptr,
   return a < hi && colind[a] == i ? a : -1;
 }
 
+// Column-sorted patterns: when the column indices never decrease over the
+// entry array (across row boundaries too, e.g. an aggregation operator whose
+// aggregates are contiguous, or its transpose), entry order is already
+// column-major order.  The transpose's entries are then the entries in
+// their own order: perm is the identity, colindT[e] is the row of e, and
+// rowptrT[j] is the first entry with column >= j.  k_mono_probe: each block
+// checks its contiguous share of the entries 256 at a time and stops (after
+// clearing *mono) at the first slice holding a decrease; blocks that start
+// after a clear return at once.  Unsorted patterns therefore cost about one
+// slice per block.
+__global__ __launch_bounds__(256) void k_mono_probe(int nnz, const int32_t* __restrict__ colind,
+                                                    int32_t* __restrict__ mono) {
+  if (*mono == 0) return;
+  const long long per = ((long long)nnz + gridDim.x - 1) / gridDim.x;
+  const long long a = (long long)blockIdx.x * per, b = min((long long)nnz, a + per);
+  for (long long base = a; base < b; base += 256) {
+    const long long e = base + threadIdx.x;
+    const bool down = e >= 1 && e < b && colind[e - 1] > colind[e];
+    if (__syncthreads_or(down)) {
+      if (threadIdx.x == 0) *mono = 0;
+      return;
+    }
+  }
+}
+
+// rowptrT for a column-sorted pattern: entry e (0 <= e <= nnz, e = nnz
+// standing for the end) owns the columns j with colind[e-1] < j <= colind[e]
+// (0 <= j and j <= n at the ends) and writes rowptrT[j] = e; every j in
+// [0, n] is owned by exactly one e.
+__global__ __launch_bounds__(256) void k_mono_rowptr(int nnz, int n,
+                                                     const int32_t* __restrict__ colind,
+                                                     int32_t* __restrict__ rowptrT,
+                                                     const int32_t* __restrict__ mono) {
+  if (*mono == 0) return;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e <= nnz;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int lo = e == 0 ? 0 : colind[e - 1] + 1;
+    const int hi = e == nnz ? n : colind[e];
+    for (int j = lo; j <= hi; ++j) rowptrT[j] = (int32_t)e;
+  }
+}
+
+// colindT and perm for a column-sorted pattern; G lanes per row (G from the
+// mean row length).
+template <int G>
+__global__ __launch_bounds__(256) void k_mono_fill(int m, const int32_t* __restrict__ rowptr,
+                                                   int32_t* __restrict__ colindT,
+                                                   int32_t* __restrict__ perm,
+                                                   const int32_t* __restrict__ mono) {
+  if (*mono == 0) return;
+  for (long long i = (long long)blockIdx.x * (256 / G) + threadIdx.x / G; i < m;
+       i += (long long)gridDim.x * (256 / G)) {
+    for (int e = rowptr[i] + threadIdx.x % G; e < rowptr[i + 1]; e += G) {
+      colindT[e] = (int32_t)i;
+      perm[e] = e;
+    }
+  }
+}
+
 // Cheap first look: one block checks 256 rows spread over the pattern and
 // clears *sym on a missing mirror, so that clearly unsymmetric patterns
 // (e.g. triangular ones) skip the full pass.
 __global__ __launch_bounds__(256) void k_sym_probe(int n, const int32_t* __restrict__ rowptr,
                                                    const int32_t* __restrict__ colind,
-                                                   int32_t* __restrict__ sym) {
+                                                   int32_t* __restrict__ sym,
+                                                   const int32_t* __restrict__ mono) {
+  if (*mono) {  // the column-sorted path covers it
+    if (threadIdx.x == 0) *sym = 0;
+    return;
+  }
   const int i = (int)(((long long)threadIdx.x * n) / 256 + (n > 256 ? 128 % (n / 256) : 0));
   if (i >= n || (n <= 256 && (int)threadIdx.x >= n)) return;
   for (int e = rowptr[i]; e < rowptr[i + 1]; ++e)
@@ -74,8 +138,10 @@ __global__ __launch_bounds__(256) void k_sym_perm(int n, const int32_t* __restri
 __global__ __launch_bounds__(256) void k_count_cols(const int32_t* __restrict__ rowptr, int n,
                                                     const int32_t* __restrict__ colind, int nnz,
                                                     const int32_t* __restrict__ sym,
+                                                    const int32_t* __restrict__ mono,
                                                     int32_t* __restrict__ cnt) {
   const long long stride = (long long)gridDim.x * blockDim.x;
+  if (*mono) return;
   if (*sym) {
     for (long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += stride)
       cnt[j] = rowptr[j + 1] - rowptr[j];
@@ -85,8 +151,18 @@ __global__ __launch_bounds__(256) void k_count_cols(const int32_t* __restrict__ 
     wave_agg_add(cnt, colind[e]);
 }
 
+__global__ void k_set3(int32_t* __restrict__ p, int32_t a, int32_t b, int32_t c) {
+  if (threadIdx.x == 0) {
+    p[0] = a;
+    p[1] = b;
+    p[2] = c;
+  }
+}
+
 __global__ __launch_bounds__(256) void k_copy_i32(const int32_t* __restrict__ src, int n,
-                                                  int32_t* __restrict__ dst) {
+                                                  int32_t* __restrict__ dst,
+                                                  const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x)
     dst[i] = src[i];
@@ -98,10 +174,11 @@ __global__ __launch_bounds__(256) void k_scatter(int m, const int32_t* __restric
                                                  int32_t* __restrict__ cursor,
                                                  int32_t* __restrict__ tkey,
                                                  int32_t* __restrict__ tval,
-                                                 const int32_t* __restrict__ sym) {
+                                                 const int32_t* __restrict__ sym,
+                                                 const int32_t* __restrict__ mono) {
   const int row = blockIdx.x * (256 / 8) + threadIdx.x / 8;
   const int sub = threadIdx.x % 8;
-  if (row >= m || *sym) return;
+  if (row >= m || *sym || *mono) return;
   const int e1 = rowptr[row + 1];
   for (int e = rowptr[row] + sub; e < e1; e += 8) {
     const int slot = wave_agg_add(cursor, colind[e]);
@@ -123,10 +200,11 @@ __global__ __launch_bounds__(256) void k_sort_short(int n, const int32_t* __rest
                                                     int32_t* __restrict__ long_list,
                                                     int32_t* __restrict__ long_count,
                                                     const int32_t* __restrict__ colind,
-                                                    const int32_t* __restrict__ sym) {
+                                                    const int32_t* __restrict__ sym,
+                                                    const int32_t* __restrict__ mono) {
   const int c = blockIdx.x * (256 / G) + threadIdx.x / G;
   const int l = threadIdx.x % G;
-  if (c >= n) return;
+  if (c >= n || *mono) return;
   const int s = rpT[c], len = rpT[c + 1] - s;
   if (*sym) {  // the transpose pattern is the pattern; perm is written
     for (int q = l; q < len; q += G) okey[s + q] = colind[s + q];
@@ -360,8 +438,10 @@ struct TransposeWs {
   int32_t* tkey;
   int32_t* tval;
   int32_t* long_list;
+  int32_t* flags;  // [0] long-column count, [1] symmetric path on, [2] column-sorted path on
   int32_t* long_count;
   int32_t* sym;
+  int32_t* mono;
 };
 
 TransposeWs carve_transpose(Carver& cv, int n, int nnz) {
@@ -373,8 +453,10 @@ TransposeWs carve_transpose(Carver& cv, int n, int nnz) {
   w.tkey = cv.take<int32_t>((size_t)nnz);
   w.tval = cv.take<int32_t>((size_t)nnz);
   w.long_list = cv.take<int32_t>((size_t)n + 1);
-  w.long_count = cv.take<int32_t>(1);
-  w.sym = cv.take<int32_t>(1);
+  w.flags = cv.take<int32_t>(3);
+  w.long_count = w.flags;
+  w.sym = w.flags + 1;
+  w.mono = w.flags + 2;
   return w;
 }
 
@@ -410,23 +492,47 @@ int transpose_pattern(int m, int n, int nnz, const int32_t* rowptr, const int32_
   TransposeWs w = carve_transpose(cv, n, nnz);
   if (!work || !cv.ok) return CSRAD_EWORKSPACE;
   CSRAD_TRY(fill_i32(w.cnt, (long long)n + 1, 0, s));
-  CSRAD_TRY(fill_i32(w.long_count, 1, 0, s));
-  CSRAD_TRY(fill_i32(w.sym, 1, (m == n && nnz > 0) ? 1 : 0, s));
+  hipLaunchKernelGGL(k_set3, dim3(1), dim3(64), 0, s, w.flags, 0, (m == n && nnz > 0) ? 1 : 0,
+                     nnz > 0 ? 1 : 0);
+  if (nnz > 0) {
+    hipLaunchKernelGGL(k_mono_probe, dim3(grid_for(nnz, 256, 2048)), dim3(256), 0, s, nnz, colind,
+                       w.mono);
+    hipLaunchKernelGGL(k_mono_rowptr, dim3(grid_for((long long)nnz + 1, 256, 2048)), dim3(256), 0,
+                       s, nnz, n, colind, rowptrT, w.mono);
+    if (m > 0) {
+      int g = 1;
+      while (g < 32 && (long long)g * m < nnz) g <<= 1;
+      const unsigned grid = grid_for((long long)m * g, 256, 4096);
+      switch (g) {
+#define CSRAD_MONO_FILL(G)                                                                       \
+  hipLaunchKernelGGL((k_mono_fill<G>), dim3(grid), dim3(256), 0, s, m, rowptr, colindT, perm, \
+                     w.mono)
+        case 1: CSRAD_MONO_FILL(1); break;
+        case 2: CSRAD_MONO_FILL(2); break;
+        case 4: CSRAD_MONO_FILL(4); break;
+        case 8: CSRAD_MONO_FILL(8); break;
+        case 16: CSRAD_MONO_FILL(16); break;
+        default: CSRAD_MONO_FILL(32); break;
+#undef CSRAD_MONO_FILL
+      }
+    }
+  }
   if (m == n && nnz > 0) {
-    hipLaunchKernelGGL(k_sym_probe, dim3(1), dim3(256), 0, s, m, rowptr, colind, w.sym);
+    hipLaunchKernelGGL(k_sym_probe, dim3(1), dim3(256), 0, s, m, rowptr, colind, w.sym, w.mono);
     hipLaunchKernelGGL(k_sym_perm, dim3((m + 31) / 32), dim3(256), 0, s, m, rowptr, colind, perm,
                        w.sym);
   }
   if (nnz > 0)
-    hipLaunchKernelGGL(k_count_cols, dim3(grid_for(nnz, 256)), dim3(256), 0, s, rowptr, n,
-                       colind, nnz, w.sym, w.cnt);
-  CSRAD_TRY(scan_exclusive(w.cnt, rowptrT, n, w.total, w.scan_ws, w.scan_bytes, s));
+    hipLaunchKernelGGL(k_count_cols, dim3(grid_for(nnz, 256, 8192)), dim3(256), 0, s, rowptr, n,
+                       colind, nnz, w.sym, w.mono, w.cnt);
+  CSRAD_TRY(scan_exclusive(w.cnt, rowptrT, n, w.total, w.scan_ws, w.scan_bytes, s, w.mono));
   if (nnz == 0) return launch_status();
   if (n > 0)
-    hipLaunchKernelGGL(k_copy_i32, dim3(grid_for(n, 256)), dim3(256), 0, s, rowptrT, n, w.cnt);
+    hipLaunchKernelGGL(k_copy_i32, dim3(grid_for(n, 256)), dim3(256), 0, s, rowptrT, n, w.cnt,
+                       w.mono);
   if (m > 0)
     hipLaunchKernelGGL(k_scatter, dim3((m + 31) / 32), dim3(256), 0, s, m, rowptr, colind, w.cnt,
-                       w.tkey, w.tval, w.sym);
+                       w.tkey, w.tval, w.sym, w.mono);
   {
     // lanes per column from the mean column length (at most kShort)
     int g = 1;
@@ -436,7 +542,7 @@ int transpose_pattern(int m, int n, int nnz, const int32_t* rowptr, const int32_
     switch (g) {
 #define CSRAD_SORT_SHORT(G)                                                                  \
   hipLaunchKernelGGL((k_sort_short<G>), dim3(grid), dim3(256), 0, s, n, rowptrT, w.tkey, w.tval, \
-                     colindT, perm, w.long_list, w.long_count, colind, w.sym)
+                     colindT, perm, w.long_list, w.long_count, colind, w.sym, w.mono)
       case 1: CSRAD_SORT_SHORT(1); break;
       case 2: CSRAD_SORT_SHORT(2); break;
       case 4: CSRAD_SORT_SHORT(4); break;

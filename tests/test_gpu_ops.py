@@ -224,10 +224,36 @@ def _few_cols():
     return gen._from_coo(100000, 3, r, c, rng.standard_normal(len(r)))
 
 
-@pytest.mark.parametrize("name,A", MATS + [("long_cols", _with_long_columns()),
-                                           ("agg", gen.aggregation(10001, 8)),
-                                           ("few_cols", _few_cols())],
-                         ids=[n for n, _ in MATS] + ["long_cols", "agg", "few_cols"])
+def _col_sorted_cases():
+    # column indices never decreasing over the entry array (the column-sorted
+    # path), with empty leading, inner and trailing columns and one column
+    # spanning many rows; and the same with one decrease near the end, which
+    # must take the general path
+    rng = np.random.default_rng(34)
+    m, n = 30000, 9000
+    cols = np.sort(rng.choice(np.arange(5, n - 7), 40000))
+    cols[(cols > 3000) & (cols < 3400)] = 3200
+    rows = np.sort(rng.integers(0, m, cols.size))
+    key = np.unique(rows.astype(np.int64) * n + cols)
+    r, c = key // n, key % n
+    sorted_ = gen._from_coo(m, n, r, c, np.ones(len(r)))
+    assert np.all(np.diff(sorted_.colind) >= 0)
+    c2 = c.copy()
+    c2[-3] = 1
+    broken = gen._from_coo(m, n, r, c2, np.ones(len(r)))
+    agg = gen.aggregation(10001, 8)
+    aggT = gen._from_coo(agg.ncols, agg.nrows, agg.colind, agg.row_of_entry(), agg.vals)
+    one_col = gen._from_coo(5000, 7, np.arange(5000), np.zeros(5000, int), np.ones(5000))
+    eye = gen._from_coo(777, 777, np.arange(777), np.arange(777), np.ones(777))
+    return [("col_sorted", sorted_), ("col_sorted_broken", broken), ("agg_T", aggT),
+            ("one_col", one_col), ("identity", eye)]
+
+
+TRANSPOSE_CASES = MATS + [("long_cols", _with_long_columns()), ("agg", gen.aggregation(10001, 8)),
+                          ("few_cols", _few_cols())] + _col_sorted_cases()
+
+
+@pytest.mark.parametrize("name,A", TRANSPOSE_CASES, ids=[n for n, _ in TRANSPOSE_CASES])
 def test_transpose_bit_exact(name, A):
     P = sp.Pattern.from_host(A)
     Pt, perm = P.transpose()
