@@ -151,3 +151,39 @@ def test_cg_converged_steps_are_identity():
     assert torch.isfinite(Ad.vals.grad).all() and torch.isfinite(bd.grad).all()
     np.testing.assert_allclose(x.detach().cpu().numpy(), np.linalg.solve(A.todense(), b),
                                rtol=1e-10, atol=1e-12)
+
+
+@pytest.mark.parametrize("name,mk", [("poisson760", lambda: gen.poisson2d(760, 760)),
+                                     ("spd_wide", lambda: _spd_banded(600_000, 12))],
+                         ids=["poisson760", "spd_wide"])
+def test_cg_large_grid_strides(name, mk):
+    # more rows than one sweep of the capped grids covers (2048 blocks of
+    # 256 rows): every block of the staged products, the entry pass and the
+    # vector kernels walks several row blocks; spd_wide (about 13 entries per
+    # row) takes the lanes form
+    A = mk()
+    b = gen.normal(A.nrows, 21)
+    t = gen.normal(A.nrows, 22)
+    K = 4
+    Ad = sp.CsrTensor.from_host(A, dtype=torch.float64, requires_grad=True)
+    bd = to_dev(b).requires_grad_(True)
+    x = cgmod.cg_solve(Ad, bd, K)
+    (0.5 * ((x - to_dev(t)) ** 2).sum()).backward()
+    xo = oracle.cg(A, b, K)
+    gvo, gbo = oracle.cg_bwd(A, b, K, gx=x.detach().cpu().numpy() - t)
+    assert rel_err(x, xo) < 1e-11
+    assert rel_err(Ad.vals.grad, gvo) < 1e-9
+    assert rel_err(bd.grad, gbo) < 1e-9
+
+
+def _spd_banded(n, half):
+    # symmetric, diagonally dominant, bandwidth `half`, every row full
+    offs = np.arange(-half // 2, half // 2 + 1)
+    offs = offs[offs != 0]
+    rows, cols, vals = [np.arange(n)], [np.arange(n)], [np.full(n, 2.0 * len(offs))]
+    for o in offs:
+        r = np.arange(max(0, -o), min(n, n - o))
+        rows.append(r)
+        cols.append(r + o)
+        vals.append(np.full(r.size, -1.0 + 0.01 * abs(o)))
+    return gen._from_coo(n, n, np.concatenate(rows), np.concatenate(cols), np.concatenate(vals))
