@@ -62,12 +62,14 @@ def _geometric_block(b):
 
 def geometric_blocks(nblocks):
     """The first `nblocks` host blocks of the batched workload, built by a
-    pool of worker processes (before this process touches the GPU)."""
-    import multiprocessing as mp
+    pool of threads (the k-NN queries and sorts release the GIL).  A pool of
+    worker processes was as fast to build them but left this process with
+    millisecond host stalls in the timed steps afterwards."""
+    import concurrent.futures as cf
 
     t0 = time.perf_counter()
-    with mp.get_context("spawn").Pool(min(16, os.cpu_count() or 1)) as pool:
-        blocks = pool.map(_geometric_block, range(nblocks))
+    with cf.ThreadPoolExecutor(min(16, os.cpu_count() or 1)) as ex:
+        blocks = list(ex.map(_geometric_block, range(nblocks)))
     return blocks, time.perf_counter() - t0
 
 
