@@ -115,47 +115,58 @@ __global__ __launch_bounds__(256) void k_sym_probe(int n, const int32_t* __restr
 // Symmetric try: entry e = (i, j) finds the position of its mirror (j, i)
 // in row j; the transpose's entry at that position is e.  The mirror map is
 // an involution, so perm[e] = mirror position is the same permutation,
-// written in order.  Clears *sym when some entry has no mirror.  8 lanes
-// per row.
+// written in order.  The transpose's pattern is the pattern itself, so
+// rowptrT and colindT are copied on the way.  Clears *sym when some entry
+// has no mirror (the general path then rewrites all three outputs).  8
+// lanes per row.
 __global__ __launch_bounds__(256) void k_sym_perm(int n, const int32_t* __restrict__ rowptr,
                                                   const int32_t* __restrict__ colind,
+                                                  int32_t* __restrict__ rowptrT,
+                                                  int32_t* __restrict__ colindT,
                                                   int32_t* __restrict__ perm,
                                                   int32_t* __restrict__ sym) {
   const int i = blockIdx.x * (256 / 8) + threadIdx.x / 8;
   if (i >= n || *sym == 0) return;
-  for (int e = rowptr[i] + threadIdx.x % 8; e < rowptr[i + 1]; e += 8) {
-    const int pos = mirror_pos(rowptr, colind, colind[e], i);
+  const int e0 = rowptr[i], e1 = rowptr[i + 1];
+  if (threadIdx.x % 8 == 0) {
+    rowptrT[i] = e0;
+    if (i == n - 1) rowptrT[n] = e1;
+  }
+  for (int e = e0 + threadIdx.x % 8; e < e1; e += 8) {
+    const int c = colind[e];
+    const int pos = mirror_pos(rowptr, colind, c, i);
     if (pos < 0) {
       *sym = 0;
       return;
     }
     perm[e] = pos;
+    colindT[e] = c;
   }
 }
 
-// Column counts: the row lengths when the pattern is symmetric, else one
-// (wave-aggregated) atomic per entry.
-__global__ __launch_bounds__(256) void k_count_cols(const int32_t* __restrict__ rowptr, int n,
-                                                    const int32_t* __restrict__ colind, int nnz,
-                                                    const int32_t* __restrict__ sym,
-                                                    const int32_t* __restrict__ mono,
+// flags[3] = flags[1] | flags[2]: one of the two fast paths produced the
+// transpose, and the general kernels have nothing to do.
+__global__ void k_fast_flag(int32_t* __restrict__ flags) {
+  if (threadIdx.x == 0) flags[3] = (flags[1] | flags[2]) != 0;
+}
+
+// Column counts, one (wave-aggregated) atomic per entry; nothing when a fast
+// path made the transpose.
+__global__ __launch_bounds__(256) void k_count_cols(const int32_t* __restrict__ colind, int nnz,
+                                                    const int32_t* __restrict__ fast,
                                                     int32_t* __restrict__ cnt) {
   const long long stride = (long long)gridDim.x * blockDim.x;
-  if (*mono) return;
-  if (*sym) {
-    for (long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += stride)
-      cnt[j] = rowptr[j + 1] - rowptr[j];
-    return;
-  }
+  if (*fast) return;
   for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += stride)
     wave_agg_add(cnt, colind[e]);
 }
 
-__global__ void k_set3(int32_t* __restrict__ p, int32_t a, int32_t b, int32_t c) {
+__global__ void k_set4(int32_t* __restrict__ p, int32_t a, int32_t b, int32_t c, int32_t d) {
   if (threadIdx.x == 0) {
     p[0] = a;
     p[1] = b;
     p[2] = c;
+    p[3] = d;
   }
 }
 
@@ -174,16 +185,16 @@ __global__ __launch_bounds__(256) void k_scatter(int m, const int32_t* __restric
                                                  int32_t* __restrict__ cursor,
                                                  int32_t* __restrict__ tkey,
                                                  int32_t* __restrict__ tval,
-                                                 const int32_t* __restrict__ sym,
-                                                 const int32_t* __restrict__ mono) {
-  const int row = blockIdx.x * (256 / 8) + threadIdx.x / 8;
+                                                 const int32_t* __restrict__ fast) {
+  if (*fast) return;
   const int sub = threadIdx.x % 8;
-  if (row >= m || *sym || *mono) return;
-  const int e1 = rowptr[row + 1];
-  for (int e = rowptr[row] + sub; e < e1; e += 8) {
-    const int slot = wave_agg_add(cursor, colind[e]);
-    tkey[slot] = row;
-    tval[slot] = e;
+  for (int row = blockIdx.x * (256 / 8) + threadIdx.x / 8; row < m; row += gridDim.x * (256 / 8)) {
+    const int e1 = rowptr[row + 1];
+    for (int e = rowptr[row] + sub; e < e1; e += 8) {
+      const int slot = wave_agg_add(cursor, colind[e]);
+      tkey[slot] = row;
+      tval[slot] = e;
+    }
   }
 }
 
@@ -199,27 +210,22 @@ __global__ __launch_bounds__(256) void k_sort_short(int n, const int32_t* __rest
                                                     int32_t* __restrict__ oval,
                                                     int32_t* __restrict__ long_list,
                                                     int32_t* __restrict__ long_count,
-                                                    const int32_t* __restrict__ colind,
-                                                    const int32_t* __restrict__ sym,
-                                                    const int32_t* __restrict__ mono) {
-  const int c = blockIdx.x * (256 / G) + threadIdx.x / G;
+                                                    const int32_t* __restrict__ fast) {
+  if (*fast) return;
   const int l = threadIdx.x % G;
-  if (c >= n || *mono) return;
-  const int s = rpT[c], len = rpT[c + 1] - s;
-  if (*sym) {  // the transpose pattern is the pattern; perm is written
-    for (int q = l; q < len; q += G) okey[s + q] = colind[s + q];
-    return;
-  }
-  if (len <= kShort) {
-    for (int q = l; q < len; q += G) {
-      const int key = tkey[s + q];
-      int r = 0;
-      for (int u = 0; u < len; ++u) r += tkey[s + u] < key;
-      okey[s + r] = key;
-      oval[s + r] = tval[s + q];
+  for (int c = blockIdx.x * (256 / G) + threadIdx.x / G; c < n; c += gridDim.x * (256 / G)) {
+    const int s = rpT[c], len = rpT[c + 1] - s;
+    if (len <= kShort) {
+      for (int q = l; q < len; q += G) {
+        const int key = tkey[s + q];
+        int r = 0;
+        for (int u = 0; u < len; ++u) r += tkey[s + u] < key;
+        okey[s + r] = key;
+        oval[s + r] = tval[s + q];
+      }
+    } else if (l == 0) {
+      long_list[atomicAdd(long_count, 1)] = c;
     }
-  } else if (l == 0) {
-    long_list[atomicAdd(long_count, 1)] = c;
   }
 }
 
@@ -438,10 +444,12 @@ struct TransposeWs {
   int32_t* tkey;
   int32_t* tval;
   int32_t* long_list;
-  int32_t* flags;  // [0] long-column count, [1] symmetric path on, [2] column-sorted path on
+  int32_t* flags;  // [0] long-column count, [1] symmetric path on, [2] column-sorted path on,
+                   // [3] either fast path on
   int32_t* long_count;
   int32_t* sym;
   int32_t* mono;
+  int32_t* fast;
 };
 
 TransposeWs carve_transpose(Carver& cv, int n, int nnz) {
@@ -453,10 +461,11 @@ TransposeWs carve_transpose(Carver& cv, int n, int nnz) {
   w.tkey = cv.take<int32_t>((size_t)nnz);
   w.tval = cv.take<int32_t>((size_t)nnz);
   w.long_list = cv.take<int32_t>((size_t)n + 1);
-  w.flags = cv.take<int32_t>(3);
+  w.flags = cv.take<int32_t>(4);
   w.long_count = w.flags;
   w.sym = w.flags + 1;
   w.mono = w.flags + 2;
+  w.fast = w.flags + 3;
   return w;
 }
 
@@ -492,8 +501,8 @@ int transpose_pattern(int m, int n, int nnz, const int32_t* rowptr, const int32_
   TransposeWs w = carve_transpose(cv, n, nnz);
   if (!work || !cv.ok) return CSRAD_EWORKSPACE;
   CSRAD_TRY(fill_i32(w.cnt, (long long)n + 1, 0, s));
-  hipLaunchKernelGGL(k_set3, dim3(1), dim3(64), 0, s, w.flags, 0, (m == n && nnz > 0) ? 1 : 0,
-                     nnz > 0 ? 1 : 0);
+  hipLaunchKernelGGL(k_set4, dim3(1), dim3(64), 0, s, w.flags, 0, (m == n && nnz > 0) ? 1 : 0,
+                     nnz > 0 ? 1 : 0, 0);
   if (nnz > 0) {
     hipLaunchKernelGGL(k_mono_probe, dim3(grid_for(nnz, 256, 2048)), dim3(256), 0, s, nnz, colind,
                        w.mono);
@@ -519,30 +528,33 @@ int transpose_pattern(int m, int n, int nnz, const int32_t* rowptr, const int32_
   }
   if (m == n && nnz > 0) {
     hipLaunchKernelGGL(k_sym_probe, dim3(1), dim3(256), 0, s, m, rowptr, colind, w.sym, w.mono);
-    hipLaunchKernelGGL(k_sym_perm, dim3((m + 31) / 32), dim3(256), 0, s, m, rowptr, colind, perm,
-                       w.sym);
+    hipLaunchKernelGGL(k_sym_perm, dim3((m + 31) / 32), dim3(256), 0, s, m, rowptr, colind,
+                       rowptrT, colindT, perm, w.sym);
   }
-  if (nnz > 0)
-    hipLaunchKernelGGL(k_count_cols, dim3(grid_for(nnz, 256, 8192)), dim3(256), 0, s, rowptr, n,
-                       colind, nnz, w.sym, w.mono, w.cnt);
-  CSRAD_TRY(scan_exclusive(w.cnt, rowptrT, n, w.total, w.scan_ws, w.scan_bytes, s, w.mono));
+  if (nnz > 0) {
+    hipLaunchKernelGGL(k_fast_flag, dim3(1), dim3(64), 0, s, w.flags);
+    hipLaunchKernelGGL(k_count_cols, dim3(grid_for(nnz, 256, 8192)), dim3(256), 0, s, colind, nnz,
+                       w.fast, w.cnt);
+  }
+  CSRAD_TRY(scan_exclusive(w.cnt, rowptrT, n, w.total, w.scan_ws, w.scan_bytes, s, w.fast));
   if (nnz == 0) return launch_status();
   if (n > 0)
-    hipLaunchKernelGGL(k_copy_i32, dim3(grid_for(n, 256)), dim3(256), 0, s, rowptrT, n, w.cnt,
-                       w.mono);
+    hipLaunchKernelGGL(k_copy_i32, dim3(grid_for(n, 256, 2048)), dim3(256), 0, s, rowptrT, n,
+                       w.cnt, w.fast);
+  // gated kernels take capped grids with grid-stride loops, so that they
+  // cost little when a fast path has made the transpose
   if (m > 0)
-    hipLaunchKernelGGL(k_scatter, dim3((m + 31) / 32), dim3(256), 0, s, m, rowptr, colind, w.cnt,
-                       w.tkey, w.tval, w.sym, w.mono);
+    hipLaunchKernelGGL(k_scatter, dim3(grid_for((long long)m * 8, 256, 8192)), dim3(256), 0, s, m,
+                       rowptr, colind, w.cnt, w.tkey, w.tval, w.fast);
   {
     // lanes per column from the mean column length (at most kShort)
     int g = 1;
     while (g < kShort && (long long)g * n < nnz) g <<= 1;
-    const long long cpb = 256 / g;
-    const unsigned grid = (unsigned)((n + cpb - 1) / cpb);
+    const unsigned grid = grid_for((long long)n * g, 256, 8192);
     switch (g) {
 #define CSRAD_SORT_SHORT(G)                                                                  \
   hipLaunchKernelGGL((k_sort_short<G>), dim3(grid), dim3(256), 0, s, n, rowptrT, w.tkey, w.tval, \
-                     colindT, perm, w.long_list, w.long_count, colind, w.sym, w.mono)
+                     colindT, perm, w.long_list, w.long_count, w.fast)
       case 1: CSRAD_SORT_SHORT(1); break;
       case 2: CSRAD_SORT_SHORT(2); break;
       case 4: CSRAD_SORT_SHORT(4); break;
