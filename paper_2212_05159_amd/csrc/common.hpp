@@ -176,6 +176,25 @@ __device__ __forceinline__ int wave_agg_add(int32_t* counter, int key) {
   return slot;
 }
 
+// Wave-aggregated count: like wave_agg_add, but nothing is returned, so
+// the atomics need not be waited for (non-returning atomics issue and go)
+// and the aggregation rounds are only ballots and shuffles.
+__device__ __forceinline__ void wave_agg_count(int32_t* counter, int key) {
+  unsigned long long todo = __ballot(1);
+  bool done = false;
+#pragma unroll
+  for (int r = 0; r < kAggRounds; ++r) {
+    if (!todo) break;
+    const int leader = __ffsll((long long)todo) - 1;
+    const int lkey = __shfl(key, leader);
+    const unsigned long long peers = __ballot(!done && key == lkey) & todo;
+    if (__lane_id() == leader) atomicAdd(&counter[lkey], __popcll(peers));
+    if ((peers >> __lane_id()) & 1ull) done = true;
+    todo &= ~peers;
+  }
+  if (!done) atomicAdd(&counter[key], 1);
+}
+
 // Wave-aggregated append to one counter: the lanes with pred set take
 // consecutive slots (in lane order) from a single atomicAdd by the first
 // of them.  Every lane of the wave must reach the call.  Returns the slot

@@ -158,7 +158,7 @@ __global__ __launch_bounds__(256) void k_count_cols(const int32_t* __restrict__ 
   const long long stride = (long long)gridDim.x * blockDim.x;
   if (*fast) return;
   for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += stride)
-    wave_agg_add(cnt, colind[e]);
+    wave_agg_count(cnt, colind[e]);
 }
 
 __global__ void k_set4(int32_t* __restrict__ p, int32_t a, int32_t b, int32_t c, int32_t d) {
@@ -179,7 +179,9 @@ __global__ __launch_bounds__(256) void k_copy_i32(const int32_t* __restrict__ sr
     dst[i] = src[i];
 }
 
-// 8 lanes per row: lanes stride over the row's entries.
+// G lanes per row (G from the mean row length): lanes stride over the row's
+// entries.
+template <int G>
 __global__ __launch_bounds__(256) void k_scatter(int m, const int32_t* __restrict__ rowptr,
                                                  const int32_t* __restrict__ colind,
                                                  int32_t* __restrict__ cursor,
@@ -187,10 +189,10 @@ __global__ __launch_bounds__(256) void k_scatter(int m, const int32_t* __restric
                                                  int32_t* __restrict__ tval,
                                                  const int32_t* __restrict__ fast) {
   if (*fast) return;
-  const int sub = threadIdx.x % 8;
-  for (int row = blockIdx.x * (256 / 8) + threadIdx.x / 8; row < m; row += gridDim.x * (256 / 8)) {
+  const int sub = threadIdx.x % G;
+  for (int row = blockIdx.x * (256 / G) + threadIdx.x / G; row < m; row += gridDim.x * (256 / G)) {
     const int e1 = rowptr[row + 1];
-    for (int e = rowptr[row] + sub; e < e1; e += 8) {
+    for (int e = rowptr[row] + sub; e < e1; e += G) {
       const int slot = wave_agg_add(cursor, colind[e]);
       tkey[slot] = row;
       tval[slot] = e;
@@ -543,9 +545,21 @@ int transpose_pattern(int m, int n, int nnz, const int32_t* rowptr, const int32_
                        w.cnt, w.fast);
   // gated kernels take capped grids with grid-stride loops, so that they
   // cost little when a fast path has made the transpose
-  if (m > 0)
-    hipLaunchKernelGGL(k_scatter, dim3(grid_for((long long)m * 8, 256, 8192)), dim3(256), 0, s, m,
-                       rowptr, colind, w.cnt, w.tkey, w.tval, w.fast);
+  if (m > 0) {
+    int g = 1;
+    while (g < 8 && (long long)g * m < nnz) g <<= 1;
+    const unsigned grid = grid_for((long long)m * g, 256, 8192);
+    switch (g) {
+#define CSRAD_SCATTER(G)                                                                     \
+  hipLaunchKernelGGL((k_scatter<G>), dim3(grid), dim3(256), 0, s, m, rowptr, colind, w.cnt, \
+                     w.tkey, w.tval, w.fast)
+      case 1: CSRAD_SCATTER(1); break;
+      case 2: CSRAD_SCATTER(2); break;
+      case 4: CSRAD_SCATTER(4); break;
+      default: CSRAD_SCATTER(8); break;
+#undef CSRAD_SCATTER
+    }
+  }
   {
     // lanes per column from the mean column length (at most kShort)
     int g = 1;
