@@ -167,8 +167,10 @@ int csr_spgemm_bwd(const csrad_csr *A, const csrad_csr *B,
  *   row that reads no other row is on level 0; otherwise it is one above
  *   the highest level among the rows it reads.  Writes level_of_row[n],
  *   level_ptr[nlevels+1], level_rows[n] (rows ascending within a level)
- *   and *nlevels_host (synchronises).  Tt is the pattern of T^T
- *   (csr_transpose).  Returns CSRAD_ESINGULAR if a diagonal is missing.
+ *   and *nlevels_host (synchronises); level_ptr_host (host memory for
+ *   n+1 entries, may be NULL) receives level_ptr's nlevels+1 entries in
+ *   the same synchronisation.  Tt is the pattern of T^T (csr_transpose).
+ *   Returns CSRAD_ESINGULAR if a diagonal is missing.
  * csr_trisolve_fwd: x = T^{-1} b, level by level.  level_ptr (device) and
  *   level_ptr_host (its host copy, nlevels+1 entries) come from
  *   csr_trisolve_analyze; the host copy schedules the launches (large
@@ -181,8 +183,8 @@ int csr_trisolve_workspace(const csrad_csr *T, size_t *bytes);
 int csr_trisolve_analyze(const csrad_csr *T, int32_t lower,
                          const csrad_csr *Tt, int32_t *level_of_row,
                          int32_t *level_ptr, int32_t *level_rows,
-                         int32_t *nlevels_host, void *work,
-                         size_t work_bytes, void *stream);
+                         int32_t *nlevels_host, int32_t *level_ptr_host,
+                         void *work, size_t work_bytes, void *stream);
 int csr_trisolve_fwd(const csrad_csr *T, int32_t lower, int32_t nlevels,
                      const int32_t *level_ptr_host, const int32_t *level_ptr,
                      const int32_t *level_rows, const void *b, void *x,

@@ -12,6 +12,7 @@ from __future__ import annotations
 import ctypes as C
 import os
 
+import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -56,7 +57,7 @@ _SIGS = {
     "csr_trisolve_workspace": (C.c_int, [C.c_void_p, C.POINTER(C.c_size_t)]),
     "csr_trisolve_analyze": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
                                        C.c_void_p, C.c_void_p, C.POINTER(C.c_int32),
-                                       C.c_void_p, C.c_size_t, C.c_void_p]),
+                                       C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
     "csr_trisolve_fwd": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
                                    C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "csr_trisolve_bwd": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32,
@@ -232,11 +233,19 @@ def csr_trisolve_workspace(T):
     return n.value
 
 
-def csr_trisolve_analyze(T, lower, Tt, level_of_row, level_ptr, level_rows, work):
+def csr_trisolve_analyze(T, lower, Tt, level_of_row, level_ptr, level_rows, work,
+                         level_ptr_host=None):
+    """Returns nlevels; level_ptr_host (int32 ndarray of n+1 entries, or
+    None) receives the level pointers on the host."""
     nl = C.c_int32(0)
+    lph = None
+    if level_ptr_host is not None:
+        assert level_ptr_host.dtype == np.int32 and level_ptr_host.flags.c_contiguous
+        assert level_ptr_host.size >= T.nrows + 1
+        lph = level_ptr_host.ctypes.data_as(C.c_void_p)
     _check("csr_trisolve_analyze", load().csr_trisolve_analyze(
         C.byref(T), int(lower), C.byref(Tt), _ptr(level_of_row), _ptr(level_ptr),
-        _ptr(level_rows), C.byref(nl), _ptr(work), work.numel(), _stream()))
+        _ptr(level_rows), C.byref(nl), lph, _ptr(work), work.numel(), _stream()))
     return nl.value
 
 

@@ -70,6 +70,17 @@ __global__ void k_tri_compact(int n, const int32_t* __restrict__ flag,
     if (flag[i]) front[pos[i]] = i;
 }
 
+// Compaction after a pull round: into the buffer not holding the frontier
+// (state[3] ? fa : fb); nothing once state[4] is set.
+__global__ void k_tri_compact_next(int n, const int32_t* __restrict__ flag,
+                                   const int32_t* __restrict__ pos, int32_t* __restrict__ fa,
+                                   int32_t* __restrict__ fb, const int32_t* __restrict__ state) {
+  if (state[4]) return;
+  int32_t* front = state[3] ? fa : fb;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    if (flag[i]) front[pos[i]] = i;
+}
+
 // Step 2, narrow levels: Kahn's algorithm by levels inside one workgroup.
 // Dependents of row j are the rows of column j of T, i.e. row j of T^T; a
 // row joins the next level (and gets its level) when its last dependency
@@ -78,6 +89,7 @@ __global__ void k_tri_compact(int n, const int32_t* __restrict__ flag,
 // row, and a row enters a frontier only once).  State on the device: [0]
 // rows in the current frontier, [2] its level, [3] which buffer holds it.
 constexpr int kKahnSmall = 8192;
+constexpr int kSpecRounds = 3;
 
 // Releases the dependents of row j (when valid).  The lanes of a wave walk
 // their rows' dependents in step so that rows made ready together are
@@ -146,12 +158,18 @@ __global__ __launch_bounds__(kKahnThreads) void k_tri_kahn_small(
 // dependencies sit on levels <= L; otherwise indeg gets the number of
 // dependencies still above L (unplaced, or on level L + 1 from this same
 // pass: either way above L), which is what Kahn's algorithm needs next.
-__global__ __launch_bounds__(kThreads) void k_tri_pull(int n, int lower, int L,
+// The frontier's level L is state[2]; nothing is done once state[4] is set
+// (the scan, compaction and level step after it are gated on it too), so
+// rounds may be launched before the host knows whether they are needed.
+__global__ __launch_bounds__(kThreads) void k_tri_pull(int n, int lower,
+                                                       const int32_t* __restrict__ state,
                                                        const int32_t* __restrict__ rp,
                                                        const int32_t* __restrict__ ci,
                                                        int32_t* __restrict__ level_of_row,
                                                        int32_t* __restrict__ indeg,
                                                        int32_t* __restrict__ flag) {
+  if (state[4]) return;
+  const int L = state[2];
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     int f = 0;
     if (level_of_row[i] == kUnset) {
@@ -171,22 +189,29 @@ __global__ __launch_bounds__(kThreads) void k_tri_pull(int n, int lower, int L,
   }
 }
 
-// state[0] = the compacted frontier size, [2] += 1, [3] ^= 1.
-__global__ void k_tri_next_level(const long long* __restrict__ total, int32_t* __restrict__ state) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    state[0] = (int32_t)*total;
+// state[0] = the compacted frontier size, [2] += 1, [3] ^= 1, [4] = no
+// further level (empty frontier, or n levels placed).  Does nothing once
+// [4] is set.
+__global__ void k_tri_next_level(int n, const long long* __restrict__ total,
+                                 int32_t* __restrict__ state) {
+  if (threadIdx.x == 0 && blockIdx.x == 0 && state[4] == 0) {
+    const int t = (int32_t)*total;
+    state[0] = t;
     state[2] += 1;
     state[3] ^= 1;
+    state[4] = t == 0 || state[2] >= n;
   }
 }
 
-// state[0] = the level-0 frontier size, [2] = 0, [3] = 0.
+// state[0] = the level-0 frontier size, [2] = 0, [3] = 0, [4] = no level.
 __global__ void k_tri_first_level(const long long* __restrict__ total,
                                   int32_t* __restrict__ state) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
-    state[0] = (int32_t)*total;
+    const int t = (int32_t)*total;
+    state[0] = t;
     state[2] = 0;
     state[3] = 0;
+    state[4] = t == 0;
   }
 }
 
@@ -380,7 +405,7 @@ struct TriWs {
   int32_t* indeg;
   int32_t* fa;
   int32_t* fb;
-  int32_t* counters;  // [0] frontier size, [1] bad row, [2] level, [3] buffer
+  int32_t* counters;  // [0] frontier size, [1] bad row, [2] level, [3] buffer, [4] done
   int32_t* flag;
   int32_t* pos;
   void* sws;
@@ -446,8 +471,9 @@ extern "C" int csr_trisolve_workspace(const csrad_csr* Tm, size_t* bytes) {
 
 extern "C" int csr_trisolve_analyze(const csrad_csr* Tm, int32_t lower, const csrad_csr* Tt,
                                     int32_t* level_of_row, int32_t* level_ptr,
-                                    int32_t* level_rows, int32_t* nlevels_host, void* work,
-                                    size_t work_bytes, void* stream) {
+                                    int32_t* level_rows, int32_t* nlevels_host,
+                                    int32_t* level_ptr_host, void* work, size_t work_bytes,
+                                    void* stream) {
   CSRAD_TRY(check_csr(Tm, false));
   CSRAD_TRY(check_csr(Tt, false));
   if (Tm->nrows != Tm->ncols || Tt->nrows != Tm->ncols || Tt->ncols != Tm->nrows ||
@@ -462,6 +488,7 @@ extern "C" int csr_trisolve_analyze(const csrad_csr* Tm, int32_t lower, const cs
   if (!work || !cv.ok) return CSRAD_EWORKSPACE;
   if (n == 0) {
     *nlevels_host = 0;
+    if (level_ptr_host) level_ptr_host[0] = 0;
     CSRAD_TRY(fill_i32(level_ptr, 1, 0, s));
     return hipStreamSynchronize(s) == hipSuccess ? CSRAD_OK : CSRAD_EHIP;
   }
@@ -475,6 +502,20 @@ extern "C" int csr_trisolve_analyze(const csrad_csr* Tm, int32_t lower, const cs
   CSRAD_TRY(scan_exclusive(w.flag, w.pos, n, w.total, w.sws, w.sws_bytes, s));
   hipLaunchKernelGGL(k_tri_compact, dim3(gn), dim3(kThreads), 0, s, n, w.flag, w.pos, w.fa);
   hipLaunchKernelGGL(k_tri_first_level, dim3(1), dim3(64), 0, s, w.total, w.counters);
+  // One wide-level round: a pull pass, its compaction, the level step.
+  auto pull_round = [&]() -> int {
+    hipLaunchKernelGGL(k_tri_pull, dim3(gn), dim3(kThreads), 0, s, n, lw, w.counters, Tm->rowptr,
+                       Tm->colind, level_of_row, w.indeg, w.flag);
+    CSRAD_TRY(scan_exclusive(w.flag, w.pos, n, w.total, w.sws, w.sws_bytes, s, w.counters + 4));
+    hipLaunchKernelGGL(k_tri_compact_next, dim3(gn), dim3(kThreads), 0, s, n, w.flag, w.pos, w.fa,
+                       w.fb, w.counters);
+    hipLaunchKernelGGL(k_tri_next_level, dim3(1), dim3(64), 0, s, n, w.total, w.counters);
+    return launch_status();
+  };
+  // Coloured orderings have a few wide levels: run kSpecRounds rounds
+  // before the first look at the state (each does nothing once the levels
+  // are exhausted), which saves a host round trip per level.
+  for (int r = 0; r < kSpecRounds; ++r) CSRAD_TRY(pull_round());
   int32_t host[8];
   auto read_state = [&]() -> int {
     if (hipMemcpyAsync(host, w.counters, sizeof(host), hipMemcpyDeviceToHost, s) != hipSuccess)
@@ -492,12 +533,7 @@ extern "C" int csr_trisolve_analyze(const csrad_csr* Tm, int32_t lower, const cs
     } else {
       // a wide level: one pass over the unplaced rows, then compaction into
       // the other frontier buffer
-      int32_t* nxt = host[3] ? w.fa : w.fb;
-      hipLaunchKernelGGL(k_tri_pull, dim3(gn), dim3(kThreads), 0, s, n, lw, host[2], Tm->rowptr,
-                         Tm->colind, level_of_row, w.indeg, w.flag);
-      CSRAD_TRY(scan_exclusive(w.flag, w.pos, n, w.total, w.sws, w.sws_bytes, s));
-      hipLaunchKernelGGL(k_tri_compact, dim3(gn), dim3(kThreads), 0, s, n, w.flag, w.pos, nxt);
-      hipLaunchKernelGGL(k_tri_next_level, dim3(1), dim3(64), 0, s, w.total, w.counters);
+      CSRAD_TRY(pull_round());
     }
     CSRAD_TRY(read_state());
   }
@@ -515,6 +551,10 @@ extern "C" int csr_trisolve_analyze(const csrad_csr* Tm, int32_t lower, const cs
     CSRAD_TRY(transpose_pattern(n, nl, n, w.iota, level_of_row, level_ptr, level_rows, w.perm,
                                 w.tws, w.tws_bytes, s));
   }
+  if (level_ptr_host &&
+      hipMemcpyAsync(level_ptr_host, level_ptr, sizeof(int32_t) * ((size_t)nl + 1),
+                     hipMemcpyDeviceToHost, s) != hipSuccess)
+    return CSRAD_EHIP;
   return hipStreamSynchronize(s) == hipSuccess ? CSRAD_OK : CSRAD_EHIP;
 }
 

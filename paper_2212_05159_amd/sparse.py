@@ -78,9 +78,9 @@ class Pattern:
             lrows = torch.empty(n, dtype=torch.int32, device=self.device)
             d = self.desc()
             ws = capi._ws(capi.csr_trisolve_workspace(d), self.device)
-            nl = capi.csr_trisolve_analyze(d, int(key), Tt.desc(), lor, lptr, lrows, ws)
-            lptr = lptr[: nl + 1].clone()
-            self._levels[key] = (nl, np.ascontiguousarray(lptr.cpu().numpy()), lptr, lrows, lor)
+            lph = np.empty(n + 1, dtype=np.int32)
+            nl = capi.csr_trisolve_analyze(d, int(key), Tt.desc(), lor, lptr, lrows, ws, lph)
+            self._levels[key] = (nl, lph[: nl + 1].copy(), lptr[: nl + 1], lrows, lor)
         return self._levels[key]
 
     @classmethod
