@@ -139,20 +139,30 @@ int csr_transpose_vals(const csrad_csr *A, const int32_t *perm, void *valsT,
  * (i,j) is stored when some k has (i,k) in A and (k,j) in B, even if the
  * sum cancels; column indices ascending.
  * csr_spgemm_symbolic: C_rowptr[m+1] and *C_nnz_host (synchronises).
+ *   The rows are classified by their number of products; with bins_host
+ *   non-NULL (CSRAD_SPGEMM_BINS int32 entries) the class boundaries are
+ *   returned in the same synchronisation.
  * csr_spgemm_fwd: C_colind[nnz(C)] and C_vals[nnz(C)] given C_rowptr.
  *   Each C_ij sums A_ik B_kj over k in A's row order (deterministic).
+ *   bins_host may be NULL (the rows are classified again); non-NULL, it
+ *   must be what csr_spgemm_symbolic returned for the same A and B, with
+ *   `work` that symbolic call's workspace, unchanged since: the
+ *   classification is then reused and empty classes launch nothing.
  * csr_spgemm_bwd: VJP with upstream gradient gC on pat(C) (Table 1):
  *   gA = (V B^T) on pat(A), gB = (A^T V) on pat(B).  C carries the
  *   pattern of C (vals ignored); At/permA (transpose of A) are required
  *   when gB is requested.
  * ------------------------------------------------------------------- */
+#define CSRAD_SPGEMM_BINS 9
 int csr_spgemm_workspace(const csrad_csr *A, const csrad_csr *B, size_t *bytes);
 int csr_spgemm_symbolic(const csrad_csr *A, const csrad_csr *B,
-                        int32_t *C_rowptr, int64_t *C_nnz_host, void *work,
-                        size_t work_bytes, void *stream);
+                        int32_t *C_rowptr, int64_t *C_nnz_host,
+                        int32_t *bins_host, void *work, size_t work_bytes,
+                        void *stream);
 int csr_spgemm_fwd(const csrad_csr *A, const csrad_csr *B,
                    const int32_t *C_rowptr, int32_t *C_colind, void *C_vals,
-                   void *work, size_t work_bytes, void *stream);
+                   const int32_t *bins_host, void *work, size_t work_bytes,
+                   void *stream);
 int csr_spgemm_bwd(const csrad_csr *A, const csrad_csr *B,
                    const csrad_csr *At, const int32_t *permA,
                    const csrad_csr *C, const void *gC, void *gA, void *gB,

@@ -50,9 +50,9 @@ _SIGS = {
     "csr_transpose_vals": (C.c_int, [C.c_void_p] * 4),
     "csr_spgemm_workspace": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_size_t)]),
     "csr_spgemm_symbolic": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p,
-                                      C.POINTER(C.c_int64), C.c_void_p, C.c_size_t,
+                                      C.POINTER(C.c_int64), C.c_void_p, C.c_void_p, C.c_size_t,
                                       C.c_void_p]),
-    "csr_spgemm_fwd": (C.c_int, [C.c_void_p] * 6 + [C.c_size_t, C.c_void_p]),
+    "csr_spgemm_fwd": (C.c_int, [C.c_void_p] * 7 + [C.c_size_t, C.c_void_p]),
     "csr_spgemm_bwd": (C.c_int, [C.c_void_p] * 9),
     "csr_trisolve_workspace": (C.c_int, [C.c_void_p, C.POINTER(C.c_size_t)]),
     "csr_trisolve_analyze": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
@@ -206,18 +206,30 @@ def csr_spgemm_workspace(A, B):
     return n.value
 
 
-def csr_spgemm_symbolic(A, B, C_rowptr, work):
+SPGEMM_BINS = 9
+
+
+def _host_i32(a, size):
+    if a is None:
+        return None
+    assert a.dtype == np.int32 and a.flags.c_contiguous and a.size >= size
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def csr_spgemm_symbolic(A, B, C_rowptr, work, bins_host=None):
+    """Returns nnz(C); bins_host (int32 ndarray of SPGEMM_BINS, or None)
+    receives the row classes for csr_spgemm_fwd."""
     nnz = C.c_int64(0)
-    _check("csr_spgemm_symbolic", load().csr_spgemm_symbolic(C.byref(A), C.byref(B), _ptr(C_rowptr),
-                                                             C.byref(nnz), _ptr(work), work.numel(),
-                                                             _stream()))
+    _check("csr_spgemm_symbolic", load().csr_spgemm_symbolic(
+        C.byref(A), C.byref(B), _ptr(C_rowptr), C.byref(nnz), _host_i32(bins_host, SPGEMM_BINS),
+        _ptr(work), work.numel(), _stream()))
     return nnz.value
 
 
-def csr_spgemm_fwd(A, B, C_rowptr, C_colind, C_vals, work):
-    _check("csr_spgemm_fwd", load().csr_spgemm_fwd(C.byref(A), C.byref(B), _ptr(C_rowptr),
-                                                   _ptr(C_colind), _ptr(C_vals), _ptr(work),
-                                                   work.numel(), _stream()))
+def csr_spgemm_fwd(A, B, C_rowptr, C_colind, C_vals, work, bins_host=None):
+    _check("csr_spgemm_fwd", load().csr_spgemm_fwd(
+        C.byref(A), C.byref(B), _ptr(C_rowptr), _ptr(C_colind), _ptr(C_vals),
+        _host_i32(bins_host, SPGEMM_BINS), _ptr(work), work.numel(), _stream()))
 
 
 def csr_spgemm_bwd(A, B, At, permA, Cpat, gC, gA, gB):

@@ -29,6 +29,7 @@ namespace {
 constexpr int kThreads = 256;
 // 0: empty, 1..4: lanes (U <= 8, 16, 32, 64), 5..6: LDS hash, 7: dense marker
 constexpr int kNumBins = 8;
+static_assert(kNumBins + 1 == CSRAD_SPGEMM_BINS, "host copy of the class boundaries");
 constexpr int kDenseBin = 7;
 constexpr int kBigU = 4096;
 constexpr size_t kMarkerBudget = size_t(16) << 20;
@@ -654,9 +655,11 @@ void sym_lanes(int bin, const csrad_csr* A, const csrad_csr* B, const SpgemmWs& 
 }
 
 template <typename T, int G>
-void num_lanes(int bin, const csrad_csr* A, const csrad_csr* B, const T* vA, const T* vB,
-               const int32_t* rpC, int32_t* ciC, T* vC, const SpgemmWs& w, hipStream_t s) {
-  const unsigned g = persistent_grid(kThreads / G, A->nrows);
+void num_lanes(int bin, int rows, const csrad_csr* A, const csrad_csr* B, const T* vA,
+               const T* vB, const int32_t* rpC, int32_t* ciC, T* vC, const SpgemmWs& w,
+               hipStream_t s) {
+  if (rows == 0) return;
+  const unsigned g = persistent_grid(kThreads / G, rows);
   if (keys32<G>(B->ncols))
     hipLaunchKernelGGL((k_num_lanes<T, G, unsigned>), dim3(g), dim3(kThreads), 0, s, bin, w.list,
                        w.bin_off, A->rowptr, A->colind, vA, B->rowptr, B->colind, vB, rpC, ciC,
@@ -667,24 +670,31 @@ void num_lanes(int bin, const csrad_csr* A, const csrad_csr* B, const T* vA, con
                        rpC, ciC, vC);
 }
 
+// bins: host copy of the class boundaries, or null (every class is then
+// launched for all m rows; the kernels read the boundaries on the device).
 template <typename T>
 int spgemm_numeric_t(const csrad_csr* A, const csrad_csr* B, const int32_t* rpC, int32_t* ciC,
-                     T* vC, const SpgemmWs& w, hipStream_t s) {
+                     T* vC, const SpgemmWs& w, const int32_t* bins, hipStream_t s) {
   const int m = A->nrows, p = B->ncols;
   const T* vA = static_cast<const T*>(A->vals);
   const T* vB = static_cast<const T*>(B->vals);
-  num_lanes<T, 8>(1, A, B, vA, vB, rpC, ciC, vC, w, s);
-  num_lanes<T, 16>(2, A, B, vA, vB, rpC, ciC, vC, w, s);
-  num_lanes<T, 32>(3, A, B, vA, vB, rpC, ciC, vC, w, s);
-  num_lanes<T, 64>(4, A, B, vA, vB, rpC, ciC, vC, w, s);
-  hipLaunchKernelGGL((k_num_hash<T, 64, 1024>), dim3(persistent_grid(4, m)), dim3(kThreads), 0, s,
-                     5, w.list, w.bin_off, A->rowptr, A->colind, vA, B->rowptr, B->colind, vB, rpC,
-                     ciC, vC);
-  hipLaunchKernelGGL((k_num_hash<T, 256, 8192>), dim3(persistent_grid(1, m)), dim3(kThreads), 0, s,
-                     6, w.list, w.bin_off, A->rowptr, A->colind, vA, B->rowptr, B->colind, vB, rpC,
-                     ciC, vC);
-  hipLaunchKernelGGL((k_num_dense<T>), dim3(w.nmark), dim3(kThreads), 0, s, p, w.list, w.bin_off,
-                     A->rowptr, A->colind, vA, B->rowptr, B->colind, vB, rpC, ciC, vC, w.markers);
+  auto rows = [&](int b) { return bins ? bins[b + 1] - bins[b] : m; };
+  num_lanes<T, 8>(1, rows(1), A, B, vA, vB, rpC, ciC, vC, w, s);
+  num_lanes<T, 16>(2, rows(2), A, B, vA, vB, rpC, ciC, vC, w, s);
+  num_lanes<T, 32>(3, rows(3), A, B, vA, vB, rpC, ciC, vC, w, s);
+  num_lanes<T, 64>(4, rows(4), A, B, vA, vB, rpC, ciC, vC, w, s);
+  if (rows(5) > 0)
+    hipLaunchKernelGGL((k_num_hash<T, 64, 1024>), dim3(persistent_grid(4, rows(5))),
+                       dim3(kThreads), 0, s, 5, w.list, w.bin_off, A->rowptr, A->colind, vA,
+                       B->rowptr, B->colind, vB, rpC, ciC, vC);
+  if (rows(6) > 0)
+    hipLaunchKernelGGL((k_num_hash<T, 256, 8192>), dim3(persistent_grid(1, rows(6))),
+                       dim3(kThreads), 0, s, 6, w.list, w.bin_off, A->rowptr, A->colind, vA,
+                       B->rowptr, B->colind, vB, rpC, ciC, vC);
+  if (rows(kDenseBin) > 0)
+    hipLaunchKernelGGL((k_num_dense<T>), dim3(w.nmark), dim3(kThreads), 0, s, p, w.list,
+                       w.bin_off, A->rowptr, A->colind, vA, B->rowptr, B->colind, vB, rpC, ciC,
+                       vC, w.markers);
   return launch_status();
 }
 
@@ -746,8 +756,8 @@ extern "C" int csr_spgemm_workspace(const csrad_csr* A, const csrad_csr* B, size
 }
 
 extern "C" int csr_spgemm_symbolic(const csrad_csr* A, const csrad_csr* B, int32_t* C_rowptr,
-                                   int64_t* C_nnz_host, void* work, size_t work_bytes,
-                                   void* stream) {
+                                   int64_t* C_nnz_host, int32_t* bins_host, void* work,
+                                   size_t work_bytes, void* stream) {
   CSRAD_TRY(check_pair(A, B, false));
   if (!C_rowptr || !C_nnz_host) return CSRAD_EINVAL;
   hipStream_t s = as_stream(stream);
@@ -777,6 +787,9 @@ extern "C" int csr_spgemm_symbolic(const csrad_csr* A, const csrad_csr* B, int32
   long long total = 0;
   if (hipMemcpyAsync(&total, w.total, sizeof(total), hipMemcpyDeviceToHost, s) != hipSuccess)
     return CSRAD_EHIP;
+  if (bins_host && hipMemcpyAsync(bins_host, w.bin_off, sizeof(int32_t) * (kNumBins + 1),
+                                  hipMemcpyDeviceToHost, s) != hipSuccess)
+    return CSRAD_EHIP;
   if (hipStreamSynchronize(s) != hipSuccess) return CSRAD_EHIP;
   *C_nnz_host = total;
   if (total > INT32_MAX) return CSRAD_EOVERFLOW;
@@ -784,8 +797,8 @@ extern "C" int csr_spgemm_symbolic(const csrad_csr* A, const csrad_csr* B, int32
 }
 
 extern "C" int csr_spgemm_fwd(const csrad_csr* A, const csrad_csr* B, const int32_t* C_rowptr,
-                              int32_t* C_colind, void* C_vals, void* work, size_t work_bytes,
-                              void* stream) {
+                              int32_t* C_colind, void* C_vals, const int32_t* bins_host,
+                              void* work, size_t work_bytes, void* stream) {
   CSRAD_TRY(check_pair(A, B, true));
   if (!C_rowptr) return CSRAD_EINVAL;
   hipStream_t s = as_stream(stream);
@@ -794,10 +807,16 @@ extern "C" int csr_spgemm_fwd(const csrad_csr* A, const csrad_csr* B, const int3
   SpgemmWs w = carve_spgemm(cv, m, p);
   if (!work || !cv.ok) return CSRAD_EWORKSPACE;
   if (m == 0) return CSRAD_OK;
-  CSRAD_TRY(classify(A, B, w, s));
+  if (bins_host) {  // the symbolic call's classification, still in `work`
+    if (bins_host[0] != 0 || bins_host[kNumBins] != m) return CSRAD_EINVAL;
+  } else {
+    CSRAD_TRY(classify(A, B, w, s));
+  }
   if (A->dtype == CSRAD_F32)
-    return spgemm_numeric_t<float>(A, B, C_rowptr, C_colind, static_cast<float*>(C_vals), w, s);
-  return spgemm_numeric_t<double>(A, B, C_rowptr, C_colind, static_cast<double*>(C_vals), w, s);
+    return spgemm_numeric_t<float>(A, B, C_rowptr, C_colind, static_cast<float*>(C_vals), w,
+                                   bins_host, s);
+  return spgemm_numeric_t<double>(A, B, C_rowptr, C_colind, static_cast<double*>(C_vals), w,
+                                  bins_host, s);
 }
 
 extern "C" int csr_spgemm_bwd(const csrad_csr* A, const csrad_csr* B, const csrad_csr* At,

@@ -143,10 +143,11 @@ def spgemm(PA, valsA, PB, valsB):
     dA, dB = PA.desc(valsA), PB.desc(valsB)
     ws = capi._ws(capi.csr_spgemm_workspace(dA, dB), valsA.device)
     rpC = torch.empty(PA.nrows + 1, dtype=torch.int32, device=valsA.device)
-    nnz = capi.csr_spgemm_symbolic(dA, dB, rpC, ws)
+    bins = np.empty(capi.SPGEMM_BINS, dtype=np.int32)  # row classes, reused by the numeric call
+    nnz = capi.csr_spgemm_symbolic(dA, dB, rpC, ws, bins)
     ciC = torch.empty(nnz, dtype=torch.int32, device=valsA.device)
     vC = torch.empty(nnz, dtype=valsA.dtype, device=valsA.device)
-    capi.csr_spgemm_fwd(dA, dB, rpC, ciC, vC, ws)
+    capi.csr_spgemm_fwd(dA, dB, rpC, ciC, vC, ws, bins)
     return Pattern(PA.nrows, PB.ncols, rpC, ciC), vC
 
 

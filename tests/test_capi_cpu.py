@@ -80,8 +80,10 @@ def test_argument_errors_return_codes(lib):
     assert lib.csr_spgemm_workspace(C.byref(d), C.byref(e), C.byref(sz)) == 0
     f = capi.csrad_csr(5, 4, 4, 0, 1, 1, 1)  # inner dimensions disagree
     nnz = C.c_int64(0)
-    assert lib.csr_spgemm_symbolic(C.byref(d), C.byref(f), 1, C.byref(nnz), 1, 1 << 30, None) == -1
+    assert lib.csr_spgemm_symbolic(C.byref(d), C.byref(f), 1, C.byref(nnz), None, 1, 1 << 30,
+                                   None) == -1
     g = capi.csrad_csr(4, 4, 4, 1, 1, 1, 1)  # dtype mismatch between A and B
-    assert lib.csr_spgemm_symbolic(C.byref(d), C.byref(g), 1, C.byref(nnz), 1, 1 << 30, None) == -2
+    assert lib.csr_spgemm_symbolic(C.byref(d), C.byref(g), 1, C.byref(nnz), None, 1, 1 << 30,
+                                   None) == -2
     # non-square triangular operand
     assert lib.csr_trisolve_fwd(C.byref(e), 1, 1, None, None, None, 1, 1, None) == -1

@@ -293,6 +293,16 @@ def test_spgemm_fwd_bwd(dtype, name, A, B):
     assert np.array_equal(PC.rowptr.cpu().numpy(), rpo)
     assert np.array_equal(PC.colind.cpu().numpy(), cio)
     assert_close(vC, vo, dtype, "C vals")
+    # the numeric call without the symbolic call's row classes classifies
+    # the rows again and launches every class: same result bit for bit
+    from paper_2212_05159_amd import capi
+    dA, dB = Ad.pattern.desc(Ad.vals), Bd.pattern.desc(Bd.vals)
+    ws = capi._ws(capi.csr_spgemm_workspace(dA, dB), Ad.vals.device)
+    rp2 = torch.empty_like(PC.rowptr)
+    assert capi.csr_spgemm_symbolic(dA, dB, rp2, ws) == PC.nnz
+    ci2, v2 = torch.empty_like(PC.colind), torch.empty_like(vC)
+    capi.csr_spgemm_fwd(dA, dB, rp2, ci2, v2, ws)
+    assert torch.equal(rp2, PC.rowptr) and torch.equal(ci2, PC.colind) and torch.equal(v2, vC)
     V = gen.normal(len(cio), 13)
     gA, gB = sp.spgemm_bwd(Ad.pattern, Ad.vals, Bd.pattern, Bd.vals, PC, to_dev(V, dtype))
     gAo, gBo = oracle.spgemm_bwd(Ao, Bo, rpo, cio, rounded(V, dtype))
