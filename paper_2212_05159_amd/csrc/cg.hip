@@ -9,7 +9,7 @@
 // Dot products accumulate in float64 whatever the vector type: per-block
 // partial sums, which every block of the kernel that needs the total adds
 // up itself in one fixed order (no separate one-block reduction launches:
-// three kernels per forward step, three per reverse step), so every step is
+// three kernels per forward step, four per reverse step), so every step is
 // bit-reproducible (checkpoint recomputation relies on it).
 //
 // Reverse step t (adjoints xb, rb, pb, qb of x, r, p, q and rhob of rho_{t+1}):
