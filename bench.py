@@ -98,6 +98,7 @@ def batched_section(blocks, gen_s, reps=5):
     PL.transpose()
     nl = PL.levels(True)[0]
     tuned = autotune.tune_spmm(P, v, X, G, reps=3, use_cache=False)
+    spmv_mode = autotune.tune_spmv_bwd(P, v, x, gy, reps=3, use_cache=False)[0]
     ops = {
         "spmv fwd": lambda: sp.spmv(P, v, x),
         "spmv bwd": lambda: sp.spmv_bwd(P, v, x, gy),
@@ -164,6 +165,7 @@ def batched_section(blocks, gen_s, reps=5):
         "per_block_ms": round(per_ms, 4),
         "batching_speedup": round(per_ms / total_ms, 2),
         "spmm_plans": {op: (list(c) if c else "natural") for op, (c, _) in tuned.items()},
+        "spmv_bwd_mode": spmv_mode,
         "generation_s": round(gen_s, 1),
     }
 
@@ -473,7 +475,7 @@ def run_step(d, marks):
     marks.mark("transpose vals P")
     sp.spmv(PA, d.A_v, d.x)
     marks.mark("spmv fwd")
-    sp.spmv_bwd(PA, d.A_v, d.x, d.gy)
+    sp.spmv_bwd(PA, d.A_v, d.x, d.gy, mode=d.spmv_bwd_mode)
     marks.mark("spmv bwd")
     sp.spmm(PA, d.A_v, d.B, plan=d.plan_fwd)
     marks.mark("spmm fwd")
@@ -609,7 +611,8 @@ def main():
     P0 = sp.Pattern(d.n, d.n, d.A_rp, d.A_ci)
     tuned = autotune.tune_spmm(P0, d.A_v, d.B, d.G, reps=3, use_cache=False)
     d.plan_fwd, d.plan_bwd = P0.plan("spmm_fwd"), P0.plan("spmm_bwd")
-    log(f"autotuned plans: {tuned}")
+    d.spmv_bwd_mode = autotune.tune_spmv_bwd(P0, d.A_v, d.x, d.gy, reps=3, use_cache=False)[0]
+    log(f"autotuned plans: {tuned}, SpMV backward: {d.spmv_bwd_mode}")
 
     for i in range(args.warmup):
         run_step(d, Marks(False))
@@ -699,7 +702,8 @@ def main():
                                f"tri-solve fwd+bwd",
                    "grid": args.grid, "k": args.k, "nnz_A": d.nnzA, "nnz_AP": nnz_ap,
                    "nnz_PtAP": nnz_c, "nnz_L": d.nnzL, "levels_L": nlev,
-                   "spmm_plans": {op: (list(c) if c else "natural") for op, (c, _) in tuned.items()}},
+                   "spmm_plans": {op: (list(c) if c else "natural") for op, (c, _) in tuned.items()},
+                   "spmv_bwd_mode": d.spmv_bwd_mode},
         "frac_hbm_peak": round(value / HBM_PEAK_GBS, 4),
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -108,3 +108,30 @@ def tune_spmm(P, vals, B, G, reps=3, use_cache=True):
     if use_cache:
         _save_cache(cache)
     return result
+
+
+def tune_spmv_bwd(P, vals, x, gy, reps=3, use_cache=True):
+    """Chooses how the SpMV backward forms its two gradients when both are
+    wanted: "fused" (one pass over A^T writes the value gradient through
+    the permutation) or "split" (A^T gy over A^T, the value gradient in a
+    second, row-wise pass over A with coalesced writes).  Patterns whose
+    transpose permutation is local (structured grids) favour the fused
+    pass; scattered ones (random graphs) the split.  Results are the same
+    bit for bit either way.  Stores the choice on P; returns (choice, ms)."""
+    from . import sparse as sp
+
+    key = f"{_arch()}|{P.nrows}x{P.ncols}|nnz{P.nnz}|{tuple(P.stats())}|{vals.dtype}|spmv_bwd"
+    cache = _load_cache() if use_cache else {}
+    if key in cache:
+        choice, ms = cache[key]["mode"], cache[key]["ms"]
+    else:
+        timed = []
+        for mode in ("fused", "split"):
+            P.set_plan("spmv_bwd", mode)
+            timed.append((mode, _time(lambda: sp.spmv_bwd(P, vals, x, gy), reps)))
+        choice, ms = min(timed, key=lambda t: t[1])
+        cache[key] = {"mode": choice, "ms": ms, "all": [list(t) for t in timed]}
+        if use_cache:
+            _save_cache(cache)
+    P.set_plan("spmv_bwd", choice)
+    return choice, ms

@@ -99,12 +99,21 @@ def spmv(P, vals, x):
     return y
 
 
-def spmv_bwd(P, vals, x, gy, need_x=True, need_vals=True, use_transpose=True):
+def spmv_bwd(P, vals, x, gy, need_x=True, need_vals=True, use_transpose=True, mode=None):
+    """(gx, gvals).  mode "fused" or "split" (see autotune.tune_spmv_bwd)
+    overrides the pattern's tuned choice; both give the same bits."""
+    mode = mode if mode is not None else P.plan("spmv_bwd")
     gx = torch.empty(P.ncols, dtype=vals.dtype, device=vals.device) if need_x else None
     gv = torch.empty(P.nnz, dtype=vals.dtype, device=vals.device) if need_vals else None
     if use_transpose:
         Pt, perm = P.transpose()
-        capi.csr_spmv_bwd(P.desc(vals), Pt.desc(dtype=vals.dtype), perm, x, gy, gx, gv)
+        if need_x and need_vals and mode == "split":
+            # A^T gy over A^T, then the value gradient row-wise over A (the
+            # autotuner's choice for patterns with a scattered transpose)
+            capi.csr_spmv_bwd(P.desc(vals), Pt.desc(dtype=vals.dtype), perm, x, gy, gx, None)
+            capi.csr_spmv_bwd(P.desc(vals), None, None, x, gy, None, gv)
+        else:
+            capi.csr_spmv_bwd(P.desc(vals), Pt.desc(dtype=vals.dtype), perm, x, gy, gx, gv)
     else:
         capi.csr_spmv_bwd(P.desc(vals), None, None, x, gy, gx, gv)
     return gx, gv

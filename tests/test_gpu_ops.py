@@ -435,3 +435,22 @@ def test_validate():
     Pbad = sp.Pattern(A.nrows, A.ncols, P.rowptr, to_dev(ci))
     st, bad = capi.csr_validate(Pbad.desc(dtype=torch.float32), ws)
     assert st == -3 and bad == r
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_spmv_bwd_split_equals_fused(dtype):
+    # the two ways of forming the SpMV backward give the same bits; the
+    # autotuner picks one of them
+    from paper_2212_05159_amd import autotune
+    for seed, A in enumerate([gen.random_csr(2000, 1500, 0.01, seed=91, empty_rows=0.1),
+                              gen.poisson2d(40, 40)]):
+        Ad = _dev(A, dtype)
+        x = to_dev(gen.normal(A.ncols, 92 + seed), dtype)
+        gy = to_dev(gen.normal(A.nrows, 94 + seed), dtype)
+        gx1, gv1 = sp.spmv_bwd(Ad.pattern, Ad.vals, x, gy, mode="fused")
+        gx2, gv2 = sp.spmv_bwd(Ad.pattern, Ad.vals, x, gy, mode="split")
+        assert torch.equal(gx1, gx2) and torch.equal(gv1, gv2)
+        choice, _ = autotune.tune_spmv_bwd(Ad.pattern, Ad.vals, x, gy, reps=1, use_cache=False)
+        assert choice in ("fused", "split")
+        gx3, gv3 = sp.spmv_bwd(Ad.pattern, Ad.vals, x, gy)
+        assert torch.equal(gx1, gx3) and torch.equal(gv1, gv3)
