@@ -31,7 +31,7 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kKahnThreads = 1024;
 constexpr int kOneBlockThreads = 1024;
-constexpr int kBigLevel = 2048;
+constexpr int kOneBlockPasses = 4;
 
 __device__ __forceinline__ bool dep_side(int lower, int row, int col) {
   return lower ? col < row : col > row;
@@ -322,7 +322,11 @@ template <typename TV, typename TX, int G, bool PERM, bool REVERSE>
 void run_levels(int nlevels, const int32_t* lp_host, const int32_t* lp_dev, const int32_t* rows,
                 int lower, const int32_t* rp, const int32_t* ci, const int32_t* perm,
                 const TV* vals, const TX* b, TX* x, hipStream_t s) {
-  auto big = [&](int l) { return lp_host[l + 1] - lp_host[l] >= kBigLevel; };
+  // A level is worth a grid launch once the single workgroup would need
+  // more than kOneBlockPasses passes over it (a pass costs a dependent
+  // memory round trip; a launch a few of them).
+  constexpr int kBig = kOneBlockPasses * (kOneBlockThreads / G);
+  auto big = [&](int l) { return lp_host[l + 1] - lp_host[l] > kBig; };
   int t = 0;
   while (t < nlevels) {
     const int l = REVERSE ? nlevels - 1 - t : t;
