@@ -115,7 +115,7 @@ def test_network_and_loss_gradients_match_reference(N):
     errs = {"L": rel_err(Lv, Lo.detach().numpy())}
     lo = mpnn_ref.pcg_loss(Ah, Lph, Lo, b)
     lo.backward()
-    errs["loss"] = abs(float(loss) - float(lo)) / abs(float(lo))
+    errs["loss"] = abs(float(loss.detach()) - float(lo.detach())) / abs(float(lo.detach()))
     for name in ("Wp", "W0", "b0"):
         errs[name] = rel_err(getattr(model, name).grad, leaves[name].grad.numpy())
     for l in range(3):
