@@ -232,19 +232,96 @@ __device__ __forceinline__ unsigned shfl_xor_key(unsigned v, int m) {
   return (unsigned)__shfl_xor((int)v, m);
 }
 
+// Lane exchanges within rows of 16 lanes through DPP moves (no LDS
+// crossbar): quad permutes, the half-row and row mirrors, and row shifts.
+template <int CTRL>
+__device__ __forceinline__ unsigned dpp_key(unsigned v) {
+  return (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ unsigned long long dpp_key(unsigned long long v) {
+  const unsigned lo = dpp_key<CTRL>((unsigned)v), hi = dpp_key<CTRL>((unsigned)(v >> 32));
+  return ((unsigned long long)hi << 32) | lo;
+}
+
+// The key of lane l ^ M, l the lane's index in its aligned group.  Both
+// row shifts of the M = 4 and M = 8 cases run on every lane before the
+// select: a DPP move reads nothing from lanes that are switched off.
+template <int M, typename K>
+__device__ __forceinline__ K partner_key(K key, int l) {
+  if constexpr (M == 1) {
+    return dpp_key<0xB1>(key);  // quad_perm [1,0,3,2]
+  } else if constexpr (M == 2) {
+    return dpp_key<0x4E>(key);  // quad_perm [2,3,0,1]
+  } else if constexpr (M == 3) {
+    return dpp_key<0x1B>(key);  // quad_perm [3,2,1,0]
+  } else if constexpr (M == 4 || M == 8) {
+    const K down = dpp_key<0x110 + M>(key);  // row_shr:M, lane l - M
+    const K up = dpp_key<0x100 + M>(key);    // row_shl:M, lane l + M
+    return (l & M) ? down : up;
+  } else if constexpr (M == 7) {
+    return dpp_key<0x141>(key);  // row_half_mirror
+  } else if constexpr (M == 15) {
+    return dpp_key<0x140>(key);  // row_mirror
+  } else {
+    return shfl_xor_key(key, M);
+  }
+}
+
+template <typename K>
+__device__ __forceinline__ K keep(K key, K other, bool keep_min) {
+  return keep_min ? (other < key ? other : key) : (other > key ? other : key);
+}
+
+// Half-cleaner steps j = J, J/2, ..., 1 of a bitonic merge (ascending).
+template <int J, typename K>
+__device__ __forceinline__ K merge_steps(K key, int l) {
+  if constexpr (J >= 1) {
+    key = keep(key, partner_key<J>(key, l), (l & J) == 0);
+    return merge_steps<J / 2>(key, l);
+  } else {
+    return key;
+  }
+}
+
+// Stages KB = 2, 4, ..., G of the bitonic network in its mirror form: each
+// stage compares lane l with l ^ (KB - 1) (the mirror in its KB-block,
+// lower half keeps the minimum), then half-cleans with l ^ KB/4, ..., l ^ 1;
+// every comparator is ascending, and the exchanges within 16 lanes are DPP
+// moves.
+template <int KB, int G, typename K>
+__device__ __forceinline__ K sort_stages(K key, int l) {
+  if constexpr (KB <= G) {
+    key = keep(key, partner_key<KB - 1>(key, l), (l & (KB >> 1)) == 0);
+    key = merge_steps<KB / 4>(key, l);
+    return sort_stages<KB * 2, G>(key, l);
+  } else {
+    return key;
+  }
+}
+
 // Ascending sort of one key per lane over aligned groups of G lanes.
 template <int G, typename K>
 __device__ __forceinline__ K group_sort(K key, int l) {
-#pragma unroll
-  for (int k = 2; k <= G; k <<= 1) {
-#pragma unroll
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      const K other = shfl_xor_key(key, j);
-      const bool keep_min = ((l & j) == 0) == ((l & k) == 0);
-      key = keep_min ? (other < key ? other : key) : (other > key ? other : key);
-    }
+  return sort_stages<2, G>(key, l);
+}
+
+// Inclusive prefix sum over an aligned group of G lanes.  Groups within one
+// row of 16 lanes shift by DPP; wider groups shuffle (a row shift does not
+// cross into the next row, which their lanes would need).
+template <int O, int G>
+__device__ __forceinline__ int scan_up(int inc, int l) {
+  if constexpr (O < G) {
+    int t;
+    if constexpr (G <= 16)
+      t = __builtin_amdgcn_update_dpp(0, inc, 0x110 + O, 0xF, 0xF, false);  // row_shr:O
+    else
+      t = __shfl_up(inc, O, G);
+    if (l >= O) inc += t;
+    return scan_up<O * 2, G>(inc, l);
+  } else {
+    return inc;
   }
-  return key;
 }
 
 // The l-th product of row i, found by the G lanes of the row together: A's
@@ -278,12 +355,7 @@ __device__ __forceinline__ void lane_product(int i, bool valid, int l,
       b0 = rpB[k];
       len = rpB[k + 1] - b0;
     }
-    int inc = len;
-#pragma unroll
-    for (int o = 1; o < G; o <<= 1) {
-      const int t = __shfl_up(inc, o, G);
-      if (l >= o) inc += t;
-    }
+    const int inc = scan_up<1, G>(len, l);
     const int total = __shfl(inc, gbase + G - 1);
     const int pidx = l - before;  // this lane's product within the chunk
     // first t with inc[t] > pidx (lanes without a product search too)
