@@ -244,6 +244,15 @@ __device__ __forceinline__ unsigned long long dpp_key(unsigned long long v) {
   return ((unsigned long long)hi << 32) | lo;
 }
 
+// The value of lane + 1 across the whole wave (DPP wave_shl:1; the last
+// lane reads 0).
+__device__ __forceinline__ float wave_next(float v) {
+  return __uint_as_float(dpp_key<0x130>(__float_as_uint(v)));
+}
+__device__ __forceinline__ double wave_next(double v) {
+  return __longlong_as_double((long long)dpp_key<0x130>((unsigned long long)__double_as_longlong(v)));
+}
+
 // The key of lane l ^ M, l the lane's index in its aligned group.  Both
 // row shifts of the M = 4 and M = 8 cases run on every lane before the
 // select: a DPP move reads nothing from lanes that are switched off.
@@ -431,7 +440,7 @@ __global__ __launch_bounds__(kThreads) void k_sym_lanes(int bin, const int32_t* 
     lane_product<G>(i, valid, l, rpA, ciA, rpB, ciB, col, ea, eb);
     const K key = group_sort<G, K>(make_key<G, K>(col, l), l);
     const int sc = key_col<G, K>(key);
-    const int prev = __shfl(sc, lane > 0 ? lane - 1 : 0);
+    const int prev = (int)dpp_key<0x138>((unsigned)sc);  // wave_shr:1, lane - 1
     const bool head = sc != INT32_MAX && (l == 0 || prev != sc);
     const int cnt = __popcll(__ballot(head) & gm);
     if (valid && l == 0) counts[i] = cnt;
@@ -461,7 +470,7 @@ __global__ __launch_bounds__(kThreads) void k_num_lanes(
     const K key = group_sort<G, K>(make_key<G, K>(col, l), l);
     const int sc = key_col<G, K>(key);
     const T v = __shfl(prod, gbase + key_idx<G, K>(key));
-    const int prev = __shfl(sc, lane > 0 ? lane - 1 : 0);
+    const int prev = (int)dpp_key<0x138>((unsigned)sc);  // wave_shr:1, lane - 1
     const bool head = sc != INT32_MAX && (l == 0 || prev != sc);
     const unsigned long long heads = __ballot(head);
     const unsigned long long used = __ballot(sc != INT32_MAX) & gm;
@@ -475,8 +484,9 @@ __global__ __launch_bounds__(kThreads) void k_num_lanes(
     const int steps = wave_max(run);
     // run sums in lane order (k ascending)
     T acc = v;
+    T w = v;
     for (int d = 1; d < steps; ++d) {
-      const T w = __shfl(v, lane + d < 64 ? lane + d : lane);
+      w = wave_next(w);  // now the value of lane + d
       if (d < run) acc += w;
     }
     if (valid && head) {
