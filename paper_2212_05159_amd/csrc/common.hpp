@@ -161,11 +161,11 @@ __device__ __forceinline__ int wave_agg_add(int32_t* counter, int key) {
   for (int r = 0; r < kAggRounds; ++r) {
     if (!todo) break;
     const int leader = __ffsll((long long)todo) - 1;
-    const int lkey = __shfl(key, leader);
+    const int lkey = __builtin_amdgcn_readlane(key, leader);
     const unsigned long long peers = __ballot(!done && key == lkey) & todo;
     int old = 0;
     if (lane == leader) old = atomicAdd(&counter[lkey], __popcll(peers));
-    old = __shfl(old, leader);
+    old = __builtin_amdgcn_readlane(old, leader);
     if ((peers >> lane) & 1ull) {
       slot = old + __popcll(peers & lt);
       done = true;
@@ -186,7 +186,7 @@ __device__ __forceinline__ void wave_agg_count(int32_t* counter, int key) {
   for (int r = 0; r < kAggRounds; ++r) {
     if (!todo) break;
     const int leader = __ffsll((long long)todo) - 1;
-    const int lkey = __shfl(key, leader);
+    const int lkey = __builtin_amdgcn_readlane(key, leader);
     const unsigned long long peers = __ballot(!done && key == lkey) & todo;
     if (__lane_id() == leader) atomicAdd(&counter[lkey], __popcll(peers));
     if ((peers >> __lane_id()) & 1ull) done = true;
@@ -206,7 +206,7 @@ __device__ __forceinline__ int wave_append(int32_t* counter, bool pred) {
   const int leader = __ffsll((long long)mask) - 1;
   int base = 0;
   if (lane == leader) base = atomicAdd(counter, __popcll(mask));
-  base = __shfl(base, leader);
+  base = __builtin_amdgcn_readlane(base, leader);
   return base + __popcll(mask & ((1ull << lane) - 1ull));
 }
 

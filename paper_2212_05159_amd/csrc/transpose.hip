@@ -406,7 +406,7 @@ __global__ __launch_bounds__(256) void k_ms_scatter(const int32_t* __restrict__ 
     unsigned long long peers = 0;
     while (todo) {
       const int leader = __ffsll((long long)todo) - 1;
-      const int lkey = __shfl(key, leader);
+      const int lkey = __builtin_amdgcn_readlane(key, leader);
       const unsigned long long m = __ballot(act && key == lkey);
       if (act && key == lkey) peers = m;
       if (lane == leader) wcount[w][lkey] = __popcll(m);
