@@ -70,6 +70,11 @@ def _load():
                                   _I32P, _I32P, _F64P]),
         "or_spgemm_bwd": (cint, [i32, i32, i32, _I32P, _I32P, _F64P, _I32P, _I32P, _F64P,
                                  _I32P, _I32P, _F64P, _F64N, _F64N]),
+        "or_spadd_rowptr": (i64, [i32, i32, _I32P, _I32P, _I32P, _I32P, _I32P]),
+        "or_spadd_fill": (cint, [i32, i32, _I32P, _I32P, _F64P, _I32P, _I32P, _F64P, dbl, dbl,
+                                 _I32P, _I32P, _F64P]),
+        "or_spadd_bwd": (cint, [i32, i32, _I32P, _I32P, _I32P, _I32P, _I32P, _I32P, _F64P, dbl,
+                                dbl, _F64N, _F64N]),
         "or_levels": (i32, [i32, _I32P, _I32P, cint, _I32P, _I32P, _I32P]),
         "or_trisolve": (i32, [i32, _I32P, _I32P, _F64P, cint, _F64P, _F64P]),
         "or_trisolve_bwd": (i32, [i32, _I32P, _I32P, _F64P, cint, _F64P, _F64P, _F64P, _F64N]),
@@ -169,6 +174,35 @@ def spgemm_bwd(A, B, rpC, ciC, gC, want_A=True, want_B=True):
                                _f64(gC), gA, gB)
     if rc != 0:
         raise MemoryError("oracle spgemm_bwd")
+    return gA, gB
+
+
+def spadd(A, B, alpha=1.0, beta=1.0):
+    """Returns (rowptrC, colindC, valsC) of C = alpha A + beta B on the
+    union of the two patterns."""
+    m, n, rpA, ciA, vA = _csr(A)
+    _, _, rpB, ciB, vB = _csr(B)
+    lib = _load()
+    rpC = np.empty(m + 1, np.int32)
+    nnz = lib.or_spadd_rowptr(m, n, rpA, ciA, rpB, ciB, rpC)
+    if nnz < 0:
+        raise MemoryError("oracle spadd")
+    ciC = np.empty(nnz, np.int32)
+    vC = np.empty(nnz)
+    if lib.or_spadd_fill(m, n, rpA, ciA, vA, rpB, ciB, vB, float(alpha), float(beta),
+                         rpC, ciC, vC) != 0:
+        raise MemoryError("oracle spadd")
+    return rpC, ciC, vC
+
+
+def spadd_bwd(A, B, rpC, ciC, gC, alpha=1.0, beta=1.0, want_A=True, want_B=True):
+    m, n, rpA, ciA, _ = _csr(A)
+    _, _, rpB, ciB, _ = _csr(B)
+    gA = np.empty(len(ciA)) if want_A else None
+    gB = np.empty(len(ciB)) if want_B else None
+    if _load().or_spadd_bwd(m, n, rpA, ciA, rpB, ciB, _i32(rpC), _i32(ciC), _f64(gC),
+                            float(alpha), float(beta), gA, gB) != 0:
+        raise MemoryError("oracle spadd_bwd")
     return gA, gB
 
 

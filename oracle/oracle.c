@@ -224,6 +224,93 @@ int or_spgemm_bwd(i32 m, i32 n, i32 p, const i32 *rpA, const i32 *ciA,
 }
 
 /* ------------------------------------------------------------------ */
+/* Sparse + sparse, Section 3.1.4; Table 1 (Sp + Sp row).              */
+/* C = alpha A + beta B for A, B of the same shape.  The pattern of C  */
+/* is the union of the two input patterns, kept structurally: (i,j) is */
+/* stored when A or B stores it, even where the sum is zero.           */
+/* ------------------------------------------------------------------ */
+
+/* Row counts of the union pattern (A and B both m x n).  Writes
+ * rpC[m+1] and returns nnz(C), or -1 on allocation failure. */
+i64 or_spadd_rowptr(i32 m, i32 n, const i32 *rpA, const i32 *ciA,
+                    const i32 *rpB, const i32 *ciB, i32 *rpC)
+{
+    i32 *mark = (i32 *)malloc(sizeof(i32) * (size_t)(n > 0 ? n : 1));
+    if (!mark) return -1;
+    for (i32 j = 0; j < n; ++j) mark[j] = -1;
+    i64 total = 0;
+    rpC[0] = 0;
+    for (i32 i = 0; i < m; ++i) {
+        i32 cnt = 0;
+        for (i32 a = rpA[i]; a < rpA[i + 1]; ++a)
+            if (mark[ciA[a]] != i) { mark[ciA[a]] = i; ++cnt; }
+        for (i32 b = rpB[i]; b < rpB[i + 1]; ++b)
+            if (mark[ciB[b]] != i) { mark[ciB[b]] = i; ++cnt; }
+        total += cnt;
+        rpC[i + 1] = (i32)total;
+    }
+    free(mark);
+    return total;
+}
+
+/* Column indices (ascending) and values of C = alpha A + beta B, given
+ * rpC: C_ij = alpha A_ij + beta B_ij, a term being absent where its
+ * input stores no (i,j).  Returns 0, or -1 on allocation failure. */
+int or_spadd_fill(i32 m, i32 n, const i32 *rpA, const i32 *ciA,
+                  const double *vA, const i32 *rpB, const i32 *ciB,
+                  const double *vB, double alpha, double beta,
+                  const i32 *rpC, i32 *ciC, double *vC)
+{
+    i32 *mark = (i32 *)malloc(sizeof(i32) * (size_t)(n > 0 ? n : 1));
+    double *acc = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    if (!mark || !acc) { free(mark); free(acc); return -1; }
+    for (i32 j = 0; j < n; ++j) { mark[j] = -1; acc[j] = 0.0; }
+    for (i32 i = 0; i < m; ++i) {
+        i32 cnt = 0;
+        i32 *cols = ciC + rpC[i];
+        for (i32 a = rpA[i]; a < rpA[i + 1]; ++a) {
+            i32 j = ciA[a];
+            if (mark[j] != i) { mark[j] = i; acc[j] = 0.0; cols[cnt++] = j; }
+            acc[j] += alpha * vA[a];
+        }
+        for (i32 b = rpB[i]; b < rpB[i + 1]; ++b) {
+            i32 j = ciB[b];
+            if (mark[j] != i) { mark[j] = i; acc[j] = 0.0; cols[cnt++] = j; }
+            acc[j] += beta * vB[b];
+        }
+        qsort(cols, (size_t)cnt, sizeof(i32), cmp_i32);
+        for (i32 t = 0; t < cnt; ++t) vC[rpC[i] + t] = acc[cols[t]];
+    }
+    free(mark);
+    free(acc);
+    return 0;
+}
+
+/* VJP of C = alpha A + beta B with upstream gradient V stored on pat(C)
+ * (gC):  gA = alpha V masked to pat(A),  gB = beta V masked to pat(B)
+ * (Table 1, Sp + Sp rows; Section 3.1.4).  Both masks lie inside pat(C).
+ * Returns 0, or -1 on allocation failure. */
+int or_spadd_bwd(i32 m, i32 n, const i32 *rpA, const i32 *ciA,
+                 const i32 *rpB, const i32 *ciB, const i32 *rpC,
+                 const i32 *ciC, const double *gC, double alpha, double beta,
+                 double *gA, double *gB)
+{
+    double *vrow = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    if (!vrow) return -1;
+    for (i32 j = 0; j < n; ++j) vrow[j] = 0.0;
+    for (i32 i = 0; i < m; ++i) {
+        for (i32 c = rpC[i]; c < rpC[i + 1]; ++c) vrow[ciC[c]] = gC[c];
+        if (gA)
+            for (i32 a = rpA[i]; a < rpA[i + 1]; ++a) gA[a] = alpha * vrow[ciA[a]];
+        if (gB)
+            for (i32 b = rpB[i]; b < rpB[i + 1]; ++b) gB[b] = beta * vrow[ciB[b]];
+        for (i32 c = rpC[i]; c < rpC[i + 1]; ++c) vrow[ciC[c]] = 0.0;
+    }
+    free(vrow);
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
 /* Level sets of a triangular matrix: the dependency DAG of the         */
 /* triangular solve of Section 3.1.5.  For a lower matrix, a row with  */
 /* no stored entry left of the diagonal is on level 0, otherwise it is */
