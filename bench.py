@@ -232,6 +232,66 @@ def cg_section(N=512, K=100, reps=5, graph=False):
     }
 
 
+def spadd_section(A, reps=10):
+    """Sparse + sparse on the Poisson operator: C = A - 0.5 B with B a
+    uniform random pattern of 7 draws per row (N(0,1) values), float32.
+    Times the union pattern (symbolic, which ends in a host sync), the
+    numeric pass with and without writing C's columns, and the VJP to
+    both value arrays, each with HIP events on the stream."""
+    import torch
+    from paper_2212_05159_amd import capi, gen
+    from paper_2212_05159_amd import sparse as sp
+
+    B = gen.random_rows(A.nrows, A.ncols, 7, seed=2)
+    Ad = sp.CsrTensor.from_host(A, dtype=torch.float32)
+    Bd = sp.CsrTensor.from_host(B, dtype=torch.float32)
+    dA, dB = Ad.pattern.desc(Ad.vals), Bd.pattern.desc(Bd.vals)
+    m, na, nb = A.nrows, A.nnz, B.nnz
+    ws = capi._ws(capi.csr_spadd_workspace(dA, dB), Ad.vals.device)
+    rpC = torch.empty(m + 1, dtype=torch.int32, device="cuda")
+    nc = capi.csr_spadd_symbolic(dA, dB, rpC, ws)
+    ciC = torch.empty(nc, dtype=torch.int32, device="cuda")
+    vC = torch.empty(nc, dtype=torch.float32, device="cuda")
+    Cp = sp.Pattern(m, A.ncols, rpC, ciC)
+    dC = Cp.desc()
+    gC = torch.randn(nc, dtype=torch.float32, device="cuda")
+    gA = torch.empty(na, dtype=torch.float32, device="cuda")
+    gB = torch.empty(nb, dtype=torch.float32, device="cuda")
+    ops = {
+        "symbolic": lambda: capi.csr_spadd_symbolic(dA, dB, rpC, ws),
+        "fwd": lambda: capi.csr_spadd_fwd(dA, dB, 1.0, -0.5, rpC, ciC, vC),
+        "fwd_values_only": lambda: capi.csr_spadd_fwd(dA, dB, 1.0, -0.5, rpC, None, vC),
+        "bwd": lambda: capi.csr_spadd_bwd(dA, dB, dC, 1.0, -0.5, gC, gA, gB),
+    }
+    rp3 = 3 * 4 * (m + 1)
+    algo = {  # bytes each pass must move at least once
+        "symbolic": rp3 + 4 * (na + nb),
+        "fwd": rp3 + 8 * (na + nb) + 8 * nc,
+        "fwd_values_only": rp3 + 8 * (na + nb) + 4 * nc,
+        "bwd": rp3 + 8 * (na + nb) + 8 * nc,
+    }
+    res = {}
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for name, fn in ops.items():
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        ms = float(np.median(ts))
+        gbs = algo[name] / (ms * 1e-3) / 1e9
+        res[name] = {"ms": round(ms, 4), "GB": round(algo[name] / 1e9, 4), "GB/s": round(gbs, 1),
+                     "frac_hbm_peak": round(gbs / HBM_PEAK_GBS, 4)}
+    res["workload"] = (f"C = A - 0.5 B, A the 3D 7-point Poisson operator (n={m}, nnz={na}), B a "
+                       f"uniform random pattern of 7 draws per row (nnz={nb}), float32; "
+                       f"nnz(C)={nc}")
+    return res
+
+
 # ----------------------------------------------------------------------
 # Measured HBM traffic of the dominant kernel (committed counter summary)
 # ----------------------------------------------------------------------
@@ -582,6 +642,7 @@ def main():
     ap.add_argument("--train-steps", type=int, default=300)
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-blocks part")
     ap.add_argument("--no-cg", action="store_true", help="skip the differentiated-CG part")
+    ap.add_argument("--no-spadd", action="store_true", help="skip the sparse + sparse part")
     ap.add_argument("--batched-blocks", type=int, default=64,
                     help="number of the 512 geometric-graph blocks in the batched part")
     ap.add_argument("--calibrate", type=int, default=0, metavar="M",
@@ -691,6 +752,13 @@ def main():
         cgres = cg_section()
         log(f"CG: {cgres['forward_ms']} ms forward, {cgres['forward_backward_ms']} ms forward+backward")
 
+    spadd = None
+    if not args.no_spadd:
+        log("sparse + sparse part ...")
+        spadd = spadd_section(h["A"])
+        log("spadd: " + ", ".join(f"{k} {v['ms']} ms ({v['GB/s']} GB/s)"
+                                  for k, v in spadd.items() if isinstance(v, dict)))
+
     out = {
         "metric": "fwd+bwd sparse-op GB/s (% HBM peak); PCG time-to-1e-6: learned vs Jacobi",
         "value": round(value, 2),
@@ -718,6 +786,7 @@ def main():
         "pcg": pcg,
         "batched": batched,
         "cg": cgres,
+        "spadd": spadd,
         "breakdown": breakdown,
         "step_bytes": total_bytes,
     }

@@ -8,9 +8,9 @@
  * library never allocates or frees memory: calls that need scratch space
  * take a caller-allocated workspace whose size a *_workspace query gives.
  * Every call is asynchronous on `stream` (a hipStream_t passed as void*;
- * NULL is the default stream) except the two that return a count to the
- * host (csr_spgemm_symbolic and csr_trisolve_analyze), which synchronise
- * the stream.  No exception or abort crosses the ABI: each call returns a
+ * NULL is the default stream) except the three that return a count to
+ * the host (csr_spgemm_symbolic, csr_spadd_symbolic and
+ * csr_trisolve_analyze), which synchronise the stream.  No exception or abort crosses the ABI: each call returns a
  * status code.  Host-side checks are O(1) (null pointers, shapes, dtype);
  * the pattern invariants below are preconditions that only csr_validate
  * checks.
@@ -167,6 +167,39 @@ int csr_spgemm_bwd(const csrad_csr *A, const csrad_csr *B,
                    const csrad_csr *At, const int32_t *permA,
                    const csrad_csr *C, const void *gC, void *gA, void *gB,
                    void *stream);
+
+/* ---------------------------------------------------------------------
+ * Sparse + sparse (Section 3.1.4; Table 1, Sp + Sp rows).
+ * C = alpha A + beta B for A and B of the same shape (m x n).  The
+ * pattern of C is the union of the two patterns, kept structurally: (i,j)
+ * is stored when A or B stores it, even if the sum cancels; column
+ * indices ascending.
+ * csr_spadd_symbolic: C_rowptr[m+1] and *C_nnz_host (synchronises).
+ *   Reads only the patterns.  `work` holds csr_spadd_workspace bytes.
+ * csr_spadd_fwd: C_vals[nnz(C)] and, unless C_colind is NULL, C_colind,
+ *   given C_rowptr from csr_spadd_symbolic for the same patterns (with
+ *   the patterns unchanged, a later call may pass C_colind = NULL to
+ *   recompute values only).  Each value is alpha A_ij + beta B_ij
+ *   evaluated in float64 with the two products and the sum rounded
+ *   separately (an absent term is left out), then rounded once to the
+ *   value type.  With both inputs empty C is empty and C_vals may be
+ *   NULL.
+ * csr_spadd_bwd: VJP with upstream gradient gC on pat(C) (Table 1):
+ *   gA = alpha V on pat(A), gB = beta V on pat(B), each product rounded
+ *   once from float64.  A, B and C carry patterns (vals ignored) and one
+ *   dtype.  Either gradient may be NULL.
+ * alpha and beta are constants of the call (not differentiated).
+ * ------------------------------------------------------------------- */
+int csr_spadd_workspace(const csrad_csr *A, const csrad_csr *B, size_t *bytes);
+int csr_spadd_symbolic(const csrad_csr *A, const csrad_csr *B,
+                       int32_t *C_rowptr, int64_t *C_nnz_host, void *work,
+                       size_t work_bytes, void *stream);
+int csr_spadd_fwd(const csrad_csr *A, const csrad_csr *B, double alpha,
+                  double beta, const int32_t *C_rowptr, int32_t *C_colind,
+                  void *C_vals, void *stream);
+int csr_spadd_bwd(const csrad_csr *A, const csrad_csr *B, const csrad_csr *C,
+                  double alpha, double beta, const void *gC, void *gA,
+                  void *gB, void *stream);
 
 /* ---------------------------------------------------------------------
  * Sparse triangular solve (Section 3.1.5; Table 1, SpSolve row).

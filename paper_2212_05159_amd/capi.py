@@ -54,6 +54,13 @@ _SIGS = {
                                       C.c_void_p]),
     "csr_spgemm_fwd": (C.c_int, [C.c_void_p] * 7 + [C.c_size_t, C.c_void_p]),
     "csr_spgemm_bwd": (C.c_int, [C.c_void_p] * 9),
+    "csr_spadd_workspace": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_size_t)]),
+    "csr_spadd_symbolic": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_int64),
+                                     C.c_void_p, C.c_size_t, C.c_void_p]),
+    "csr_spadd_fwd": (C.c_int, [C.c_void_p, C.c_void_p, C.c_double, C.c_double, C.c_void_p,
+                                C.c_void_p, C.c_void_p, C.c_void_p]),
+    "csr_spadd_bwd": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_double,
+                                C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "csr_trisolve_workspace": (C.c_int, [C.c_void_p, C.POINTER(C.c_size_t)]),
     "csr_trisolve_analyze": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
                                        C.c_void_p, C.c_void_p, C.POINTER(C.c_int32),
@@ -237,6 +244,33 @@ def csr_spgemm_bwd(A, B, At, permA, Cpat, gC, gA, gB):
                                                    C.byref(At) if At is not None else None,
                                                    _ptr(permA), C.byref(Cpat), _ptr(gC), _ptr(gA),
                                                    _ptr(gB), _stream()))
+
+
+def csr_spadd_workspace(A, B):
+    n = C.c_size_t(0)
+    _check("csr_spadd_workspace", load().csr_spadd_workspace(C.byref(A), C.byref(B), C.byref(n)))
+    return n.value
+
+
+def csr_spadd_symbolic(A, B, C_rowptr, work):
+    """Returns nnz(C) of the union pattern (synchronises the stream)."""
+    nnz = C.c_int64(0)
+    _check("csr_spadd_symbolic", load().csr_spadd_symbolic(
+        C.byref(A), C.byref(B), _ptr(C_rowptr), C.byref(nnz), _ptr(work), work.numel(),
+        _stream()))
+    return nnz.value
+
+
+def csr_spadd_fwd(A, B, alpha, beta, C_rowptr, C_colind, C_vals):
+    _check("csr_spadd_fwd", load().csr_spadd_fwd(
+        C.byref(A), C.byref(B), float(alpha), float(beta), _ptr(C_rowptr), _ptr(C_colind),
+        _ptr(C_vals), _stream()))
+
+
+def csr_spadd_bwd(A, B, Cpat, alpha, beta, gC, gA, gB):
+    _check("csr_spadd_bwd", load().csr_spadd_bwd(
+        C.byref(A), C.byref(B), C.byref(Cpat), float(alpha), float(beta), _ptr(gC), _ptr(gA),
+        _ptr(gB), _stream()))
 
 
 def csr_trisolve_workspace(T):

@@ -265,6 +265,21 @@ def random_csr(m: int, n: int, density: float, seed, empty_rows: float = 0.0,
     return _from_coo(m, n, rows, cols, rng.standard_normal(len(rows)))
 
 
+def random_rows(m: int, n: int, per_row: int, seed) -> Csr:
+    """per_row uniform column draws in [0, n) for every row (repeats
+    dropped, so a row holds at most per_row entries) with N(0,1) values.
+    Built row-vectorised, for matrices too large for a dense mask."""
+    rng = np.random.default_rng(seed)
+    cols = np.sort(rng.integers(0, n, size=(m, per_row), dtype=np.int64), axis=1)
+    keep = np.ones(cols.shape, dtype=bool)
+    keep[:, 1:] = cols[:, 1:] != cols[:, :-1]
+    rowptr = np.zeros(m + 1, dtype=np.int64)
+    np.cumsum(keep.sum(axis=1), out=rowptr[1:])
+    assert rowptr[-1] < 2**31, "int32 CSR index space exceeded"
+    colind = cols[keep].astype(np.int32)
+    return Csr(m, n, rowptr.astype(np.int32), colind, rng.standard_normal(len(colind)))
+
+
 def random_lower(n: int, density: float, seed, diag_shift: float = 2.0) -> Csr:
     """Random lower-triangular matrix with a full, well-conditioned
     diagonal (|L_ii| >= diag_shift) and N(0,1)/sqrt(row length) below it."""

@@ -170,6 +170,42 @@ def spgemm_bwd(PA, valsA, PB, valsB, PC, gC, need_A=True, need_B=True):
     return gA, gB
 
 
+def spadd(PA, valsA, PB, valsB, alpha=1.0, beta=1.0):
+    """C = alpha A + beta B on the union pattern.  Returns (Pattern of C, valsC).
+
+    The union pattern is cached on PA for PB (patterns are immutable), so a
+    repeated sum recomputes values only."""
+    if PA.nrows != PB.nrows or PA.ncols != PB.ncols:
+        raise ValueError("spadd: operands differ in shape")
+    dA, dB = PA.desc(valsA), PB.desc(valsB)
+    key = ("spadd", id(PB))
+    hit = PA.plan(key)
+    if hit is not None and hit[0] is PB:
+        PC, cols = hit[1], None
+    else:
+        dev = valsA.device
+        ws = capi._ws(capi.csr_spadd_workspace(dA, dB), dev)
+        rpC = torch.empty(PA.nrows + 1, dtype=torch.int32, device=dev)
+        nnz = capi.csr_spadd_symbolic(dA, dB, rpC, ws)
+        PC = Pattern(PA.nrows, PA.ncols, rpC,
+                     torch.empty(nnz, dtype=torch.int32, device=dev))
+        cols = PC.colind
+    vC = torch.empty(PC.nnz, dtype=valsA.dtype, device=valsA.device)
+    capi.csr_spadd_fwd(dA, dB, alpha, beta, PC.rowptr, cols, vC)
+    if cols is not None:
+        PA.set_plan(key, (PB, PC))
+    return PC, vC
+
+
+def spadd_bwd(PA, PB, PC, gC, alpha=1.0, beta=1.0, need_A=True, need_B=True, dtype=None):
+    dtype = dtype or gC.dtype
+    gA = torch.empty(PA.nnz, dtype=dtype, device=gC.device) if need_A else None
+    gB = torch.empty(PB.nnz, dtype=dtype, device=gC.device) if need_B else None
+    capi.csr_spadd_bwd(PA.desc(dtype=dtype), PB.desc(dtype=dtype), PC.desc(dtype=dtype), alpha,
+                       beta, gC, gA, gB)
+    return gA, gB
+
+
 def trisolve(P, vals, b, lower=True):
     nl, lph, lp, lr, _ = P.levels(lower)
     x = torch.empty_like(b)
@@ -241,6 +277,24 @@ class SpGEMM(torch.autograd.Function):
         return None, gA, None, gB, None
 
 
+class SpAdd(torch.autograd.Function):
+    """alpha A + beta B; returns the value array of C, whose pattern is
+    stored on ``out_pattern``."""
+
+    @staticmethod
+    def forward(ctx, PA, valsA, PB, valsB, alpha, beta, out_pattern):
+        PC, vC = spadd(PA, valsA, PB, valsB, alpha, beta)
+        out_pattern.append(PC)
+        ctx.PA, ctx.PB, ctx.PC, ctx.alpha, ctx.beta = PA, PB, PC, alpha, beta
+        return vC
+
+    @staticmethod
+    def backward(ctx, gC):
+        gA, gB = spadd_bwd(ctx.PA, ctx.PB, ctx.PC, gC.contiguous(), ctx.alpha, ctx.beta,
+                           need_A=ctx.needs_input_grad[1], need_B=ctx.needs_input_grad[3])
+        return None, gA, None, gB, None, None, None
+
+
 class TriSolve(torch.autograd.Function):
     @staticmethod
     def forward(ctx, P, vals, b, lower):
@@ -282,6 +336,27 @@ class CsrTensor:
         if other.dim() == 1:
             return SpMV.apply(self.pattern, self.vals, other)
         return SpMM.apply(self.pattern, self.vals, other)
+
+    def add(self, other, alpha=1.0, beta=1.0):
+        """alpha self + beta other on the union of the two patterns."""
+        box = []
+        vC = SpAdd.apply(self.pattern, self.vals, other.pattern, other.vals, float(alpha),
+                         float(beta), box)
+        return CsrTensor(box[0], vC)
+
+    def __add__(self, other):
+        return self.add(other, 1.0, 1.0)
+
+    def __sub__(self, other):
+        return self.add(other, 1.0, -1.0)
+
+    def __mul__(self, scalar):
+        return CsrTensor(self.pattern, self.vals * scalar)
+
+    __rmul__ = __mul__
+
+    def __neg__(self):
+        return CsrTensor(self.pattern, -self.vals)
 
     def solve_triangular(self, b, lower=True):
         return TriSolve.apply(self.pattern, self.vals, b, lower)
