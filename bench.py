@@ -268,7 +268,7 @@ def spadd_section(A, reps=10):
         "symbolic": rp3 + 4 * (na + nb),
         "fwd": rp3 + 8 * (na + nb) + 8 * nc,
         "fwd_values_only": rp3 + 8 * (na + nb) + 4 * nc,
-        "bwd": rp3 + 8 * (na + nb) + 8 * nc,
+        "bwd": rp3 + 8 * (na + nb) + 4 * nc,  # A's and B's columns, V, gA and gB
     }
     res = {}
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
