@@ -257,10 +257,10 @@ def cg_bwd(A, b, K, gx=None, gR=None):
 def pcg(A, b, mode="jacobi", L=None, tol=1e-6, maxit=10000):
     """Returns (x, iterations, history) ; iterations = -1 on breakdown."""
     n, _, rp, ci, v = _csr(A)
-    m = {"jacobi": 0, "factor": 1, "none": 2}[mode]
+    m = {"jacobi": 0, "factor": 1, "none": 2, "fsai": 3}[mode]
     x = np.empty(n)
     hist = np.full(maxit + 1, np.nan)
-    if m == 1:
+    if m in (1, 3):
         _, _, lrp, lci, lv = _csr(L)
     else:
         lrp = lci = lv = None

@@ -518,7 +518,10 @@ int or_cg_bwd(i32 n, const i32 *rp, const i32 *ci, const double *v,
 /* Preconditioned CG (Section 4.3; Saad).  z = M^{-1} r, rho = r.z,     */
 /* p = z + beta p.  The preconditioner is either Jacobi (mode 0:        */
 /* z = r / diag(A)) or a lower factor L with M = L L^T (mode 1:         */
-/* z = L^{-T} (L^{-1} r), two triangular solves), or none (mode 2).     */
+/* z = L^{-T} (L^{-1} r), two triangular solves), or none (mode 2), or  */
+/* the approximate-inverse form of Section 4.3 (mode 3): M = L L^T      */
+/* approximates A^{-1} itself and is applied as z = L (L^T r), two      */
+/* sparse products.                                                     */
 /* Iterates until ||r|| / ||b|| <= tol or maxit; returns the iteration  */
 /* count, or -1 on breakdown (non-finite or non-positive curvature).    */
 /* hist (maxit+1, may be NULL) receives ||r_t||/||b||.                  */
@@ -538,6 +541,10 @@ static void apply_prec(i32 n, const i32 *rp, const i32 *ci, const double *v,
         or_trisolve(n, lrp, lci, lv, 1, r, tmp);
         /* L^T z = tmp: the adjoint solve of or_trisolve_bwd gives T^{-T} */
         or_trisolve_bwd(n, lrp, lci, lv, 1, tmp, tmp, z, NULL);
+    } else if (mode == 3) {
+        /* tmp = L^T r is the input gradient of the SpMV y = L x */
+        or_spmv_bwd(n, n, lrp, lci, lv, r, r, tmp, NULL);
+        or_spmv(n, lrp, lci, lv, tmp, z);
     } else {
         for (i32 i = 0; i < n; ++i) z[i] = r[i];
     }
