@@ -283,7 +283,10 @@ int csr_cg_finish_bwd(const csrad_csr *A, const void *b, const void *rb,
  * (z = L^{-T} L^{-1} r with L lower triangular, its transpose Lt/perm and
  * its level sets from csr_trisolve_analyze; when Lt->vals is non-NULL it
  * holds L^T's values (csr_transpose_vals, same dtype as L) and perm is not
- * read), 2 none.  scal (16 float64 on
+ * read), 2 none, 3 inverse factor (the form learned in Section 4.3:
+ * M = L L^T approximates A^{-1} and z = L (L^T r) by two sparse products;
+ * L any square sparse matrix, Lt/perm as for kind 1, no level sets:
+ * nlevels 0 and NULL level pointers).  scal (16 float64 on
  * the device): [0] r.z, [1] p.q, [2] alpha, [3] beta, [4] ||b||,
  * [5] ||r||/||b||, [6] done flag, [7] breakdown flag, [8] steps taken,
  * [9] tolerance.  A step that finds ||r||/||b|| <= tol sets done; p.q not
@@ -292,11 +295,12 @@ int csr_cg_finish_bwd(const csrad_csr *A, const void *b, const void *rb,
  * and read scal in between.  hist (hist_cap float64, may be NULL)
  * receives ||r||/||b|| per step.
  * csr_pcg_workspace sizes the workspace shared by init and the steps; for
- * the factor kind pass L and its levels (else NULL, 0, NULL).  init copies
+ * the factor kind pass L and its levels, for the inverse-factor kind L
+ * with nlevels 0 and NULL (else NULL, 0, NULL).  init copies
  * A into an ELL layout inside the workspace and, when every level of L
- * has at least 1024 rows, L and L^T by level as well (values included:
- * call init again after A's or L's values change); the steps read those
- * copies.  A segment whose ELL copy would exceed twice the matrix's nnz is
+ * has at least 1024 rows, L and L^T by level as well (for the inverse
+ * factor, L and L^T whole; values included: call init again after A's or
+ * L's values change); the steps read those copies.  A segment whose ELL copy would exceed twice the matrix's nnz is
  * read from the CSR arrays instead.
  * ------------------------------------------------------------------- */
 int csr_pcg_workspace(const csrad_csr *A, const csrad_csr *L, int32_t nlevels,

@@ -131,15 +131,19 @@ def _dense_lower(Lpat, Lv, n):
     return M
 
 
-def pcg_loss(A, Lpat, Lv, b, nit=4, gamma=0.6):
-    """Residual-history loss of nit PCG iterations with M = L L^T (dense
-    float64 solves; small systems only)."""
+def pcg_loss(A, Lpat, Lv, b, nit=4, gamma=0.6, form="factor"):
+    """Residual-history loss of nit PCG iterations (dense float64; small
+    systems only).  form "factor": M = L L^T approximates A, so the
+    preconditioned residual is z = L^{-T} L^{-1} r (two triangular solves);
+    form "fsai": M = L L^T approximates A^{-1} (Section 4.3), z = L L^T r."""
     n = A.nrows
     Ad = torch.as_tensor(A.todense())
     Ld = _dense_lower(Lpat, Lv, n)
     b = torch.as_tensor(np.asarray(b, np.float64))
 
     def minv(r):
+        if form == "fsai":
+            return Ld @ (Ld.T @ r)
         y = torch.linalg.solve_triangular(Ld, r[:, None], upper=False)
         return torch.linalg.solve_triangular(Ld.T, y, upper=True)[:, 0]
 

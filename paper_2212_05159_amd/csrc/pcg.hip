@@ -11,8 +11,11 @@
 //   factor:  z = L^{-T} (L^{-1} r), L lower triangular with a stored
 //            diagonal (M = L L^T), solved level by level.
 //   none:    z = r
-// init copies A (and, when every level of L is wide, L and L^T by level)
-// into ELL layouts in the workspace; the steps read those copies.
+//   inverse factor: z = L (L^T r), M = L L^T approximating A^{-1} itself
+//            (the form Section 4.3 learns), two sparse products.
+// init copies A (and, when every level of L is wide, L and L^T by level;
+// for the inverse factor, L and L^T whole) into ELL layouts in the
+// workspace; the steps read those copies.
 #include "internal.hpp"
 
 namespace csrad {
@@ -309,6 +312,40 @@ __global__ __launch_bounds__(kThreads) void k_pcg_spmv_ell(
   if (threadIdx.x == 0) part[blockIdx.x] = d;
 }
 
+// out = M in over a one-segment ELL copy of M (or its CSR rows, values
+// through perm when given); with dot_r set, the block's share of
+// <dot_r, out> goes to dot_part[blockIdx.x].  No done check: the inputs do
+// not change once the state is final.
+template <typename TV>
+__global__ __launch_bounds__(kThreads) void k_pcg_ell_apply(
+    int n, const int32_t* __restrict__ w, const int32_t* __restrict__ col,
+    const TV* __restrict__ val, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+    const TV* __restrict__ v, const int32_t* __restrict__ perm, const double* __restrict__ in,
+    double* __restrict__ out, const double* __restrict__ dot_r, double* __restrict__ dot_part) {
+  __shared__ double sm[kThreads / kWave];
+  const int ws = w[0];
+  double d = 0;
+  for (int i = blockIdx.x * kThreads + threadIdx.x; i < n; i += gridDim.x * kThreads) {
+    double s = 0;
+    if (ws >= 0) {
+      for (int k = 0; k < ws; ++k) {
+        const int c = col[(long long)k * n + i];
+        const TV a = val[(long long)k * n + i];
+        if (c >= 0) s += (double)a * in[c];
+      }
+    } else {
+      for (int e = rp[i]; e < rp[i + 1]; ++e)
+        s += (double)(perm ? v[perm[e]] : v[e]) * in[ci[e]];
+    }
+    out[i] = s;
+    if (dot_r) d += dot_r[i] * s;
+  }
+  if (dot_r) {  // uniform over the block
+    d = block_sum(d, sm);
+    if (threadIdx.x == 0) dot_part[blockIdx.x] = d;
+  }
+}
+
 int spmv_blocks(int n) {
   int b = (n + kThreads - 1) / kThreads;
   return b < 1 ? 1 : (b > kSpmvBlocksMax ? kSpmvBlocksMax : b);
@@ -521,7 +558,7 @@ void factor_solves_ell(const Precond& pc, const double* r, double* y, double* z,
                        const double* scal, hipStream_t s, bool level0_done);
 
 struct Precond {
-  int kind;  // 0 Jacobi, 1 factor, 2 none
+  int kind;  // 0 Jacobi, 1 factor, 2 none, 3 inverse factor
   const double* dinv;
   const csrad_csr* L;
   const csrad_csr* Lt;
@@ -531,6 +568,7 @@ struct Precond {
   const int32_t* lp_dev;
   const int32_t* rows;
   FactorPlan plan;
+  Ell invL, invLt;  // inverse factor: one-segment ELL copies of L and L^T
 };
 
 // z = L^{-T} L^{-1} r over the ELL copies, level by level.  The last
@@ -568,6 +606,23 @@ void factor_solves_ell(const Precond& pc, const double* r, double* y, double* z,
   }
 }
 
+// z = L (L^T r) over the inverse factor's ELL copies, with the r.z
+// partials.
+template <typename TV>
+void inverse_factor_apply(int n, const Precond& pc, const double* r, double* y, double* z,
+                          double* rz_parts, hipStream_t s) {
+  const int nbv = vec_blocks(n);
+  const TV* vL = static_cast<const TV*>(pc.L->vals);
+  const TV* vT = pc.Lt->vals ? static_cast<const TV*>(pc.Lt->vals) : vL;
+  const int32_t* pT = pc.Lt->vals ? nullptr : pc.perm;
+  hipLaunchKernelGGL((k_pcg_ell_apply<TV>), dim3(nbv), dim3(kThreads), 0, s, n, pc.invLt.w,
+                     pc.invLt.col, static_cast<const TV*>(pc.invLt.val), pc.Lt->rowptr,
+                     pc.Lt->colind, vT, pT, r, y, nullptr, nullptr);
+  hipLaunchKernelGGL((k_pcg_ell_apply<TV>), dim3(nbv), dim3(kThreads), 0, s, n, pc.invL.w,
+                     pc.invL.col, static_cast<const TV*>(pc.invL.val), pc.L->rowptr,
+                     pc.L->colind, vL, nullptr, y, z, r, rz_parts);
+}
+
 // z = M^{-1} r followed by the r.z and r.r partials.  The factor solves
 // are not conditional on the done flag, so their cost is paid until the
 // host stops stepping.
@@ -593,6 +648,14 @@ int precond_dots(int n, const Precond& pc, const double* r, double* z, double* y
       hipLaunchKernelGGL(k_pcg_precond_dots<1>, dim3(nbv), dim3(kThreads), 0, s, n, pc.dinv, r,
                          z, parts, scal);
     }
+  } else if (pc.kind == 3) {
+    // y = L^T r, then z = L y with the r.z partials (vec_blocks grid, as
+    // the update kernel's, so the partials fit the r.z slots)
+    if (pc.L->dtype == CSRAD_F32) {
+      inverse_factor_apply<float>(n, pc, r, y, z, parts.rz, s);
+    } else {
+      inverse_factor_apply<double>(n, pc, r, y, z, parts.rz, s);
+    }
   } else {
     hipLaunchKernelGGL(k_pcg_precond_dots<2>, dim3(nbv), dim3(kThreads), 0, s, n, pc.dinv, r, z,
                        parts, scal);
@@ -605,7 +668,17 @@ int check_pc(const csrad_csr* A, int kind, const double* dinv, const csrad_csr* 
              const int32_t* lp_dev, const int32_t* rows) {
   if (kind == 0) return dinv ? CSRAD_OK : CSRAD_EINVAL;
   if (kind == 2) return CSRAD_OK;
-  if (kind != 1 || !L || !Lt) return CSRAD_EINVAL;
+  if ((kind != 1 && kind != 3) || !L || !Lt) return CSRAD_EINVAL;
+  if (kind == 3) {
+    CSRAD_TRY(check_csr(L, true));
+    CSRAD_TRY(check_csr(Lt, false));
+    if (L->nrows != A->nrows || L->ncols != A->nrows || Lt->nrows != A->nrows ||
+        Lt->ncols != A->nrows || Lt->nnz != L->nnz)
+      return CSRAD_EINVAL;
+    if (L->nnz > 0 && !perm && !Lt->vals) return CSRAD_EINVAL;
+    if (Lt->vals && Lt->dtype != L->dtype) return CSRAD_EDTYPE;
+    return CSRAD_OK;
+  }
   CSRAD_TRY(check_csr(L, true));
   CSRAD_TRY(check_csr(Lt, false));
   if (L->nrows != A->nrows || L->ncols != A->nrows || Lt->nrows != A->nrows ||
@@ -628,6 +701,7 @@ struct PcgWs {
   double* y;
   Ell ellA;
   FactorPlan plan;
+  Ell invL, invLt;
 };
 
 Ell carve_ell(Carver& cv, int nseg, long long cap, size_t vs) {
@@ -646,7 +720,7 @@ long long ell_cap(long long nnz, int n) {
 }
 
 PcgWs carve_pcg(Carver& cv, const csrad_csr* A, const csrad_csr* L, bool with_plan, int nlevels,
-                const int32_t* lp_host) {
+                const int32_t* lp_host, bool inverse) {
   const int n = A->nrows;
   PcgWs w;
   double* pd = cv.take<double>(kPartsDoubles);
@@ -667,6 +741,12 @@ PcgWs carve_pcg(Carver& cv, const csrad_csr* A, const csrad_csr* L, bool with_pl
     w.plan.diag = cv.take<char>((size_t)(n > 0 ? n : 1) * vs);
     w.plan.d0 = cv.take<double>((size_t)(n > 0 ? n : 1));
     w.plan.ident = cv.take<int32_t>(1);
+  }
+  w.invL = w.invLt = Ell{};
+  if (inverse && L) {
+    const size_t vs = L->dtype == CSRAD_F32 ? 4 : 8;
+    w.invL = carve_ell(cv, 1, ell_cap(L->nnz, n), vs);
+    w.invLt = carve_ell(cv, 1, ell_cap(L->nnz, n), vs);
   }
   return w;
 }
@@ -718,6 +798,18 @@ int build_ell_factor(int n, const Precond& pc, hipStream_t s) {
   return launch_status();
 }
 
+// The inverse factor's one-segment ELL copies of L and L^T (all entries,
+// the diagonal included; L^T's values from Lt's own or through perm).
+template <typename TV>
+int build_ell_inverse(int n, const Precond& pc, hipStream_t s) {
+  const TV* vL = static_cast<const TV*>(pc.L->vals);
+  CSRAD_TRY(build_ell<TV>(pc.invL, n, 1, nullptr, nullptr, nullptr, pc.L->rowptr, pc.L->colind,
+                          vL, nullptr, nullptr, s));
+  const TV* vT = pc.Lt->vals ? static_cast<const TV*>(pc.Lt->vals) : vL;
+  return build_ell<TV>(pc.invLt, n, 1, nullptr, nullptr, nullptr, pc.Lt->rowptr, pc.Lt->colind,
+                       vT, pc.Lt->vals ? nullptr : pc.perm, nullptr, s);
+}
+
 }  // namespace
 }  // namespace csrad
 
@@ -729,7 +821,7 @@ extern "C" int csr_pcg_workspace(const csrad_csr* A, const csrad_csr* L, int32_t
   if (L && (L->nnz < 0 || (nlevels > 0 && !level_ptr_host))) return CSRAD_EINVAL;
   const bool plan = L && nlevels > 0 && ell_levels(nlevels, level_ptr_host);
   Carver cv(nullptr, 0);
-  carve_pcg(cv, A, L, plan, nlevels, level_ptr_host);
+  carve_pcg(cv, A, L, plan, nlevels, level_ptr_host, L && nlevels == 0);
   *bytes = cv.off + 256;
   return CSRAD_OK;
 }
@@ -758,19 +850,19 @@ static int pcg_common(const csrad_csr* A, int kind, const double* dinv, const cs
   CSRAD_TRY(check_csr(A, true));
   if (A->nrows != A->ncols) return CSRAD_EINVAL;
   CSRAD_TRY(check_pc(A, kind, dinv, L, Lt, perm, nlevels, lp_host, lp_dev, rows));
-  const bool fac = kind == 1;
+  const bool fac = kind == 1, inv = kind == 3;
   size_t need = 0;
-  CSRAD_TRY(csr_pcg_workspace(A, fac ? L : nullptr, fac ? nlevels : 0, fac ? lp_host : nullptr,
-                              &need));
+  CSRAD_TRY(csr_pcg_workspace(A, fac || inv ? L : nullptr, fac ? nlevels : 0,
+                              fac ? lp_host : nullptr, &need));
   if (!work || work_bytes < need) return CSRAD_EWORKSPACE;
   Carver cv(work, work_bytes);
-  PcgWs w = carve_pcg(cv, A, fac ? L : nullptr, fac && ell_levels(nlevels, lp_host), nlevels,
-                      lp_host);
+  PcgWs w = carve_pcg(cv, A, fac || inv ? L : nullptr, fac && ell_levels(nlevels, lp_host),
+                      fac ? nlevels : 0, fac ? lp_host : nullptr, inv);
   if (!cv.ok) return CSRAD_EWORKSPACE;
   *parts = w.parts;
   *y = w.y;
   *ellA = w.ellA;
-  *pc = Precond{kind, dinv, L, Lt, perm, nlevels, lp_host, lp_dev, rows, w.plan};
+  *pc = Precond{kind, dinv, L, Lt, perm, nlevels, lp_host, lp_dev, rows, w.plan, w.invL, w.invLt};
   return CSRAD_OK;
 }
 
@@ -799,6 +891,10 @@ extern "C" int csr_pcg_init(const csrad_csr* A, int32_t kind, const double* dinv
   if (pc.kind == 1 && pc.plan.on) {
     if (L->dtype == CSRAD_F32) CSRAD_TRY(build_ell_factor<float>(n, pc, s));
     else CSRAD_TRY(build_ell_factor<double>(n, pc, s));
+  }
+  if (pc.kind == 3) {
+    if (L->dtype == CSRAD_F32) CSRAD_TRY(build_ell_inverse<float>(n, pc, s));
+    else CSRAD_TRY(build_ell_inverse<double>(n, pc, s));
   }
   CSRAD_TRY(precond_dots(n, pc, r, z, y, parts, scal, s));
   hipLaunchKernelGGL(k_pcg_start, dim3(nbv), dim3(kThreads), 0, s, n, parts, z, p, scal);
@@ -833,7 +929,11 @@ extern "C" int csr_pcg_step(const csrad_csr* A, int32_t kind, const double* dinv
                        static_cast<const double*>(A->vals), p, q, parts.pq, scal);
   }
   hipLaunchKernelGGL(k_pcg_alpha, dim3(1), dim3(kRedThreads), 0, s, parts.pq, nbs, scal);
-  if (kind == 1) {
+  if (kind == 3) {
+    hipLaunchKernelGGL(k_pcg_update<1>, dim3(nbv), dim3(kThreads), 0, s, n, p, q, x, r, dinv, z,
+                       parts, nullptr, nullptr, scal);
+    CSRAD_TRY(precond_dots(n, pc, r, z, y, parts, scal, s));
+  } else if (kind == 1) {
     const bool fuse0 = pc.plan.on && nlevels > 1;
     hipLaunchKernelGGL(k_pcg_update<1>, dim3(nbv), dim3(kThreads), 0, s, n, p, q, x, r, dinv, z,
                        parts, fuse0 ? pc.plan.d0 : nullptr, y, scal);

@@ -182,9 +182,15 @@ def loss_weights(nit, gamma):
     return w / w.sum()
 
 
-def pcg_residual_loss(A, Lpat, Lv, b, nit=4, gamma=0.6):
-    """sum_i w_i ||r_i|| / ||b|| over nit PCG iterations with M = L L^T."""
+def pcg_residual_loss(A, Lpat, Lv, b, nit=4, gamma=0.6, form="factor"):
+    """sum_i w_i ||r_i|| / ||b|| over nit PCG iterations with M = L L^T.
+
+    form "factor": M approximates A and z = L^{-T} L^{-1} r (two triangular
+    solves); form "fsai": M approximates A^{-1}, the form Section 4.3
+    learns, and z = L (L^T r) (two sparse products)."""
     def minv(r):
+        if form == "fsai":
+            return sp.SpMV.apply(Lpat, Lv, sp.SpMVT.apply(Lpat, Lv, r))
         return TriSolveT.apply(Lpat, Lv, sp.TriSolve.apply(Lpat, Lv, r, True))
 
     w = loss_weights(nit, gamma)

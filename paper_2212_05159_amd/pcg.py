@@ -3,8 +3,11 @@
 ``pcg(A, b, precond=...)`` runs the library's device-resident PCG steps in
 chunks, reading the device state once per chunk (the steps after
 convergence are no-ops).  Preconditioners: ``"jacobi"`` (1/diag(A)),
-``"factor"`` with a lower-triangular ``L`` (M = L L^T, two level-scheduled
-solves per step) and ``"none"``.  A breakdown (non-positive curvature or a
+``"factor"`` with a lower-triangular ``L`` (M = L L^T approximating A,
+z = L^{-T} L^{-1} r by two level-scheduled solves per step), ``"fsai"``
+with a lower-triangular ``L`` (the form Section 4.3 learns: M = L L^T
+approximating A^{-1}, z = L (L^T r) by two sparse products) and
+``"none"``.  A breakdown (non-positive curvature or a
 non-finite value, e.g. from an indefinite learned M) falls back to
 Jacobi-PCG when ``fallback`` is set.  Vectors and dots are float64; the
 matrix values may be float32.
@@ -17,7 +20,7 @@ import torch
 from . import capi
 from . import sparse as sp
 
-_KIND = {"jacobi": 0, "factor": 1, "none": 2}
+_KIND = {"jacobi": 0, "factor": 1, "none": 2, "fsai": 3}
 
 
 class PCG:
@@ -46,9 +49,17 @@ class PCG:
             Ld, Ltd = L.pattern.desc(L.vals), Lt.desc(Ltv)
             self.Lkeep = (L, Lt, Ltv, Ld, Ltd, lph, lp, lr, perm)
             self.pc = (1, None, Ld, Ltd, perm, nl, lph, lp, lr)
+        elif self.kind == 3:
+            if L is None:
+                raise ValueError("fsai preconditioner needs L")
+            Lt, perm = L.pattern.transpose()
+            Ltv = sp.transpose_vals(L.pattern, L.vals)
+            Ld, Ltd = L.pattern.desc(L.vals), Lt.desc(Ltv)
+            self.Lkeep = (L, Lt, Ltv, Ld, Ltd, perm)
+            self.pc = (3, None, Ld, Ltd, perm, 0, None, None, None)
         else:
             self.pc = (2, None, None, None, None, 0, None, None, None)
-        if self.kind == 1:
+        if self.kind in (1, 3):
             bytes_ = capi.csr_pcg_workspace(self.Ad, self.pc[2], self.pc[5], self.pc[6])
         else:
             bytes_ = capi.csr_pcg_workspace(self.Ad)

@@ -243,6 +243,30 @@ class SpMV(torch.autograd.Function):
         return None, gv, gx
 
 
+class SpMVT(torch.autograd.Function):
+    """y = A^T x through the library's transpose product (the input-gradient
+    kernel of SpMV).  VJP: g_x = A g, g_vals[(i,j)] = x_i g_j on pat(A)."""
+
+    @staticmethod
+    def forward(ctx, P, vals, x):
+        ctx.P = P
+        x = x.contiguous()
+        ctx.save_for_backward(vals, x)
+        y, _ = spmv_bwd(P, vals, x, x, need_x=True, need_vals=False)
+        return y
+
+    @staticmethod
+    def backward(ctx, g):
+        vals, x = ctx.saved_tensors
+        g = g.contiguous()
+        gx = spmv(ctx.P, vals, g) if ctx.needs_input_grad[2] else None
+        gv = None
+        if ctx.needs_input_grad[1]:
+            # the value gradient of SpMV with its roles swapped: g_y -> x, x -> g
+            _, gv = spmv_bwd(ctx.P, vals, g, x, need_x=False, need_vals=True)
+        return None, gv, gx
+
+
 class SpMM(torch.autograd.Function):
     @staticmethod
     def forward(ctx, P, vals, B):
@@ -357,6 +381,10 @@ class CsrTensor:
 
     def __neg__(self):
         return CsrTensor(self.pattern, -self.vals)
+
+    def tmatvec(self, x):
+        """A^T x (differentiable in the values and x)."""
+        return SpMVT.apply(self.pattern, self.vals, x)
 
     def solve_triangular(self, b, lower=True):
         return TriSolve.apply(self.pattern, self.vals, b, lower)

@@ -5,9 +5,14 @@ Independent checks: a diagonal L = D^{-1/2} gives Jacobi's iterates and
 L = I gives plain CG's (other branches of the oracle), an exact inverse
 factor (L L^T = A^{-1}, dense Cholesky of the inverse) converges in one
 step, and the first residual matches dense NumPy arithmetic with M = L L^T
-(so a transposed product M = L^T L would fail it)."""
+(so a transposed product M = L^T L would fail it).  The reference loss of
+the learned form: a diagonal L gives the same loss as the factor form with
+the reciprocal diagonal (the same M, through triangular solves), and its
+gradient matches central differences."""
 import numpy as np
+import torch
 
+from oracle import mpnn_ref
 from paper_2212_05159_amd import gen
 
 
@@ -70,3 +75,38 @@ def test_first_residual_matches_dense_m_equals_l_lt(orc):
     zt = Mt @ b
     rt = b - (b @ zt) / (zt @ Ad @ zt) * (Ad @ zt)
     assert abs(np.linalg.norm(rt) - np.linalg.norm(r1)) / np.linalg.norm(b) > 1e-6
+
+
+def test_loss_diagonal_fsai_equals_factor_form():
+    A = gen.poisson2d(8, 8)
+    Lp = gen.tril(A)
+    d = np.diag(A.todense())
+    diag = Lp.rowptr[1:] - 1  # the diagonal is last in each row of tril(A)
+    v_inv = np.zeros(Lp.nnz)
+    v_inv[diag] = 1.0 / np.sqrt(d)
+    v_fac = np.zeros(Lp.nnz)
+    v_fac[diag] = np.sqrt(d)
+    b = gen.normal(64, seed=6)
+    l_inv = mpnn_ref.pcg_loss(A, Lp, torch.as_tensor(v_inv), b, form="fsai")
+    l_fac = mpnn_ref.pcg_loss(A, Lp, torch.as_tensor(v_fac), b, form="factor")
+    assert abs(float(l_inv) - float(l_fac)) < 1e-13 * float(l_fac)
+
+
+def test_loss_fsai_gradient_matches_central_differences():
+    A = gen.poisson2d(8, 8)
+    rows = np.arange(64)
+    P = gen._from_coo(64, 64, np.concatenate([rows, rows[1:]]),
+                      np.concatenate([rows, rows[:-1]]), np.ones(127))  # bidiagonal
+    rng = np.random.default_rng(7)
+    v = 0.5 + 0.1 * rng.standard_normal(P.nnz)
+    b = gen.normal(64, seed=8)
+    t = torch.as_tensor(v).requires_grad_(True)
+    mpnn_ref.pcg_loss(A, P, t, b, form="fsai").backward()
+    h = 1e-6
+    for e in (0, 5, 40, 100):
+        vp, vm = v.copy(), v.copy()
+        vp[e] += h
+        vm[e] -= h
+        fd = (float(mpnn_ref.pcg_loss(A, P, torch.as_tensor(vp), b, form="fsai")) -
+              float(mpnn_ref.pcg_loss(A, P, torch.as_tensor(vm), b, form="fsai"))) / (2 * h)
+        assert abs(fd - float(t.grad[e])) < 1e-6 * max(1.0, abs(fd)), (e, fd, float(t.grad[e]))
