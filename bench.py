@@ -339,13 +339,23 @@ def pcg_section(n_eval, n_train, train_steps, systems):
     log(f"trained the network: {train_steps} systems of {n_train}^2 in {train_s:.1f} s "
         f"(loss {np.mean(hist[:20]):.4f} -> {np.mean(hist[-20:]):.4f}; selected parameters: "
         f"{model.selected_score:.1f} mean validation iterations)")
+    # the approximate-inverse form of the same network (M = L L^T ~ A^{-1})
+    t0 = time.perf_counter()
+    model_inv = learned.MPNN(seed=1, form="fsai")
+    hist_inv = learned.train(model_inv, N=n_train, steps=train_steps, lr=3e-3, nit=16, seed=5,
+                             val_systems=val, eval_every=50)
+    torch.cuda.synchronize()
+    train_inv_s = time.perf_counter() - t0
+    log(f"trained the inverse-form network in {train_inv_s:.1f} s (loss "
+        f"{np.mean(hist_inv[:20]):.4f} -> {np.mean(hist_inv[-20:]):.4f}; selected parameters: "
+        f"{model_inv.selected_score:.1f} mean validation iterations)")
     fam = learned.Q1Family(n_eval)
     t0 = time.perf_counter()
     nl = fam.Lpat.levels(True)[0]
     fam.Lpat.transpose()
     torch.cuda.synchronize()
     analysis_ms = (time.perf_counter() - t0) * 1e3
-    methods = ("learned", "untrained", "jacobi", "cg")
+    methods = ("learned", "untrained", "fsai", "jacobi", "cg")
     maxit = 40000
 
     def solve(key, A, b, cap=maxit):
@@ -357,6 +367,10 @@ def pcg_section(n_eval, n_train, train_steps, systems):
             # than replayed from a captured graph; the short Jacobi and plain
             # steps run faster from the graph: each method runs its faster way
             return pcgmod.pcg(A, b, "factor", L=L, tol=1e-6, maxit=cap, chunk=50, graph=False)
+        if key == "fsai":
+            with torch.no_grad():
+                L = sp.CsrTensor(fam.Lpat, model_inv(A, fam.Lpat))
+            return pcgmod.pcg(A, b, "fsai", L=L, tol=1e-6, maxit=cap, chunk=50, graph=False)
         return pcgmod.pcg(A, b, "jacobi" if key == "jacobi" else "none", tol=1e-6, maxit=cap,
                           chunk=50, graph=True)
 
@@ -394,12 +408,15 @@ def pcg_section(n_eval, n_train, train_steps, systems):
         "median_ms": med,
         "median_iterations": {k: float(np.median(v)) for k, v in iters.items()},
         "learned_speedup_vs_jacobi": round(med["jacobi"] / med["learned"], 3),
+        "fsai_speedup_vs_jacobi": round(med["jacobi"] / med["fsai"], 3),
         "fallbacks": fallbacks,
         "level_analysis_ms": round(analysis_ms, 3),
         "train": {"systems": train_steps, "grid": n_train, "seconds": round(train_s, 2),
                   "lr": 3e-3, "pcg_steps_in_loss": 16,
                   "selection": "best mean PCG iterations on 4 held-out systems of the training grid",
-                  "validation_iterations": model.selected_score},
+                  "validation_iterations": model.selected_score,
+                  "fsai_seconds": round(train_inv_s, 2),
+                  "fsai_validation_iterations": model_inv.selected_score},
     }
 
 

@@ -135,8 +135,16 @@ class TriSolveT(torch.autograd.Function):
 # The network
 # ----------------------------------------------------------------------
 class MPNN(torch.nn.Module):
-    def __init__(self, seed=0, device="cuda"):
+    """form "factor": L approximates A's Cholesky factor (M^{-1} = L^{-T} L^{-1}).
+    form "fsai": the approximate-inverse form of Section 4.3 (M = L L^T
+    approximates A^{-1}); the readout's factor F is mapped entrywise to
+    L_ii = F_ii / d_i and L_ij = -F_ij / d_i, so the untrained network gives
+    the first-order inverse factor L = D^{-1} (D - A_L) D^{-1/2} (A_L the
+    strictly lower part of A, up to the 1e-3 on the diagonal)."""
+
+    def __init__(self, seed=0, device="cuda", form="factor"):
         super().__init__()
+        self.form = form
         g = torch.Generator().manual_seed(seed)
 
         def init(k, scale=1.0):
@@ -171,7 +179,20 @@ class MPNN(torch.nn.Module):
             H = Dense.apply(H, AH, W, b, True)
         P = Dense.apply(H, None, self.Wp, None, False)
         t = SDDMM.apply(Lpat, P, H)
-        return Readout.apply(t, Lpat, ahatL, dsqrt)
+        F = Readout.apply(t, Lpat, ahatL, dsqrt)
+        if self.form == "fsai":
+            F = F * inverse_factor_scale(Lpat, dsqrt)
+        return F
+
+
+def inverse_factor_scale(Lpat, dsqrt):
+    """Per-entry scale of the approximate-inverse mapping: 1/d_i on the
+    diagonal, -1/d_i below it (d_i = dsqrt_i^2)."""
+    n = Lpat.nrows
+    rows = torch.repeat_interleave(torch.arange(n, device=dsqrt.device),
+                                   (Lpat.rowptr[1:] - Lpat.rowptr[:-1]).long())
+    sign = torch.where(rows == Lpat.colind.long(), 1.0, -1.0).to(dsqrt.dtype)
+    return sign / (dsqrt * dsqrt)[rows]
 
 
 # ----------------------------------------------------------------------
@@ -285,7 +306,8 @@ def mean_iterations(model, fam, systems, tol=1e-6):
     with torch.no_grad():
         for A, b in systems:
             L = sp.CsrTensor(fam.Lpat, model(A, fam.Lpat))
-            _, info = pcgmod.pcg(A, b, "factor", L=L, tol=tol, fallback=False)
+            _, info = pcgmod.pcg(A, b, getattr(model, "form", "factor"), L=L, tol=tol,
+                                 fallback=False)
             its.append(info["iters"] if info["converged"] else float("inf"))
     return float(np.mean(its))
 
@@ -317,7 +339,8 @@ def train(model, N=256, steps=200, lr=1e-3, nit=4, gamma=0.6, seed=5, log_every=
         b = torch.as_tensor(rng.standard_normal(fam.P.nrows), device=A.vals.device).float()
         opt.zero_grad()
         Lv = model(A, fam.Lpat)
-        loss = pcg_residual_loss(A, fam.Lpat, Lv, b, nit, gamma)
+        loss = pcg_residual_loss(A, fam.Lpat, Lv, b, nit, gamma,
+                                 form=getattr(model, "form", "factor"))
         loss.backward()
         opt.step()
         history.append(float(loss.detach()))

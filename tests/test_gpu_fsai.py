@@ -186,3 +186,21 @@ def test_paper_8x8_bidiagonal_training():
         it_n.append(i_n["iters"])
     print(f"mean iterations to 1e-6: learned M {np.mean(it_f):.2f}, plain CG {np.mean(it_n):.2f}")
     assert np.mean(it_f) < np.mean(it_n) - 1.0
+
+
+def test_untrained_inverse_form_is_first_order_inverse_factor():
+    """Wp = 0: L = D^{-1} (D - A_L) D^{-1/2}, the diagonal times (1 + 1e-3)."""
+    fam = learned.Q1Family(24)
+    A, vals = fam.system(1e-2, 0.3)
+    model = learned.MPNN(form="fsai")
+    with torch.no_grad():
+        Lv = model(A, fam.Lpat)
+    Ah = gen.Csr(fam.pattern_host.nrows, fam.pattern_host.ncols, fam.pattern_host.rowptr,
+                 fam.pattern_host.colind, vals.astype(np.float32).astype(np.float64))
+    T = gen.tril(Ah)
+    rows = T.row_of_entry()
+    d = np.zeros(T.nrows)
+    d[rows[T.colind == rows]] = T.vals[T.colind == rows]
+    want = np.where(T.colind < rows, -T.vals / (d[rows] * np.sqrt(d[T.colind])),
+                    (1 + learned.DELTA) / np.sqrt(d[rows]))
+    assert rel_err(Lv, want) < 1e-6
