@@ -292,6 +292,38 @@ def spadd_section(A, reps=10):
     return res
 
 
+def spai_section(grids=(256, 1024)):
+    """Sparse approximate inverse by direct minimisation on the 2D 5-point
+    Poisson matrix (float32): from M = mask(A), steepest descent with exact
+    steps until ||grad|| < 0.01, timed whole (HIP events around the solve,
+    one host read of the gradient norm per iteration) after one untimed
+    solve; 256^2 is the largest size of the paper's timing study."""
+    import torch
+    from paper_2212_05159_amd import gen
+    from paper_2212_05159_amd import sparse as sp
+    from paper_2212_05159_amd.spai import Spai
+
+    out = {}
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for N in grids:
+        A = gen.poisson2d(N, N)
+        prob = Spai(sp.CsrTensor.from_host(A, dtype=torch.float32))
+        prob.solve(tol=0.01, max_iter=200)
+        torch.cuda.synchronize()
+        e0.record()
+        _, info = prob.solve(tol=0.01, max_iter=200)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        out[f"{N}^2"] = {"n": A.nrows, "nnz": A.nnz, "iterations": info["iters"],
+                         "converged": info["converged"], "loss_start": info["history"][0],
+                         "loss": round(info["loss"], 4), "solve_ms": round(ms, 3),
+                         "ms_per_iteration": round(ms / max(info["iters"], 1), 4)}
+    out["workload"] = ("||I - M A||_F^2 over mask(M) = mask(A), 2D 5-point Poisson, float32, "
+                       "from M = mask(A) to ||grad|| < 0.01")
+    return out
+
+
 # ----------------------------------------------------------------------
 # Measured HBM traffic of the dominant kernel (committed counter summary)
 # ----------------------------------------------------------------------
@@ -660,6 +692,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-blocks part")
     ap.add_argument("--no-cg", action="store_true", help="skip the differentiated-CG part")
     ap.add_argument("--no-spadd", action="store_true", help="skip the sparse + sparse part")
+    ap.add_argument("--no-spai", action="store_true", help="skip the sparse-approximate-inverse part")
     ap.add_argument("--batched-blocks", type=int, default=64,
                     help="number of the 512 geometric-graph blocks in the batched part")
     ap.add_argument("--calibrate", type=int, default=0, metavar="M",
@@ -776,6 +809,13 @@ def main():
         log("spadd: " + ", ".join(f"{k} {v['ms']} ms ({v['GB/s']} GB/s)"
                                   for k, v in spadd.items() if isinstance(v, dict)))
 
+    spai = None
+    if not args.no_spai:
+        log("sparse approximate inverse part ...")
+        spai = spai_section()
+        log("spai: " + ", ".join(f"{k} {v['iterations']} it {v['solve_ms']} ms"
+                                 for k, v in spai.items() if isinstance(v, dict)))
+
     out = {
         "metric": "fwd+bwd sparse-op GB/s (% HBM peak); PCG time-to-1e-6: learned vs Jacobi",
         "value": round(value, 2),
@@ -804,6 +844,7 @@ def main():
         "batched": batched,
         "cg": cgres,
         "spadd": spadd,
+        "spai": spai,
         "breakdown": breakdown,
         "step_bytes": total_bytes,
     }
