@@ -190,6 +190,34 @@ def geometric_graph_laplacian(block: int, shift: float = 1e-2,
     return _from_coo(n, n, rows, cols, vals)
 
 
+def geometric_graph(n: int, k: int, seed) -> Csr:
+    """Adjacency of a random geometric graph: points ~ U[0,1)^2 from
+    default_rng(seed), exact k nearest neighbours, union-symmetrised, unit
+    weights, no self loops (k = 4 gives about 5 incident edges per node)."""
+    from scipy.spatial import cKDTree
+
+    rng = np.random.default_rng(seed)
+    pts = rng.random((n, 2))
+    _, nbr = cKDTree(pts).query(pts, k=k + 1)
+    src = np.repeat(np.arange(n, dtype=np.int64), k)
+    dst = nbr[:, 1:].reshape(-1).astype(np.int64)
+    keep = src != dst
+    src, dst = src[keep], dst[keep]
+    key = np.unique(np.concatenate([src * n + dst, dst * n + src]))
+    g = _from_coo(n, n, key // n, key % n, np.ones(len(key)))
+    g.points = pts
+    return g
+
+
+def node_classes(points: np.ndarray, nclass: int, seed) -> np.ndarray:
+    """Class of each point: its nearest of nclass centres ~ U[0,1)^2 drawn
+    from default_rng(seed) (spatially coherent labels on a geometric graph)."""
+    from scipy.spatial import cKDTree
+
+    centres = np.random.default_rng(seed).random((nclass, 2))
+    return cKDTree(centres).query(points, k=1)[1].astype(np.int64)
+
+
 def block_diag(blocks: list[Csr]) -> tuple[Csr, np.ndarray]:
     """Concatenate square CSR blocks block-diagonally.
 
