@@ -324,6 +324,50 @@ def spai_section(grids=(256, 1024)):
     return out
 
 
+def gcn_section(sizes=(2708, 19717, 89250, 343565, 914231), C=128, epochs=20):
+    """Training epochs of the two-layer GCN (hidden 16, 6 classes, dropout
+    0.5, Adam with L2 5e-4) on synthetic random geometric graphs (k = 4
+    nearest neighbours, union-symmetrised: about 5 incident edges per node)
+    with the node counts of the paper's GCN timings; C input features
+    (noisy one-hot of a spatial class), 20 labelled nodes per class.  One
+    epoch is the forward pass, the backward pass and the optimiser step;
+    HIP events around `epochs` epochs after 3 untimed ones."""
+    import torch
+    from paper_2212_05159_amd import gcn, gen
+    from paper_2212_05159_amd import sparse as sp
+
+    out = {}
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for n in sizes:
+        A = gen.geometric_graph(n, 4, seed=[11, n])
+        y = gen.node_classes(A.points, 6, seed=[12, n])
+        rng = np.random.default_rng([13, n])
+        X = torch.as_tensor(0.6 * np.eye(C, dtype=np.float32)[y] +
+                            rng.standard_normal((n, C), dtype=np.float32), device="cuda")
+        mask = np.zeros(n, bool)
+        for c in range(6):
+            idx = np.flatnonzero(y == c)
+            mask[rng.choice(idx, min(20, len(idx)), replace=False)] = True
+        G = sp.CsrTensor.from_host(A)
+        G.pattern.transpose()  # the SpMM backward's transpose, built once per graph
+        labels = torch.as_tensor(y, device="cuda")
+        tm = torch.as_tensor(mask, device="cuda")
+        model = gcn.GCN(C, 16, 6, seed=0)
+        gcn.train(model, G, X, labels, tm, epochs=3)
+        torch.cuda.synchronize()
+        e0.record()
+        hist = gcn.train(model, G, X, labels, tm, epochs=epochs)
+        e1.record()
+        torch.cuda.synchronize()
+        out[str(n)] = {"nnz": A.nnz, "edges_per_node": round(A.nnz / n, 2),
+                       "ms_per_epoch": round(e0.elapsed_time(e1) / epochs, 4),
+                       "loss": round(hist[-1], 4)}
+    out["workload"] = (f"two-layer GCN (C={C} -> 16 -> 6), random geometric graphs (kNN k=4, "
+                       f"union-symmetrised), float32; ms per training epoch (forward, backward, "
+                       f"Adam step) over {epochs} epochs")
+    return out
+
+
 # ----------------------------------------------------------------------
 # Measured HBM traffic of the dominant kernel (committed counter summary)
 # ----------------------------------------------------------------------
@@ -693,6 +737,7 @@ def main():
     ap.add_argument("--no-cg", action="store_true", help="skip the differentiated-CG part")
     ap.add_argument("--no-spadd", action="store_true", help="skip the sparse + sparse part")
     ap.add_argument("--no-spai", action="store_true", help="skip the sparse-approximate-inverse part")
+    ap.add_argument("--no-gcn", action="store_true", help="skip the graph-convolution part")
     ap.add_argument("--batched-blocks", type=int, default=64,
                     help="number of the 512 geometric-graph blocks in the batched part")
     ap.add_argument("--calibrate", type=int, default=0, metavar="M",
@@ -816,6 +861,13 @@ def main():
         log("spai: " + ", ".join(f"{k} {v['iterations']} it {v['solve_ms']} ms"
                                  for k, v in spai.items() if isinstance(v, dict)))
 
+    gcnres = None
+    if not args.no_gcn:
+        log("graph-convolution part ...")
+        gcnres = gcn_section()
+        log("gcn: " + ", ".join(f"N={k} {v['ms_per_epoch']} ms/epoch"
+                                for k, v in gcnres.items() if isinstance(v, dict)))
+
     out = {
         "metric": "fwd+bwd sparse-op GB/s (% HBM peak); PCG time-to-1e-6: learned vs Jacobi",
         "value": round(value, 2),
@@ -845,6 +897,7 @@ def main():
         "cg": cgres,
         "spadd": spadd,
         "spai": spai,
+        "gcn": gcnres,
         "breakdown": breakdown,
         "step_bytes": total_bytes,
     }
