@@ -12,7 +12,9 @@
 //            diagonal (M = L L^T), solved level by level.
 //   none:    z = r
 //   inverse factor: z = L (L^T r), M = L L^T approximating A^{-1} itself
-//            (the form Section 4.3 learns), two sparse products.
+//            (the form Section 4.3 learns), two sparse products; r.z is
+//            taken as ||L^T r||^2 from the first, and the second is fused
+//            with the p update.
 // init copies A (and, when every level of L is wide, L and L^T by level;
 // for the inverse factor, L and L^T whole) into ELL layouts in the
 // workspace; the steps read those copies.
@@ -313,16 +315,21 @@ __global__ __launch_bounds__(kThreads) void k_pcg_spmv_ell(
 }
 
 // out = M in over a one-segment ELL copy of M (or its CSR rows, values
-// through perm when given); with dot_r set, the block's share of
-// <dot_r, out> goes to dot_part[blockIdx.x].  No done check: the inputs do
-// not change once the state is final.
-template <typename TV>
+// through perm when given).  MODE 0: nothing else; MODE 1: the block's
+// share of <out, out> goes to dot_part[blockIdx.x]; MODE 2: p = out +
+// beta p with beta from scal (the whole kernel is skipped once the state
+// is final, as the p update is).  Modes 0 and 1 have no done check: their
+// inputs do not change once the state is final.
+template <typename TV, int MODE>
 __global__ __launch_bounds__(kThreads) void k_pcg_ell_apply(
     int n, const int32_t* __restrict__ w, const int32_t* __restrict__ col,
     const TV* __restrict__ val, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
     const TV* __restrict__ v, const int32_t* __restrict__ perm, const double* __restrict__ in,
-    double* __restrict__ out, const double* __restrict__ dot_r, double* __restrict__ dot_part) {
+    double* __restrict__ out, double* __restrict__ p, double* __restrict__ dot_part,
+    const double* __restrict__ scal) {
   __shared__ double sm[kThreads / kWave];
+  if (MODE == 2 && scal[P_DONE] != 0.0) return;
+  const double beta = MODE == 2 ? scal[P_BETA] : 0.0;
   const int ws = w[0];
   double d = 0;
   for (int i = blockIdx.x * kThreads + threadIdx.x; i < n; i += gridDim.x * kThreads) {
@@ -338,9 +345,10 @@ __global__ __launch_bounds__(kThreads) void k_pcg_ell_apply(
         s += (double)(perm ? v[perm[e]] : v[e]) * in[ci[e]];
     }
     out[i] = s;
-    if (dot_r) d += dot_r[i] * s;
+    if (MODE == 1) d += s * s;
+    if (MODE == 2) p[i] = s + beta * p[i];
   }
-  if (dot_r) {  // uniform over the block
+  if (MODE == 1) {
     d = block_sum(d, sm);
     if (threadIdx.x == 0) dot_part[blockIdx.x] = d;
   }
@@ -606,21 +614,34 @@ void factor_solves_ell(const Precond& pc, const double* r, double* y, double* z,
   }
 }
 
-// z = L (L^T r) over the inverse factor's ELL copies, with the r.z
-// partials.
+// The inverse factor's two products over its ELL copies.  y = L^T r with
+// the partials of r.z = r.(L L^T r) = ||y||^2 (vec_blocks grid, as the
+// update kernel's, so they fit the r.z slots); then z = L y, fused with
+// p = z + beta p inside a step (fuse_p), plain at init.
 template <typename TV>
-void inverse_factor_apply(int n, const Precond& pc, const double* r, double* y, double* z,
-                          double* rz_parts, hipStream_t s) {
-  const int nbv = vec_blocks(n);
+void inverse_factor_y(int n, const Precond& pc, const double* r, double* y, double* rz_parts,
+                      hipStream_t s) {
   const TV* vL = static_cast<const TV*>(pc.L->vals);
   const TV* vT = pc.Lt->vals ? static_cast<const TV*>(pc.Lt->vals) : vL;
   const int32_t* pT = pc.Lt->vals ? nullptr : pc.perm;
-  hipLaunchKernelGGL((k_pcg_ell_apply<TV>), dim3(nbv), dim3(kThreads), 0, s, n, pc.invLt.w,
-                     pc.invLt.col, static_cast<const TV*>(pc.invLt.val), pc.Lt->rowptr,
-                     pc.Lt->colind, vT, pT, r, y, nullptr, nullptr);
-  hipLaunchKernelGGL((k_pcg_ell_apply<TV>), dim3(nbv), dim3(kThreads), 0, s, n, pc.invL.w,
-                     pc.invL.col, static_cast<const TV*>(pc.invL.val), pc.L->rowptr,
-                     pc.L->colind, vL, nullptr, y, z, r, rz_parts);
+  hipLaunchKernelGGL((k_pcg_ell_apply<TV, 1>), dim3(vec_blocks(n)), dim3(kThreads), 0, s, n,
+                     pc.invLt.w, pc.invLt.col, static_cast<const TV*>(pc.invLt.val),
+                     pc.Lt->rowptr, pc.Lt->colind, vT, pT, r, y, nullptr, rz_parts, nullptr);
+}
+
+template <typename TV>
+void inverse_factor_z(int n, const Precond& pc, const double* y, double* z, double* p,
+                      const double* scal, hipStream_t s) {
+  const TV* vL = static_cast<const TV*>(pc.L->vals);
+  if (p) {
+    hipLaunchKernelGGL((k_pcg_ell_apply<TV, 2>), dim3(vec_blocks(n)), dim3(kThreads), 0, s, n,
+                       pc.invL.w, pc.invL.col, static_cast<const TV*>(pc.invL.val),
+                       pc.L->rowptr, pc.L->colind, vL, nullptr, y, z, p, nullptr, scal);
+  } else {
+    hipLaunchKernelGGL((k_pcg_ell_apply<TV, 0>), dim3(vec_blocks(n)), dim3(kThreads), 0, s, n,
+                       pc.invL.w, pc.invL.col, static_cast<const TV*>(pc.invL.val),
+                       pc.L->rowptr, pc.L->colind, vL, nullptr, y, z, nullptr, nullptr, scal);
+  }
 }
 
 // z = M^{-1} r followed by the r.z and r.r partials.  The factor solves
@@ -648,13 +669,13 @@ int precond_dots(int n, const Precond& pc, const double* r, double* z, double* y
       hipLaunchKernelGGL(k_pcg_precond_dots<1>, dim3(nbv), dim3(kThreads), 0, s, n, pc.dinv, r,
                          z, parts, scal);
     }
-  } else if (pc.kind == 3) {
-    // y = L^T r, then z = L y with the r.z partials (vec_blocks grid, as
-    // the update kernel's, so the partials fit the r.z slots)
+  } else if (pc.kind == 3) {  // init: y = L^T r (+ r.z partials), z = L y
     if (pc.L->dtype == CSRAD_F32) {
-      inverse_factor_apply<float>(n, pc, r, y, z, parts.rz, s);
+      inverse_factor_y<float>(n, pc, r, y, parts.rz, s);
+      inverse_factor_z<float>(n, pc, y, z, nullptr, scal, s);
     } else {
-      inverse_factor_apply<double>(n, pc, r, y, z, parts.rz, s);
+      inverse_factor_y<double>(n, pc, r, y, parts.rz, s);
+      inverse_factor_z<double>(n, pc, y, z, nullptr, scal, s);
     }
   } else {
     hipLaunchKernelGGL(k_pcg_precond_dots<2>, dim3(nbv), dim3(kThreads), 0, s, n, pc.dinv, r, z,
@@ -930,9 +951,17 @@ extern "C" int csr_pcg_step(const csrad_csr* A, int32_t kind, const double* dinv
   }
   hipLaunchKernelGGL(k_pcg_alpha, dim3(1), dim3(kRedThreads), 0, s, parts.pq, nbs, scal);
   if (kind == 3) {
+    // x, r and r.r; y = L^T r with r.z = ||y||^2; rho', beta; then z = L y
+    // fused with the p update
     hipLaunchKernelGGL(k_pcg_update<1>, dim3(nbv), dim3(kThreads), 0, s, n, p, q, x, r, dinv, z,
                        parts, nullptr, nullptr, scal);
-    CSRAD_TRY(precond_dots(n, pc, r, z, y, parts, scal, s));
+    if (L->dtype == CSRAD_F32) inverse_factor_y<float>(n, pc, r, y, parts.rz, s);
+    else inverse_factor_y<double>(n, pc, r, y, parts.rz, s);
+    hipLaunchKernelGGL(k_pcg_beta, dim3(1), dim3(kRedThreads), 0, s, parts, nbv, scal, hist,
+                       hist_cap);
+    if (L->dtype == CSRAD_F32) inverse_factor_z<float>(n, pc, y, z, p, scal, s);
+    else inverse_factor_z<double>(n, pc, y, z, p, scal, s);
+    return launch_status();
   } else if (kind == 1) {
     const bool fuse0 = pc.plan.on && nlevels > 1;
     hipLaunchKernelGGL(k_pcg_update<1>, dim3(nbv), dim3(kThreads), 0, s, n, p, q, x, r, dinv, z,
