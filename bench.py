@@ -33,6 +33,7 @@ Prints one JSON line on stdout; progress goes to stderr.
 from __future__ import annotations
 
 import argparse
+import concurrent.futures as cf
 import json
 import os
 import sys
@@ -613,7 +614,15 @@ class Marks:
         return out
 
 
-def run_step(d, marks):
+def _keep(outs, **kw):
+    if outs is not None:
+        outs.update(kw)
+
+
+def run_step(d, marks, outs=None):
+    """One step, every op in sequence on the current stream (per-op event
+    marks give an exact attribution of the step time).  With outs (a dict),
+    the step's outputs are stored in it."""
     from paper_2212_05159_amd import sparse as sp
 
     marks.mark("start")
@@ -626,13 +635,13 @@ def run_step(d, marks):
     marks.mark("transpose P")
     vPt = sp.transpose_vals(PP, d.P_v)
     marks.mark("transpose vals P")
-    sp.spmv(PA, d.A_v, d.x)
+    y = sp.spmv(PA, d.A_v, d.x)
     marks.mark("spmv fwd")
-    sp.spmv_bwd(PA, d.A_v, d.x, d.gy, mode=d.spmv_bwd_mode)
+    gx, gv = sp.spmv_bwd(PA, d.A_v, d.x, d.gy, mode=d.spmv_bwd_mode)
     marks.mark("spmv bwd")
-    sp.spmm(PA, d.A_v, d.B, plan=d.plan_fwd)
+    C = sp.spmm(PA, d.A_v, d.B, plan=d.plan_fwd)
     marks.mark("spmm fwd")
-    sp.spmm_bwd(PA, d.A_v, d.B, d.G, plan=d.plan_bwd)
+    gB, gvm = sp.spmm_bwd(PA, d.A_v, d.B, d.G, plan=d.plan_bwd)
     marks.mark("spmm bwd")
     PAP, vAP = sp.spgemm(PA, d.A_v, PP, d.P_v)
     marks.mark("spgemm A.P")
@@ -640,9 +649,9 @@ def run_step(d, marks):
     marks.mark("spgemm Pt.AP")
     PPt.transpose()
     marks.mark("transpose Pt")
-    _, gAP = sp.spgemm_bwd(PPt, vPt, PAP, vAP, PC, d.V)
+    gPt, gAP = sp.spgemm_bwd(PPt, vPt, PAP, vAP, PC, d.V)
     marks.mark("spgemm bwd Pt.AP")
-    sp.spgemm_bwd(PA, d.A_v, PP, d.P_v, PAP, gAP)
+    gA, gP = sp.spgemm_bwd(PA, d.A_v, PP, d.P_v, PAP, gAP)
     marks.mark("spgemm bwd A.P")
     PL.transpose()
     marks.mark("transpose L")
@@ -650,9 +659,102 @@ def run_step(d, marks):
     marks.mark("levels L")
     xL = sp.trisolve(PL, d.L_v, d.bL, True)
     marks.mark("trisolve fwd")
-    sp.trisolve_bwd(PL, d.L_v, xL, d.gL, True)
+    gbL, gvL = sp.trisolve_bwd(PL, d.L_v, xL, d.gL, True)
     marks.mark("trisolve bwd")
+    _keep(outs, y=y, gx=gx, gv=gv, C=C, gB=gB, gvm=gvm, ciAP=PAP.colind, vAP=vAP,
+          ciC=PC.colind, vC=vC, gPt=gPt, gAP=gAP, gA=gA, gP=gP, xL=xL, gbL=gbL, gvL=gvL)
     return PAP.nnz, PC.nnz, nl
+
+
+def run_step_streams(d, chain_marks, outs=None):
+    """The same step as three independent chains on their own HIP streams
+    (default priority), joined at the end on the current stream:
+      1. A's transpose, SpMV and SpMM forward and backward (HBM-bound);
+      2. the Galerkin product P^T A P forward and backward (its symbolic
+         passes synchronise their own stream);
+      3. L's transpose, level sets and the triangular solves (the level
+         analysis synchronises its own stream).
+    Chains 2 and 3 are driven by two host threads (d.pool), so their
+    synchronisations hold up neither each other nor chain 1; library calls
+    release the interpreter lock while they wait.  The one cross-chain
+    input, A's cached transpose (the SpGEMM VJP of A P needs it), is made
+    before the threads start and handed over with an event.  chain_marks:
+    three Marks, each recording on its chain's stream."""
+    import torch
+    from paper_2212_05159_amd import sparse as sp
+
+    main = torch.cuda.current_stream()
+    s1, s2, s3 = d.streams
+    start = torch.cuda.Event()
+    start.record(main)
+    for st in d.streams:
+        st.wait_event(start)
+    m1, m2, m3 = chain_marks
+    PA = sp.Pattern(d.n, d.n, d.A_rp, d.A_ci)
+    PP = sp.Pattern(d.n, d.nc, d.P_rp, d.P_ci)
+    PL = sp.Pattern(d.n, d.n, d.L_rp, d.L_ci)
+    with torch.cuda.stream(s1):
+        m1.mark("start")
+        PA.transpose()
+        m1.mark("transpose A")
+        tA = torch.cuda.Event()
+        tA.record(s1)
+
+    def chain2():
+        with torch.cuda.stream(s2):
+            m2.mark("start")
+            PPt, _ = PP.transpose()
+            m2.mark("transpose P")
+            vPt = sp.transpose_vals(PP, d.P_v)
+            m2.mark("transpose vals P")
+            PAP, vAP = sp.spgemm(PA, d.A_v, PP, d.P_v)
+            m2.mark("spgemm A.P")
+            PC, vC = sp.spgemm(PPt, vPt, PAP, vAP)
+            m2.mark("spgemm Pt.AP")
+            PPt.transpose()
+            m2.mark("transpose Pt")
+            gPt, gAP = sp.spgemm_bwd(PPt, vPt, PAP, vAP, PC, d.V)
+            m2.mark("spgemm bwd Pt.AP")
+            s2.wait_event(tA)
+            gA, gP = sp.spgemm_bwd(PA, d.A_v, PP, d.P_v, PAP, gAP)
+            m2.mark("spgemm bwd A.P")
+            _keep(outs, ciAP=PAP.colind, vAP=vAP, ciC=PC.colind, vC=vC, gPt=gPt, gAP=gAP,
+                  gA=gA, gP=gP)
+            return PAP.nnz, PC.nnz
+
+    def chain3():
+        with torch.cuda.stream(s3):
+            m3.mark("start")
+            PL.transpose()
+            m3.mark("transpose L")
+            nl = PL.levels(True)[0]
+            m3.mark("levels L")
+            xL = sp.trisolve(PL, d.L_v, d.bL, True)
+            m3.mark("trisolve fwd")
+            gbL, gvL = sp.trisolve_bwd(PL, d.L_v, xL, d.gL, True)
+            m3.mark("trisolve bwd")
+            _keep(outs, xL=xL, gbL=gbL, gvL=gvL)
+            return nl
+
+    f2 = d.pool.submit(chain2)
+    f3 = d.pool.submit(chain3)
+    with torch.cuda.stream(s1):
+        y = sp.spmv(PA, d.A_v, d.x)
+        m1.mark("spmv fwd")
+        gx, gv = sp.spmv_bwd(PA, d.A_v, d.x, d.gy, mode=d.spmv_bwd_mode)
+        m1.mark("spmv bwd")
+        C = sp.spmm(PA, d.A_v, d.B, plan=d.plan_fwd)
+        m1.mark("spmm fwd")
+        gB, gvm = sp.spmm_bwd(PA, d.A_v, d.B, d.G, plan=d.plan_bwd)
+        m1.mark("spmm bwd")
+        _keep(outs, y=y, gx=gx, gv=gv, C=C, gB=gB, gvm=gvm)
+    nnz_ap, nnz_c = f2.result()
+    nl = f3.result()
+    for st in d.streams:
+        done = torch.cuda.Event()
+        done.record(st)
+        main.wait_event(done)
+    return nnz_ap, nnz_c, nl
 
 
 # ----------------------------------------------------------------------
@@ -738,6 +840,9 @@ def main():
     ap.add_argument("--no-spadd", action="store_true", help="skip the sparse + sparse part")
     ap.add_argument("--no-spai", action="store_true", help="skip the sparse-approximate-inverse part")
     ap.add_argument("--no-gcn", action="store_true", help="skip the graph-convolution part")
+    ap.add_argument("--serial", action="store_true",
+                    help="run the step's ops in sequence on one stream (exact per-op attribution) "
+                         "instead of three concurrent chains")
     ap.add_argument("--batched-blocks", type=int, default=64,
                     help="number of the 512 geometric-graph blocks in the batched part")
     ap.add_argument("--calibrate", type=int, default=0, metavar="M",
@@ -778,28 +883,54 @@ def main():
     d.spmv_bwd_mode = autotune.tune_spmv_bwd(P0, d.A_v, d.x, d.gy, reps=3, use_cache=False)[0]
     log(f"autotuned plans: {tuned}, SpMV backward: {d.spmv_bwd_mode}")
 
+    d.streams = tuple(torch.cuda.Stream() for _ in range(3))
+    d.pool = cf.ThreadPoolExecutor(2)  # host threads of the step's chains 2 and 3
+
+    def step(enabled):
+        if args.serial:
+            mk = [Marks(enabled)]
+            return run_step(d, mk[0]), mk
+        mk = [Marks(enabled) for _ in range(3)]
+        return run_step_streams(d, mk), mk
+
     for i in range(args.warmup):
-        run_step(d, Marks(False))
+        step(False)
         log(f"warmup step {i + 1}/{args.warmup} done")
     torch.cuda.synchronize()
 
-    # Timed region: exactly `steps` steps, per-op HIP events on the stream.
-    marks_all = []
+    # Timed region: exactly `steps` steps (three concurrent chains unless
+    # --serial), bracketed by synchronisations.
     t_start = torch.cuda.Event(enable_timing=True)
     t_end = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t_start.record()
     w0 = time.perf_counter()
     for i in range(args.steps):
-        mk = Marks(True)
-        nnz_ap, nnz_c, nlev = run_step(d, mk)
-        marks_all.append(mk)
+        (nnz_ap, nnz_c, nlev), _ = step(False)
     t_end.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - w0
     ms_total = t_start.elapsed_time(t_end)
     ms_step = ms_total / args.steps
     log(f"{args.steps} steps: {ms_step:.3f} ms/step (wall {wall / args.steps * 1e3:.3f} ms/step)")
+
+    # Attribution pass: the same number of steps with every op in sequence
+    # on one stream and HIP events between ops (events on overlapping
+    # streams would time the interleaving, not the kernels).  The per-op
+    # breakdown and the dominant kernel's roofline come from this pass.
+    marks_all = []
+    a_start = torch.cuda.Event(enable_timing=True)
+    a_end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a_start.record()
+    for i in range(args.steps):
+        mk = Marks(True)
+        run_step(d, mk)
+        marks_all.append(mk)
+    a_end.record()
+    torch.cuda.synchronize()
+    serial_ms = a_start.elapsed_time(a_end) / args.steps
+    log(f"attribution pass (one stream): {serial_ms:.3f} ms/step")
 
     bm = byte_model(d, nnz_ap, nnz_c, nlev)
     total_bytes = sum(bm.values())
@@ -888,7 +1019,9 @@ def main():
                    "grid": args.grid, "k": args.k, "nnz_A": d.nnzA, "nnz_AP": nnz_ap,
                    "nnz_PtAP": nnz_c, "nnz_L": d.nnzL, "levels_L": nlev,
                    "spmm_plans": {op: (list(c) if c else "natural") for op, (c, _) in tuned.items()},
-                   "spmv_bwd_mode": d.spmv_bwd_mode},
+                   "spmv_bwd_mode": d.spmv_bwd_mode,
+                   "streams": 1 if args.serial else 3,
+                   "serial_ms_per_step": round(serial_ms, 4)},
         "frac_hbm_peak": round(value / HBM_PEAK_GBS, 4),
         "roofline": roofline,
         "cpu_baseline": cpu,
