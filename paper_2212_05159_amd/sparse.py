@@ -382,6 +382,22 @@ class CsrTensor:
     def __neg__(self):
         return CsrTensor(self.pattern, -self.vals)
 
+    def row_sum(self):
+        """Row sums (the SpMV A 1; differentiable in the values)."""
+        ones = torch.ones(self.pattern.ncols, dtype=self.vals.dtype, device=self.vals.device)
+        return SpMV.apply(self.pattern, self.vals, ones)
+
+    def diagonal(self):
+        """The stored diagonal as a dense vector (zero where not stored;
+        differentiable in the values)."""
+        P = self.pattern
+        n = min(P.nrows, P.ncols)
+        rows = torch.repeat_interleave(torch.arange(P.nrows, device=self.vals.device),
+                                       (P.rowptr[1:] - P.rowptr[:-1]).long())
+        on = rows == P.colind.long()
+        out = torch.zeros(n, dtype=self.vals.dtype, device=self.vals.device)
+        return out.index_put((rows[on],), self.vals[on])
+
     def tmatvec(self, x):
         """A^T x (differentiable in the values and x)."""
         return SpMVT.apply(self.pattern, self.vals, x)
@@ -393,3 +409,23 @@ class CsrTensor:
         """A^T with its values gathered by the library (not differentiable)."""
         Pt, _ = self.pattern.transpose()
         return CsrTensor(Pt, transpose_vals(self.pattern, self.vals.detach()))
+
+
+def eye(n, k=0, dtype=torch.float32, device="cuda"):
+    """n x n matrix with ones on diagonal k (k > 0 above the main diagonal)."""
+    i = torch.arange(max(0, -k), min(n, n - k), device=device, dtype=torch.int32)
+    counts = torch.zeros(n, dtype=torch.int32, device=device)
+    counts[i.long()] = 1
+    rowptr = torch.zeros(n + 1, dtype=torch.int32, device=device)
+    rowptr[1:] = torch.cumsum(counts, 0, dtype=torch.int32)
+    P = Pattern(n, n, rowptr, (i + k).to(torch.int32))
+    return CsrTensor(P, torch.ones(P.nnz, dtype=dtype, device=device))
+
+
+def diag(v):
+    """Diagonal matrix with the entries of v as its values (differentiable:
+    the values are v itself)."""
+    n = v.numel()
+    ar = torch.arange(n + 1, dtype=torch.int32, device=v.device)
+    return CsrTensor(Pattern(n, n, ar, ar[:n].clone()), v)
+
