@@ -661,7 +661,7 @@ def run_step(d, marks, outs=None):
     marks.mark("trisolve fwd")
     gbL, gvL = sp.trisolve_bwd(PL, d.L_v, xL, d.gL, True)
     marks.mark("trisolve bwd")
-    _keep(outs, y=y, gx=gx, gv=gv, C=C, gB=gB, gvm=gvm, ciAP=PAP.colind, vAP=vAP,
+    _keep(outs, y=y, gx=gx, gv=gv, C=C, gB=gB, gvm=gvm, rpAP=PAP.rowptr, ciAP=PAP.colind, vAP=vAP,
           ciC=PC.colind, vC=vC, gPt=gPt, gAP=gAP, gA=gA, gP=gP, xL=xL, gbL=gbL, gvL=gvL)
     return PAP.nnz, PC.nnz, nl
 
@@ -718,8 +718,8 @@ def run_step_streams(d, chain_marks, outs=None):
             s2.wait_event(tA)
             gA, gP = sp.spgemm_bwd(PA, d.A_v, PP, d.P_v, PAP, gAP)
             m2.mark("spgemm bwd A.P")
-            _keep(outs, ciAP=PAP.colind, vAP=vAP, ciC=PC.colind, vC=vC, gPt=gPt, gAP=gAP,
-                  gA=gA, gP=gP)
+            _keep(outs, rpAP=PAP.rowptr, ciAP=PAP.colind, vAP=vAP, ciC=PC.colind, vC=vC,
+                  gPt=gPt, gAP=gAP, gA=gA, gP=gP)
             return PAP.nnz, PC.nnz
 
     def chain3():
@@ -923,15 +923,23 @@ def main():
     a_end = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     a_start.record()
+    last_outs = {}
     for i in range(args.steps):
         mk = Marks(True)
-        run_step(d, mk)
+        run_step(d, mk, last_outs if i + 1 == args.steps else None)
         marks_all.append(mk)
     a_end.record()
     torch.cuda.synchronize()
     serial_ms = a_start.elapsed_time(a_end) / args.steps
     log(f"attribution pass (one stream): {serial_ms:.3f} ms/step")
 
+    # intermediate products of the two SpGEMMs, from the last attribution
+    # step's A P: sum over A's entries of the length of the P row each
+    # selects, and sum over k of len(P row k) * len(AP row k) for P^T (A P)
+    with torch.no_grad():
+        lenP = (d.P_rp[1:] - d.P_rp[:-1]).long()
+        lenAP = (last_outs["rpAP"][1:] - last_outs["rpAP"][:-1]).long()
+        products = {"A.P": int(lenP[d.A_ci.long()].sum()), "Pt.AP": int((lenP * lenAP).sum())}
     bm = byte_model(d, nnz_ap, nnz_c, nlev)
     total_bytes = sum(bm.values())
     op_ms = {}
@@ -1017,7 +1025,8 @@ def main():
                                f"(SpGEMM symbolic+numeric+bwd), transposes, red-black L level sets + "
                                f"tri-solve fwd+bwd",
                    "grid": args.grid, "k": args.k, "nnz_A": d.nnzA, "nnz_AP": nnz_ap,
-                   "nnz_PtAP": nnz_c, "nnz_L": d.nnzL, "levels_L": nlev,
+                   "nnz_PtAP": nnz_c, "spgemm_products": products, "nnz_L": d.nnzL,
+                   "levels_L": nlev,
                    "spmm_plans": {op: (list(c) if c else "natural") for op, (c, _) in tuned.items()},
                    "spmv_bwd_mode": d.spmv_bwd_mode,
                    "streams": 1 if args.serial else 3,
