@@ -87,3 +87,26 @@ def test_argument_errors_return_codes(lib):
                                    None) == -2
     # non-square triangular operand
     assert lib.csr_trisolve_fwd(C.byref(e), 1, 1, None, None, None, 1, 1, None) == -1
+
+
+def test_sparse_add_and_inverse_factor_argument_errors(lib):
+    # sparse + sparse: operands of different shapes, missing outputs, dtype mismatch
+    d = capi.csrad_csr(4, 4, 4, 0, 1, 1, 1)
+    e = capi.csrad_csr(4, 5, 4, 0, 1, 1, 1)
+    sz = C.c_size_t(0)
+    assert lib.csr_spadd_workspace(C.byref(d), C.byref(d), C.byref(sz)) == 0 and sz.value > 0
+    assert lib.csr_spadd_workspace(C.byref(d), C.byref(e), C.byref(sz)) == -1
+    nnz = C.c_int64(0)
+    assert lib.csr_spadd_symbolic(C.byref(d), C.byref(d), None, C.byref(nnz), 1, 1 << 30,
+                                  None) == -1
+    assert lib.csr_spadd_symbolic(C.byref(d), C.byref(d), 1, C.byref(nnz), 1, 8, None) == -5
+    g = capi.csrad_csr(4, 4, 4, 1, 1, 1, 1)
+    assert lib.csr_spadd_fwd(C.byref(d), C.byref(g), 1.0, 1.0, 1, 1, 1, None) == -2
+    assert lib.csr_spadd_fwd(C.byref(d), C.byref(d), 1.0, 1.0, 1, 1, None, None) == -1
+    assert lib.csr_spadd_bwd(C.byref(d), C.byref(d), C.byref(e), 1.0, 1.0, 1, 1, 1, None) == -1
+    # PCG kind 3 (inverse factor): L and its transpose are required, shapes must agree
+    assert lib.csr_pcg_step(C.byref(d), 3, None, None, None, None, 0, None, None, None,
+                            1, 1, 1, 1, 1, 1, None, 0, 1, 1 << 30, None) == -1
+    Lt = capi.csrad_csr(4, 4, 3, 0, 1, 1, None)  # nnz differs from L's
+    assert lib.csr_pcg_step(C.byref(d), 3, None, C.byref(d), C.byref(Lt), 1, 0, None, None,
+                            None, 1, 1, 1, 1, 1, 1, None, 0, 1, 1 << 30, None) == -1

@@ -204,3 +204,24 @@ def test_untrained_inverse_form_is_first_order_inverse_factor():
     want = np.where(T.colind < rows, -T.vals / (d[rows] * np.sqrt(d[T.colind])),
                     (1 + learned.DELTA) / np.sqrt(d[rows]))
     assert rel_err(Lv, want) < 1e-6
+
+
+def test_fsai_transpose_values_through_perm_equal_stored():
+    """Kind 3 with L^T's values read through perm (Lt without values) gives
+    the same iterates, bit for bit, as with L^T's values stored."""
+    from paper_2212_05159_amd import capi
+
+    A = gen.anisotropic_q1(30, 1e-2, 0.6)
+    L = _inverse_factor(A)
+    b = gen.normal(A.nrows, 9)
+    Ad = sp.CsrTensor.from_host(A, dtype=torch.float32)
+    Ld = sp.CsrTensor.from_host(L, dtype=torch.float32)
+    x1, i1 = pcgmod.pcg(Ad, to_dev(b), precond="fsai", L=Ld, tol=1e-7, record=True)
+    solver = pcgmod.PCG(Ad, "fsai", L=Ld)
+    Lt, perm = Ld.pattern.transpose()
+    kind, dinv, Ldesc, _, _, nl, lph, lp, lr = solver.pc
+    solver.pc = (kind, dinv, Ldesc, Lt.desc(dtype=torch.float32), perm, nl, lph, lp, lr)
+    x2, i2 = solver.solve(to_dev(b), tol=1e-7, record=True)
+    assert i1["iters"] == i2["iters"] and i1["converged"]
+    np.testing.assert_array_equal(i1["hist"], i2["hist"])
+    assert torch.equal(x1, x2)
