@@ -857,8 +857,8 @@ def main():
 
     host_blocks = None
     if not args.no_batched and not args.calibrate:
-        # host inputs of the batched part first: worker processes are
-        # started before this process uses the GPU
+        # host inputs of the batched part first (a thread pool; the host
+        # work overlaps nothing on the GPU)
         host_blocks = geometric_blocks(args.batched_blocks)
         log(f"built {args.batched_blocks} geometric-graph blocks in {host_blocks[1]:.1f} s")
 

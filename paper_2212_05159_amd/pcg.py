@@ -123,12 +123,3 @@ def pcg(A, b, precond="jacobi", L=None, tol=1e-6, maxit=10000, chunk=25, fallbac
         info2["first_try"] = info
         return x, info2
     return x, info
-
-
-def true_residual(A_host, x, b):
-    """||b - A x|| / ||b|| in float64 on the host (for checks)."""
-    xs = x.detach().cpu().numpy().astype(np.float64)
-    bs = np.asarray(b.detach().cpu().numpy() if torch.is_tensor(b) else b, np.float64)
-    rows = np.repeat(np.arange(A_host.nrows), np.diff(A_host.rowptr))
-    Ax = np.bincount(rows, weights=A_host.vals * xs[A_host.colind], minlength=A_host.nrows)
-    return float(np.linalg.norm(bs - Ax) / np.linalg.norm(bs))

@@ -90,10 +90,60 @@ class Pattern:
 
 
 # ----------------------------------------------------------------------
+# Argument checks.  The C ABI receives bare pointers and cannot tell a
+# host pointer, a short buffer or another value type from a valid operand,
+# so every functional form checks its tensors here and raises before any
+# launch.
+# ----------------------------------------------------------------------
+
+def _check_vals(P, vals, what="vals"):
+    if not torch.is_tensor(vals):
+        raise TypeError(f"{what}: expected a tensor, got {type(vals).__name__}")
+    if vals.dtype not in (torch.float32, torch.float64):
+        raise TypeError(f"{what}: value type must be float32 or float64, got {vals.dtype}")
+    if vals.device.type != "cuda":
+        raise TypeError(f"{what}: must be on a CUDA device, got {vals.device}")
+    if P.rowptr.device != vals.device or P.colind.device != vals.device:
+        raise TypeError(f"{what}: on {vals.device}, pattern on {P.rowptr.device}")
+    if vals.dim() != 1 or vals.numel() != P.nnz or not vals.is_contiguous():
+        raise ValueError(f"{what}: expected a contiguous vector of nnz = {P.nnz} values, "
+                         f"got shape {tuple(vals.shape)}")
+
+
+def _check_dense(t, ref, shape, what):
+    """t must be a tensor on ref's device with ref's dtype and the given
+    shape (rows may carry a leading dimension >= the column count, but the
+    columns must be unit-stride)."""
+    if not torch.is_tensor(t):
+        raise TypeError(f"{what}: expected a tensor, got {type(t).__name__}")
+    if t.device != ref.device:
+        raise TypeError(f"{what}: on {t.device}, expected {ref.device}")
+    if t.dtype != ref.dtype:
+        raise TypeError(f"{what}: dtype {t.dtype}, expected {ref.dtype} (the values' type)")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{what}: shape {tuple(t.shape)}, expected {tuple(shape)}")
+    if t.dim() == 1 and t.numel() > 0 and t.stride(0) != 1:
+        raise ValueError(f"{what}: must be contiguous")
+    if t.dim() == 2 and t.numel() > 0 and (t.stride(1) != 1 or t.stride(0) < t.shape[1]):
+        raise ValueError(f"{what}: rows must be unit-stride with a leading dimension >= "
+                         f"{t.shape[1]}")
+
+
+def _cols(t, what):
+    if not torch.is_tensor(t) or t.dim() != 2:
+        raise ValueError(f"{what}: expected a 2-D tensor")
+    if t.shape[1] <= 0:
+        raise ValueError(f"{what}: needs at least one column")
+    return int(t.shape[1])
+
+
+# ----------------------------------------------------------------------
 # Functional forms (allocate outputs, call the library).
 # ----------------------------------------------------------------------
 
 def spmv(P, vals, x):
+    _check_vals(P, vals)
+    _check_dense(x, vals, (P.ncols,), "x")
     y = torch.empty(P.nrows, dtype=vals.dtype, device=vals.device)
     capi.csr_spmv_fwd(P.desc(vals), x, y)
     return y
@@ -102,6 +152,10 @@ def spmv(P, vals, x):
 def spmv_bwd(P, vals, x, gy, need_x=True, need_vals=True, use_transpose=True, mode=None):
     """(gx, gvals).  mode "fused" or "split" (see autotune.tune_spmv_bwd)
     overrides the pattern's tuned choice; both give the same bits."""
+    _check_vals(P, vals)
+    _check_dense(gy, vals, (P.nrows,), "gy")
+    if need_vals:
+        _check_dense(x, vals, (P.ncols,), "x")
     mode = mode if mode is not None else P.plan("spmv_bwd")
     gx = torch.empty(P.ncols, dtype=vals.dtype, device=vals.device) if need_x else None
     gv = torch.empty(P.nnz, dtype=vals.dtype, device=vals.device) if need_vals else None
@@ -120,7 +174,9 @@ def spmv_bwd(P, vals, x, gy, need_x=True, need_vals=True, use_transpose=True, mo
 
 
 def spmm(P, vals, B, plan=None):
-    k = B.shape[1]
+    _check_vals(P, vals)
+    k = _cols(B, "B")
+    _check_dense(B, vals, (P.ncols, k), "B")
     out = torch.empty(P.nrows, k, dtype=vals.dtype, device=vals.device)
     capi.csr_spmm_fwd(P.desc(vals), k, B, B.stride(0), out, out.stride(0),
                       plan if plan is not None else P.plan("spmm_fwd"))
@@ -128,7 +184,11 @@ def spmm(P, vals, B, plan=None):
 
 
 def spmm_bwd(P, vals, B, gC, need_B=True, need_vals=True, plan=None):
-    k = gC.shape[1]
+    _check_vals(P, vals)
+    k = _cols(gC, "gC")
+    _check_dense(gC, vals, (P.nrows, k), "gC")
+    if need_vals:
+        _check_dense(B, vals, (P.ncols, k), "B")
     gB = torch.empty(P.ncols, k, dtype=vals.dtype, device=vals.device) if need_B else None
     gv = torch.empty(P.nnz, dtype=vals.dtype, device=vals.device) if need_vals else None
     Pt, perm = P.transpose() if need_B else (None, None)
@@ -141,6 +201,7 @@ def spmm_bwd(P, vals, B, gC, need_B=True, need_vals=True, plan=None):
 
 def transpose_vals(P, vals):
     """Values of A^T in the order of P.transpose()'s pattern."""
+    _check_vals(P, vals)
     _, perm = P.transpose()
     out = torch.empty_like(vals)
     capi.csr_transpose_vals(P.desc(vals), perm, out)
@@ -149,6 +210,12 @@ def transpose_vals(P, vals):
 
 def spgemm(PA, valsA, PB, valsB):
     """C = A B.  Returns (Pattern of C, valsC)."""
+    _check_vals(PA, valsA, "valsA")
+    _check_vals(PB, valsB, "valsB")
+    if PA.ncols != PB.nrows:
+        raise ValueError(f"spgemm: inner dimensions differ ({PA.ncols} vs {PB.nrows})")
+    if valsA.dtype != valsB.dtype:
+        raise TypeError("spgemm: operands differ in value type")
     dA, dB = PA.desc(valsA), PB.desc(valsB)
     ws = capi._ws(capi.csr_spgemm_workspace(dA, dB), valsA.device)
     rpC = torch.empty(PA.nrows + 1, dtype=torch.int32, device=valsA.device)
@@ -161,6 +228,9 @@ def spgemm(PA, valsA, PB, valsB):
 
 
 def spgemm_bwd(PA, valsA, PB, valsB, PC, gC, need_A=True, need_B=True):
+    _check_vals(PA, valsA, "valsA")
+    _check_vals(PB, valsB, "valsB")
+    _check_dense(gC, valsA, (PC.nnz,), "gC")
     gA = torch.empty(PA.nnz, dtype=valsA.dtype, device=valsA.device) if need_A else None
     gB = torch.empty(PB.nnz, dtype=valsB.dtype, device=valsB.device) if need_B else None
     At, permA = PA.transpose() if need_B else (None, None)
@@ -177,6 +247,10 @@ def spadd(PA, valsA, PB, valsB, alpha=1.0, beta=1.0):
     repeated sum recomputes values only."""
     if PA.nrows != PB.nrows or PA.ncols != PB.ncols:
         raise ValueError("spadd: operands differ in shape")
+    _check_vals(PA, valsA, "valsA")
+    _check_vals(PB, valsB, "valsB")
+    if valsA.dtype != valsB.dtype:
+        raise TypeError("spadd: operands differ in value type")
     dA, dB = PA.desc(valsA), PB.desc(valsB)
     key = ("spadd", id(PB))
     hit = PA.plan(key)
@@ -199,6 +273,9 @@ def spadd(PA, valsA, PB, valsB, alpha=1.0, beta=1.0):
 
 def spadd_bwd(PA, PB, PC, gC, alpha=1.0, beta=1.0, need_A=True, need_B=True, dtype=None):
     dtype = dtype or gC.dtype
+    if not torch.is_tensor(gC) or gC.device.type != "cuda":
+        raise TypeError("spadd_bwd: gC must be a CUDA tensor")
+    _check_dense(gC, torch.empty(0, dtype=dtype, device=gC.device), (PC.nnz,), "gC")
     gA = torch.empty(PA.nnz, dtype=dtype, device=gC.device) if need_A else None
     gB = torch.empty(PB.nnz, dtype=dtype, device=gC.device) if need_B else None
     capi.csr_spadd_bwd(PA.desc(dtype=dtype), PB.desc(dtype=dtype), PC.desc(dtype=dtype), alpha,
@@ -206,7 +283,15 @@ def spadd_bwd(PA, PB, PC, gC, alpha=1.0, beta=1.0, need_A=True, need_B=True, dty
     return gA, gB
 
 
+def _check_square(P, what):
+    if P.nrows != P.ncols:
+        raise ValueError(f"{what}: the triangular matrix must be square, got {P.nrows}x{P.ncols}")
+
+
 def trisolve(P, vals, b, lower=True):
+    _check_square(P, "trisolve")
+    _check_vals(P, vals)
+    _check_dense(b, vals, (P.nrows,), "b")
     nl, lph, lp, lr, _ = P.levels(lower)
     x = torch.empty_like(b)
     capi.csr_trisolve_fwd(P.desc(vals), int(lower), nl, lph, lp, lr, b, x)
@@ -214,6 +299,10 @@ def trisolve(P, vals, b, lower=True):
 
 
 def trisolve_bwd(P, vals, x, gx, lower=True, need_vals=True):
+    _check_square(P, "trisolve_bwd")
+    _check_vals(P, vals)
+    _check_dense(x, vals, (P.nrows,), "x")
+    _check_dense(gx, vals, (P.nrows,), "gx")
     nl, lph, lp, lr, _ = P.levels(lower)
     Pt, perm = P.transpose()
     gb = torch.empty_like(gx)

@@ -1,7 +1,10 @@
 """GPU parity of PCG (Section 4.3) against the FP64 oracle.
 
-Float64 runs reproduce the oracle's residual history to 1e-8 relative and
-stop within one step of it; exact factors converge in one step; float32
+Float64 runs (float64 vectors and dots) reproduce the oracle's residual
+history entry by entry within 10x the oracle's own rounding band plus
+1e-12 (how far the oracle's history moves when b is perturbed at the level
+of float64 rounding: the GPU takes every sum in another order, which is a
+perturbation of that size at every step), and stop within one step of it; exact factors converge in one step; float32
 values with float64 vectors reach ||b - A x||/||b|| <= 1e-6 (checked on the
 host in float64); breakdowns are reported and fall back to Jacobi."""
 import numpy as np
@@ -13,7 +16,7 @@ from paper_2212_05159_amd import gen
 from paper_2212_05159_amd import pcg as pcgmod
 from paper_2212_05159_amd import sparse as sp
 
-from _util import rel_err, to_dev, upcast
+from _util import assert_pcg_f64_parity, pcg_rounding_band, rel_err, to_dev, true_residual, upcast
 
 pytestmark = pytest.mark.gpu
 
@@ -37,15 +40,10 @@ def test_pcg_fp64_matches_oracle(precond, name, mk):
     b = gen.normal(A.nrows, 2)
     Ad = sp.CsrTensor.from_host(A, dtype=torch.float64)
     x, info = pcgmod.pcg(Ad, to_dev(b), precond=precond, tol=1e-8, record=True)
-    xo, ito, ho = oracle.pcg(A, b, precond, tol=1e-8)
-    assert info["converged"] and ito > 0
-    assert abs(info["iters"] - ito) <= 1
-    m = min(info["iters"], ito)
-    # rounding differences grow over hundreds of steps: absolute floor 1e-9
-    # on the relative residual (the initial one is 1)
-    np.testing.assert_allclose(info["hist"][:m], ho[1:m + 1], rtol=1e-6, atol=1e-9)
-    assert rel_err(x, xo) < 1e-6
-    assert pcgmod.true_residual(A, x, b) < 2e-8
+    ref = pcg_rounding_band(A, b, precond, tol=1e-8)
+    assert info["converged"] and ref["iters"] > 0
+    assert_pcg_f64_parity(info, x, ref, f"{name}/{precond}")
+    assert true_residual(A, x, b) < 2e-8
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
@@ -61,11 +59,10 @@ def test_pcg_arrow_matrix_reads_csr_rows(dtype):
     Ad = sp.CsrTensor.from_host(A, dtype=dtype)
     x, info = pcgmod.pcg(Ad, to_dev(b), precond="jacobi", tol=1e-8, record=True)
     Ao = upcast(A, dtype)
-    xo, ito, ho = oracle.pcg(Ao, b, "jacobi", tol=1e-8)
-    assert info["converged"] and abs(info["iters"] - ito) <= 1
-    m = min(info["iters"], ito)
-    np.testing.assert_allclose(info["hist"][:m], ho[1:m + 1], rtol=1e-6, atol=1e-9)
-    assert pcgmod.true_residual(Ao, x, b) < 2e-8
+    ref = pcg_rounding_band(Ao, b, "jacobi", tol=1e-8)
+    assert info["converged"]
+    assert_pcg_f64_parity(info, x, ref, "arrow")
+    assert true_residual(Ao, x, b) < 2e-8
 
 
 def test_pcg_exact_factor_converges_in_one_step():
@@ -77,7 +74,7 @@ def test_pcg_exact_factor_converges_in_one_step():
     Ld = sp.CsrTensor.from_host(L, dtype=torch.float64)
     x, info = pcgmod.pcg(Ad, to_dev(b), precond="factor", L=Ld, tol=1e-10)
     assert info["converged"] and info["iters"] == 1
-    assert pcgmod.true_residual(A, x, b) < 1e-10
+    assert true_residual(A, x, b) < 1e-10
 
 
 @pytest.mark.parametrize("graph", [False, True])
@@ -88,7 +85,7 @@ def test_pcg_fp32_values_reach_1e6(graph):
     x, info = pcgmod.pcg(Ad, to_dev(b), precond="jacobi", tol=1e-6, graph=graph)
     assert info["converged"]
     # the system solved is the float32-rounded matrix
-    assert pcgmod.true_residual(upcast(A, torch.float32), x, b) <= 1.05e-6
+    assert true_residual(upcast(A, torch.float32), x, b) <= 1.05e-6
     _, ito, _ = oracle.pcg(upcast(A, torch.float32), b, "jacobi", tol=1e-6)
     assert abs(info["iters"] - ito) <= 2
 
@@ -105,12 +102,11 @@ def test_pcg_factor_matches_oracle_factor():
     Ad = sp.CsrTensor.from_host(A, dtype=torch.float64)
     Ld = sp.CsrTensor.from_host(L, dtype=torch.float64)
     x, info = pcgmod.pcg(Ad, to_dev(b), precond="factor", L=Ld, tol=1e-8, record=True)
-    xo, ito, ho = oracle.pcg(A, b, "factor", L=L, tol=1e-8)
-    assert info["converged"] and abs(info["iters"] - ito) <= 1
-    m = min(info["iters"], ito)
-    np.testing.assert_allclose(info["hist"][:m], ho[1:m + 1], rtol=1e-6, atol=1e-9)
+    ref = pcg_rounding_band(A, b, "factor", L=L, tol=1e-8)
+    assert info["converged"]
+    assert_pcg_f64_parity(info, x, ref, "sgs-factor")
     _, itj, _ = oracle.pcg(A, b, "jacobi", tol=1e-8)
-    assert ito < itj  # the factor helps
+    assert ref["iters"] < itj  # the factor helps
 
 
 def _sgs_factor(A):
@@ -141,13 +137,12 @@ def test_pcg_level_ordered_factor_matches_oracle(dtype, graph):
     Ao, Lo = upcast(A, dtype), upcast(L, dtype)
     x, info = pcgmod.pcg(Ad, to_dev(b), precond="factor", L=Ld, tol=1e-8, graph=graph,
                          record=not graph)
-    xo, ito, ho = oracle.pcg(Ao, b, "factor", L=Lo, tol=1e-8)
-    assert info["converged"] and abs(info["iters"] - ito) <= 1
-    if not graph:
-        m = min(info["iters"], ito)
-        np.testing.assert_allclose(info["hist"][:m], ho[1:m + 1], rtol=1e-6, atol=1e-9)
-    assert rel_err(x, xo) < 1e-6
-    assert pcgmod.true_residual(Ao, x, b) < 2e-8
+    ref = pcg_rounding_band(Ao, b, "factor", L=Lo, tol=1e-8)
+    assert info["converged"]
+    if graph:
+        info["hist"] = ref["hist"][1:]  # no history under capture: x and the count only
+    assert_pcg_f64_parity(info, x, ref, f"level-ordered/{dtype}/graph={graph}")
+    assert true_residual(Ao, x, b) < 2e-8
 
 
 def test_pcg_ell_factor_interleaved_levels():
@@ -169,11 +164,10 @@ def test_pcg_ell_factor_interleaved_levels():
     assert not np.array_equal(lr.cpu().numpy(), np.arange(n))
     b = gen.normal(n, 9)
     x, info = pcgmod.pcg(Ad, to_dev(b), precond="factor", L=Ld, tol=1e-8, record=True)
-    xo, ito, ho = oracle.pcg(A, b, "factor", L=L, tol=1e-8)
-    assert info["converged"] and abs(info["iters"] - ito) <= 1
-    m = min(info["iters"], ito)
-    np.testing.assert_allclose(info["hist"][:m], ho[1:m + 1], rtol=1e-6, atol=1e-9)
-    assert pcgmod.true_residual(A, x, b) < 2e-8
+    ref = pcg_rounding_band(A, b, "factor", L=L, tol=1e-8)
+    assert info["converged"]
+    assert_pcg_f64_parity(info, x, ref, "interleaved")
+    assert true_residual(A, x, b) < 2e-8
 
 
 def test_pcg_breakdown_falls_back_to_jacobi():
@@ -188,4 +182,4 @@ def test_pcg_breakdown_falls_back_to_jacobi():
     assert info["breakdown"] and not info["converged"]
     x, info = pcgmod.pcg(Ad, to_dev(b), precond="factor", L=Ld, tol=1e-8, fallback=True)
     assert info["fallback"] and info["converged"]
-    assert pcgmod.true_residual(A, x, b) < 2e-8
+    assert true_residual(A, x, b) < 2e-8
