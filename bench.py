@@ -74,40 +74,48 @@ def geometric_blocks(nblocks):
     return blocks, time.perf_counter() - t0
 
 
-def batched_section(blocks, gen_s, reps=5):
-    """SpMV / SpMM (64 columns) fwd+bwd and the tri-solve fwd+adjoint over
-    random geometric-graph Laplacians (+1e-2 I; n from 1k to 64k, kNN with
-    k from 6 to 14), float32, concatenated block-diagonally: each op is one
-    launch over the whole batch.  Also timed: the same ops launched block
-    by block."""
+def batched_section(blocks, gen_s, reps=5, skew=None):
+    """Batched uneven blocks: random geometric-graph Laplacians + 1e-2 I
+    (n from 1k to 64k, kNN with k from 6 to 14), float32, concatenated
+    block-diagonally; IC(0) factors per block computed on the GPU.  SpMV and
+    SpMM (64 columns) forward and backward and the IC(0) solve forward and
+    adjoint, each ONE persistent launch over the plan's work queue, with
+    the variants the autotuner picks per class of blocks.  Beside them: the
+    same plans with the automatic variants (untuned), the library's
+    per-matrix kernels over the whole concatenation (one launch per op, one
+    per level for the solves), and the ops launched block by block.  With
+    `skew` (blocks with heavy-tailed row lengths), SpMV and SpMM forward and
+    backward there under row-split, merge-path and the tuned choice."""
     import torch
-    from paper_2212_05159_amd import autotune, batch as bt, gen
+    from paper_2212_05159_amd import batch as bt, gen
     from paper_2212_05159_amd import sparse as sp
 
     nblocks = len(blocks)
+    t0 = time.perf_counter()
     B = bt.Batch(blocks)
-    L = bt.Batch([gen.tril(b) for b in blocks])
-    n, nnz, nnzL = B.host.nrows, B.host.nnz, L.host.nnz
+    Lh = gen.tril(B.host)
+    LB = bt.Batch(host=Lh, block_rowptr=B.block_rowptr)
+    Lv = LB.ic0(LB.A)  # IC(0) of each block on the GPU
+    L = sp.CsrTensor(LB.pattern, Lv)
+    torch.cuda.synchronize()
+    if not bool(torch.isfinite(Lv).all()):
+        raise RuntimeError("IC(0) broke down on a block")
+    n, nnz, nnzL = B.host.nrows, B.host.nnz, Lh.nnz
     k = 64
-    rng = np.random.default_rng(7)
-    dev = lambda a: torch.as_tensor(np.asarray(a, np.float32), device="cuda")
-    x, gy = dev(rng.standard_normal(n)), dev(rng.standard_normal(n))
-    X, G = dev(rng.standard_normal((n, k))), dev(rng.standard_normal((n, k)))
-    bL, gL = dev(rng.standard_normal(n)), dev(rng.standard_normal(n))
-    P, v, PL, vL = B.pattern, B.A.vals, L.pattern, L.A.vals
+    g = torch.Generator(device="cuda")
+    g.manual_seed(3)
+    rnd = lambda *shape: torch.randn(*shape, generator=g, device="cuda", dtype=torch.float32)
+    x, gy, bL, gL = rnd(n), rnd(n), rnd(n), rnd(n)
+    X, G = rnd(n, k), rnd(n, k)
+    P, v = B.pattern, B.A.vals
     P.transpose()
-    PL.transpose()
-    nl = PL.levels(True)[0]
-    tuned = autotune.tune_spmm(P, v, X, G, reps=3, use_cache=False)
-    spmv_mode = autotune.tune_spmv_bwd(P, v, x, gy, reps=3, use_cache=False)[0]
-    ops = {
-        "spmv fwd": lambda: sp.spmv(P, v, x),
-        "spmv bwd": lambda: sp.spmv_bwd(P, v, x, gy),
-        "spmm fwd": lambda: sp.spmm(P, v, X),
-        "spmm bwd": lambda: sp.spmm_bwd(P, v, X, G),
-        "trisolve fwd": lambda: sp.trisolve(PL, vL, bL, True),
-        "trisolve bwd": lambda: sp.trisolve_bwd(PL, vL, bL, gL, True),
-    }
+    L.pattern.transpose()
+    nl = L.pattern.levels(True)[0]
+    xL = torch.empty_like(bL)
+    setup_s = time.perf_counter() - t0
+    log(f"batched: {nblocks} blocks, n={n} nnz={nnz}, IC(0) nnz={nnzL} ({nl} levels), "
+        f"setup {setup_s:.1f} s")
+
     V, I = 4, I4
     pat = lambda rows, z: (rows + 1) * I + z * I
     model = {"spmv fwd": pat(n, nnz) + nnz * V + 2 * n * V,
@@ -117,58 +125,178 @@ def batched_section(blocks, gen_s, reps=5):
              "trisolve fwd": pat(n, nnzL) + nnzL * V + 2 * n * V + n * I,
              "trisolve bwd": (pat(n, nnzL) + nnzL * (I + V) + 2 * n * V + n * I)
              + (pat(n, nnzL) + nnzL * I + 2 * n * V + nnzL * V)}
+
+    def batched_ops(Bt):
+        return {
+            "spmv fwd": lambda: Bt.spmv(x),
+            "spmv bwd": lambda: Bt.spmv_bwd(x, gy),
+            "spmm fwd": lambda: Bt.spmm(X),
+            "spmm bwd": lambda: Bt.spmm_bwd(X, G),
+            "trisolve fwd": lambda: LB.trisolve(L, bL, True),
+            "trisolve bwd": lambda: LB.trisolve_bwd(L, xL, gL, True),
+        }
+
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
-    def timed(fn):
+    def timed(fn, r=reps):
         fn()
         torch.cuda.synchronize()
-        e0.record()
-        for _ in range(reps):
+        ts = []
+        for _ in range(r):
+            e0.record()
             fn()
-        e1.record()
-        torch.cuda.synchronize()
-        return e0.elapsed_time(e1) / reps
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return float(np.median(ts))
 
-    res = {}
-    for name, fn in ops.items():
-        ms = timed(fn)
-        res[name] = {"ms": round(ms, 4), "GB/s": round(model[name] / (ms * 1e-3) / 1e9, 1)}
-    total_ms = sum(r["ms"] for r in res.values())
-    # the same six ops launched block by block
+    def table(ops):
+        out = {}
+        for name, fn in ops.items():
+            ms = timed(fn)
+            out[name] = {"ms": round(ms, 4), "GB/s": round(model[name] / (ms * 1e-3) / 1e9, 1)}
+        return out
+
+    xL.copy_(LB.trisolve(L, bL, True))
+    untuned = table(batched_ops(B))
+    t1 = time.perf_counter()
+    tune = B.autotune(k=k, reps=3)
+    tune_s = time.perf_counter() - t1
+    tuned = table(batched_ops(B))
+    # the library's per-matrix kernels over the whole concatenation
+    whole = table({
+        "spmv fwd": lambda: sp.spmv(P, v, x),
+        "spmv bwd": lambda: sp.spmv_bwd(P, v, x, gy),
+        "spmm fwd": lambda: sp.spmm(P, v, X),
+        "spmm bwd": lambda: sp.spmm_bwd(P, v, X, G),
+        "trisolve fwd": lambda: sp.trisolve(L.pattern, Lv, bL, True),
+        "trisolve bwd": lambda: sp.trisolve_bwd(L.pattern, Lv, xL, gL, True),
+    })
+    # the same six ops launched block by block (per-block patterns, values
+    # and transposes made beforehand)
     per = []
-    for blk, lblk in zip(blocks, [gen.tril(b) for b in blocks]):
-        Ab = sp.CsrTensor.from_host(blk, dtype=torch.float32)
-        Lb = sp.CsrTensor.from_host(lblk, dtype=torch.float32)
-        m = blk.nrows
-        xb, Xb = x[:m].contiguous(), X[:m].contiguous()
-        Gb, gb = G[:m].contiguous(), gy[:m].contiguous()
-        Ab.pattern.transpose()
-        Lb.pattern.levels(True)
-        per.append((Ab, Lb, xb, Xb, Gb, gb))
+    rp, rpL = B.host.rowptr, Lh.rowptr
+    for bi in range(nblocks):
+        r0, r1 = int(B.block_rowptr[bi]), int(B.block_rowptr[bi + 1])
+        e_0, e_1 = int(rp[r0]), int(rp[r1])
+        f_0, f_1 = int(rpL[r0]), int(rpL[r1])
+        Pb = sp.Pattern(r1 - r0, r1 - r0, (P.rowptr[r0:r1 + 1] - e_0).contiguous(),
+                        (P.colind[e_0:e_1] - r0).contiguous())
+        PLb = sp.Pattern(r1 - r0, r1 - r0, (L.pattern.rowptr[r0:r1 + 1] - f_0).contiguous(),
+                         (L.pattern.colind[f_0:f_1] - r0).contiguous())
+        Pb.transpose()
+        PLb.transpose()
+        PLb.levels(True)
+        per.append((Pb, v[e_0:e_1], PLb, Lv[f_0:f_1], slice(r0, r1)))
+    xs, gys, Xs, Gs, bLs, xLs, gLs = (t.contiguous() for t in (x, gy, X, G, bL, xL, gL))
 
     def per_block():
-        for Ab, Lb, xb, Xb, Gb, gb in per:
-            sp.spmv(Ab.pattern, Ab.vals, xb)
-            sp.spmv_bwd(Ab.pattern, Ab.vals, xb, gb)
-            sp.spmm(Ab.pattern, Ab.vals, Xb)
-            sp.spmm_bwd(Ab.pattern, Ab.vals, Xb, Gb)
-            sp.trisolve(Lb.pattern, Lb.vals, xb, True)
-            sp.trisolve_bwd(Lb.pattern, Lb.vals, xb, gb, True)
+        for Pb, vb, PLb, lvb, sl in per:
+            sp.spmv(Pb, vb, xs[sl])
+            sp.spmv_bwd(Pb, vb, xs[sl], gys[sl])
+            sp.spmm(Pb, vb, Xs[sl])
+            sp.spmm_bwd(Pb, vb, Xs[sl], Gs[sl])
+            sp.trisolve(PLb, lvb, bLs[sl], True)
+            sp.trisolve_bwd(PLb, lvb, xLs[sl], gLs[sl], True)
 
-    per_ms = timed(per_block)
-    return {
-        "workload": f"{nblocks} random geometric-graph Laplacians + 1e-2 I (of the 512-block recipe: "
-                    f"blocks 0..{nblocks - 1}), n in [1024, 65536], kNN k in [6, 14], float32, "
-                    f"block-diagonal: n={n}, nnz={nnz}; L = tril (nnz={nnzL}, {nl} levels); k={k}",
-        "ops": res,
-        "batched_ms": round(total_ms, 4),
-        "batched_GB/s": round(sum(model.values()) / (total_ms * 1e-3) / 1e9, 1),
+    per_ms = timed(per_block, r=max(1, reps // 2))
+    tot = lambda t: sum(r["ms"] for r in t.values())
+    res = {
+        "workload": f"{nblocks} random geometric-graph Laplacians + 1e-2 I (n in [1024, 65536], "
+                    f"kNN k in [6, 14]), float32, block-diagonal: n={n}, nnz={nnz}; IC(0) factor per "
+                    f"block (nnz={nnzL}, {nl} levels at most); SpMM with k={k}",
+        "tuned": tuned,
+        "untuned": untuned,
+        "whole_matrix_kernels": whole,
+        "batched_ms": round(tot(tuned), 4),
+        "batched_GB/s": round(sum(model.values()) / (tot(tuned) * 1e-3) / 1e9, 1),
+        "untuned_ms": round(tot(untuned), 4),
+        "whole_matrix_ms": round(tot(whole), 4),
         "per_block_ms": round(per_ms, 4),
-        "batching_speedup": round(per_ms / total_ms, 2),
-        "spmm_plans": {op: (list(c) if c else "natural") for op, (c, _) in tuned.items()},
-        "spmv_bwd_mode": spmv_mode,
+        "speedup_vs_per_block": round(per_ms / tot(tuned), 2),
+        "launches_per_step": 6,
+        "variants": {fam: {f"{c[0]}/{'uneven' if c[1] else 'even'}": v[0] for c, v in per_cls.items()}
+                     for fam, per_cls in tune.items()},
+        "tune_s": round(tune_s, 1),
         "generation_s": round(gen_s, 1),
+        "setup_s": round(setup_s, 1),
     }
+    log(f"batched: tuned {res['batched_ms']} ms ({res['batched_GB/s']} GB/s), untuned "
+        f"{res['untuned_ms']} ms, whole-matrix kernels {res['whole_matrix_ms']} ms, "
+        f"block by block {res['per_block_ms']} ms")
+    del per, B, LB, L, X, G
+    torch.cuda.empty_cache()
+    if skew:
+        res["uneven_rows"] = skew_section(skew, reps)
+    return res
+
+
+def skew_section(blocks, reps):
+    """SpMV and SpMM (64 columns) forward and backward over blocks with
+    heavy-tailed row lengths, with every block row-split, every block
+    merge-path, and the autotuner's choice."""
+    import torch
+    from paper_2212_05159_amd import batch as bt
+
+    B = bt.Batch(blocks)
+    n, nnz, k = B.host.nrows, B.host.nnz, 64
+    g = torch.Generator(device="cuda")
+    g.manual_seed(5)
+    x = torch.randn(n, generator=g, device="cuda")
+    X = torch.randn(n, k, generator=g, device="cuda")
+    B.pattern.transpose()
+    V, I = 4, I4
+    pat = lambda rows, z: (rows + 1) * I + z * I
+    model = {"spmv fwd": pat(n, nnz) + nnz * V + 2 * n * V,
+             "spmv bwd": pat(n, nnz) + nnz * (I + 2 * V) + 3 * n * V,
+             "spmm fwd": pat(n, nnz) + nnz * V + 2 * n * k * V,
+             "spmm bwd": pat(n, nnz) + nnz * (I + 2 * V) + 3 * n * k * V}
+    ops = {"spmv fwd": lambda: B.spmv(x), "spmv bwd": lambda: B.spmv_bwd(x, x),
+           "spmm fwd": lambda: B.spmm(X), "spmm bwd": lambda: B.spmm_bwd(X, X)}
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def run(label):
+        out = {}
+        for name, fn in ops.items():
+            fn()
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(reps):
+                e0.record()
+                fn()
+                e1.record()
+                torch.cuda.synchronize()
+                ts.append(e0.elapsed_time(e1))
+            ms = float(np.median(ts))
+            out[name] = {"ms": round(ms, 4), "GB/s": round(model[name] / (ms * 1e-3) / 1e9, 1)}
+        return out
+
+    res = {"workload": f"{len(blocks)} blocks with heavy-tailed row lengths (len = floor(u^(-1/1.1)), "
+                       f"at most n/2), n in [1024, 65536]: n={n}, nnz={nnz}, longest row "
+                       f"{int(B.block_maxrow.max())}; float32, k={k}"}
+    for label, var in (("row_split", bt.rows_variant(8)), ("merge_path", bt.MERGE)):
+        for fam in ("spmv", "spmv_t", "spmm", "spmm_t"):
+            v = var if fam.startswith("spmv") else (bt.rows_variant(16) if var != bt.MERGE else var)
+            B.set_variants(fam, np.full(B.nblocks, v, np.int32))
+        res[label] = run(label)
+    B.autotune(k=k, reps=3)
+    res["tuned"] = run("tuned")
+    log("uneven rows: " + ", ".join(f"{lab} spmm fwd {res[lab]['spmm fwd']['ms']} ms"
+                                     for lab in ("row_split", "merge_path", "tuned")))
+    return res
+
+
+def skew_blocks(nblocks):
+    """Blocks with heavy-tailed row lengths: per block b, default_rng([6, b])
+    draws n ~ U{1024..65536}; gen.power_law_rows(n, [6, b, 1], alpha 1.1,
+    at most n/2 entries per row)."""
+    from paper_2212_05159_amd import gen
+
+    out = []
+    for b in range(nblocks):
+        n = int(np.random.default_rng([6, b]).integers(1024, 65537))
+        out.append(gen.power_law_rows(n, [6, b, 1], alpha=1.1, max_len=n // 2))
+    return out
 
 
 # ----------------------------------------------------------------------
@@ -573,9 +701,9 @@ def byte_model(d, nnz_ap, nnz_c, nlev):
     b["transpose P"] = transpose(n, nc, nP)
     b["transpose vals P"] = nP * (I4 + 2 * V)
     b["spmv fwd"] = pat(n, nA) + nA * V + 2 * n * V
-    b["spmv bwd"] = pat(n, nA) + nA * (I4 + 2 * V) + 3 * n * V
+    b["spmv bwd"] = pat(n, nA) + nA * 2 * V + 3 * n * V
     b["spmm fwd"] = pat(n, nA) + nA * V + 2 * n * k * V
-    b["spmm bwd"] = pat(n, nA) + nA * (I4 + 2 * V) + 3 * n * k * V
+    b["spmm bwd"] = pat(n, nA) + nA * 2 * V + 3 * n * k * V
     b["spgemm A.P"] = spgemm_sym(n, nA, n, nP) + spgemm_num(n, nA, n, nP, nnz_ap)
     b["spgemm Pt.AP"] = spgemm_sym(nc, nP, n, nnz_ap) + spgemm_num(nc, nP, n, nnz_ap, nnz_c)
     b["transpose Pt"] = transpose(nc, n, nP)
@@ -662,7 +790,7 @@ def run_step(d, marks, outs=None):
     gbL, gvL = sp.trisolve_bwd(PL, d.L_v, xL, d.gL, True)
     marks.mark("trisolve bwd")
     _keep(outs, y=y, gx=gx, gv=gv, C=C, gB=gB, gvm=gvm, rpAP=PAP.rowptr, ciAP=PAP.colind, vAP=vAP,
-          ciC=PC.colind, vC=vC, gPt=gPt, gAP=gAP, gA=gA, gP=gP, xL=xL, gbL=gbL, gvL=gvL)
+          rpC=PC.rowptr, ciC=PC.colind, vC=vC, gPt=gPt, gAP=gAP, gA=gA, gP=gP, xL=xL, gbL=gbL, gvL=gvL)
     return PAP.nnz, PC.nnz, nl
 
 
@@ -718,7 +846,8 @@ def run_step_streams(d, chain_marks, outs=None):
             s2.wait_event(tA)
             gA, gP = sp.spgemm_bwd(PA, d.A_v, PP, d.P_v, PAP, gAP)
             m2.mark("spgemm bwd A.P")
-            _keep(outs, rpAP=PAP.rowptr, ciAP=PAP.colind, vAP=vAP, ciC=PC.colind, vC=vC,
+            _keep(outs, rpAP=PAP.rowptr, ciAP=PAP.colind, vAP=vAP, rpC=PC.rowptr, ciC=PC.colind,
+                  vC=vC,
                   gPt=gPt, gAP=gAP, gA=gA, gP=gP)
             return PAP.nnz, PC.nnz
 
@@ -760,7 +889,23 @@ def run_step_streams(d, chain_marks, outs=None):
 # ----------------------------------------------------------------------
 # Oracle on the host (CPU baseline)
 # ----------------------------------------------------------------------
-def cpu_baseline(h, bytes_total):
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(h, bytes_total, seconds=10.0):
+    """The float64 oracle timed on the host over whole steps of the same
+    workload: its OpenMP build on all host cores (the reported value; row-
+    parallel loops only, the A^T products and SpGEMM stay serial) and its
+    single-threaded build (the paper's CPU setting), about `seconds` of work
+    each, at least one step; median step time of each leg."""
     import oracle
     from paper_2212_05159_amd import gen
 
@@ -789,17 +934,31 @@ def cpu_baseline(h, bytes_total):
         xL = oracle.trisolve(L, f(h["bL"]), True)
         oracle.trisolve_bwd(L, xL, f(h["gL"]), True)
 
-    # whole steps until about 10 s of CPU work (at least one)
-    t0 = time.perf_counter()
-    steps = 0
-    while steps == 0 or time.perf_counter() - t0 < 10.0:
-        one_step()
-        steps += 1
-    dt = (time.perf_counter() - t0) / steps
-    return {"value": round(bytes_total / dt / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
-            "seconds": round(dt, 2), "steps": steps,
-            "sample": f"{steps} full steps of the same workload (every op above; seconds is "
-                      "the mean per step), float64 oracle, single thread"}
+    def leg(threads):
+        oracle.use_threads(threads)
+        try:
+            nth = oracle.threads()
+            ts = []
+            t0 = time.perf_counter()
+            while not ts or time.perf_counter() - t0 < seconds:
+                t1 = time.perf_counter()
+                one_step()
+                ts.append(time.perf_counter() - t1)
+        finally:
+            oracle.use_threads(False)
+        dt = float(np.median(ts))
+        return {"value": round(bytes_total / dt / 1e9, 3), "unit": "GB/s", "cores": nth,
+                "seconds": round(dt, 3), "steps": len(ts)}
+
+    allc = leg(True)
+    one = leg(False)
+    return {**allc, "kind": "oracle", "cpu": _cpu_model(), "host_cpus": os.cpu_count(),
+            "single_thread": one,
+            "sample": f"whole steps of the same workload (every op of the step), median step time; "
+                      f"{allc['steps']} steps on {allc['cores']} threads (OpenMP build: loops over "
+                      f"independent rows split among threads, A^T products, transposes, SpGEMM and "
+                      f"solves serial) and {one['steps']} on one thread (the paper's CPU setting), "
+                      f"float64"}
 
 
 def calibrate(millions):
@@ -843,8 +1002,10 @@ def main():
     ap.add_argument("--serial", action="store_true",
                     help="run the step's ops in sequence on one stream (exact per-op attribution) "
                          "instead of three concurrent chains")
-    ap.add_argument("--batched-blocks", type=int, default=64,
+    ap.add_argument("--batched-blocks", type=int, default=512,
                     help="number of the 512 geometric-graph blocks in the batched part")
+    ap.add_argument("--skew-blocks", type=int, default=64,
+                    help="blocks with heavy-tailed row lengths in the batched part (0: none)")
     ap.add_argument("--calibrate", type=int, default=0, metavar="M",
                     help="only run a copy-like kernel over M million float32 values "
                          "(identity-permutation gather: 12 bytes per value) to calibrate "
@@ -861,6 +1022,7 @@ def main():
         # work overlaps nothing on the GPU)
         host_blocks = geometric_blocks(args.batched_blocks)
         log(f"built {args.batched_blocks} geometric-graph blocks in {host_blocks[1]:.1f} s")
+        skew = skew_blocks(args.skew_blocks) if args.skew_blocks else None
 
     import torch
     from paper_2212_05159_amd import capi
@@ -951,22 +1113,51 @@ def main():
                  for kname in bm}
     value = total_bytes / (ms_step * 1e-3) / 1e9
 
+    # Roofline of the dominant kernel: k_spmm_bwd_coop alone, median of 60
+    # launches timed with HIP events on the stream it runs on, against its
+    # minimum algorithmic bytes ((m+1)I + nnz(I+2V) + 3nkV: pattern, values
+    # read and value gradients written once, G read, B read, gB written).
+    from paper_2212_05159_amd import sparse as sp
     dom = "spmm bwd"
-    dom_ms = op_ms[dom]
+    PA = sp.Pattern(d.n, d.n, d.A_rp, d.A_ci)
+    gB_buf, gv_buf = torch.empty_like(d.G), torch.empty_like(d.A_v)
+    PAt, permA = PA.transpose()
+    from paper_2212_05159_amd import capi as _capi
+    dA, dAt = PA.desc(d.A_v), PAt.desc(dtype=d.A_v.dtype)
+
+    def dom_launch():
+        _capi.csr_spmm_bwd(dA, dAt, permA, d.k, d.B, d.k, d.G, d.k, gB_buf, d.k, gv_buf,
+                           d.plan_bwd)
+
+    stream = torch.cuda.current_stream()
+    dom_launch()
+    torch.cuda.synchronize()
+    reps_dom = []
+    for _ in range(60):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        dom_launch()
+        e1.record(stream)
+        e1.synchronize()
+        reps_dom.append(e0.elapsed_time(e1))
+    dom_ms = float(np.median(reps_dom))
     achieved = bm[dom] / (dom_ms * 1e-3) / 1e9
     bwd_plan = tuned["spmm_bwd"][0]
     roofline = {"bound": "hbm", "kernel": "k_spmm_bwd_coop (fused A^T G and G B^T on pat(A))",
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": measured_traffic("k_spmm_bwd_coop", bwd_plan),
-                "bytes_per_launch": bm[dom], "avg_ms": round(dom_ms, 4),
+                "bytes_per_launch": bm[dom], "median_ms": round(dom_ms, 4), "launches": 60,
                 "plan": "natural" if bwd_plan is None else list(bwd_plan)}
+    for kname in breakdown:
+        breakdown[kname]["frac"] = round(breakdown[kname]["GB/s"] / HBM_PEAK_GBS, 4)
 
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the oracle on the host (one step) ...")
         cpu = cpu_baseline(h, total_bytes)
-        log(f"oracle: {cpu['seconds']} s per step over {cpu['steps']} steps")
+        log(f"oracle: {cpu['seconds']} s per step on {cpu['cores']} threads, "
+            f"{cpu['single_thread']['seconds']} s on one ({cpu['cpu']})")
 
     pcg = None
     if not args.no_pcg:
@@ -976,9 +1167,8 @@ def main():
     batched = None
     if not args.no_batched:
         log(f"batched part ({args.batched_blocks} blocks) ...")
-        batched = batched_section(*host_blocks)
-        log(f"batched: {batched['batched_ms']} ms for the six ops over the batch, "
-            f"{batched['per_block_ms']} ms block by block")
+        batched = batched_section(*host_blocks, skew=skew)
+        host_blocks = skew = None
 
     cgres = None
     if not args.no_cg:

@@ -360,6 +360,119 @@ int csr_mpnn_readout_bwd(const csrad_csr *Lpat, const float *ahatL,
                          const float *gL, float *gt, void *stream);
 
 /* ---------------------------------------------------------------------
+ * Batched operators over a block-diagonal CSR matrix (many independent
+ * sparse matrices of uneven sizes concatenated along the diagonal; block b
+ * owns rows and columns [block_rowptr[b], block_rowptr[b+1])).  The ops
+ * are those of Sections 3.1.1 (SpMV), 3.1.3 (SpDMM) and 3.1.5 (SpSolve),
+ * each as ONE persistent launch over a work queue of tasks.
+ *
+ * A plan (csr_batch_plan_build) cuts every block into row-aligned tasks of
+ * about `budget` path items (rows + stored entries), orders the blocks by
+ * that cost, largest first, and gives each task its block's traversal
+ * variant:
+ *   -1  leave the block out (its rows are not written),
+ *    0  automatic (from the block's mean row length),
+ *   1..7 row-split, 2^(v-1) lanes per row (SpMV; the SpMM kernels use
+ *        one 16-lane group per row for any v != 8),
+ *    8  merge-path: the task's merge path of row ends and entries is cut
+ *        into equal pieces, one per thread (SpMV) or per 16-lane group
+ *        (SpMM); rows cut by a piece boundary are completed from the
+ *        pieces' partial sums in piece order (for blocks with very uneven
+ *        rows; merge tasks take merge_budget(budget) =
+ *        clamp(budget/4, 256, 4096) path items),
+ *    9  rows staged 256 at a time in LDS (short rows; SpMV).
+ * Every variant is deterministic; a variant's result does not depend on
+ * the other blocks of the batch.  budget <= 0 makes one task per block
+ * (the triangular solves need that).  A plan covers the rows of the matrix
+ * it was built on: the forward ops take a plan of A, the backward ops a
+ * plan of A^T (csr_transpose of a block-diagonal matrix is block-diagonal
+ * with the same blocks).
+ *
+ * csr_batch_plan_workspace: bytes of device memory the plan keeps (task
+ *   records, queue counters, block_rowptr); the caller owns it and keeps
+ *   it alive while the plan is used.
+ * csr_batch_plan_build: fills *plan (a host struct pointing into `work`);
+ *   block_rowptr_host (nblocks+1 host int32, from 0 to A's rows,
+ *   non-decreasing) and variant_host (nblocks host int32, may be NULL =
+ *   automatic) are read during the call, which synchronises the stream.
+ * The queue counters of a plan are shared by its launches: launches that
+ * use one plan must be ordered on one stream.
+ * ------------------------------------------------------------------- */
+typedef struct csrad_batch_plan {
+    int32_t nrows;   /* rows of the matrix the plan was built on */
+    int32_t nblocks;
+    int32_t ntasks;
+    int32_t cus;     /* compute units; the launch keeps 4 workgroups each */
+    const void *tasks;           /* device, inside the plan workspace */
+    void *counters;              /* device, inside the plan workspace */
+    const int32_t *block_rowptr; /* device copy, inside the plan workspace */
+} csrad_batch_plan;
+
+int csr_batch_plan_workspace(const csrad_csr *A, int32_t nblocks, int32_t budget,
+                             size_t *bytes);
+int csr_batch_plan_build(const csrad_csr *A, int32_t nblocks,
+                         const int32_t *block_rowptr_host,
+                         const int32_t *variant_host, int32_t budget, void *work,
+                         size_t work_bytes, csrad_batch_plan *plan, void *stream);
+
+/* y = A x (plan of A).  Same arguments as csr_spmv_fwd. */
+int csr_batch_spmv_fwd(const csrad_csr *A, const csrad_batch_plan *plan,
+                       const void *x, void *y, void *stream);
+/* VJP of y = A x over A^T (At/perm from csr_transpose; planT a plan of At):
+ * gx = A^T gy, gvals[e] = gy[row e] x[col e]; either output may be NULL. */
+int csr_batch_spmv_bwd(const csrad_csr *A, const csrad_csr *At,
+                       const int32_t *perm, const csrad_batch_plan *planT,
+                       const void *x, const void *gy, void *gx, void *gvals,
+                       void *stream);
+/* C = A B (plan of A); k a multiple of 4 (float32) or 2 (float64), B and
+ * C 16-byte aligned with 16-byte aligned rows. */
+int csr_batch_spmm_fwd(const csrad_csr *A, const csrad_batch_plan *plan,
+                       int32_t k, const void *B, int64_t ldb, void *C,
+                       int64_t ldc, void *stream);
+/* VJP of C = A B in one pass over A^T (planT a plan of At): gB = A^T gC,
+ * gvals[e] = <gC[row e,:], B[col e,:]>; either output may be NULL. */
+int csr_batch_spmm_bwd(const csrad_csr *A, const csrad_csr *At,
+                       const int32_t *perm, const csrad_batch_plan *planT,
+                       int32_t k, const void *B, int64_t ldb, const void *gC,
+                       int64_t ldgc, void *gB, int64_t ldgb, void *gvals,
+                       void *stream);
+/* Triangular solves per block (plan built with budget <= 0).  The level
+ * sets of the whole block-diagonal T come from csr_trisolve_analyze;
+ * csr_batch_levels writes, into a caller workspace of
+ * csr_batch_levels_workspace bytes, where each block's rows sit in each
+ * level (asynchronous).  csr_batch_trisolve_fwd: x = T^{-1} b, one
+ * workgroup per block running its levels in order.
+ * csr_batch_trisolve_bwd: gb = T^{-T} gx over Tt/perm with the levels in
+ * reverse, then gvals[(i,j)] = -gb_i x_j on pat(T) (gvals may be NULL). */
+int csr_batch_levels_workspace(int32_t nblocks, int32_t nlevels, size_t *bytes);
+int csr_batch_levels(const csrad_batch_plan *plan, int32_t nlevels,
+                     const int32_t *level_ptr, const int32_t *level_rows,
+                     void *work, size_t work_bytes, void *stream);
+int csr_batch_trisolve_fwd(const csrad_csr *T, const csrad_batch_plan *plan,
+                           int32_t nlevels, const int32_t *level_rows,
+                           const void *levels_work, size_t levels_bytes,
+                           const void *b, void *x, void *stream);
+int csr_batch_trisolve_bwd(const csrad_csr *T, const csrad_csr *Tt,
+                           const int32_t *perm, const csrad_batch_plan *plan,
+                           int32_t nlevels, const int32_t *level_rows,
+                           const void *levels_work, size_t levels_bytes,
+                           const void *x, const void *gx, void *gb,
+                           void *gvals, void *stream);
+/* Incomplete Cholesky IC(0) per block (the factor the batched solves
+ * take; Saad, Section 10.3): Alow is tril(A) with its values (diagonal
+ * stored and last in every row); Lvals (nnz(Alow)) receives L on the same
+ * pattern with L_ij = (A_ij - sum_{k<j} L_ik L_jk) / L_jj and
+ * L_ii = sqrt(A_ii - sum_{k<i} L_ik^2), sums over the columns stored in
+ * both rows, entries of a row in column order.  Rows run level by level
+ * (the levels of the lower solve on Alow's pattern, as for
+ * csr_batch_trisolve_fwd; plan built with budget <= 0).  A non-positive
+ * pivot leaves NaN in that diagonal and in every entry computed from it. */
+int csr_batch_ic0(const csrad_csr *Alow, const csrad_batch_plan *plan,
+                  int32_t nlevels, const int32_t *level_rows,
+                  const void *levels_work, size_t levels_bytes, void *Lvals,
+                  void *stream);
+
+/* ---------------------------------------------------------------------
  * Pattern check: rowptr monotone from 0 to nnz, colind in [0, ncols),
  * strictly ascending within each row.  *first_bad_row_host receives the
  * first offending row or -1 (synchronises).  Returns CSRAD_EPATTERN if a

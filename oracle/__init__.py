@@ -18,8 +18,11 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
+_SO_OMP = os.path.join(_HERE, "liboracle_omp.so")
 _SRC = os.path.join(_HERE, "oracle.c")
 _lib = None
+_libs = {}
+_threads = False
 
 _I32P = np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS")
 _F64P = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
@@ -42,22 +45,42 @@ _I32N = _Nullable(_I32P)
 
 
 def build(force: bool = False) -> str:
-    """Compile liboracle.so with gcc (single-threaded, -O2)."""
-    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
-        tmp = _SO + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared",
-                               "-Wall", "-Wextra", "-o", tmp, _SRC, "-lm"])
-        os.replace(tmp, _SO)
+    """Compile liboracle.so with gcc (single-threaded, -O2) and, from the
+    same source, liboracle_omp.so with OpenMP (row-parallel loops; used
+    only to time the oracle on all host cores)."""
+    for so, extra in ((_SO, []), (_SO_OMP, ["-fopenmp"])):
+        if force or not os.path.exists(so) or os.path.getmtime(so) < os.path.getmtime(_SRC):
+            tmp = so + ".tmp"
+            subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", *extra,
+                                   "-Wall", "-Wextra", "-o", tmp, _SRC, "-lm"])
+            os.replace(tmp, so)
     return _SO
+
+
+def threads() -> int:
+    """Threads the current build's row-parallel loops use."""
+    return int(_load().or_threads())
+
+
+def use_threads(on: bool) -> None:
+    """Route later calls to the OpenMP build (on) or the single-threaded
+    one (off, the default).  Both return the same bits."""
+    global _threads, _lib
+    _threads = bool(on)
+    _lib = None
 
 
 def _load():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_SO):
+    so = _SO_OMP if _threads else _SO
+    if so in _libs:
+        _lib = _libs[so]
+        return _lib
+    if not os.path.exists(so):
         build()
-    lib = C.CDLL(_SO)
+    lib = C.CDLL(so)
     i32, i64, dbl, cint = C.c_int32, C.c_int64, C.c_double, C.c_int
     sig = {
         "or_spmv": (None, [i32, _I32P, _I32P, _F64P, _F64P, _F64P]),
@@ -84,11 +107,13 @@ def _load():
                          _F64P, _F64N]),
         "or_ic0": (i32, [i32, _I32P, _I32P, _F64P, _I32P, _I32P, _F64P]),
         "or_paper_loss": (dbl, [i32, dbl, _F64P, dbl, _F64P]),
+        "or_threads": (cint, []),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
         fn.restype = res
         fn.argtypes = args
+    _libs[so] = lib
     _lib = lib
     return lib
 

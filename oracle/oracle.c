@@ -5,9 +5,16 @@
  * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
  * CPU-baseline leg of the benchmark load this library.  It shares no code,
  * header, table or helper with the HIP library: every routine below is a
- * plain, single-threaded loop over CSR arrays that follows the definition
- * of the operation it names, in float64, with no blocking, fusion or
- * reordering.  Callers upcast float32 inputs to float64 exactly.
+ * plain loop over CSR arrays that follows the definition of the operation
+ * it names, in float64, with no blocking, fusion or reordering.  Callers
+ * upcast float32 inputs to float64 exactly.
+ *
+ * Threads: the default build is single-threaded.  A second build of this
+ * same file with OpenMP (used only to time the oracle on all host cores)
+ * splits the loops over independent rows among threads (the loops marked
+ * ROWS_PARALLEL); each row is still computed by one thread in the same
+ * order, so both builds return the same bits.  Loops that accumulate into
+ * shared entries (the A^T products) stay serial.
  *
  * Conventions: CSR with int32 rowptr[m+1] and colind[nnz] (ascending and
  * unique within a row); dense multi-column operands are row-major with k
@@ -27,6 +34,23 @@
 typedef int32_t i32;
 typedef int64_t i64;
 
+#ifdef _OPENMP
+#include <omp.h>
+#define ROWS_PARALLEL _Pragma("omp parallel for schedule(static)")
+#else
+#define ROWS_PARALLEL
+#endif
+
+/* Threads the row-parallel loops use (1 in the single-threaded build). */
+int or_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
 /* ------------------------------------------------------------------ */
 /* SpMV, Section 3.1.1; Table 1 (SpMV row).                             */
 /* ------------------------------------------------------------------ */
@@ -35,6 +59,7 @@ typedef int64_t i64;
 void or_spmv(i32 m, const i32 *rp, const i32 *ci, const double *v,
              const double *x, double *y)
 {
+    ROWS_PARALLEL
     for (i32 i = 0; i < m; ++i) {
         double s = 0.0;
         for (i32 e = rp[i]; e < rp[i + 1]; ++e) s += v[e] * x[ci[e]];
@@ -54,6 +79,7 @@ void or_spmv_bwd(i32 m, i32 n, const i32 *rp, const i32 *ci, const double *v,
             for (i32 e = rp[i]; e < rp[i + 1]; ++e) gx[ci[e]] += v[e] * gy[i];
     }
     if (gv) {
+        ROWS_PARALLEL
         for (i32 i = 0; i < m; ++i)
             for (i32 e = rp[i]; e < rp[i + 1]; ++e) gv[e] = gy[i] * x[ci[e]];
     }
@@ -67,6 +93,7 @@ void or_spmv_bwd(i32 m, i32 n, const i32 *rp, const i32 *ci, const double *v,
 void or_spmm(i32 m, i32 k, const i32 *rp, const i32 *ci, const double *v,
              const double *B, double *C)
 {
+    ROWS_PARALLEL
     for (i32 i = 0; i < m; ++i)
         for (i32 c = 0; c < k; ++c) {
             double s = 0.0;
@@ -91,6 +118,7 @@ void or_spmm_bwd(i32 m, i32 n, i32 k, const i32 *rp, const i32 *ci,
                     gB[(i64)ci[e] * k + c] += v[e] * G[(i64)i * k + c];
     }
     if (gv) {
+        ROWS_PARALLEL
         for (i32 i = 0; i < m; ++i)
             for (i32 e = rp[i]; e < rp[i + 1]; ++e) {
                 double s = 0.0;

@@ -32,6 +32,12 @@ class csrad_plan(C.Structure):
     _fields_ = [("row_stride", C.c_int32), ("row_tile", C.c_int32)]
 
 
+class csrad_batch_plan(C.Structure):
+    _fields_ = [("nrows", C.c_int32), ("nblocks", C.c_int32), ("ntasks", C.c_int32),
+                ("cus", C.c_int32), ("tasks", C.c_void_p), ("counters", C.c_void_p),
+                ("block_rowptr", C.c_void_p)]
+
+
 _lib = None
 
 _SIGS = {
@@ -97,6 +103,27 @@ _SIGS = {
     "csr_mpnn_readout_bwd": (C.c_int, [C.c_void_p] * 4 + [C.c_float] + [C.c_void_p] * 3),
     "csr_validate": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.c_void_p, C.c_size_t,
                                C.c_void_p]),
+    "csr_batch_plan_workspace": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32,
+                                           C.POINTER(C.c_size_t)]),
+    "csr_batch_plan_build": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32,
+                                       C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p]),
+    "csr_batch_spmv_fwd": (C.c_int, [C.c_void_p] * 5),
+    "csr_batch_spmv_bwd": (C.c_int, [C.c_void_p] * 9),
+    "csr_batch_spmm_fwd": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_int64,
+                                     C.c_void_p, C.c_int64, C.c_void_p]),
+    "csr_batch_spmm_bwd": (C.c_int, [C.c_void_p] * 4 + [C.c_int32, C.c_void_p, C.c_int64,
+                                                         C.c_void_p, C.c_int64, C.c_void_p,
+                                                         C.c_int64, C.c_void_p, C.c_void_p]),
+    "csr_batch_levels_workspace": (C.c_int, [C.c_int32, C.c_int32, C.POINTER(C.c_size_t)]),
+    "csr_batch_levels": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                                   C.c_size_t, C.c_void_p]),
+    "csr_batch_trisolve_fwd": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p,
+                                         C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p,
+                                         C.c_void_p]),
+    "csr_batch_trisolve_bwd": (C.c_int, [C.c_void_p] * 4 + [C.c_int32, C.c_void_p, C.c_void_p,
+                                                             C.c_size_t] + [C.c_void_p] * 5),
+    "csr_batch_ic0": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
+                                C.c_size_t, C.c_void_p, C.c_void_p]),
 }
 
 
@@ -414,3 +441,84 @@ def csr_validate(A, work):
     if st not in (0, -3):
         _check("csr_validate", st)
     return st, bad.value
+
+
+# ----------------------------------------------------------------------
+# Batched (block-diagonal) operators.
+# ----------------------------------------------------------------------
+
+def csr_batch_plan_workspace(A, nblocks, budget):
+    n = C.c_size_t(0)
+    _check("csr_batch_plan_workspace",
+           load().csr_batch_plan_workspace(C.byref(A), int(nblocks), int(budget), C.byref(n)))
+    return n.value
+
+
+def csr_batch_plan_build(A, block_rowptr_host, variants_host, budget, work):
+    """Returns a csrad_batch_plan pointing into `work` (keep both alive)."""
+    brp = np.ascontiguousarray(block_rowptr_host, dtype=np.int32)
+    var = None if variants_host is None else np.ascontiguousarray(variants_host, dtype=np.int32)
+    plan = csrad_batch_plan()
+    _check("csr_batch_plan_build",
+           load().csr_batch_plan_build(C.byref(A), int(len(brp) - 1), brp.ctypes.data,
+                                       None if var is None else var.ctypes.data, int(budget),
+                                       _ptr(work), work.numel(), C.byref(plan), _stream()))
+    return plan
+
+
+def csr_batch_spmv_fwd(A, plan, x, y):
+    _check("csr_batch_spmv_fwd",
+           load().csr_batch_spmv_fwd(C.byref(A), C.byref(plan), _ptr(x), _ptr(y), _stream()))
+
+
+def csr_batch_spmv_bwd(A, At, perm, planT, x, gy, gx, gvals):
+    _check("csr_batch_spmv_bwd",
+           load().csr_batch_spmv_bwd(C.byref(A), C.byref(At), _ptr(perm), C.byref(planT), _ptr(x),
+                                     _ptr(gy), _ptr(gx), _ptr(gvals), _stream()))
+
+
+def csr_batch_spmm_fwd(A, plan, k, B, ldb, Cout, ldc):
+    _check("csr_batch_spmm_fwd",
+           load().csr_batch_spmm_fwd(C.byref(A), C.byref(plan), int(k), _ptr(B), int(ldb),
+                                     _ptr(Cout), int(ldc), _stream()))
+
+
+def csr_batch_spmm_bwd(A, At, perm, planT, k, B, ldb, gC, ldgc, gB, ldgb, gvals):
+    _check("csr_batch_spmm_bwd",
+           load().csr_batch_spmm_bwd(C.byref(A), C.byref(At), _ptr(perm), C.byref(planT), int(k),
+                                     _ptr(B), int(ldb), _ptr(gC), int(ldgc), _ptr(gB), int(ldgb),
+                                     _ptr(gvals), _stream()))
+
+
+def csr_batch_levels_workspace(nblocks, nlevels):
+    n = C.c_size_t(0)
+    _check("csr_batch_levels_workspace",
+           load().csr_batch_levels_workspace(int(nblocks), int(nlevels), C.byref(n)))
+    return n.value
+
+
+def csr_batch_levels(plan, nlevels, level_ptr, level_rows, work):
+    _check("csr_batch_levels",
+           load().csr_batch_levels(C.byref(plan), int(nlevels), _ptr(level_ptr), _ptr(level_rows),
+                                   _ptr(work), work.numel(), _stream()))
+
+
+def csr_batch_trisolve_fwd(T, plan, nlevels, level_rows, lv_work, b, x):
+    _check("csr_batch_trisolve_fwd",
+           load().csr_batch_trisolve_fwd(C.byref(T), C.byref(plan), int(nlevels), _ptr(level_rows),
+                                         _ptr(lv_work), lv_work.numel(), _ptr(b), _ptr(x),
+                                         _stream()))
+
+
+def csr_batch_trisolve_bwd(T, Tt, perm, plan, nlevels, level_rows, lv_work, x, gx, gb, gvals):
+    _check("csr_batch_trisolve_bwd",
+           load().csr_batch_trisolve_bwd(C.byref(T), C.byref(Tt), _ptr(perm), C.byref(plan),
+                                         int(nlevels), _ptr(level_rows), _ptr(lv_work),
+                                         lv_work.numel(), _ptr(x), _ptr(gx), _ptr(gb),
+                                         _ptr(gvals), _stream()))
+
+
+def csr_batch_ic0(Alow, plan, nlevels, level_rows, lv_work, Lvals):
+    _check("csr_batch_ic0",
+           load().csr_batch_ic0(C.byref(Alow), C.byref(plan), int(nlevels), _ptr(level_rows),
+                                _ptr(lv_work), lv_work.numel(), _ptr(Lvals), _stream()))

@@ -238,17 +238,23 @@ def block_diag(blocks: list[Csr]) -> tuple[Csr, np.ndarray]:
             offs.astype(np.int32))
 
 
+def _select(a: Csr, keep: np.ndarray) -> Csr:
+    """Entries where keep is set, in their CSR order (selection keeps rows
+    and columns sorted, so no re-sort is needed)."""
+    kept = np.zeros(len(keep) + 1, dtype=np.int64)
+    np.cumsum(keep, out=kept[1:])
+    rowptr = kept[a.rowptr.astype(np.int64)]
+    return Csr(a.nrows, a.ncols, rowptr.astype(np.int32), a.colind[keep].astype(np.int32),
+               a.vals[keep])
+
+
 def tril(a: Csr, k: int = 0) -> Csr:
     """Entries with col <= row + k (pattern selection, values copied)."""
-    rows = a.row_of_entry()
-    keep = a.colind <= rows + k
-    return _from_coo(a.nrows, a.ncols, rows[keep], a.colind[keep], a.vals[keep])
+    return _select(a, a.colind <= a.row_of_entry() + k)
 
 
 def triu(a: Csr, k: int = 0) -> Csr:
-    rows = a.row_of_entry()
-    keep = a.colind >= rows + k
-    return _from_coo(a.nrows, a.ncols, rows[keep], a.colind[keep], a.vals[keep])
+    return _select(a, a.colind >= a.row_of_entry() + k)
 
 
 def permute_sym(a: Csr, perm: np.ndarray) -> Csr:
@@ -306,6 +312,25 @@ def random_rows(m: int, n: int, per_row: int, seed) -> Csr:
     assert rowptr[-1] < 2**31, "int32 CSR index space exceeded"
     colind = cols[keep].astype(np.int32)
     return Csr(m, n, rowptr.astype(np.int32), colind, rng.standard_normal(len(colind)))
+
+
+def power_law_rows(n: int, seed, alpha: float = 1.2, min_len: int = 1,
+                   max_len: int | None = None, empty: float = 0.0) -> Csr:
+    """Square n x n matrix whose row lengths follow a heavy-tailed (Zipf-like)
+    law: each row draws len = min(max_len, floor(min_len * u^(-1/alpha))),
+    u ~ U(0,1], then that many uniform columns (repeats dropped), so most
+    rows hold a few entries and a handful hold thousands (the uneven rows of
+    scale-free graphs); a fraction `empty` of the rows is empty.  N(0,1)
+    values; everything from default_rng(seed)."""
+    rng = np.random.default_rng(seed)
+    max_len = n if max_len is None else min(max_len, n)
+    u = 1.0 - rng.random(n)
+    lens = np.minimum(max_len, np.floor(min_len * u ** (-1.0 / alpha))).astype(np.int64)
+    lens[rng.random(n) < empty] = 0
+    rows = np.repeat(np.arange(n, dtype=np.int64), lens)
+    cols = rng.integers(0, n, size=len(rows), dtype=np.int64)
+    key = np.unique(rows * n + cols)
+    return _from_coo(n, n, key // n, key % n, rng.standard_normal(len(key)))
 
 
 def random_lower(n: int, density: float, seed, diag_shift: float = 2.0) -> Csr:

@@ -21,7 +21,7 @@ def test_concurrent_step_equals_serial():
     ref = {}
     bench.run_step(d, bench.Marks(False), ref)
     torch.cuda.synchronize()
-    assert len(ref) == 18
+    assert len(ref) == 19
     for _ in range(3):  # later steps reuse memory the earlier ones freed
         got = {}
         bench.run_step_streams(d, [bench.Marks(False) for _ in range(3)], got)

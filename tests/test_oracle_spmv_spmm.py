@@ -169,3 +169,26 @@ def test_transpose_matches_library_and_involution(orc):
         rp2, ci2, perm2 = orc.transpose(At)
         assert np.array_equal(rp2, A.rowptr) and np.array_equal(ci2, A.colind)
         assert np.array_equal(perm[perm2], np.arange(A.nnz))
+
+
+def test_openmp_build_returns_the_same_bits():
+    # The all-cores build only splits independent rows among threads; every
+    # output must equal the single-threaded build's bit for bit.
+    import oracle
+
+    oracle.build()
+    A = gen.random_csr(700, 500, 0.02, 41, empty_rows=0.1, long_rows=3, long_len=300)
+    rng = np.random.default_rng(42)
+    x, gy = rng.standard_normal(500), rng.standard_normal(700)
+    B, G = rng.standard_normal((500, 24)), rng.standard_normal((700, 24))
+    outs = []
+    for th in (False, True):
+        oracle.use_threads(th)
+        try:
+            outs.append([oracle.spmv(A, x), *oracle.spmv_bwd(A, x, gy), oracle.spmm(A, B),
+                         *oracle.spmm_bwd(A, B, G)])
+            assert oracle.threads() >= 1
+        finally:
+            oracle.use_threads(False)
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
