@@ -537,8 +537,9 @@ def pcg_section(n_eval, n_train, train_steps, systems):
     model = learned.MPNN(seed=1)
     untrained = learned.MPNN(seed=1)
     val = learned.held_out(learned.Q1Family(n_train), 4, 52)
+    every = max(50, train_steps // 16)
     hist = learned.train(model, N=n_train, steps=train_steps, lr=3e-3, nit=16, seed=5,
-                         val_systems=val, eval_every=50)
+                         val_systems=val, eval_every=every)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
     log(f"trained the network: {train_steps} systems of {n_train}^2 in {train_s:.1f} s "
@@ -548,7 +549,7 @@ def pcg_section(n_eval, n_train, train_steps, systems):
     t0 = time.perf_counter()
     model_inv = learned.MPNN(seed=1, form="fsai")
     hist_inv = learned.train(model_inv, N=n_train, steps=train_steps, lr=3e-3, nit=16, seed=5,
-                             val_systems=val, eval_every=50)
+                             val_systems=val, eval_every=every)
     torch.cuda.synchronize()
     train_inv_s = time.perf_counter() - t0
     log(f"trained the inverse-form network in {train_inv_s:.1f} s (loss "
@@ -560,7 +561,8 @@ def pcg_section(n_eval, n_train, train_steps, systems):
     fam.Lpat.transpose()
     torch.cuda.synchronize()
     analysis_ms = (time.perf_counter() - t0) * 1e3
-    methods = ("learned", "untrained", "fsai", "jacobi", "cg")
+    untrained_inv = learned.MPNN(seed=1, form="fsai")
+    methods = ("learned", "untrained", "fsai", "fsai_untrained", "jacobi", "cg")
     maxit = 40000
 
     def solve(key, A, b, cap=maxit):
@@ -572,9 +574,10 @@ def pcg_section(n_eval, n_train, train_steps, systems):
             # than replayed from a captured graph; the short Jacobi and plain
             # steps run faster from the graph: each method runs its faster way
             return pcgmod.pcg(A, b, "factor", L=L, tol=1e-6, maxit=cap, chunk=50, graph=False)
-        if key == "fsai":
+        if key in ("fsai", "fsai_untrained"):
+            net = model_inv if key == "fsai" else untrained_inv
             with torch.no_grad():
-                L = sp.CsrTensor(fam.Lpat, model_inv(A, fam.Lpat))
+                L = sp.CsrTensor(fam.Lpat, net(A, fam.Lpat))
             return pcgmod.pcg(A, b, "fsai", L=L, tol=1e-6, maxit=cap, chunk=50, graph=False)
         return pcgmod.pcg(A, b, "jacobi" if key == "jacobi" else "none", tol=1e-6, maxit=cap,
                           chunk=50, graph=True)
@@ -602,8 +605,9 @@ def pcg_section(n_eval, n_train, train_steps, systems):
             fallbacks += int(info.get("fallback", False))
             times[key].append(e0.elapsed_time(e1))
             iters[key].append(info["iters"])
-        log(f"pcg system {j}: eps {eps:.2e} theta {theta:.2f} " +
-            " ".join(f"{k} {times[k][-1]:.1f} ms/{iters[k][-1]} it" for k in methods))
+        if j < 4 or j + 1 == systems or (j + 1) % 16 == 0:
+            log(f"pcg system {j}: eps {eps:.2e} theta {theta:.2f} " +
+                " ".join(f"{k} {times[k][-1]:.1f} ms/{iters[k][-1]} it" for k in methods))
     med = {k: round(float(np.median(v)), 3) for k, v in times.items()}
     return {
         "workload": f"2D anisotropic Q1 diffusion {n_eval}^2 (n={fam.P.nrows}, nnz={fam.P.nnz}), "
@@ -612,8 +616,20 @@ def pcg_section(n_eval, n_train, train_steps, systems):
         "systems": systems, "tol": 1e-6,
         "median_ms": med,
         "median_iterations": {k: float(np.median(v)) for k, v in iters.items()},
+        "methods": {"learned": "trained network, factor form (M = L L^T ~ A, two level-scheduled "
+                               "triangular solves)",
+                    "untrained": "the same network untrained: symmetric Gauss-Seidel factor",
+                    "fsai": "trained network, the inverse form of Section 4.3 (M = L L^T ~ A^-1, "
+                            "two sparse products)",
+                    "fsai_untrained": "the inverse-form network untrained: first-order inverse "
+                                      "factor D^-1 (D - A_L) D^-1/2",
+                    "jacobi": "Jacobi-PCG", "cg": "plain CG"},
         "learned_speedup_vs_jacobi": round(med["jacobi"] / med["learned"], 3),
         "fsai_speedup_vs_jacobi": round(med["jacobi"] / med["fsai"], 3),
+        "fsai_training_gain_iterations": round(float(np.median(iters["fsai_untrained"])) /
+                                               float(np.median(iters["fsai"])), 3),
+        "factor_training_gain_iterations": round(float(np.median(iters["untrained"])) /
+                                                 float(np.median(iters["learned"])), 3),
         "fallbacks": fallbacks,
         "level_analysis_ms": round(analysis_ms, 3),
         "train": {"systems": train_steps, "grid": n_train, "seconds": round(train_s, 2),
@@ -991,9 +1007,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-pcg", action="store_true", help="skip the PCG time-to-1e-6 part")
     ap.add_argument("--pcg-grid", type=int, default=1024)
-    ap.add_argument("--pcg-systems", type=int, default=4)
+    ap.add_argument("--pcg-systems", type=int, default=64)
     ap.add_argument("--train-grid", type=int, default=256)
-    ap.add_argument("--train-steps", type=int, default=300)
+    ap.add_argument("--train-steps", type=int, default=4096,
+                    help="training systems (one Adam step each) per network")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-blocks part")
     ap.add_argument("--no-cg", action="store_true", help="skip the differentiated-CG part")
     ap.add_argument("--no-spadd", action="store_true", help="skip the sparse + sparse part")

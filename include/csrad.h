@@ -473,6 +473,48 @@ int csr_batch_ic0(const csrad_csr *Alow, const csrad_batch_plan *plan,
                   void *stream);
 
 /* ---------------------------------------------------------------------
+ * The vector and scalar steps of a short PCG unroll and their reverse
+ * mode, for training a preconditioner on the residual-history loss of
+ * Section 4.3, l = sum_i w_i ||r_i|| / ||b|| (the products q = A p and
+ * the preconditioner z = M^{-1} r are the library's other calls).  Vectors
+ * of n entries of `dtype`; scalars float64 on the device; dot products
+ * summed in a fixed order (bit-reproducible).  `work` holds
+ * csr_pcgl_workspace(n) bytes; none of the calls synchronises.
+ * csr_pcgl_start:  scal[0] = rho_0 = b.z_0, scal[1] = ||b||.
+ * csr_pcgl_res_fwd: sigma = p.q, alpha = rho/sigma, r1 = r - alpha q,
+ *   nr = ||r1||, acc1 = acc + w nr / bnorm; scal[0..2] = sigma, alpha, nr.
+ * csr_pcgl_res_bwd: given the adjoints gr1 (may be NULL) and gacc1 of r1
+ *   and acc1, writes those of r, q, p and rho (acc's adjoint is gacc1).
+ * csr_pcgl_dir_fwd: rho1 = r1.z1, beta = rho1/rho, p1 = z1 + beta p.
+ * csr_pcgl_dir_bwd: given gp1 (may be NULL) and grho1 (may be NULL),
+ *   writes the adjoints of r1, z1, p and rho.
+ * csr_pcgl_start_bwd: gz0 = grho0 b + gp0 (either may be NULL).
+ * ------------------------------------------------------------------- */
+int csr_pcgl_workspace(int32_t n, size_t *bytes);
+int csr_pcgl_start(int32_t n, int32_t dtype, const void *b, const void *z,
+                   double *scal, void *work, size_t work_bytes, void *stream);
+int csr_pcgl_res_fwd(int32_t n, int32_t dtype, const void *p, const void *q,
+                     const void *r, const double *rho, double w,
+                     const double *bnorm, const double *acc, void *r1,
+                     double *scal, double *acc1, void *work, size_t work_bytes,
+                     void *stream);
+int csr_pcgl_res_bwd(int32_t n, int32_t dtype, const void *p, const void *q,
+                     const void *r1, const double *rho, const double *scal,
+                     double w, const double *bnorm, const void *gr1,
+                     const double *gacc1, void *gr, void *gq, void *gp,
+                     double *grho, void *work, size_t work_bytes, void *stream);
+int csr_pcgl_dir_fwd(int32_t n, int32_t dtype, const void *r1, const void *z1,
+                     const double *rho, const void *p, double *rho1, void *p1,
+                     void *work, size_t work_bytes, void *stream);
+int csr_pcgl_dir_bwd(int32_t n, int32_t dtype, const void *r1, const void *z1,
+                     const double *rho, const void *p, const double *rho1,
+                     const void *gp1, const double *grho1, void *gr1, void *gz1,
+                     void *gp, double *grho, void *work, size_t work_bytes,
+                     void *stream);
+int csr_pcgl_start_bwd(int32_t n, int32_t dtype, const void *b, const void *gp0,
+                       const double *grho0, void *gz0, void *stream);
+
+/* ---------------------------------------------------------------------
  * Pattern check: rowptr monotone from 0 to nnz, colind in [0, ncols),
  * strictly ascending within each row.  *first_bad_row_host receives the
  * first offending row or -1 (synchronises).  Returns CSRAD_EPATTERN if a

@@ -124,6 +124,18 @@ _SIGS = {
                                                              C.c_size_t] + [C.c_void_p] * 5),
     "csr_batch_ic0": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
                                 C.c_size_t, C.c_void_p, C.c_void_p]),
+    "csr_pcgl_workspace": (C.c_int, [C.c_int32, C.POINTER(C.c_size_t)]),
+    "csr_pcgl_start": (C.c_int, [C.c_int32, C.c_int32] + [C.c_void_p] * 4
+                       + [C.c_size_t, C.c_void_p]),
+    "csr_pcgl_res_fwd": (C.c_int, [C.c_int32, C.c_int32] + [C.c_void_p] * 4
+                         + [C.c_double] + [C.c_void_p] * 6 + [C.c_size_t, C.c_void_p]),
+    "csr_pcgl_res_bwd": (C.c_int, [C.c_int32, C.c_int32] + [C.c_void_p] * 5
+                         + [C.c_double] + [C.c_void_p] * 8 + [C.c_size_t, C.c_void_p]),
+    "csr_pcgl_dir_fwd": (C.c_int, [C.c_int32, C.c_int32] + [C.c_void_p] * 7
+                         + [C.c_size_t, C.c_void_p]),
+    "csr_pcgl_dir_bwd": (C.c_int, [C.c_int32, C.c_int32] + [C.c_void_p] * 12
+                         + [C.c_size_t, C.c_void_p]),
+    "csr_pcgl_start_bwd": (C.c_int, [C.c_int32, C.c_int32] + [C.c_void_p] * 5),
 }
 
 
@@ -522,3 +534,54 @@ def csr_batch_ic0(Alow, plan, nlevels, level_rows, lv_work, Lvals):
     _check("csr_batch_ic0",
            load().csr_batch_ic0(C.byref(Alow), C.byref(plan), int(nlevels), _ptr(level_rows),
                                 _ptr(lv_work), lv_work.numel(), _ptr(Lvals), _stream()))
+
+
+# ----------------------------------------------------------------------
+# PCG unroll steps of the residual-history loss (vectors of one dtype,
+# float64 device scalars).
+# ----------------------------------------------------------------------
+
+def csr_pcgl_workspace(n):
+    nb = C.c_size_t(0)
+    _check("csr_pcgl_workspace", load().csr_pcgl_workspace(int(n), C.byref(nb)))
+    return nb.value
+
+
+def _dt(t):
+    return _DT[t.dtype]
+
+
+def csr_pcgl_start(b, z, scal, work):
+    _check("csr_pcgl_start", load().csr_pcgl_start(b.numel(), _dt(b), _ptr(b), _ptr(z), _ptr(scal),
+                                                   _ptr(work), work.numel(), _stream()))
+
+
+def csr_pcgl_res_fwd(p, q, r, rho, w, bnorm, acc, r1, scal, acc1, work):
+    _check("csr_pcgl_res_fwd", load().csr_pcgl_res_fwd(
+        p.numel(), _dt(p), _ptr(p), _ptr(q), _ptr(r), _ptr(rho), float(w), _ptr(bnorm), _ptr(acc),
+        _ptr(r1), _ptr(scal), _ptr(acc1), _ptr(work), work.numel(), _stream()))
+
+
+def csr_pcgl_res_bwd(p, q, r1, rho, scal, w, bnorm, gr1, gacc1, gr, gq, gp, grho, work):
+    _check("csr_pcgl_res_bwd", load().csr_pcgl_res_bwd(
+        p.numel(), _dt(p), _ptr(p), _ptr(q), _ptr(r1), _ptr(rho), _ptr(scal), float(w),
+        _ptr(bnorm), _ptr(gr1), _ptr(gacc1), _ptr(gr), _ptr(gq), _ptr(gp), _ptr(grho), _ptr(work),
+        work.numel(), _stream()))
+
+
+def csr_pcgl_dir_fwd(r1, z1, rho, p, rho1, p1, work):
+    _check("csr_pcgl_dir_fwd", load().csr_pcgl_dir_fwd(
+        r1.numel(), _dt(r1), _ptr(r1), _ptr(z1), _ptr(rho), _ptr(p), _ptr(rho1), _ptr(p1),
+        _ptr(work), work.numel(), _stream()))
+
+
+def csr_pcgl_dir_bwd(r1, z1, rho, p, rho1, gp1, grho1, gr1, gz1, gp, grho, work):
+    _check("csr_pcgl_dir_bwd", load().csr_pcgl_dir_bwd(
+        r1.numel(), _dt(r1), _ptr(r1), _ptr(z1), _ptr(rho), _ptr(p), _ptr(rho1), _ptr(gp1),
+        _ptr(grho1), _ptr(gr1), _ptr(gz1), _ptr(gp), _ptr(grho), _ptr(work), work.numel(),
+        _stream()))
+
+
+def csr_pcgl_start_bwd(b, gp0, grho0, gz0):
+    _check("csr_pcgl_start_bwd", load().csr_pcgl_start_bwd(
+        b.numel(), _dt(b), _ptr(b), _ptr(gp0), _ptr(grho0), _ptr(gz0), _stream()))

@@ -3,21 +3,24 @@
 //
 // Rows of C are binned by the product count U_i = sum over A's row of the
 // lengths of the B rows it selects, an upper bound on nnz(C_i):
-//   U <= 8, 16, 32, 64     : 8 / 16 / 32 / 64 lanes per row, one product
-//                            per lane, sorted across the lanes in registers;
+//   U <= 64                : row merge, G = 8 / 16 / 32 / 64 lanes per row
+//                            (at least one lane per non-empty B row the
+//                            row selects); each lane walks one sorted B
+//                            row and the group merges the lists;
 //   U <= 512, 4096         : LDS hash table of H = 2U slots per row,
 //                            64 / 256 lanes per row;
 //   U > 4096               : a dense per-workgroup marker array in the
 //                            workspace (tagged with the row id).
-// Symbolic: count the distinct columns (run heads after the lane sort for
-//           U <= 32; hash insert with CAS up to 4096; marker tags beyond).
-// Numeric : small bins sum each run of equal columns in k order; the
-//           others rebuild the set, sort it (bitonic sort of the table in
-//           LDS, empty slots last; for the dense path a block scan of the
-//           marker array), write ascending column indices, then each
-//           output entry C_ij = sum_k A_ik B_kj with k in A's row order and
-//           B_kj found by binary search in B's sorted row k.  No floating
-//           point atomics: values are bit-identical between runs.
+// Symbolic: count the distinct columns (merge steps for U <= 64; hash
+//           insert with CAS up to 4096; marker tags beyond).
+// Numeric : the merge emits each column with the sum of the products that
+//           meet there; the others rebuild the set, sort it (bitonic sort
+//           of the table in LDS, empty slots last; for the dense path a
+//           block scan of the marker array), write ascending column
+//           indices, then each output entry C_ij = sum_k A_ik B_kj with k
+//           in A's row order and B_kj found by binary search in B's sorted
+//           row k.  No floating-point atomics: values are bit-identical
+//           between runs.
 // Backward (both gathers, no atomics):
 //   gA[(i,k)] = sum_{j in pat(C_i) and pat(B_k)} V_ij B_kj   (row-aligned)
 //   gB[(k,j)] = sum_{i in column k of A} A_ik V_ij           (over A^T)
@@ -27,19 +30,20 @@ namespace csrad {
 namespace {
 
 constexpr int kThreads = 256;
-// 0: empty, 1..4: lanes (U <= 8, 16, 32, 64), 5..6: LDS hash, 7: dense marker
+// 0: empty, 1..4: row merge (U <= 64; 8, 16, 32, 64 lanes), 5..6: LDS hash,
+// 7: dense marker
 constexpr int kNumBins = 8;
 static_assert(kNumBins + 1 == CSRAD_SPGEMM_BINS, "host copy of the class boundaries");
 constexpr int kDenseBin = 7;
 constexpr int kBigU = 4096;
 constexpr size_t kMarkerBudget = size_t(16) << 20;
 
-__host__ __device__ inline int bin_of(long long u) {
+// u: products of the row; lists: A entries of the row whose B row is not
+// empty (at most u).  Rows with u <= 64 take the row merge with as many
+// lanes as lists, rounded up to 8, 16, 32 or 64.
+__host__ __device__ inline int bin_of(long long u, int lists) {
   if (u == 0) return 0;
-  if (u <= 8) return 1;
-  if (u <= 16) return 2;
-  if (u <= 32) return 3;
-  if (u <= 64) return 4;
+  if (u <= 64) return lists <= 8 ? 1 : lists <= 16 ? 2 : lists <= 32 ? 3 : 4;
   if (u <= 512) return 5;
   if (u <= kBigU) return 6;
   return kDenseBin;
@@ -53,11 +57,14 @@ __global__ __launch_bounds__(kThreads) void k_bin_of(int m, const int32_t* __res
                                                      int32_t* __restrict__ binid) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x) {
     long long u = 0;
+    int lists = 0;
     for (int a = rpA[i]; a < rpA[i + 1]; ++a) {
       const int k = ciA[a];
-      u += rpB[k + 1] - rpB[k];
+      const int len = rpB[k + 1] - rpB[k];
+      u += len;
+      lists += len > 0;
     }
-    binid[i] = bin_of(u);
+    binid[i] = bin_of(u, lists);
   }
 }
 
@@ -215,177 +222,31 @@ __global__ __launch_bounds__(kThreads) void k_num_hash(
 }
 
 // ---------------------------------------------------------------------
-// Small bins (U <= G, G = 16 or 64): G lanes per row, no LDS.  Lane l holds
-// the row's l-th product in k order (A's row order, then B's row order);
-// the G keys (column, product index) are sorted across the lanes by a
-// register bitonic network, so equal columns form runs ordered by k.  A
-// run's first lane ("head") stands for one output entry: the heads count
-// the row (symbolic), give each entry its rank, and sum their run's
-// products in lane order, i.e. k ascending (numeric).
+// Small bins (U <= 64 products): row merge.  The B rows that A's row i
+// selects are sorted lists; row i of C is their merge, and the value of a
+// column the sum of the products that meet there.  A group of G lanes owns
+// a row (G at least the number of A entries whose B row is not empty:
+// bins 1..4 are G = 8, 16, 32, 64): lane t holds list t (the t-th such
+// entry in A's row order).  One step takes the group minimum m of the
+// list heads, sums the products of the lanes whose head is m, and
+// advances those lanes; columns come out ascending and the number of
+// steps is nnz(C_i).  Each lane keeps a window of W entries of its list in
+// registers, refilled one entry ahead, so no step waits on a fresh load
+// unless a list runs W entries in a row.  Output entries are kept one per
+// lane and written G at a time.
 // ---------------------------------------------------------------------
-__device__ __forceinline__ unsigned long long shfl_xor_key(unsigned long long v, int m) {
-  const unsigned lo = (unsigned)__shfl_xor((int)(unsigned)v, m);
-  const unsigned hi = (unsigned)__shfl_xor((int)(unsigned)(v >> 32), m);
-  return ((unsigned long long)hi << 32) | lo;
-}
-__device__ __forceinline__ unsigned shfl_xor_key(unsigned v, int m) {
-  return (unsigned)__shfl_xor((int)v, m);
-}
+constexpr int kWin = 4;
 
-// Lane exchanges within rows of 16 lanes through DPP moves (no LDS
-// crossbar): quad permutes, the half-row and row mirrors, and row shifts.
-template <int CTRL>
-__device__ __forceinline__ unsigned dpp_key(unsigned v) {
-  return (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, false);
-}
-template <int CTRL>
-__device__ __forceinline__ unsigned long long dpp_key(unsigned long long v) {
-  const unsigned lo = dpp_key<CTRL>((unsigned)v), hi = dpp_key<CTRL>((unsigned)(v >> 32));
-  return ((unsigned long long)hi << 32) | lo;
-}
-
-// The value of lane + 1 across the whole wave (DPP wave_shl:1; the last
-// lane reads 0).
-__device__ __forceinline__ float wave_next(float v) {
-  return __uint_as_float(dpp_key<0x130>(__float_as_uint(v)));
-}
-__device__ __forceinline__ double wave_next(double v) {
-  return __longlong_as_double((long long)dpp_key<0x130>((unsigned long long)__double_as_longlong(v)));
-}
-
-// The key of lane l ^ M, l the lane's index in its aligned group.  Both
-// row shifts of the M = 4 and M = 8 cases run on every lane before the
-// select: a DPP move reads nothing from lanes that are switched off.
-template <int M, typename K>
-__device__ __forceinline__ K partner_key(K key, int l) {
-  if constexpr (M == 1) {
-    return dpp_key<0xB1>(key);  // quad_perm [1,0,3,2]
-  } else if constexpr (M == 2) {
-    return dpp_key<0x4E>(key);  // quad_perm [2,3,0,1]
-  } else if constexpr (M == 3) {
-    return dpp_key<0x1B>(key);  // quad_perm [3,2,1,0]
-  } else if constexpr (M == 4 || M == 8) {
-    const K down = dpp_key<0x110 + M>(key);  // row_shr:M, lane l - M
-    const K up = dpp_key<0x100 + M>(key);    // row_shl:M, lane l + M
-    return (l & M) ? down : up;
-  } else if constexpr (M == 7) {
-    return dpp_key<0x141>(key);  // row_half_mirror
-  } else if constexpr (M == 15) {
-    return dpp_key<0x140>(key);  // row_mirror
-  } else {
-    return shfl_xor_key(key, M);
-  }
-}
-
-template <typename K>
-__device__ __forceinline__ K keep(K key, K other, bool keep_min) {
-  return keep_min ? (other < key ? other : key) : (other > key ? other : key);
-}
-
-// Half-cleaner steps j = J, J/2, ..., 1 of a bitonic merge (ascending).
-template <int J, typename K>
-__device__ __forceinline__ K merge_steps(K key, int l) {
-  if constexpr (J >= 1) {
-    key = keep(key, partner_key<J>(key, l), (l & J) == 0);
-    return merge_steps<J / 2>(key, l);
-  } else {
-    return key;
-  }
-}
-
-// Stages KB = 2, 4, ..., G of the bitonic network in its mirror form: each
-// stage compares lane l with l ^ (KB - 1) (the mirror in its KB-block,
-// lower half keeps the minimum), then half-cleans with l ^ KB/4, ..., l ^ 1;
-// every comparator is ascending, and the exchanges within 16 lanes are DPP
-// moves.
-template <int KB, int G, typename K>
-__device__ __forceinline__ K sort_stages(K key, int l) {
-  if constexpr (KB <= G) {
-    key = keep(key, partner_key<KB - 1>(key, l), (l & (KB >> 1)) == 0);
-    key = merge_steps<KB / 4>(key, l);
-    return sort_stages<KB * 2, G>(key, l);
-  } else {
-    return key;
-  }
-}
-
-// Ascending sort of one key per lane over aligned groups of G lanes.
-template <int G, typename K>
-__device__ __forceinline__ K group_sort(K key, int l) {
-  return sort_stages<2, G>(key, l);
-}
-
-// Inclusive prefix sum over an aligned group of G lanes.  Groups within one
-// row of 16 lanes shift by DPP; wider groups shuffle (a row shift does not
-// cross into the next row, which their lanes would need).
-template <int O, int G>
-__device__ __forceinline__ int scan_up(int inc, int l) {
-  if constexpr (O < G) {
-    int t;
-    if constexpr (G <= 16)
-      t = __builtin_amdgcn_update_dpp(0, inc, 0x110 + O, 0xF, 0xF, false);  // row_shr:O
-    else
-      t = __shfl_up(inc, O, G);
-    if (l >= O) inc += t;
-    return scan_up<O * 2, G>(inc, l);
-  } else {
-    return inc;
-  }
-}
-
-// The l-th product of row i, found by the G lanes of the row together: A's
-// row is taken G entries at a time, each lane loads one entry and the
-// length of the B row it selects, a scan over the group gives every
-// entry's first product, and each lane finds the entry holding its product
-// by binary search over the scan.  col = INT32_MAX when the row has at most
-// l products.  Every lane of the wave must reach the call.
 template <int G>
-__device__ __forceinline__ void lane_product(int i, bool valid, int l,
-                                             const int32_t* __restrict__ rpA,
-                                             const int32_t* __restrict__ ciA,
-                                             const int32_t* __restrict__ rpB,
-                                             const int32_t* __restrict__ ciB, int& col, int& ea,
-                                             int& eb) {
-  col = INT32_MAX;
-  ea = eb = -1;
-  const int gbase = __lane_id() & ~(G - 1);
-  int a0 = 0, a1 = 0;
-  if (valid) {
-    a0 = rpA[i];
-    a1 = rpA[i + 1];
-  }
-  const int chunks = wave_max((a1 - a0 + G - 1) / G);
-  int before = 0;  // products of the row's earlier chunks
-  for (int c = 0; c < chunks; ++c) {
-    const int a = a0 + c * G + l;
-    int b0 = 0, len = 0;
-    if (a < a1) {
-      const int k = ciA[a];
-      b0 = rpB[k];
-      len = rpB[k + 1] - b0;
-    }
-    const int inc = scan_up<1, G>(len, l);
-    const int total = __shfl(inc, gbase + G - 1);
-    const int pidx = l - before;  // this lane's product within the chunk
-    // first t with inc[t] > pidx (lanes without a product search too)
-    int lo = 0, hi = G - 1;
-#pragma unroll
-    for (int st = G; st > 1; st >>= 1) {
-      const int mid = (lo + hi) >> 1;
-      const int v = __shfl(inc, gbase + mid);
-      if (v > pidx) hi = mid;
-      else lo = mid + 1;
-    }
-    const int t = lo;
-    const int st_b0 = __shfl(b0, gbase + t);
-    const int st_ex = __shfl(inc - len, gbase + t);
-    if (pidx >= 0 && pidx < total) {
-      ea = a0 + c * G + t;
-      eb = st_b0 + (pidx - st_ex);
-      col = ciB[eb];
-    }
-    before += total;
-  }
+__device__ __forceinline__ int group_min(int v) {
+  // a move from a switched-off lane returns the lane's own value (old = v)
+  if constexpr (G >= 2) v = min(v, __builtin_amdgcn_update_dpp(v, v, kDppXor1, 0xF, 0xF, false));
+  if constexpr (G >= 4) v = min(v, __builtin_amdgcn_update_dpp(v, v, kDppXor2, 0xF, 0xF, false));
+  if constexpr (G >= 8) v = min(v, __builtin_amdgcn_update_dpp(v, v, kDppHalfMirror, 0xF, 0xF, false));
+  if constexpr (G >= 16) v = min(v, __builtin_amdgcn_update_dpp(v, v, kDppMirror, 0xF, 0xF, false));
+  if constexpr (G >= 32) v = min(v, __builtin_amdgcn_ds_swizzle(v, 0x401F));
+  if constexpr (G >= 64) v = min(v, __shfl_xor(v, 32));
+  return v;
 }
 
 // Mask of the lanes of this lane's group.
@@ -394,106 +255,107 @@ __device__ __forceinline__ unsigned long long group_mask(int lane) {
   return G == 64 ? ~0ull : (((1ull << G) - 1ull) << (lane & ~(G - 1)));
 }
 
-// Sort key of (column, product index): 32 bits when the column fits in
-// 32 - log2(G) bits, else 64.
-template <int G>
-constexpr int log2_of() {
-  return G == 8 ? 3 : G == 16 ? 4 : G == 32 ? 5 : 6;
-}
-
-template <int G, typename K>
-__device__ __forceinline__ K make_key(int col, int l) {
-  constexpr int LG = log2_of<G>();
-  if (sizeof(K) == 4)
-    return col == INT32_MAX ? (K)0xffffffffu : (K)(((unsigned)col << LG) | (unsigned)l);
-  return (K)(((unsigned long long)(unsigned)col << 32) | (unsigned)l);
-}
-template <int G, typename K>
-__device__ __forceinline__ int key_col(K key) {
-  constexpr int LG = log2_of<G>();
-  if (sizeof(K) == 4) return key == (K)0xffffffffu ? INT32_MAX : (int)((unsigned)key >> LG);
-  return (int)((unsigned long long)key >> 32);
-}
-template <int G, typename K>
-__device__ __forceinline__ int key_idx(K key) {
-  if (sizeof(K) == 4) return (int)((unsigned)key & (G - 1));
-  return (int)((unsigned long long)key & 0xffffffffull);
-}
-
-template <int G, typename K>
-__global__ __launch_bounds__(kThreads) void k_sym_lanes(int bin, const int32_t* __restrict__ list,
-                                                        const int32_t* __restrict__ bin_off,
-                                                        const int32_t* __restrict__ rpA,
-                                                        const int32_t* __restrict__ ciA,
-                                                        const int32_t* __restrict__ rpB,
-                                                        const int32_t* __restrict__ ciB,
-                                                        int32_t* __restrict__ counts) {
-  constexpr int RPB = kThreads / G;
-  const int first = bin_off[bin], nrows = bin_off[bin + 1] - first;
-  const int lane = __lane_id(), l = threadIdx.x % G;
-  const unsigned long long gm = group_mask<G>(lane);
-  for (int base = blockIdx.x * RPB; base < nrows; base += gridDim.x * RPB) {
-    const int idx = base + threadIdx.x / G;
-    const bool valid = idx < nrows;
-    const int i = valid ? list[first + idx] : 0;
-    int col, ea, eb;
-    lane_product<G>(i, valid, l, rpA, ciA, rpB, ciB, col, ea, eb);
-    const K key = group_sort<G, K>(make_key<G, K>(col, l), l);
-    const int sc = key_col<G, K>(key);
-    const int prev = (int)dpp_key<0x138>((unsigned)sc);  // wave_shr:1, lane - 1
-    const bool head = sc != INT32_MAX && (l == 0 || prev != sc);
-    const int cnt = __popcll(__ballot(head) & gm);
-    if (valid && l == 0) counts[i] = cnt;
-  }
-}
-
-template <typename T, int G, typename K>
-__global__ __launch_bounds__(kThreads) void k_num_lanes(
+template <typename T, int G, bool NUM>
+__global__ __launch_bounds__(kThreads) void k_merge(
     int bin, const int32_t* __restrict__ list, const int32_t* __restrict__ bin_off,
     const int32_t* __restrict__ rpA, const int32_t* __restrict__ ciA, const T* __restrict__ vA,
     const int32_t* __restrict__ rpB, const int32_t* __restrict__ ciB, const T* __restrict__ vB,
-    const int32_t* __restrict__ rpC, int32_t* __restrict__ ciC, T* __restrict__ vC) {
+    const int32_t* __restrict__ rpC, int32_t* __restrict__ ciC, T* __restrict__ vC,
+    int32_t* __restrict__ counts) {
   constexpr int RPB = kThreads / G;
+  __shared__ int s_b0[kThreads], s_len[kThreads], s_a[kThreads];
   const int first = bin_off[bin], nrows = bin_off[bin + 1] - first;
-  const int lane = __lane_id(), l = threadIdx.x % G;
-  const int gbase = lane & ~(G - 1);
+  const int lane = __lane_id(), l = threadIdx.x % G, g0 = threadIdx.x - l;
   const unsigned long long gm = group_mask<G>(lane);
   const unsigned long long below = gm & ((1ull << lane) - 1ull);
-  const unsigned long long above = gm & ~((2ull << lane) - 1ull);
-  for (int base = blockIdx.x * RPB; base < nrows; base += gridDim.x * RPB) {
+  for (int base = blockIdx.x * RPB; base < nrows; base += gridDim.x * RPB) {  // uniform
     const int idx = base + threadIdx.x / G;
     const bool valid = idx < nrows;
     const int i = valid ? list[first + idx] : 0;
-    int col, ea, eb;
-    lane_product<G>(i, valid, l, rpA, ciA, rpB, ciB, col, ea, eb);
-    const T prod = ea >= 0 ? vA[ea] * vB[eb] : T(0);
-    const K key = group_sort<G, K>(make_key<G, K>(col, l), l);
-    const int sc = key_col<G, K>(key);
-    const T v = __shfl(prod, gbase + key_idx<G, K>(key));
-    const int prev = (int)dpp_key<0x138>((unsigned)sc);  // wave_shr:1, lane - 1
-    const bool head = sc != INT32_MAX && (l == 0 || prev != sc);
-    const unsigned long long heads = __ballot(head);
-    const unsigned long long used = __ballot(sc != INT32_MAX) & gm;
-    // run length of a head: up to the next head, else to the last product
-    int run = 0;
-    if (head) {
-      const unsigned long long nxt = heads & above;
-      const int end = nxt ? __ffsll((long long)nxt) - 1 : gbase + __popcll(used);
-      run = end - lane;
+    int a0 = 0, a1 = 0;
+    if (valid) {
+      a0 = rpA[i];
+      a1 = rpA[i + 1];
     }
-    const int steps = wave_max(run);
-    // run sums in lane order (k ascending)
-    T acc = v;
-    T w = v;
-    for (int d = 1; d < steps; ++d) {
-      w = wave_next(w);  // now the value of lane + d
-      if (d < run) acc += w;
+    // the non-empty lists of the row, compacted into the group's slots in
+    // A's row order (the bin guarantees at most G of them)
+    const int chunks = wave_max((a1 - a0 + G - 1) / G);
+    int nl = 0;
+    for (int c = 0; c < chunks; ++c) {
+      const int a = a0 + c * G + l;
+      int b0 = 0, len = 0;
+      if (a < a1) {
+        const int k = ciA[a];
+        b0 = rpB[k];
+        len = rpB[k + 1] - b0;
+      }
+      const unsigned long long ne = __ballot(len > 0) & gm;
+      const int rank = nl + __popcll(ne & below);
+      if (len > 0 && rank < G) {  // rank < G holds for every row of the bin
+        const int slot = g0 + rank;
+        s_b0[slot] = b0;
+        s_len[slot] = len;
+        s_a[slot] = a;
+      }
+      nl += __popcll(ne);
     }
-    if (valid && head) {
-      const int pos = rpC[i] + __popcll(heads & below);
-      ciC[pos] = sc;
-      vC[pos] = acc;
+    __syncthreads();
+    int p = 0, e = 0;
+    T av = 0;
+    if (l < nl) {
+      p = s_b0[g0 + l];
+      e = p + s_len[g0 + l];
+      if (NUM) av = vA[s_a[g0 + l]];
     }
+    int hc[kWin];
+    T hv[kWin];
+#pragma unroll
+    for (int w = 0; w < kWin; ++w) {
+      const bool in = p + w < e;
+      hc[w] = in ? ciB[p + w] : INT32_MAX;
+      hv[w] = (NUM && in) ? vB[p + w] : T(0);
+    }
+    const int c0 = (NUM && valid) ? rpC[i] : 0;
+    int steps = 0, oc = 0;
+    T ov = 0;
+    while (__ballot(hc[0] != INT32_MAX)) {  // uniform over the wave
+      const int m = group_min<G>(hc[0]);
+      const bool live = m != INT32_MAX;
+      const bool hit = live && hc[0] == m;
+      if (NUM) {
+        const T sv = group_sum<G>(hit ? av * hv[0] : T(0));
+        if (l == (steps & (G - 1))) {
+          oc = m;
+          ov = sv;
+        }
+        if (live && (steps & (G - 1)) == G - 1) {  // a full set of G entries
+          ciC[c0 + steps - (G - 1) + l] = oc;
+          vC[c0 + steps - (G - 1) + l] = ov;
+        }
+      }
+      steps += live;
+      if (hit) {
+#pragma unroll
+        for (int w = 0; w + 1 < kWin; ++w) {
+          hc[w] = hc[w + 1];
+          hv[w] = hv[w + 1];
+        }
+        ++p;
+        const bool in = p + kWin - 1 < e;
+        hc[kWin - 1] = in ? ciB[p + kWin - 1] : INT32_MAX;
+        hv[kWin - 1] = (NUM && in) ? vB[p + kWin - 1] : T(0);
+      }
+    }
+    if (NUM) {
+      const int rem = steps & (G - 1);
+      if (valid && l < rem) {
+        ciC[c0 + steps - rem + l] = oc;
+        vC[c0 + steps - rem + l] = ov;
+      }
+    } else if (valid && l == 0) {
+      counts[i] = steps;
+    }
+    __syncthreads();  // the slots are rewritten by the next rows
   }
 }
 
@@ -717,39 +579,15 @@ int check_pair(const csrad_csr* A, const csrad_csr* B, bool vals) {
   return CSRAD_OK;
 }
 
-// Launches of the lane bins; 32-bit sort keys while (column, product
-// index) fits in 32 bits.
-template <int G>
-bool keys32(int ncols) {
-  return (long long)ncols < (1ll << (32 - log2_of<G>())) - 1;
-}
-
-template <int G>
-void sym_lanes(int bin, const csrad_csr* A, const csrad_csr* B, const SpgemmWs& w,
-               hipStream_t s) {
-  const unsigned g = persistent_grid(kThreads / G, A->nrows);
-  if (keys32<G>(B->ncols))
-    hipLaunchKernelGGL((k_sym_lanes<G, unsigned>), dim3(g), dim3(kThreads), 0, s, bin, w.list,
-                       w.bin_off, A->rowptr, A->colind, B->rowptr, B->colind, w.counts);
-  else
-    hipLaunchKernelGGL((k_sym_lanes<G, unsigned long long>), dim3(g), dim3(kThreads), 0, s, bin,
-                       w.list, w.bin_off, A->rowptr, A->colind, B->rowptr, B->colind, w.counts);
-}
-
-template <typename T, int G>
-void num_lanes(int bin, int rows, const csrad_csr* A, const csrad_csr* B, const T* vA,
+// Launches of the row-merge bins (1..4: G = 8, 16, 32, 64).
+template <typename T, int G, bool NUM>
+void merge_bin(int bin, int rows, const csrad_csr* A, const csrad_csr* B, const T* vA,
                const T* vB, const int32_t* rpC, int32_t* ciC, T* vC, const SpgemmWs& w,
                hipStream_t s) {
   if (rows == 0) return;
   const unsigned g = persistent_grid(kThreads / G, rows);
-  if (keys32<G>(B->ncols))
-    hipLaunchKernelGGL((k_num_lanes<T, G, unsigned>), dim3(g), dim3(kThreads), 0, s, bin, w.list,
-                       w.bin_off, A->rowptr, A->colind, vA, B->rowptr, B->colind, vB, rpC, ciC,
-                       vC);
-  else
-    hipLaunchKernelGGL((k_num_lanes<T, G, unsigned long long>), dim3(g), dim3(kThreads), 0, s,
-                       bin, w.list, w.bin_off, A->rowptr, A->colind, vA, B->rowptr, B->colind, vB,
-                       rpC, ciC, vC);
+  hipLaunchKernelGGL((k_merge<T, G, NUM>), dim3(g), dim3(kThreads), 0, s, bin, w.list, w.bin_off,
+                     A->rowptr, A->colind, vA, B->rowptr, B->colind, vB, rpC, ciC, vC, w.counts);
 }
 
 // bins: host copy of the class boundaries, or null (every class is then
@@ -761,10 +599,10 @@ int spgemm_numeric_t(const csrad_csr* A, const csrad_csr* B, const int32_t* rpC,
   const T* vA = static_cast<const T*>(A->vals);
   const T* vB = static_cast<const T*>(B->vals);
   auto rows = [&](int b) { return bins ? bins[b + 1] - bins[b] : m; };
-  num_lanes<T, 8>(1, rows(1), A, B, vA, vB, rpC, ciC, vC, w, s);
-  num_lanes<T, 16>(2, rows(2), A, B, vA, vB, rpC, ciC, vC, w, s);
-  num_lanes<T, 32>(3, rows(3), A, B, vA, vB, rpC, ciC, vC, w, s);
-  num_lanes<T, 64>(4, rows(4), A, B, vA, vB, rpC, ciC, vC, w, s);
+  merge_bin<T, 8, true>(1, rows(1), A, B, vA, vB, rpC, ciC, vC, w, s);
+  merge_bin<T, 16, true>(2, rows(2), A, B, vA, vB, rpC, ciC, vC, w, s);
+  merge_bin<T, 32, true>(3, rows(3), A, B, vA, vB, rpC, ciC, vC, w, s);
+  merge_bin<T, 64, true>(4, rows(4), A, B, vA, vB, rpC, ciC, vC, w, s);
   if (rows(5) > 0)
     hipLaunchKernelGGL((k_num_hash<T, 64, 1024>), dim3(persistent_grid(4, rows(5))),
                        dim3(kThreads), 0, s, 5, w.list, w.bin_off, A->rowptr, A->colind, vA,
@@ -850,14 +688,12 @@ extern "C" int csr_spgemm_symbolic(const csrad_csr* A, const csrad_csr* B, int32
   CSRAD_TRY(classify(A, B, w, s));
   if (m > 0) {
     CSRAD_TRY(fill_i32(w.counts, m, 0, s));
-    sym_lanes<8>(1, A, B, w, s);
-    sym_lanes<16>(2, A, B, w, s);
-    sym_lanes<32>(3, A, B, w, s);
-    // counting alone: for U <= 64 an LDS hash with 16 lanes per row beats
-    // sorting across a whole wave per row
-    hipLaunchKernelGGL((k_sym_hash<16, 128>), dim3(persistent_grid(16, m)), dim3(kThreads), 0, s,
-                       4, w.list, w.bin_off, A->rowptr, A->colind, B->rowptr, B->colind,
-                       w.counts);
+    // the row-merge bins count their steps (the classes' sizes are still on
+    // the device: every class is launched over up to m rows)
+    merge_bin<float, 8, false>(1, m, A, B, nullptr, nullptr, nullptr, nullptr, nullptr, w, s);
+    merge_bin<float, 16, false>(2, m, A, B, nullptr, nullptr, nullptr, nullptr, nullptr, w, s);
+    merge_bin<float, 32, false>(3, m, A, B, nullptr, nullptr, nullptr, nullptr, nullptr, w, s);
+    merge_bin<float, 64, false>(4, m, A, B, nullptr, nullptr, nullptr, nullptr, nullptr, w, s);
     hipLaunchKernelGGL((k_sym_hash<64, 1024>), dim3(persistent_grid(4, m)), dim3(kThreads), 0, s, 5,
                        w.list, w.bin_off, A->rowptr, A->colind, B->rowptr, B->colind, w.counts);
     hipLaunchKernelGGL((k_sym_hash<256, 8192>), dim3(persistent_grid(1, m)), dim3(kThreads), 0, s,

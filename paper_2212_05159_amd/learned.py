@@ -203,37 +203,104 @@ def loss_weights(nit, gamma):
     return w / w.sum()
 
 
+class _PcgStart(torch.autograd.Function):
+    """(rho_0, ||b||) with rho_0 = b.z_0 (b is data)."""
+
+    @staticmethod
+    def forward(ctx, b, z, ws):
+        scal = torch.empty(2, dtype=torch.float64, device=b.device)
+        capi.csr_pcgl_start(b, z.contiguous(), scal, ws)
+        ctx.save_for_backward(b)
+        return scal[0:1], scal[1:2]
+
+    @staticmethod
+    def backward(ctx, grho, gbn):
+        (b,) = ctx.saved_tensors
+        gz = torch.empty_like(b)
+        capi.csr_pcgl_start_bwd(b, None, None if grho is None else grho.contiguous(), gz)
+        return None, gz, None
+
+
+class _PcgRes(torch.autograd.Function):
+    """One iteration's update of r and of the loss accumulator (see
+    csr_pcgl_res_fwd)."""
+
+    @staticmethod
+    def forward(ctx, p, q, r, rho, acc, w, bnorm, ws):
+        r1 = torch.empty_like(r)
+        scal = torch.empty(3, dtype=torch.float64, device=r.device)
+        acc1 = torch.empty(1, dtype=torch.float64, device=r.device)
+        capi.csr_pcgl_res_fwd(p, q, r, rho, w, bnorm, acc, r1, scal, acc1, ws)
+        ctx.w, ctx.ws = w, ws
+        ctx.save_for_backward(p, q, r1, rho, scal, bnorm)
+        return r1, acc1
+
+    @staticmethod
+    def backward(ctx, gr1, gacc1):
+        p, q, r1, rho, scal, bnorm = ctx.saved_tensors
+        if gacc1 is None:
+            gacc1 = torch.zeros(1, dtype=torch.float64, device=p.device)
+        gr, gq, gp = torch.empty_like(r1), torch.empty_like(q), torch.empty_like(p)
+        grho = torch.empty(1, dtype=torch.float64, device=p.device)
+        capi.csr_pcgl_res_bwd(p, q, r1, rho, scal, ctx.w, bnorm,
+                              None if gr1 is None else gr1.contiguous(), gacc1.contiguous(), gr,
+                              gq, gp, grho, ctx.ws)
+        return gp, gq, gr, grho, gacc1, None, None, None
+
+
+class _PcgDir(torch.autograd.Function):
+    """rho' = r'.z', p' = z' + (rho'/rho) p (see csr_pcgl_dir_fwd)."""
+
+    @staticmethod
+    def forward(ctx, r1, z1, rho, p, ws):
+        z1 = z1.contiguous()
+        rho1 = torch.empty(1, dtype=torch.float64, device=r1.device)
+        p1 = torch.empty_like(p)
+        capi.csr_pcgl_dir_fwd(r1, z1, rho, p, rho1, p1, ws)
+        ctx.ws = ws
+        ctx.save_for_backward(r1, z1, rho, p, rho1)
+        return rho1, p1
+
+    @staticmethod
+    def backward(ctx, grho1, gp1):
+        r1, z1, rho, p, rho1 = ctx.saved_tensors
+        gr1, gz1, gp = torch.empty_like(r1), torch.empty_like(z1), torch.empty_like(p)
+        grho = torch.empty(1, dtype=torch.float64, device=p.device)
+        capi.csr_pcgl_dir_bwd(r1, z1, rho, p, rho1, None if gp1 is None else gp1.contiguous(),
+                              None if grho1 is None else grho1.contiguous(), gr1, gz1, gp, grho,
+                              ctx.ws)
+        return gr1, gz1, grho, gp, None
+
+
 def pcg_residual_loss(A, Lpat, Lv, b, nit=4, gamma=0.6, form="factor"):
     """sum_i w_i ||r_i|| / ||b|| over nit PCG iterations with M = L L^T.
 
     form "factor": M approximates A and z = L^{-T} L^{-1} r (two triangular
     solves); form "fsai": M approximates A^{-1}, the form Section 4.3
-    learns, and z = L (L^T r) (two sparse products)."""
+    learns, and z = L (L^T r) (two sparse products).  Every step runs in
+    the library: the products and solves, and the iteration's dot
+    products, updates and norms (csr_pcgl_*), each with its hand-written
+    reverse; the result is a one-element float64 tensor."""
     def minv(r):
         if form == "fsai":
             return sp.SpMV.apply(Lpat, Lv, sp.SpMVT.apply(Lpat, Lv, r))
         return TriSolveT.apply(Lpat, Lv, sp.TriSolve.apply(Lpat, Lv, r, True))
 
     w = loss_weights(nit, gamma)
-    bn = torch.linalg.norm(b)
-    x = torch.zeros_like(b)
-    r = b
-    z = minv(r)
-    p = z
-    rho = (r * z).sum()
-    loss = 0.0
+    b = b.contiguous()
+    ws = capi._ws(capi.csr_pcgl_workspace(b.numel()), b.device)
+    z = minv(b)
+    rho, bnorm = _PcgStart.apply(b, z, ws)
+    bnorm = bnorm.detach()
+    acc = torch.zeros(1, dtype=torch.float64, device=b.device)
+    r, p = b, z
     for i in range(nit):
         q = sp.SpMV.apply(A.pattern, A.vals, p)
-        alpha = rho / (p * q).sum()
-        x = x + alpha * p
-        r = r - alpha * q
-        loss = loss + float(w[i]) * torch.linalg.norm(r) / bn
+        r, acc = _PcgRes.apply(p, q, r, rho, acc, float(w[i]), bnorm, ws)
         if i + 1 < nit:
             z = minv(r)
-            rho_new = (r * z).sum()
-            p = z + (rho_new / rho) * p
-            rho = rho_new
-    return loss
+            rho, p = _PcgDir.apply(r, z, rho, p, ws)
+    return acc[0]
 
 
 # ----------------------------------------------------------------------
