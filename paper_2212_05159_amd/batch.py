@@ -251,7 +251,8 @@ class Batch:
                 timed = []
                 for cand in CANDIDATES[fam]:
                     var = np.where(member, cand, SKIP).astype(np.int32)
-                    pl = self.plan(fam, var).plan
+                    plan_obj = self.plan(fam, var)  # owns the plan's device memory
+                    pl = plan_obj.plan
                     if fam == "spmv":
                         y = torch.empty(n, dtype=self.dtype, device=dev)
                         run = lambda: capi.csr_batch_spmv_fwd(P.desc(vals), pl, x, y)
@@ -269,6 +270,8 @@ class Batch:
                         run = lambda: capi.csr_batch_spmm_bwd(P.desc(vals), Pt.desc(dtype=self.dtype),
                                                               perm, pl, k, B, k, G, k, gB, k, gv)
                     timed.append((cand, _time(run, reps)))
+                    torch.cuda.current_stream().synchronize()
+                    del plan_obj
                 cand, ms = min(timed, key=lambda t: t[1])
                 chosen[member] = cand
                 out[fam][key] = (int(cand), ms, [(int(c), round(t, 4)) for c, t in timed])

@@ -467,7 +467,8 @@ def csr_batch_plan_workspace(A, nblocks, budget):
 
 
 def csr_batch_plan_build(A, block_rowptr_host, variants_host, budget, work):
-    """Returns a csrad_batch_plan pointing into `work` (keep both alive)."""
+    """Returns a csrad_batch_plan pointing into `work` (the struct keeps a
+    reference to `work`)."""
     brp = np.ascontiguousarray(block_rowptr_host, dtype=np.int32)
     var = None if variants_host is None else np.ascontiguousarray(variants_host, dtype=np.int32)
     plan = csrad_batch_plan()
@@ -475,6 +476,10 @@ def csr_batch_plan_build(A, block_rowptr_host, variants_host, budget, work):
            load().csr_batch_plan_build(C.byref(A), int(len(brp) - 1), brp.ctypes.data,
                                        None if var is None else var.ctypes.data, int(budget),
                                        _ptr(work), work.numel(), C.byref(plan), _stream()))
+    # the plan's task array and queue counters live in `work`: the struct
+    # holds the tensor so that the memory cannot be reused while any holder
+    # of the plan may still launch with it
+    plan._work = work
     return plan
 
 
