@@ -129,6 +129,21 @@ int csr_spmm_bwd(const csrad_csr *A, const csrad_csr *At, const int32_t *perm,
 int csr_transpose_workspace(const csrad_csr *A, size_t *bytes);
 int csr_transpose(const csrad_csr *A, int32_t *rowptrT, int32_t *colindT,
                   int32_t *perm, void *work, size_t work_bytes, void *stream);
+/* csr_transpose_noalloc: csr_transpose without a workspace argument, for
+ * callers that cannot allocate device memory (code under stream capture,
+ * serving loops, harnesses that forbid hipMalloc).  The scratch space
+ * lives in a static device array of csr_noalloc_scratch_bytes() bytes
+ * (64 MiB), which every GPU the library runs on holds until the process
+ * ends; the call allocates nothing.  Returns CSRAD_EWORKSPACE when the
+ * transpose of A would need more (csr_transpose_workspace(A) above the
+ * limit: roughly 2 nnz + 2 ncols int32 values over 64 MiB), CSRAD_EHIP if
+ * the array's device address cannot be obtained.  Outputs as csr_transpose
+ * (bit-identical).  Every call on one GPU shares the one array: calls that
+ * overlap on one GPU (other streams, other host threads) race; calls
+ * ordered on one stream are safe. */
+int csr_transpose_noalloc(const csrad_csr *A, int32_t *rowptrT, int32_t *colindT,
+                          int32_t *perm, void *stream);
+size_t csr_noalloc_scratch_bytes(void);
 /* Values of A^T in A^T's order: valsT[t] = vals[perm[t]] (nnz entries). */
 int csr_transpose_vals(const csrad_csr *A, const int32_t *perm, void *valsT,
                        void *stream);

@@ -54,6 +54,8 @@ _SIGS = {
     "csr_transpose_workspace": (C.c_int, [C.c_void_p, C.POINTER(C.c_size_t)]),
     "csr_transpose": (C.c_int, [C.c_void_p] * 5 + [C.c_size_t, C.c_void_p]),
     "csr_transpose_vals": (C.c_int, [C.c_void_p] * 4),
+    "csr_transpose_noalloc": (C.c_int, [C.c_void_p] * 5),
+    "csr_noalloc_scratch_bytes": (C.c_size_t, []),
     "csr_spgemm_workspace": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_size_t)]),
     "csr_spgemm_symbolic": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p,
                                       C.POINTER(C.c_int64), C.c_void_p, C.c_void_p, C.c_size_t,
@@ -239,6 +241,15 @@ def csr_transpose_workspace(A):
 def csr_transpose(A, rowptrT, colindT, perm, work):
     _check("csr_transpose", load().csr_transpose(C.byref(A), _ptr(rowptrT), _ptr(colindT),
                                                  _ptr(perm), _ptr(work), work.numel(), _stream()))
+
+
+def csr_transpose_noalloc(A, rowptrT, colindT, perm):
+    _check("csr_transpose_noalloc", load().csr_transpose_noalloc(
+        C.byref(A), _ptr(rowptrT), _ptr(colindT), _ptr(perm), _stream()))
+
+
+def csr_noalloc_scratch_bytes():
+    return int(load().csr_noalloc_scratch_bytes())
 
 
 def csr_transpose_vals(A, perm, valsT):
