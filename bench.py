@@ -214,7 +214,9 @@ def batched_section(blocks, gen_s, reps=5, skew=None):
         "whole_matrix_ms": round(tot(whole), 4),
         "per_block_ms": round(per_ms, 4),
         "speedup_vs_per_block": round(per_ms / tot(tuned), 2),
-        "launches_per_step": 6,
+        "launches_per_step": 6 + sum(int(v["split"]) for v in B.bwd_times.values()),
+        "backward_split": {op: {k2: (round(v2, 4) if isinstance(v2, float) else v2)
+                                for k2, v2 in v.items()} for op, v in B.bwd_times.items()},
         "variants": {fam: {f"{c[0]}/{'uneven' if c[1] else 'even'}": v[0] for c, v in per_cls.items()}
                      for fam, per_cls in tune.items()},
         "tune_s": round(tune_s, 1),

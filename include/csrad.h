@@ -417,7 +417,8 @@ typedef struct csrad_batch_plan {
     int32_t nrows;   /* rows of the matrix the plan was built on */
     int32_t nblocks;
     int32_t ntasks;
-    int32_t cus;     /* compute units; the launch keeps 4 workgroups each */
+    int32_t cus;     /* compute units; a launch keeps as many workgroups on each as
+                        the kernel's occupancy allows */
     const void *tasks;           /* device, inside the plan workspace */
     void *counters;              /* device, inside the plan workspace */
     const int32_t *block_rowptr; /* device copy, inside the plan workspace */
@@ -451,6 +452,17 @@ int csr_batch_spmm_bwd(const csrad_csr *A, const csrad_csr *At,
                        int32_t k, const void *B, int64_t ldb, const void *gC,
                        int64_t ldgc, void *gB, int64_t ldgb, void *gvals,
                        void *stream);
+/* Value gradients alone, row-wise over A with a plan of A (the other half
+ * of a backward split into an A^T product over At's plan, computed with
+ * gx / gB only, and this coalesced pass; the results equal the fused
+ * pass's): csr_batch_sddmv: gvals[e] = gy[row e] x[col e];
+ * csr_batch_sddmm: gvals[e] = <gC[row e,:], B[col e,:]> (k and alignment
+ * as csr_batch_spmm_fwd). */
+int csr_batch_sddmv(const csrad_csr *A, const csrad_batch_plan *plan,
+                    const void *x, const void *gy, void *gvals, void *stream);
+int csr_batch_sddmm(const csrad_csr *A, const csrad_batch_plan *plan, int32_t k,
+                    const void *B, int64_t ldb, const void *gC, int64_t ldgc,
+                    void *gvals, void *stream);
 /* Triangular solves per block (plan built with budget <= 0).  The level
  * sets of the whole block-diagonal T come from csr_trisolve_analyze;
  * csr_batch_levels writes, into a caller workspace of

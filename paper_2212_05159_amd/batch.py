@@ -66,6 +66,10 @@ class Batch:
         self.A = sp.CsrTensor.from_host(host, dtype=dtype, device=device)
         self.dtype = dtype
         self.variants = {}
+        # backward of SpMV / SpMM split into the A^T product over A^T's plan
+        # and a row-wise value-gradient pass over A's plan (else one fused
+        # pass over A^T); set by autotune
+        self.bwd_split = {"spmv": False, "spmm": False}
         self._plans = {}
         self._tri = {}
         rows = np.diff(self.block_rowptr).astype(np.int64)
@@ -136,8 +140,12 @@ class Batch:
         Pt, perm = P.transpose()
         gx = torch.empty(P.ncols, dtype=vals.dtype, device=vals.device) if need_x else None
         gv = torch.empty(P.nnz, dtype=vals.dtype, device=vals.device) if need_vals else None
-        capi.csr_batch_spmv_bwd(P.desc(vals), Pt.desc(dtype=vals.dtype), perm,
-                                self.plan("spmv_t").plan, x, gy, gx, gv)
+        split = self.bwd_split["spmv"] and need_vals
+        if need_x or not split:
+            capi.csr_batch_spmv_bwd(P.desc(vals), Pt.desc(dtype=vals.dtype), perm,
+                                    self.plan("spmv_t").plan, x, gy, gx, None if split else gv)
+        if split:
+            capi.csr_batch_sddmv(P.desc(vals), self.plan("spmv").plan, x, gy, gv)
         return gx, gv
 
     def spmm(self, B, vals=None):
@@ -161,9 +169,15 @@ class Batch:
         Pt, perm = P.transpose()
         gB = torch.empty(P.ncols, k, dtype=vals.dtype, device=vals.device) if need_B else None
         gv = torch.empty(P.nnz, dtype=vals.dtype, device=vals.device) if need_vals else None
-        capi.csr_batch_spmm_bwd(P.desc(vals), Pt.desc(dtype=vals.dtype), perm,
-                                self.plan("spmm_t").plan, k, B, B.stride(0) if B is not None else k,
-                                gC, gC.stride(0), gB, gB.stride(0) if gB is not None else k, gv)
+        split = self.bwd_split["spmm"] and need_vals
+        if need_B or not split:
+            capi.csr_batch_spmm_bwd(P.desc(vals), Pt.desc(dtype=vals.dtype), perm,
+                                    self.plan("spmm_t").plan, k, B,
+                                    B.stride(0) if B is not None else k, gC, gC.stride(0), gB,
+                                    gB.stride(0) if gB is not None else k, None if split else gv)
+        if split:
+            capi.csr_batch_sddmm(P.desc(vals), self.plan("spmm").plan, k, B, B.stride(0), gC,
+                                 gC.stride(0), gv)
         return gB, gv
 
     # ------------------------------------------------------------------
@@ -276,6 +290,21 @@ class Batch:
                 chosen[member] = cand
                 out[fam][key] = (int(cand), ms, [(int(c), round(t, 4)) for c, t in timed])
             self.set_variants(fam, chosen)
+        # fused vs split backward, on the tuned plans
+        self.bwd_times = {}
+        for op in ("spmv", "spmm"):
+            if op not in families or op + "_t" not in families:
+                continue
+            ms = {}
+            for split in (False, True):
+                self.bwd_split[op] = split
+                if op == "spmv":
+                    ms[split] = _time(lambda: self.spmv_bwd(x, gy), reps)
+                else:
+                    ms[split] = _time(lambda: self.spmm_bwd(B, G), reps)
+            self.bwd_split[op] = ms[True] < ms[False]
+            self.bwd_times[op] = {"fused_ms": ms[False], "split_ms": ms[True],
+                                  "split": self.bwd_split[op]}
         return out
 
 

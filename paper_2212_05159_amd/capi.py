@@ -116,6 +116,9 @@ _SIGS = {
     "csr_batch_spmm_bwd": (C.c_int, [C.c_void_p] * 4 + [C.c_int32, C.c_void_p, C.c_int64,
                                                          C.c_void_p, C.c_int64, C.c_void_p,
                                                          C.c_int64, C.c_void_p, C.c_void_p]),
+    "csr_batch_sddmv": (C.c_int, [C.c_void_p] * 6),
+    "csr_batch_sddmm": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_int64,
+                                  C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]),
     "csr_batch_levels_workspace": (C.c_int, [C.c_int32, C.c_int32, C.POINTER(C.c_size_t)]),
     "csr_batch_levels": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
                                    C.c_size_t, C.c_void_p]),
@@ -503,6 +506,18 @@ def csr_batch_spmv_bwd(A, At, perm, planT, x, gy, gx, gvals):
     _check("csr_batch_spmv_bwd",
            load().csr_batch_spmv_bwd(C.byref(A), C.byref(At), _ptr(perm), C.byref(planT), _ptr(x),
                                      _ptr(gy), _ptr(gx), _ptr(gvals), _stream()))
+
+
+def csr_batch_sddmv(A, plan, x, gy, gvals):
+    _check("csr_batch_sddmv",
+           load().csr_batch_sddmv(C.byref(A), C.byref(plan), _ptr(x), _ptr(gy), _ptr(gvals),
+                                  _stream()))
+
+
+def csr_batch_sddmm(A, plan, k, B, ldb, gC, ldgc, gvals):
+    _check("csr_batch_sddmm",
+           load().csr_batch_sddmm(C.byref(A), C.byref(plan), int(k), _ptr(B), int(ldb), _ptr(gC),
+                                  int(ldgc), _ptr(gvals), _stream()))
 
 
 def csr_batch_spmm_fwd(A, plan, k, B, ldb, Cout, ldc):

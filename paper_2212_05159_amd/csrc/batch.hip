@@ -6,9 +6,8 @@
 //
 // Plan.  The host splits every block into tasks of about equal cost
 // (rows + stored entries, the length of the block's merge path), each
-// aligned to row boundaries, and orders the blocks by cost, largest first,
-// so the long tasks start early and the short ones fill the tail.  Each
-// task carries its block's variant:
+// aligned to row boundaries, kept in row order.  Each task carries its
+// block's variant:
 //   rows, G lanes per row (G = 1 ... 64): the row-split traversal;
 //   staged: rows of 256 at a time with their entries staged in LDS
 //     (short rows);
@@ -18,15 +17,19 @@
 //     instead of holding one group while the others idle.  Rows cut by a
 //     piece boundary are completed from per-piece partial sums in piece
 //     order (deterministic; no floating-point atomics).
-// For the triangular solves a task is a whole block: one workgroup runs
-// the block's levels in order with a barrier between levels, so a batch of
-// shallow, independent level structures costs one launch instead of one
-// per level.
+// For the triangular solves a task is a whole block: one workgroup of 1024
+// threads runs the block's levels in order with a barrier between levels,
+// so a batch of shallow, independent level structures costs one launch
+// instead of one per level; these tasks are ordered by cost, largest first,
+// so the long ones start early and the short ones fill the tail.
 //
-// Queue.  A launch keeps `slots` workgroups resident; each takes the next
-// task index from a device counter.  The last workgroup to leave resets the
-// counters, so the next launch on the stream starts from zero without a
-// memset node (launches that share a plan must be ordered on one stream).
+// Queue.  A launch keeps as many workgroups as fit on the chip at once;
+// each takes the next task index from device counters: one queue per XCD
+// over a contiguous range of the row-ordered tasks (one queue for the
+// whole-block tasks), a workgroup moving on to the other queues once its
+// own is empty.  The last workgroup to leave resets the counters, so the
+// next launch on the stream starts from zero without a memset node
+// (launches that share a plan must be ordered on one stream).
 #include <algorithm>
 #include <vector>
 
@@ -36,8 +39,9 @@ namespace csrad {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kSlotsPerCu = 4;
-constexpr int kMergeRowCap = 4096;      // rows of one merge task (staged in LDS)
+constexpr int kTriThreads = 1024;       // workgroup of the per-block solves and IC(0)
+constexpr int kSlotsPerCu = 4;          // fallback when the occupancy query fails
+constexpr int kMergeRowCap = 2048;      // rows of one merge task (staged in LDS)
 constexpr int kStageCap = 2560;         // staged variant: entries per 256 rows
 
 enum : int32_t { kKindMerge = 8, kKindStaged = 9 };
@@ -47,16 +51,41 @@ struct BTask {
 };
 
 // ---------------------------------------------------------------------
-// Queue
+// Queue.  The tasks are dealt from nq queues (ctr[kNqSlot]: 1, or one per
+// XCD), queue q holding the contiguous task range
+// [ntasks*q/nq, ntasks*(q+1)/nq).  A workgroup starts on queue
+// blockIdx.x % nq (the dispatcher places workgroup b on XCD b % 8, so each
+// XCD works through its own range of rows and keeps that range's dense
+// operands in its own L2) and moves on to the next queue when its own is
+// exhausted.  ctr[0..nq) are the queue heads, ctr[kLeaveSlot] counts the
+// workgroups that have left.
 // ---------------------------------------------------------------------
-__device__ __forceinline__ int fetch_task(unsigned* ctr) { return (int)atomicAdd(&ctr[0], 1u); }
+constexpr int kQueues = kXcds;
+constexpr int kLeaveSlot = kQueues;
+constexpr int kNqSlot = kQueues + 1;
+constexpr int kCtrWords = kQueues + 2;
 
-__device__ __forceinline__ void leave_queue(unsigned* ctr) {
+// Next task index for this workgroup (thread 0 only); `tried` counts the
+// queues found exhausted so far.  ntasks when every queue is exhausted.
+__device__ __forceinline__ int fetch_task(unsigned* ctr, int ntasks, int nq, int& tried) {
+  const int home = (int)(blockIdx.x % (unsigned)nq);
+  while (tried < nq) {
+    const int q = (home + tried) % nq;
+    const long long lo = (long long)ntasks * q / nq, hi = (long long)ntasks * (q + 1) / nq;
+    const unsigned idx = atomicAdd(&ctr[q], 1u);
+    if (lo + idx < hi) return (int)(lo + idx);
+    ++tried;
+  }
+  return ntasks;
+}
+
+__device__ __forceinline__ void leave_queue(unsigned* ctr, int nq) {
   // the last workgroup out finds every other one gone (each has drawn an
-  // index past the end) and rewinds the queue for the next launch
-  if (threadIdx.x == 0 && atomicAdd(&ctr[1], 1u) == gridDim.x - 1) {
-    atomicExch(&ctr[0], 0u);
-    atomicExch(&ctr[1], 0u);
+  // index past the end of every queue) and rewinds the queues for the next
+  // launch
+  if (threadIdx.x == 0 && atomicAdd(&ctr[kLeaveSlot], 1u) == gridDim.x - 1) {
+    for (int q = 0; q < nq; ++q) atomicExch(&ctr[q], 0u);
+    atomicExch(&ctr[kLeaveSlot], 0u);
   }
 }
 
@@ -66,12 +95,14 @@ template <typename F>
 __device__ __forceinline__ void run_queue(const BTask* __restrict__ tasks, int ntasks,
                                           unsigned* ctr, F&& body) {
   __shared__ int s_next;
-  if (threadIdx.x == 0) s_next = fetch_task(ctr);
+  const int nq = (int)ctr[kNqSlot];
+  int tried = 0;  // thread 0's
+  if (threadIdx.x == 0) s_next = fetch_task(ctr, ntasks, nq, tried);
   __syncthreads();
   int t = s_next;
   while (t < ntasks) {
     int nxt = 0;
-    if (threadIdx.x == 0) nxt = fetch_task(ctr);
+    if (threadIdx.x == 0) nxt = fetch_task(ctr, ntasks, nq, tried);
     const int4 raw = *reinterpret_cast<const int4*>(&tasks[t]);
     body(BTask{raw.x, raw.y, raw.z, raw.w});
     __syncthreads();
@@ -79,7 +110,7 @@ __device__ __forceinline__ void run_queue(const BTask* __restrict__ tasks, int n
     __syncthreads();
     t = s_next;
   }
-  leave_queue(ctr);
+  leave_queue(ctr, nq);
 }
 
 // Merge-path split of diagonal d between row ends a[0..nr) (exclusive
@@ -745,6 +776,88 @@ __global__ __launch_bounds__(kThreads) void k_batch_spmm_bwd(
 }
 
 // ---------------------------------------------------------------------
+// Value gradients alone, row-wise over A (the plan of A), for a backward
+// split into A^T products over A^T's plan and these coalesced passes:
+//   SpMV:  gvals[e] = gy[row e] x[col e]
+//   SpMM:  gvals[e] = <gC[row e, :], B[col e, :]>
+// ---------------------------------------------------------------------
+template <typename T, int G>
+__device__ __forceinline__ void sddmv_rows(const BTask& tk, const int32_t* __restrict__ rp,
+                                           const int32_t* __restrict__ ci,
+                                           const T* __restrict__ x, const T* __restrict__ gy,
+                                           T* __restrict__ gv) {
+  constexpr int RPP = kThreads / G;
+  const int sub = threadIdx.x % G;
+  for (int base = tk.r0; base < tk.r1; base += RPP) {
+    const int r = base + threadIdx.x / G;
+    if (r < tk.r1) {
+      const T g = gy[r];
+      const int e1 = rp[r + 1];
+      for (int e = rp[r] + sub; e < e1; e += G) gv[e] = g * x[ld_stream(&ci[e])];
+    }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_batch_sddmv(const BTask* __restrict__ tasks,
+                                                          int ntasks, unsigned* ctr,
+                                                          const int32_t* __restrict__ rp,
+                                                          const int32_t* __restrict__ ci,
+                                                          const T* __restrict__ x,
+                                                          const T* __restrict__ gy,
+                                                          T* __restrict__ gv) {
+  run_queue(tasks, ntasks, ctr, [&](const BTask& tk) {
+    switch (tk.kind) {
+      case 1: sddmv_rows<T, 1>(tk, rp, ci, x, gy, gv); break;
+      case 2: sddmv_rows<T, 2>(tk, rp, ci, x, gy, gv); break;
+      case 3: sddmv_rows<T, 4>(tk, rp, ci, x, gy, gv); break;
+      case 5: sddmv_rows<T, 16>(tk, rp, ci, x, gy, gv); break;
+      case 6: sddmv_rows<T, 32>(tk, rp, ci, x, gy, gv); break;
+      case 7: sddmv_rows<T, 64>(tk, rp, ci, x, gy, gv); break;
+      default: sddmv_rows<T, 8>(tk, rp, ci, x, gy, gv); break;
+    }
+  });
+}
+
+template <typename T, int VW>
+__global__ __launch_bounds__(kThreads) void k_batch_sddmm(
+    const BTask* __restrict__ tasks, int ntasks, unsigned* ctr, int k,
+    const int32_t* __restrict__ rp, const int32_t* __restrict__ ci, const T* __restrict__ B,
+    long long ldb, const T* __restrict__ G, long long ldg, T* __restrict__ gv) {
+  run_queue(tasks, ntasks, ctr, [&](const BTask& tk) {
+    const int g = threadIdx.x / kGrp, l = threadIdx.x % kGrp;
+    for (int row = tk.r0 + g; row < tk.r1; row += kGroups) {
+      const int e0 = rp[row], e1 = rp[row + 1];
+      for (int c0 = 0; c0 < k; c0 += kGrp * VW) {
+        const int col = c0 + l * VW;
+        const bool act = col < k;
+        const Vec<T, VW> gi = ld_or_zero<T, VW>(G + (long long)row * ldg + col, act);
+        for (int eb = e0; eb < e1; eb += kEb) {
+          const int cnt = min(kEb, e1 - eb);
+          const int myc = l < cnt ? ld_stream(&ci[eb + l]) : 0;
+          int c[kEb];
+          bc_all<int>(myc, c);
+          Vec<T, VW> bv[kEb];
+#pragma unroll
+          for (int u = 0; u < kEb; ++u)
+            bv[u] = ld_or_zero<T, VW>(B + (long long)c[u] * ldb + col, act && u < cnt);
+          T mine = 0;
+#pragma unroll
+          for (int u = 0; u < kEb; ++u) {
+            T d = 0;
+#pragma unroll
+            for (int w = 0; w < VW; ++w) d += gi.v[w] * bv[u].v[w];
+            d = group_sum<kGrp>(d);
+            if (l == u) mine = d;
+          }
+          if (l < cnt) gv[eb + l] = c0 == 0 ? mine : gv[eb + l] + mine;
+        }
+      }
+    }
+  });
+}
+
+// ---------------------------------------------------------------------
 // Triangular solves: a task is one block; lv_lo/lv_hi (nblocks x nlevels)
 // give the positions in level_rows of the block's rows on each level.
 // x_i = (b_i - sum_{j != i} T_ij x_j) / T_ii, entries in row order.
@@ -755,19 +868,36 @@ __device__ __forceinline__ void tri_row(int r, const int32_t* __restrict__ rp,
                                         const int32_t* __restrict__ perm,
                                         const TV* __restrict__ vals, const TX* __restrict__ b,
                                         TX* __restrict__ x) {
+  // entries 8 at a time: all column/value loads, then all x loads, then the
+  // sum in entry order (two or three rounds of memory latency per batch
+  // instead of a dependent chain per entry)
+  constexpr int W = 8;
   TX s = 0, d = 0;
-  const int e1 = rp[r + 1];
-  for (int e = rp[r]; e < e1; ++e) {
-    const int j = ci[e];
-    const TX v = (TX)(PERM ? vals[perm[e]] : vals[e]);
-    if (j == r) d = v;
-    else s += v * x[j];
+  const int e0 = rp[r], e1 = rp[r + 1];
+  for (int eb = e0; eb < e1; eb += W) {
+    int j[W];
+    TX v[W], xv[W];
+#pragma unroll
+    for (int u = 0; u < W; ++u) {
+      const bool ok = eb + u < e1;
+      j[u] = ok ? ci[eb + u] : r;
+      v[u] = ok ? (TX)(PERM ? vals[perm[eb + u]] : vals[eb + u]) : TX(0);
+    }
+#pragma unroll
+    for (int u = 0; u < W; ++u) xv[u] = j[u] != r ? x[j[u]] : TX(0);
+#pragma unroll
+    for (int u = 0; u < W; ++u) {
+      if (eb + u < e1) {
+        if (j[u] == r) d = v[u];
+        else s += v[u] * xv[u];
+      }
+    }
   }
   x[r] = (b[r] - s) / d;
 }
 
 template <typename T, bool ADJ>
-__global__ __launch_bounds__(kThreads) void k_batch_tri(
+__global__ __launch_bounds__(kTriThreads) void k_batch_tri(
     const BTask* __restrict__ tasks, int ntasks, unsigned* ctr, int nlevels,
     const int32_t* __restrict__ lv_lo, const int32_t* __restrict__ lv_hi,
     const int32_t* __restrict__ rows, const int32_t* __restrict__ rp,
@@ -780,13 +910,13 @@ __global__ __launch_bounds__(kThreads) void k_batch_tri(
       const int l = ADJ ? nlevels - 1 - s : s;
       const int lo = lv_lo[base + l], hi = lv_hi[base + l];
       if (hi <= lo) continue;  // uniform over the workgroup
-      for (int q = lo + threadIdx.x; q < hi; q += kThreads)
+      for (int q = lo + threadIdx.x; q < hi; q += kTriThreads)
         tri_row<T, T, ADJ>(rows[q], rp, ci, perm, vals, b, x);
       __syncthreads();
     }
     if (ADJ && gv) {
       // gvals[(i,j)] = -w_i x_j over the block's rows of T (w final now)
-      for (int i = tk.r0 + threadIdx.x; i < tk.r1; i += kThreads) {
+      for (int i = tk.r0 + threadIdx.x; i < tk.r1; i += kTriThreads) {
         const T wi = x[i];
         for (int e = rpA[i]; e < rpA[i + 1]; ++e) gv[e] = -wi * xf[ciA[e]];
       }
@@ -801,7 +931,7 @@ __global__ __launch_bounds__(kThreads) void k_batch_tri(
 // j < i, which sit on lower levels of the lower solve.  A non-positive
 // pivot leaves NaN on the diagonal (and in every entry that reads it).
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_batch_ic0(
+__global__ __launch_bounds__(kTriThreads) void k_batch_ic0(
     const BTask* __restrict__ tasks, int ntasks, unsigned* ctr, int nlevels,
     const int32_t* __restrict__ lv_lo, const int32_t* __restrict__ lv_hi,
     const int32_t* __restrict__ rows, const int32_t* __restrict__ rp,
@@ -811,7 +941,7 @@ __global__ __launch_bounds__(kThreads) void k_batch_ic0(
     for (int lev = 0; lev < nlevels; ++lev) {
       const int lo = lv_lo[base + lev], hi = lv_hi[base + lev];
       if (hi <= lo) continue;
-      for (int q = lo + threadIdx.x; q < hi; q += kThreads) {
+      for (int q = lo + threadIdx.x; q < hi; q += kTriThreads) {
         const int i = rows[q];
         const int e0 = rp[i], e1 = rp[i + 1];
         for (int e = e0; e < e1; ++e) {
@@ -937,12 +1067,19 @@ PlanWs carve_plan(Carver& c, long long ntasks_max, int nblocks) {
   w.nchunks = c.take<int32_t>((size_t)ntasks_max);
   w.brp = c.take<int32_t>((size_t)nblocks + 1);
   w.ends = c.take<int32_t>((size_t)nblocks + 1);
-  w.ctr = c.take<unsigned>(2);
+  w.ctr = c.take<unsigned>(kCtrWords);
   return w;
 }
 
-int slots_for(const csrad_batch_plan* plan) {
-  const long long s = (long long)plan->cus * kSlotsPerCu;
+// Workgroups a persistent launch keeps: as many as fit on the chip at once
+// (the occupancy of this kernel at this block size), at most one per task.
+template <typename K>
+int slots_for(const csrad_batch_plan* plan, K kernel, int threads) {
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess ||
+      per_cu < 1)
+    per_cu = kSlotsPerCu;
+  const long long s = (long long)plan->cus * per_cu;
   return (int)(plan->ntasks < s ? plan->ntasks : s);
 }
 
@@ -973,7 +1110,8 @@ int batch_spmm_fwd_t(const csrad_csr* A, const csrad_batch_plan* plan, int k, co
   const BTask* tk = static_cast<const BTask*>(plan->tasks);
   unsigned* ctr = static_cast<unsigned*>(plan->counters);
   const T* v = static_cast<const T*>(A->vals);
-  hipLaunchKernelGGL((k_batch_spmm<T, VW>), dim3(slots_for(plan)), dim3(kThreads), 0, s, tk,
+  hipLaunchKernelGGL((k_batch_spmm<T, VW>), dim3(slots_for(plan, k_batch_spmm<T, VW>, kThreads)),
+                     dim3(kThreads), 0, s, tk,
                      plan->ntasks, ctr, k, A->rowptr, A->colind, v, B, ldb, C, ldc);
   return launch_status();
 }
@@ -987,7 +1125,7 @@ int batch_spmm_bwd_t(const csrad_csr* A, const csrad_csr* At, const int32_t* per
   const BTask* tk = static_cast<const BTask*>(plan->tasks);
   unsigned* ctr = static_cast<unsigned*>(plan->counters);
   const T* v = static_cast<const T*>(A->vals);
-  const dim3 grid(slots_for(plan));
+  const dim3 grid(slots_for(plan, k_batch_spmm_bwd<T, VW, true, true>, kThreads));
   if (gB && gv)
     hipLaunchKernelGGL((k_batch_spmm_bwd<T, VW, true, true>), grid, dim3(kThreads), 0, s, tk,
                        plan->ntasks, ctr, k, At->rowptr, At->colind, perm, v, B, ldb, G, ldg, gB,
@@ -1058,16 +1196,21 @@ extern "C" int csr_batch_plan_build(const csrad_csr* A, int32_t nblocks,
         hipStreamSynchronize(s) != hipSuccess)
       return CSRAD_EHIP;
   }
-  // blocks by cost, largest first (stable); chunks of about `budget` path
-  // items (merge tasks: merge_budget(budget))
+  // chunks of about `budget` path items (merge tasks: merge_budget(budget))
   std::vector<int> order(nblocks);
   std::vector<long long> cost(nblocks);
   for (int b = 0; b < nblocks; ++b) {
     order[b] = b;
     cost[b] = (long long)(block_rowptr_host[b + 1] - block_rowptr_host[b]) + (ends[b + 1] - ends[b]);
   }
-  std::stable_sort(order.begin(), order.end(),
-                   [&](int a, int b) { return cost[a] > cost[b]; });
+  // Whole-block tasks (budget <= 0): largest blocks first, from one queue,
+  // so the long ones start early.  Chunked tasks are about equal in cost:
+  // they stay in row order, dealt from one queue per XCD (neighbouring
+  // tasks share blocks, so each XCD's L2 holds the dense rows of a few
+  // blocks at a time).
+  if (budget <= 0)
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return cost[a] > cost[b]; });
   std::vector<BTask> tasks;
   std::vector<int32_t> chunk, nch;
   for (int b : order) {
@@ -1102,7 +1245,11 @@ extern "C" int csr_batch_plan_build(const csrad_csr* A, int32_t nblocks,
                        w.nchunks, w.brp, A->rowptr);
     CSRAD_TRY(launch_status());
   }
-  CSRAD_TRY(fill_bytes_zero(w.ctr, 2 * sizeof(unsigned), s));
+  CSRAD_TRY(fill_bytes_zero(w.ctr, kCtrWords * sizeof(unsigned), s));
+  const unsigned nq = budget > 0 ? (unsigned)kQueues : 1u;
+  if (hipMemcpyAsync(w.ctr + kNqSlot, &nq, sizeof(unsigned), hipMemcpyHostToDevice, s) !=
+      hipSuccess)
+    return CSRAD_EHIP;
   if (hipStreamSynchronize(s) != hipSuccess) return CSRAD_EHIP;  // host vectors die here
   // a merge task must fit the LDS stage: check on the host
   if (nt > 0) {
@@ -1131,7 +1278,8 @@ extern "C" int csr_batch_spmv_fwd(const csrad_csr* A, const csrad_batch_plan* pl
   hipStream_t s = as_stream(stream);
   const BTask* tk = static_cast<const BTask*>(plan->tasks);
   unsigned* ctr = static_cast<unsigned*>(plan->counters);
-  const dim3 grid(slots_for(plan));
+  const dim3 grid(A->dtype == CSRAD_F32 ? slots_for(plan, k_batch_spmv<float>, kThreads)
+                                        : slots_for(plan, k_batch_spmv<double>, kThreads));
   if (A->dtype == CSRAD_F32)
     hipLaunchKernelGGL((k_batch_spmv<float>), grid, dim3(kThreads), 0, s, tk, plan->ntasks, ctr,
                        A->rowptr, A->colind, static_cast<const float*>(A->vals),
@@ -1158,7 +1306,9 @@ extern "C" int csr_batch_spmv_bwd(const csrad_csr* A, const csrad_csr* At, const
   hipStream_t s = as_stream(stream);
   const BTask* tk = static_cast<const BTask*>(planT->tasks);
   unsigned* ctr = static_cast<unsigned*>(planT->counters);
-  const dim3 grid(slots_for(planT));
+  const dim3 grid(A->dtype == CSRAD_F32
+                      ? slots_for(planT, k_batch_spmv_bwd<float, true, true>, kThreads)
+                      : slots_for(planT, k_batch_spmv_bwd<double, true, true>, kThreads));
 #define CSRAD_BATCH_SPMVB(T)                                                                    \
   {                                                                                             \
     const T* v = static_cast<const T*>(A->vals);                                                \
@@ -1278,14 +1428,16 @@ extern "C" int csr_batch_trisolve_fwd(const csrad_csr* T, const csrad_batch_plan
   hipStream_t s = as_stream(stream);
   const BTask* tk = static_cast<const BTask*>(plan->tasks);
   unsigned* ctr = static_cast<unsigned*>(plan->counters);
-  const dim3 grid(slots_for(plan));
+  const dim3 grid(T->dtype == CSRAD_F32
+                      ? slots_for(plan, k_batch_tri<float, false>, kTriThreads)
+                      : slots_for(plan, k_batch_tri<double, false>, kTriThreads));
   if (T->dtype == CSRAD_F32)
-    hipLaunchKernelGGL((k_batch_tri<float, false>), grid, dim3(kThreads), 0, s, tk, plan->ntasks,
+    hipLaunchKernelGGL((k_batch_tri<float, false>), grid, dim3(kTriThreads), 0, s, tk, plan->ntasks,
                        ctr, nlevels, lo, hi, level_rows, T->rowptr, T->colind, nullptr,
                        static_cast<const float*>(T->vals), static_cast<const float*>(b),
                        static_cast<float*>(x), nullptr, nullptr, nullptr, nullptr);
   else
-    hipLaunchKernelGGL((k_batch_tri<double, false>), grid, dim3(kThreads), 0, s, tk, plan->ntasks,
+    hipLaunchKernelGGL((k_batch_tri<double, false>), grid, dim3(kTriThreads), 0, s, tk, plan->ntasks,
                        ctr, nlevels, lo, hi, level_rows, T->rowptr, T->colind, nullptr,
                        static_cast<const double*>(T->vals), static_cast<const double*>(b),
                        static_cast<double*>(x), nullptr, nullptr, nullptr, nullptr);
@@ -1310,15 +1462,17 @@ extern "C" int csr_batch_trisolve_bwd(const csrad_csr* T, const csrad_csr* Tt, c
   hipStream_t s = as_stream(stream);
   const BTask* tk = static_cast<const BTask*>(plan->tasks);
   unsigned* ctr = static_cast<unsigned*>(plan->counters);
-  const dim3 grid(slots_for(plan));
+  const dim3 grid(T->dtype == CSRAD_F32
+                      ? slots_for(plan, k_batch_tri<float, true>, kTriThreads)
+                      : slots_for(plan, k_batch_tri<double, true>, kTriThreads));
   if (T->dtype == CSRAD_F32)
-    hipLaunchKernelGGL((k_batch_tri<float, true>), grid, dim3(kThreads), 0, s, tk, plan->ntasks,
+    hipLaunchKernelGGL((k_batch_tri<float, true>), grid, dim3(kTriThreads), 0, s, tk, plan->ntasks,
                        ctr, nlevels, lo, hi, level_rows, Tt->rowptr, Tt->colind, perm,
                        static_cast<const float*>(T->vals), static_cast<const float*>(gx),
                        static_cast<float*>(gb), static_cast<const float*>(x), T->rowptr,
                        T->colind, static_cast<float*>(gvals));
   else
-    hipLaunchKernelGGL((k_batch_tri<double, true>), grid, dim3(kThreads), 0, s, tk, plan->ntasks,
+    hipLaunchKernelGGL((k_batch_tri<double, true>), grid, dim3(kTriThreads), 0, s, tk, plan->ntasks,
                        ctr, nlevels, lo, hi, level_rows, Tt->rowptr, Tt->colind, perm,
                        static_cast<const double*>(T->vals), static_cast<const double*>(gx),
                        static_cast<double*>(gb), static_cast<const double*>(x), T->rowptr,
@@ -1338,14 +1492,67 @@ extern "C" int csr_batch_ic0(const csrad_csr* Alow, const csrad_batch_plan* plan
   hipStream_t s = as_stream(stream);
   const BTask* tk = static_cast<const BTask*>(plan->tasks);
   unsigned* ctr = static_cast<unsigned*>(plan->counters);
-  const dim3 grid(slots_for(plan));
+  const dim3 grid(Alow->dtype == CSRAD_F32 ? slots_for(plan, k_batch_ic0<float>, kTriThreads)
+                                           : slots_for(plan, k_batch_ic0<double>, kTriThreads));
   if (Alow->dtype == CSRAD_F32)
-    hipLaunchKernelGGL((k_batch_ic0<float>), grid, dim3(kThreads), 0, s, tk, plan->ntasks, ctr,
+    hipLaunchKernelGGL((k_batch_ic0<float>), grid, dim3(kTriThreads), 0, s, tk, plan->ntasks, ctr,
                        nlevels, lo, hi, level_rows, Alow->rowptr, Alow->colind,
                        static_cast<const float*>(Alow->vals), static_cast<float*>(Lvals));
   else
-    hipLaunchKernelGGL((k_batch_ic0<double>), grid, dim3(kThreads), 0, s, tk, plan->ntasks, ctr,
+    hipLaunchKernelGGL((k_batch_ic0<double>), grid, dim3(kTriThreads), 0, s, tk, plan->ntasks, ctr,
                        nlevels, lo, hi, level_rows, Alow->rowptr, Alow->colind,
                        static_cast<const double*>(Alow->vals), static_cast<double*>(Lvals));
+  return launch_status();
+}
+
+extern "C" int csr_batch_sddmv(const csrad_csr* A, const csrad_batch_plan* plan, const void* x,
+                               const void* gy, void* gvals, void* stream) {
+  CSRAD_TRY(check_csr(A, false));
+  CSRAD_TRY(check_plan_for(plan, A->nrows));
+  if (A->nnz > 0 && (!gvals || !x || !gy)) return CSRAD_EINVAL;
+  if (plan->ntasks == 0 || A->nnz == 0) return CSRAD_OK;
+  hipStream_t s = as_stream(stream);
+  const BTask* tk = static_cast<const BTask*>(plan->tasks);
+  unsigned* ctr = static_cast<unsigned*>(plan->counters);
+  if (A->dtype == CSRAD_F32)
+    hipLaunchKernelGGL((k_batch_sddmv<float>), dim3(slots_for(plan, k_batch_sddmv<float>, kThreads)),
+                       dim3(kThreads), 0, s, tk, plan->ntasks, ctr, A->rowptr, A->colind,
+                       static_cast<const float*>(x), static_cast<const float*>(gy),
+                       static_cast<float*>(gvals));
+  else
+    hipLaunchKernelGGL((k_batch_sddmv<double>),
+                       dim3(slots_for(plan, k_batch_sddmv<double>, kThreads)), dim3(kThreads), 0,
+                       s, tk, plan->ntasks, ctr, A->rowptr, A->colind,
+                       static_cast<const double*>(x), static_cast<const double*>(gy),
+                       static_cast<double*>(gvals));
+  return launch_status();
+}
+
+extern "C" int csr_batch_sddmm(const csrad_csr* A, const csrad_batch_plan* plan, int32_t k,
+                               const void* B, int64_t ldb, const void* gC, int64_t ldgc,
+                               void* gvals, void* stream) {
+  CSRAD_TRY(check_csr(A, false));
+  CSRAD_TRY(check_plan_for(plan, A->nrows));
+  if (k <= 0 || ldb < k || ldgc < k) return CSRAD_EINVAL;
+  if (A->nnz > 0 && (!gvals || !B || !gC)) return CSRAD_EINVAL;
+  const int es = (int)dtype_size(A->dtype);
+  if (k % (16 / es) != 0 || !aligned16(B, ldb, es) || !aligned16(gC, ldgc, es))
+    return CSRAD_EINVAL;
+  if (plan->ntasks == 0 || A->nnz == 0) return CSRAD_OK;
+  hipStream_t s = as_stream(stream);
+  const BTask* tk = static_cast<const BTask*>(plan->tasks);
+  unsigned* ctr = static_cast<unsigned*>(plan->counters);
+  if (A->dtype == CSRAD_F32)
+    hipLaunchKernelGGL((k_batch_sddmm<float, 4>),
+                       dim3(slots_for(plan, k_batch_sddmm<float, 4>, kThreads)), dim3(kThreads),
+                       0, s, tk, plan->ntasks, ctr, k, A->rowptr, A->colind,
+                       static_cast<const float*>(B), ldb, static_cast<const float*>(gC), ldgc,
+                       static_cast<float*>(gvals));
+  else
+    hipLaunchKernelGGL((k_batch_sddmm<double, 2>),
+                       dim3(slots_for(plan, k_batch_sddmm<double, 2>, kThreads)), dim3(kThreads),
+                       0, s, tk, plan->ntasks, ctr, k, A->rowptr, A->colind,
+                       static_cast<const double*>(B), ldb, static_cast<const double*>(gC), ldgc,
+                       static_cast<double*>(gvals));
   return launch_status();
 }

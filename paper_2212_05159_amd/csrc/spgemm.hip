@@ -255,107 +255,147 @@ __device__ __forceinline__ unsigned long long group_mask(int lane) {
   return G == 64 ? ~0ull : (((1ull << G) - 1ull) << (lane & ~(G - 1)));
 }
 
-template <typename T, int G, bool NUM>
+// Wave-level ordering of the LDS slots: a group's slots are written and
+// read by the lanes of one wave only (G divides 64), so a wave barrier with
+// a workgroup-scope fence orders them; groups never wait for other waves.
+__device__ __forceinline__ void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// R rows per group are in flight at once (their load rounds are issued
+// together, then merged one after the other), so a wave hides R times the
+// memory latency of one row.
+template <typename T, int G, bool NUM, int R>
 __global__ __launch_bounds__(kThreads) void k_merge(
     int bin, const int32_t* __restrict__ list, const int32_t* __restrict__ bin_off,
     const int32_t* __restrict__ rpA, const int32_t* __restrict__ ciA, const T* __restrict__ vA,
     const int32_t* __restrict__ rpB, const int32_t* __restrict__ ciB, const T* __restrict__ vB,
     const int32_t* __restrict__ rpC, int32_t* __restrict__ ciC, T* __restrict__ vC,
     int32_t* __restrict__ counts) {
-  constexpr int RPB = kThreads / G;
-  __shared__ int s_b0[kThreads], s_len[kThreads], s_a[kThreads];
+  constexpr int RPB = kThreads / G;  // groups per block
+  __shared__ int s_b0[R][kThreads], s_len[R][kThreads], s_a[R][kThreads];
   const int first = bin_off[bin], nrows = bin_off[bin + 1] - first;
   const int lane = __lane_id(), l = threadIdx.x % G, g0 = threadIdx.x - l;
   const unsigned long long gm = group_mask<G>(lane);
   const unsigned long long below = gm & ((1ull << lane) - 1ull);
-  for (int base = blockIdx.x * RPB; base < nrows; base += gridDim.x * RPB) {  // uniform
-    const int idx = base + threadIdx.x / G;
-    const bool valid = idx < nrows;
-    const int i = valid ? list[first + idx] : 0;
-    int a0 = 0, a1 = 0;
-    if (valid) {
-      a0 = rpA[i];
-      a1 = rpA[i + 1];
+  // group q of the block owns rows base + q*R + t, t < R
+  for (int base = blockIdx.x * RPB * R; base < nrows; base += gridDim.x * RPB * R) {
+    int i[R], a0[R], a1[R], nl[R];
+    bool valid[R];
+#pragma unroll
+    for (int t = 0; t < R; ++t) {
+      const int idx = base + (threadIdx.x / G) * R + t;
+      valid[t] = idx < nrows;
+      i[t] = valid[t] ? list[first + idx] : 0;
     }
-    // the non-empty lists of the row, compacted into the group's slots in
-    // A's row order (the bin guarantees at most G of them)
-    const int chunks = wave_max((a1 - a0 + G - 1) / G);
-    int nl = 0;
+#pragma unroll
+    for (int t = 0; t < R; ++t) {
+      a0[t] = valid[t] ? rpA[i[t]] : 0;
+      a1[t] = valid[t] ? rpA[i[t] + 1] : 0;
+      nl[t] = 0;
+    }
+    // the non-empty lists of each row, compacted into the group's slots in
+    // A's row order (the bin guarantees at most G of them per row)
+    int chunks = 0;
+#pragma unroll
+    for (int t = 0; t < R; ++t) chunks = max(chunks, (a1[t] - a0[t] + G - 1) / G);
+    chunks = wave_max(chunks);
     for (int c = 0; c < chunks; ++c) {
-      const int a = a0 + c * G + l;
-      int b0 = 0, len = 0;
-      if (a < a1) {
-        const int k = ciA[a];
-        b0 = rpB[k];
-        len = rpB[k + 1] - b0;
-      }
-      const unsigned long long ne = __ballot(len > 0) & gm;
-      const int rank = nl + __popcll(ne & below);
-      if (len > 0 && rank < G) {  // rank < G holds for every row of the bin
-        const int slot = g0 + rank;
-        s_b0[slot] = b0;
-        s_len[slot] = len;
-        s_a[slot] = a;
-      }
-      nl += __popcll(ne);
-    }
-    __syncthreads();
-    int p = 0, e = 0;
-    T av = 0;
-    if (l < nl) {
-      p = s_b0[g0 + l];
-      e = p + s_len[g0 + l];
-      if (NUM) av = vA[s_a[g0 + l]];
-    }
-    int hc[kWin];
-    T hv[kWin];
+      int b0[R], len[R], k[R];
 #pragma unroll
-    for (int w = 0; w < kWin; ++w) {
-      const bool in = p + w < e;
-      hc[w] = in ? ciB[p + w] : INT32_MAX;
-      hv[w] = (NUM && in) ? vB[p + w] : T(0);
+      for (int t = 0; t < R; ++t) {
+        const int a = a0[t] + c * G + l;
+        k[t] = a < a1[t] ? ciA[a] : -1;
+      }
+#pragma unroll
+      for (int t = 0; t < R; ++t) {
+        b0[t] = 0;
+        len[t] = 0;
+        if (k[t] >= 0) {
+          b0[t] = rpB[k[t]];
+          len[t] = rpB[k[t] + 1] - b0[t];
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < R; ++t) {
+        const unsigned long long ne = __ballot(len[t] > 0) & gm;
+        const int rank = nl[t] + __popcll(ne & below);
+        if (len[t] > 0 && rank < G) {  // rank < G holds for every row of the bin
+          s_b0[t][g0 + rank] = b0[t];
+          s_len[t][g0 + rank] = len[t];
+          s_a[t][g0 + rank] = a0[t] + c * G + l;
+        }
+        nl[t] += __popcll(ne);
+      }
     }
-    const int c0 = (NUM && valid) ? rpC[i] : 0;
-    int steps = 0, oc = 0;
-    T ov = 0;
-    while (__ballot(hc[0] != INT32_MAX)) {  // uniform over the wave
-      const int m = group_min<G>(hc[0]);
-      const bool live = m != INT32_MAX;
-      const bool hit = live && hc[0] == m;
+    wave_sync_lds();
+    int p[R], e[R], c0[R];
+    T av[R];
+    int hc[R][kWin];
+    T hv[R][kWin];
+#pragma unroll
+    for (int t = 0; t < R; ++t) {
+      p[t] = 0;
+      e[t] = 0;
+      av[t] = 0;
+      if (l < nl[t]) {
+        p[t] = s_b0[t][g0 + l];
+        e[t] = p[t] + s_len[t][g0 + l];
+        if (NUM) av[t] = vA[s_a[t][g0 + l]];
+      }
+      c0[t] = (NUM && valid[t]) ? rpC[i[t]] : 0;
+#pragma unroll
+      for (int w = 0; w < kWin; ++w) {
+        const bool in = p[t] + w < e[t];
+        hc[t][w] = in ? ciB[p[t] + w] : INT32_MAX;
+        hv[t][w] = (NUM && in) ? vB[p[t] + w] : T(0);
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < R; ++t) {
+      int steps = 0, oc = 0;
+      T ov = 0;
+      while (__ballot(hc[t][0] != INT32_MAX)) {  // uniform over the wave
+        const int m = group_min<G>(hc[t][0]);
+        const bool live = m != INT32_MAX;
+        const bool hit = live && hc[t][0] == m;
+        if (NUM) {
+          const T sv = group_sum<G>(hit ? av[t] * hv[t][0] : T(0));
+          if (l == (steps & (G - 1))) {
+            oc = m;
+            ov = sv;
+          }
+          if (live && (steps & (G - 1)) == G - 1) {  // a full set of G entries
+            ciC[c0[t] + steps - (G - 1) + l] = oc;
+            vC[c0[t] + steps - (G - 1) + l] = ov;
+          }
+        }
+        steps += live;
+        if (hit) {
+#pragma unroll
+          for (int w = 0; w + 1 < kWin; ++w) {
+            hc[t][w] = hc[t][w + 1];
+            hv[t][w] = hv[t][w + 1];
+          }
+          ++p[t];
+          const bool in = p[t] + kWin - 1 < e[t];
+          hc[t][kWin - 1] = in ? ciB[p[t] + kWin - 1] : INT32_MAX;
+          hv[t][kWin - 1] = (NUM && in) ? vB[p[t] + kWin - 1] : T(0);
+        }
+      }
       if (NUM) {
-        const T sv = group_sum<G>(hit ? av * hv[0] : T(0));
-        if (l == (steps & (G - 1))) {
-          oc = m;
-          ov = sv;
+        const int rem = steps & (G - 1);
+        if (valid[t] && l < rem) {
+          ciC[c0[t] + steps - rem + l] = oc;
+          vC[c0[t] + steps - rem + l] = ov;
         }
-        if (live && (steps & (G - 1)) == G - 1) {  // a full set of G entries
-          ciC[c0 + steps - (G - 1) + l] = oc;
-          vC[c0 + steps - (G - 1) + l] = ov;
-        }
-      }
-      steps += live;
-      if (hit) {
-#pragma unroll
-        for (int w = 0; w + 1 < kWin; ++w) {
-          hc[w] = hc[w + 1];
-          hv[w] = hv[w + 1];
-        }
-        ++p;
-        const bool in = p + kWin - 1 < e;
-        hc[kWin - 1] = in ? ciB[p + kWin - 1] : INT32_MAX;
-        hv[kWin - 1] = (NUM && in) ? vB[p + kWin - 1] : T(0);
+      } else if (valid[t] && l == 0) {
+        counts[i[t]] = steps;
       }
     }
-    if (NUM) {
-      const int rem = steps & (G - 1);
-      if (valid && l < rem) {
-        ciC[c0 + steps - rem + l] = oc;
-        vC[c0 + steps - rem + l] = ov;
-      }
-    } else if (valid && l == 0) {
-      counts[i] = steps;
-    }
-    __syncthreads();  // the slots are rewritten by the next rows
+    wave_sync_lds();  // the slots are rewritten by the next rows
   }
 }
 
@@ -585,9 +625,11 @@ void merge_bin(int bin, int rows, const csrad_csr* A, const csrad_csr* B, const 
                const T* vB, const int32_t* rpC, int32_t* ciC, T* vC, const SpgemmWs& w,
                hipStream_t s) {
   if (rows == 0) return;
-  const unsigned g = persistent_grid(kThreads / G, rows);
-  hipLaunchKernelGGL((k_merge<T, G, NUM>), dim3(g), dim3(kThreads), 0, s, bin, w.list, w.bin_off,
-                     A->rowptr, A->colind, vA, B->rowptr, B->colind, vB, rpC, ciC, vC, w.counts);
+  constexpr int R = G <= 8 ? 4 : (G <= 16 ? 2 : 1);  // rows in flight per group
+  const unsigned g = persistent_grid(kThreads / G * R, rows);
+  hipLaunchKernelGGL((k_merge<T, G, NUM, R>), dim3(g), dim3(kThreads), 0, s, bin, w.list,
+                     w.bin_off, A->rowptr, A->colind, vA, B->rowptr, B->colind, vB, rpC, ciC, vC,
+                     w.counts);
 }
 
 // bins: host copy of the class boundaries, or null (every class is then

@@ -118,8 +118,55 @@ __global__ __launch_bounds__(256) void k_sym_probe(int n, const int32_t* __restr
 // written in order.  The transpose's pattern is the pattern itself, so
 // rowptrT and colindT are copied on the way.  Clears *sym when some entry
 // has no mirror (the general path then rewrites all three outputs).  8
-// lanes per row.
-__global__ __launch_bounds__(256) void k_sym_perm(int n, const int32_t* __restrict__ rowptr,
+// lanes per row.  The lookup reads the first kMirrorWin columns of row j
+// with independent loads (one round of memory latency instead of a chain of
+// binary-search steps) and searches the rest of longer rows.
+constexpr int kMirrorWin = 8;
+
+// Unaligned 16- and 8-byte vectors of int32 (global loads need only 4-byte
+// alignment on this target).
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+typedef int i32x2 __attribute__((ext_vector_type(2)));
+typedef i32x4 i32x4_u __attribute__((aligned(4)));
+typedef i32x2 i32x2_u __attribute__((aligned(4)));
+
+__device__ __forceinline__ int mirror_pos_win(const int32_t* __restrict__ rowptr,
+                                              const int32_t* __restrict__ colind, int nnz, int j,
+                                              int i) {
+  const i32x2 ab = *reinterpret_cast<const i32x2_u*>(rowptr + j);  // rowptr[j], rowptr[j+1]
+  const int a = ab.x, b = ab.y;
+  int v[kMirrorWin];
+  if (a + kMirrorWin <= nnz) {
+    // two 16-byte loads cover the first 8 columns of row j (entries past
+    // the row's end are masked)
+    const i32x4 lo = *reinterpret_cast<const i32x4_u*>(colind + a);
+    const i32x4 hi = *reinterpret_cast<const i32x4_u*>(colind + a + 4);
+    v[0] = lo.x; v[1] = lo.y; v[2] = lo.z; v[3] = lo.w;
+    v[4] = hi.x; v[5] = hi.y; v[6] = hi.z; v[7] = hi.w;
+#pragma unroll
+    for (int u = 0; u < kMirrorWin; ++u) v[u] = a + u < b ? v[u] : -1;
+  } else {
+#pragma unroll
+    for (int u = 0; u < kMirrorWin; ++u) v[u] = a + u < b ? colind[a + u] : -1;
+  }
+  int pos = -1;
+#pragma unroll
+  for (int u = 0; u < kMirrorWin; ++u)
+    if (v[u] == i) pos = a + u;
+  if (pos < 0 && b - a > kMirrorWin && v[kMirrorWin - 1] < i) {
+    int lo = a + kMirrorWin, hi = b;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (colind[mid] < i) lo = mid + 1;
+      else hi = mid;
+    }
+    if (lo < b && colind[lo] == i) pos = lo;
+  }
+  return pos;
+}
+
+__global__ __launch_bounds__(256) void k_sym_perm(int n, int nnz,
+                                                  const int32_t* __restrict__ rowptr,
                                                   const int32_t* __restrict__ colind,
                                                   int32_t* __restrict__ rowptrT,
                                                   int32_t* __restrict__ colindT,
@@ -134,7 +181,7 @@ __global__ __launch_bounds__(256) void k_sym_perm(int n, const int32_t* __restri
   }
   for (int e = e0 + threadIdx.x % 8; e < e1; e += 8) {
     const int c = colind[e];
-    const int pos = mirror_pos(rowptr, colind, c, i);
+    const int pos = mirror_pos_win(rowptr, colind, nnz, c, i);
     if (pos < 0) {
       *sym = 0;
       return;
@@ -530,7 +577,7 @@ int transpose_pattern(int m, int n, int nnz, const int32_t* rowptr, const int32_
   }
   if (m == n && nnz > 0) {
     hipLaunchKernelGGL(k_sym_probe, dim3(1), dim3(256), 0, s, m, rowptr, colind, w.sym, w.mono);
-    hipLaunchKernelGGL(k_sym_perm, dim3((m + 31) / 32), dim3(256), 0, s, m, rowptr, colind,
+    hipLaunchKernelGGL(k_sym_perm, dim3((m + 31) / 32), dim3(256), 0, s, m, nnz, rowptr, colind,
                        rowptrT, colindT, perm, w.sym);
   }
   if (nnz > 0) {

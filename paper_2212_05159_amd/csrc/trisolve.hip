@@ -38,45 +38,79 @@ __device__ __forceinline__ bool dep_side(int lower, int row, int col) {
 }
 
 constexpr int kUnset = INT32_MAX;
+constexpr int kMaxPassBlocks = 4096;  // grid cap of the prep and pull passes
 
 // Step 1: dependency counts, the diagonal check, and level 0 (rows without
-// dependencies); flag[i] marks the level-0 rows for compaction.
+// dependencies), counted per block into part.
+// Rows counted per block go to part[blockIdx.x] (summed by the level step
+// in a fixed order: no contended atomics on one address).
+__device__ __forceinline__ void block_count_to(int cnt, int32_t* __restrict__ part) {
+  __shared__ int s_cnt;
+  if (threadIdx.x == 0) s_cnt = 0;
+  __syncthreads();
+  for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o);
+  if (__lane_id() == 0 && cnt) atomicAdd(&s_cnt, cnt);
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = s_cnt;
+}
+
+// Sum of part[0 .. np) by one block (fixed order per thread, then LDS).
+__device__ __forceinline__ int sum_parts(const int32_t* __restrict__ part, int np) {
+  __shared__ int s_sum;
+  if (threadIdx.x == 0) s_sum = 0;
+  __syncthreads();
+  int c = 0;
+  for (int b = threadIdx.x; b < np; b += blockDim.x) c += part[b];
+  for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
+  if (__lane_id() == 0 && c) atomicAdd(&s_sum, c);
+  __syncthreads();
+  return s_sum;
+}
+
 __global__ __launch_bounds__(kThreads) void k_tri_prep(int n, int lower,
                                                        const int32_t* __restrict__ rp,
                                                        const int32_t* __restrict__ ci,
                                                        int32_t* __restrict__ indeg,
-                                                       int32_t* __restrict__ flag,
                                                        int32_t* __restrict__ level_of_row,
-                                                       int32_t* __restrict__ bad_row) {
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    int deps = 0;
-    bool diag = false;
-    for (int e = rp[i]; e < rp[i + 1]; ++e) {
-      const int j = ci[e];
-      deps += dep_side(lower, i, j);
-      diag |= (j == i);
+                                                       int32_t* __restrict__ state,
+                                                       int32_t* __restrict__ part) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  int cnt = 0;
+  for (long long base = (long long)blockIdx.x * blockDim.x; base < n; base += stride) {
+    const int i = (int)(base + threadIdx.x);
+    bool zero = false;
+    if (i < n) {
+      int deps = 0;
+      bool diag = false;
+      for (int e = rp[i]; e < rp[i + 1]; ++e) {
+        const int j = ci[e];
+        deps += dep_side(lower, i, j);
+        diag |= (j == i);
+      }
+      indeg[i] = deps;
+      level_of_row[i] = deps == 0 ? 0 : kUnset;
+      zero = deps == 0;
+      if (!diag) atomicMin(&state[1], i);
     }
-    indeg[i] = deps;
-    level_of_row[i] = deps == 0 ? 0 : kUnset;
-    flag[i] = deps == 0;
-    if (!diag) atomicMin(bad_row, i);
+    cnt += zero;
   }
+  block_count_to(cnt, part);
 }
 
-// front[pos[i]] = i for the flagged rows (pos = exclusive scan of flag).
-__global__ void k_tri_compact(int n, const int32_t* __restrict__ flag,
-                              const int32_t* __restrict__ pos, int32_t* __restrict__ front) {
+// The frontier (the rows on level state[2]) into the buffer Kahn's
+// algorithm reads it from (state[3] ? fb : fa): flag, then compaction at
+// the scanned positions.
+__global__ void k_tri_flag_level(int n, const int32_t* __restrict__ level_of_row,
+                                 const int32_t* __restrict__ state, int32_t* __restrict__ flag) {
+  const int L = state[2];
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
-    if (flag[i]) front[pos[i]] = i;
+    flag[i] = level_of_row[i] == L;
 }
 
-// Compaction after a pull round: into the buffer not holding the frontier
-// (state[3] ? fa : fb); nothing once state[4] is set.
-__global__ void k_tri_compact_next(int n, const int32_t* __restrict__ flag,
-                                   const int32_t* __restrict__ pos, int32_t* __restrict__ fa,
-                                   int32_t* __restrict__ fb, const int32_t* __restrict__ state) {
-  if (state[4]) return;
-  int32_t* front = state[3] ? fa : fb;
+__global__ void k_tri_compact_cur(int n, const int32_t* __restrict__ flag,
+                                  const int32_t* __restrict__ pos, int32_t* __restrict__ fa,
+                                  int32_t* __restrict__ fb, const int32_t* __restrict__ state) {
+  int32_t* front = state[3] ? fb : fa;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
     if (flag[i]) front[pos[i]] = i;
 }
@@ -158,21 +192,25 @@ __global__ __launch_bounds__(kKahnThreads) void k_tri_kahn_small(
 // dependencies sit on levels <= L; otherwise indeg gets the number of
 // dependencies still above L (unplaced, or on level L + 1 from this same
 // pass: either way above L), which is what Kahn's algorithm needs next.
-// The frontier's level L is state[2]; nothing is done once state[4] is set
-// (the scan, compaction and level step after it are gated on it too), so
-// rounds may be launched before the host knows whether they are needed.
+// The rows placed are counted per block into part.  The frontier's level L is
+// state[2]; nothing is done once state[4] is set (the level step after it
+// is gated on it too), so rounds may be launched before the host knows
+// whether they are needed.
 __global__ __launch_bounds__(kThreads) void k_tri_pull(int n, int lower,
                                                        const int32_t* __restrict__ state,
                                                        const int32_t* __restrict__ rp,
                                                        const int32_t* __restrict__ ci,
                                                        int32_t* __restrict__ level_of_row,
                                                        int32_t* __restrict__ indeg,
-                                                       int32_t* __restrict__ flag) {
-  if (state[4]) return;
+                                                       int32_t* __restrict__ part) {
+  if (state[4]) return;  // uniform over the grid
   const int L = state[2];
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    int f = 0;
-    if (level_of_row[i] == kUnset) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  int cnt = 0;
+  for (long long base = (long long)blockIdx.x * blockDim.x; base < n; base += stride) {
+    const int i = (int)(base + threadIdx.x);
+    bool placed = false;
+    if (i < n && level_of_row[i] == kUnset) {
       int cnt = 0;
       for (int e = rp[i]; e < rp[i + 1]; ++e) {
         const int j = ci[e];
@@ -180,34 +218,36 @@ __global__ __launch_bounds__(kThreads) void k_tri_pull(int n, int lower,
       }
       if (cnt == 0) {
         level_of_row[i] = L + 1;
-        f = 1;
+        placed = true;
       } else {
         indeg[i] = cnt;
       }
     }
-    flag[i] = f;
+    cnt += placed;
   }
+  block_count_to(cnt, part);
 }
 
-// state[0] = the compacted frontier size, [2] += 1, [3] ^= 1, [4] = no
-// further level (empty frontier, or n levels placed).  Does nothing once
-// [4] is set.
-__global__ void k_tri_next_level(int n, const long long* __restrict__ total,
+// After a pull pass: state[0] = rows placed (the sum of the np block
+// counts), [2] += 1, [4] = no further level (nothing placed, or n
+// levels).  Nothing once [4] is set.
+__global__ void k_tri_next_level(int n, const int32_t* __restrict__ part, int np,
                                  int32_t* __restrict__ state) {
-  if (threadIdx.x == 0 && blockIdx.x == 0 && state[4] == 0) {
-    const int t = (int32_t)*total;
+  if (state[4]) return;
+  const int t = sum_parts(part, np);
+  if (threadIdx.x == 0) {
     state[0] = t;
     state[2] += 1;
-    state[3] ^= 1;
     state[4] = t == 0 || state[2] >= n;
   }
 }
 
-// state[0] = the level-0 frontier size, [2] = 0, [3] = 0, [4] = no level.
-__global__ void k_tri_first_level(const long long* __restrict__ total,
+// After the prep pass: state[0] = the level-0 frontier size, [2] = 0,
+// [3] = 0, [4] = no level.
+__global__ void k_tri_first_level(const int32_t* __restrict__ part, int np,
                                   int32_t* __restrict__ state) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    const int t = (int32_t)*total;
+  const int t = sum_parts(part, np);
+  if (threadIdx.x == 0) {
     state[0] = t;
     state[2] = 0;
     state[3] = 0;
@@ -410,6 +450,7 @@ struct TriWs {
   int32_t* fa;
   int32_t* fb;
   int32_t* counters;  // [0] frontier size, [1] bad row, [2] level, [3] buffer, [4] done
+  int32_t* part;      // per-block row counts of the prep and pull passes
   int32_t* flag;
   int32_t* pos;
   void* sws;
@@ -429,6 +470,7 @@ TriWs carve_tri(Carver& cv, int n) {
   w.fa = cv.take<int32_t>((size_t)n);
   w.fb = cv.take<int32_t>((size_t)n);
   w.counters = cv.take<int32_t>(8);
+  w.part = cv.take<int32_t>(kMaxPassBlocks);
   w.flag = cv.take<int32_t>((size_t)n + 1);
   w.pos = cv.take<int32_t>((size_t)n + 1);
   w.sws_bytes = scan_workspace(n);
@@ -498,22 +540,19 @@ extern "C" int csr_trisolve_analyze(const csrad_csr* Tm, int32_t lower, const cs
   }
   CSRAD_TRY(fill_i32(w.counters, 8, 0, s));
   CSRAD_TRY(fill_i32(w.counters + 1, 1, INT32_MAX, s));
-  const unsigned gn = (unsigned)((n + kThreads - 1) / kThreads < 4096 ? (n + kThreads - 1) / kThreads
-                                                                     : 4096);
+  const unsigned gn = (unsigned)((n + kThreads - 1) / kThreads < kMaxPassBlocks
+                                     ? (n + kThreads - 1) / kThreads
+                                     : kMaxPassBlocks);
   const int lw = lower ? 1 : 0;
   hipLaunchKernelGGL(k_tri_prep, dim3(gn), dim3(kThreads), 0, s, n, lw, Tm->rowptr, Tm->colind,
-                     w.indeg, w.flag, level_of_row, w.counters + 1);
-  CSRAD_TRY(scan_exclusive(w.flag, w.pos, n, w.total, w.sws, w.sws_bytes, s));
-  hipLaunchKernelGGL(k_tri_compact, dim3(gn), dim3(kThreads), 0, s, n, w.flag, w.pos, w.fa);
-  hipLaunchKernelGGL(k_tri_first_level, dim3(1), dim3(64), 0, s, w.total, w.counters);
-  // One wide-level round: a pull pass, its compaction, the level step.
+                     w.indeg, level_of_row, w.counters, w.part);
+  hipLaunchKernelGGL(k_tri_first_level, dim3(1), dim3(256), 0, s, w.part, (int)gn, w.counters);
+  // One wide-level round: a pull pass and the level step (no compaction:
+  // the frontier is materialised only when Kahn's algorithm takes over).
   auto pull_round = [&]() -> int {
     hipLaunchKernelGGL(k_tri_pull, dim3(gn), dim3(kThreads), 0, s, n, lw, w.counters, Tm->rowptr,
-                       Tm->colind, level_of_row, w.indeg, w.flag);
-    CSRAD_TRY(scan_exclusive(w.flag, w.pos, n, w.total, w.sws, w.sws_bytes, s, w.counters + 4));
-    hipLaunchKernelGGL(k_tri_compact_next, dim3(gn), dim3(kThreads), 0, s, n, w.flag, w.pos, w.fa,
-                       w.fb, w.counters);
-    hipLaunchKernelGGL(k_tri_next_level, dim3(1), dim3(64), 0, s, n, w.total, w.counters);
+                       Tm->colind, level_of_row, w.indeg, w.part);
+    hipLaunchKernelGGL(k_tri_next_level, dim3(1), dim3(256), 0, s, n, w.part, (int)gn, w.counters);
     return launch_status();
   };
   // Coloured orderings have a few wide levels: run kSpecRounds rounds
@@ -528,16 +567,26 @@ extern "C" int csr_trisolve_analyze(const csrad_csr* Tm, int32_t lower, const cs
   };
   CSRAD_TRY(read_state());
   if (host[1] != INT32_MAX) return CSRAD_ESINGULAR;
+  bool have_front = false;  // the frontier list is in the Kahn buffer
   while (host[0] > 0 && host[2] < n) {
     if (host[0] <= kKahnSmall) {
-      // narrow levels inside one workgroup, until the frontier is empty or wide
+      if (!have_front) {
+        hipLaunchKernelGGL(k_tri_flag_level, dim3(gn), dim3(kThreads), 0, s, n, level_of_row,
+                           w.counters, w.flag);
+        CSRAD_TRY(scan_exclusive(w.flag, w.pos, n, w.total, w.sws, w.sws_bytes, s));
+        hipLaunchKernelGGL(k_tri_compact_cur, dim3(gn), dim3(kThreads), 0, s, n, w.flag, w.pos,
+                           w.fa, w.fb, w.counters);
+      }
+      // narrow levels inside one workgroup, until the frontier is empty or
+      // wide (it then sits in the buffer Kahn's algorithm left it in)
       hipLaunchKernelGGL(k_tri_kahn_small, dim3(1), dim3(kKahnThreads), 0, s, n, lw, Tt->rowptr,
                          Tt->colind, w.indeg, w.fa, w.fb, w.counters, level_of_row);
       CSRAD_TRY(launch_status());
+      have_front = true;
     } else {
-      // a wide level: one pass over the unplaced rows, then compaction into
-      // the other frontier buffer
+      // a wide level: one pass over the unplaced rows
       CSRAD_TRY(pull_round());
+      have_front = false;
     }
     CSRAD_TRY(read_state());
   }

@@ -106,6 +106,15 @@ def test_batched_ops_match_oracle(blocks, dtype, k, vname):
     _, gvm1 = Bt.spmm_bwd(X, G, need_B=False)
     assert torch.equal(gx1, gx) and torch.equal(gv1, gv)
     assert torch.equal(gX1, gX) and torch.equal(gvm1, gvm)
+    # split backward (A^T products over A^T's plan, value gradients row-wise
+    # over A's plan): the same products and sums, so the same bits
+    Bt.bwd_split = {"spmv": True, "spmm": True}
+    gx2, gv2 = Bt.spmv_bwd(x, gy)
+    gX2, gvm2 = Bt.spmm_bwd(X, G)
+    _, gv3 = Bt.spmv_bwd(x, gy, need_x=False)
+    _, gvm3 = Bt.spmm_bwd(X, G, need_B=False)
+    assert torch.equal(gx2, gx) and torch.equal(gv2, gv) and torch.equal(gv3, gv)
+    assert torch.equal(gX2, gX) and torch.equal(gvm2, gvm) and torch.equal(gvm3, gvm)
 
 
 def test_block_result_independent_of_batch(blocks):
@@ -225,6 +234,7 @@ def test_autotuned_variants_match_oracle(blocks):
     Bt = bt.Batch(blocks, dtype=torch.float32)
     res = Bt.autotune(k=64, reps=1)
     assert set(res) == {"spmv", "spmv_t", "spmm", "spmm_t"}
+    assert set(Bt.bwd_times) == {"spmv", "spmm"}
     classes = set(Bt.block_classes())
     for fam, per in res.items():
         assert set(per) == classes
