@@ -20,13 +20,15 @@ kernel (the fused SpMM backward) is also timed on its own with HIP events
 on the launch stream for the roofline entry.
 
 Second part (the "pcg" entry): preconditioned CG to ||r||/||b|| <= 1e-6 on
-held-out 2D anisotropic Q1 diffusion systems of 1024^2 (2x2 four-coloured
-order, float32 values, float64 vectors), wall time per system with HIP
-events, for the learned factor L L^T (the network briefly trained here on
-256^2 systems), the untrained network (the Gauss-Seidel factor), Jacobi
-and plain CG.  Each timed solve includes building its preconditioner
-(network inference, values of L^T, 1/diag); the level sets of L's pattern
-are shared by all systems and analysed once beforehand.
+64 held-out 2D anisotropic Q1 diffusion systems of 1024^2 (2x2
+four-coloured order, float32 values, float64 vectors), wall time per
+system with HIP events, for the learned preconditioner M = L L^T in the
+paper's form (L L^T approximates A^-1; the network trained here on 4096
+systems of 256^2), the same network untrained, the factor reading of M
+(L L^T approximates A, two triangular solves) trained and untrained,
+Jacobi and plain CG.  Each timed solve includes building its
+preconditioner (network inference, values of L^T, 1/diag); the level sets
+of L's pattern are shared by all systems and analysed once beforehand.
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -63,9 +65,7 @@ def _geometric_block(b):
 
 def geometric_blocks(nblocks):
     """The first `nblocks` host blocks of the batched workload, built by a
-    pool of threads (the k-NN queries and sorts release the GIL).  A pool of
-    worker processes was as fast to build them but left this process with
-    millisecond host stalls in the timed steps afterwards."""
+    pool of threads (the k-NN queries and sorts release the GIL)."""
     import concurrent.futures as cf
 
     t0 = time.perf_counter()
@@ -161,6 +161,7 @@ def batched_section(blocks, gen_s, reps=5, skew=None):
     untuned = table(batched_ops(B))
     t1 = time.perf_counter()
     tune = B.autotune(k=k, reps=3)
+    tri_modes = LB.autotune_trisolve(L, True, reps=3)
     tune_s = time.perf_counter() - t1
     tuned = table(batched_ops(B))
     # the library's per-matrix kernels over the whole concatenation
@@ -215,6 +216,8 @@ def batched_section(blocks, gen_s, reps=5, skew=None):
         "per_block_ms": round(per_ms, 4),
         "speedup_vs_per_block": round(per_ms / tot(tuned), 2),
         "launches_per_step": 6 + sum(int(v["split"]) for v in B.bwd_times.values()),
+        "trisolve_modes_ms": {m: round(v, 4) for m, v in tri_modes.items()},
+        "trisolve_mode": LB.tri_mode,
         "backward_split": {op: {k2: (round(v2, 4) if isinstance(v2, float) else v2)
                                 for k2, v2 in v.items()} for op, v in B.bwd_times.items()},
         "variants": {fam: {f"{c[0]}/{'uneven' if c[1] else 'even'}": v[0] for c, v in per_cls.items()}
@@ -527,7 +530,7 @@ def measured_traffic(kernel, plan):
 
 
 # ----------------------------------------------------------------------
-# PCG time to 1e-6: learned factor vs Jacobi
+# PCG time to 1e-6: learned preconditioner vs Jacobi
 # ----------------------------------------------------------------------
 def pcg_section(n_eval, n_train, train_steps, systems):
     import torch
@@ -564,20 +567,23 @@ def pcg_section(n_eval, n_train, train_steps, systems):
     torch.cuda.synchronize()
     analysis_ms = (time.perf_counter() - t0) * 1e3
     untrained_inv = learned.MPNN(seed=1, form="fsai")
-    methods = ("learned", "untrained", "fsai", "fsai_untrained", "jacobi", "cg")
+    # "learned": the paper's form (Section 4.3: M = L L^T approximates A^-1,
+    # applied by two sparse products); "factor_*": the factor reading (M
+    # approximates A, two level-scheduled triangular solves)
+    methods = ("learned", "untrained", "factor_learned", "factor_untrained", "jacobi", "cg")
     maxit = 40000
 
     def solve(key, A, b, cap=maxit):
-        if key in ("learned", "untrained"):
-            net = model if key == "learned" else untrained
+        if key in ("factor_learned", "factor_untrained"):
+            net = model if key == "factor_learned" else untrained
             with torch.no_grad():
                 L = sp.CsrTensor(fam.Lpat, net(A, fam.Lpat))
             # the factor step (a dozen launches) runs faster from the stream
             # than replayed from a captured graph; the short Jacobi and plain
             # steps run faster from the graph: each method runs its faster way
             return pcgmod.pcg(A, b, "factor", L=L, tol=1e-6, maxit=cap, chunk=50, graph=False)
-        if key in ("fsai", "fsai_untrained"):
-            net = model_inv if key == "fsai" else untrained_inv
+        if key in ("learned", "untrained"):
+            net = model_inv if key == "learned" else untrained_inv
             with torch.no_grad():
                 L = sp.CsrTensor(fam.Lpat, net(A, fam.Lpat))
             return pcgmod.pcg(A, b, "fsai", L=L, tol=1e-6, maxit=cap, chunk=50, graph=False)
@@ -618,28 +624,29 @@ def pcg_section(n_eval, n_train, train_steps, systems):
         "systems": systems, "tol": 1e-6,
         "median_ms": med,
         "median_iterations": {k: float(np.median(v)) for k, v in iters.items()},
-        "methods": {"learned": "trained network, factor form (M = L L^T ~ A, two level-scheduled "
+        "methods": {"factor_learned": "trained network, factor form (M = L L^T ~ A, two level-scheduled "
                                "triangular solves)",
-                    "untrained": "the same network untrained: symmetric Gauss-Seidel factor",
-                    "fsai": "trained network, the inverse form of Section 4.3 (M = L L^T ~ A^-1, "
+                    "factor_untrained": "the same network untrained: symmetric Gauss-Seidel factor",
+                    "learned": "trained network, the inverse form of Section 4.3 (M = L L^T ~ A^-1, "
                             "two sparse products)",
-                    "fsai_untrained": "the inverse-form network untrained: first-order inverse "
+                    "untrained": "the inverse-form network untrained: first-order inverse "
                                       "factor D^-1 (D - A_L) D^-1/2",
                     "jacobi": "Jacobi-PCG", "cg": "plain CG"},
         "learned_speedup_vs_jacobi": round(med["jacobi"] / med["learned"], 3),
-        "fsai_speedup_vs_jacobi": round(med["jacobi"] / med["fsai"], 3),
-        "fsai_training_gain_iterations": round(float(np.median(iters["fsai_untrained"])) /
-                                               float(np.median(iters["fsai"])), 3),
-        "factor_training_gain_iterations": round(float(np.median(iters["untrained"])) /
-                                                 float(np.median(iters["learned"])), 3),
+        "learned_speedup_vs_untrained": round(med["untrained"] / med["learned"], 3),
+        "training_gain_iterations": round(float(np.median(iters["untrained"])) /
+                                          float(np.median(iters["learned"])), 3),
+        "factor_learned_speedup_vs_jacobi": round(med["jacobi"] / med["factor_learned"], 3),
+        "factor_training_gain_iterations": round(float(np.median(iters["factor_untrained"])) /
+                                                 float(np.median(iters["factor_learned"])), 3),
         "fallbacks": fallbacks,
         "level_analysis_ms": round(analysis_ms, 3),
-        "train": {"systems": train_steps, "grid": n_train, "seconds": round(train_s, 2),
-                  "lr": 3e-3, "pcg_steps_in_loss": 16,
+        "train": {"systems": train_steps, "grid": n_train, "lr": 3e-3, "pcg_steps_in_loss": 16,
                   "selection": "best mean PCG iterations on 4 held-out systems of the training grid",
-                  "validation_iterations": model.selected_score,
-                  "fsai_seconds": round(train_inv_s, 2),
-                  "fsai_validation_iterations": model_inv.selected_score},
+                  "seconds": round(train_inv_s, 2),
+                  "validation_iterations": model_inv.selected_score,
+                  "factor_seconds": round(train_s, 2),
+                  "factor_validation_iterations": model.selected_score},
     }
 
 

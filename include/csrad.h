@@ -485,6 +485,25 @@ int csr_batch_trisolve_bwd(const csrad_csr *T, const csrad_csr *Tt,
                            const void *levels_work, size_t levels_bytes,
                            const void *x, const void *gx, void *gb,
                            void *gvals, void *stream);
+/* Level-synchronous batched solves: ONE cooperative launch over the whole
+ * block-diagonal T (every workgroup resident at once; the levels of the
+ * batch, from csr_trisolve_analyze on T, are the unions of the blocks'
+ * levels).  Each level's rows are shared by all workgroups, one row per
+ * thread, with a grid barrier between levels, so large blocks use the whole
+ * chip instead of one workgroup each.  csr_batch_trisolve_levels_fwd:
+ * x = T^{-1} b.  csr_batch_trisolve_levels_bwd: gb = T^{-T} gx over Tt/perm
+ * with the levels in reverse, then gvals[(i,j)] = -gb_i x_j on pat(T)
+ * (gvals may be NULL).  level_ptr (nlevels+1) and level_rows are device
+ * arrays.  Returns CSRAD_EHIP if the runtime refuses the cooperative launch
+ * (the chip cannot hold the grid). */
+int csr_batch_trisolve_levels_fwd(const csrad_csr *T, int32_t nlevels,
+                                  const int32_t *level_ptr, const int32_t *level_rows,
+                                  const void *b, void *x, void *stream);
+int csr_batch_trisolve_levels_bwd(const csrad_csr *T, const csrad_csr *Tt,
+                                  const int32_t *perm, int32_t nlevels,
+                                  const int32_t *level_ptr, const int32_t *level_rows,
+                                  const void *x, const void *gx, void *gb, void *gvals,
+                                  void *stream);
 /* Incomplete Cholesky IC(0) per block (the factor the batched solves
  * take; Saad, Section 10.3): Alow is tril(A) with its values (diagonal
  * stored and last in every row); Lvals (nnz(Alow)) receives L on the same

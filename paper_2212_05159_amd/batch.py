@@ -70,6 +70,11 @@ class Batch:
         # and a row-wise value-gradient pass over A's plan (else one fused
         # pass over A^T); set by autotune
         self.bwd_split = {"spmv": False, "spmm": False}
+        # triangular solves: "blocks" (a workgroup per block, levels in
+        # order inside it) or "levels" (one cooperative launch, all
+        # workgroups on each level of the batch, grid barriers between);
+        # set by autotune_trisolve
+        self.tri_mode = "blocks"
         self._plans = {}
         self._tri = {}
         rows = np.diff(self.block_rowptr).astype(np.int64)
@@ -202,8 +207,12 @@ class Batch:
         sp._check_square(PT, "batch trisolve")
         sp._check_vals(PT, T.vals)
         sp._check_dense(b, T.vals, (PT.nrows,), "b")
-        plan, nl, lr, lv = self._tri_setup(PT, lower)
         x = torch.empty_like(b)
+        if self.tri_mode == "levels":
+            nl, _, lp, lr, _ = PT.levels(lower)
+            capi.csr_batch_trisolve_levels_fwd(PT.desc(T.vals), nl, lp, lr, b, x)
+            return x
+        plan, nl, lr, lv = self._tri_setup(PT, lower)
         capi.csr_batch_trisolve_fwd(PT.desc(T.vals), plan.plan, nl, lr, lv, b, x)
         return x
 
@@ -213,10 +222,15 @@ class Batch:
         sp._check_vals(PT, T.vals)
         sp._check_dense(x, T.vals, (PT.nrows,), "x")
         sp._check_dense(gx, T.vals, (PT.nrows,), "gx")
-        plan, nl, lr, lv = self._tri_setup(PT, lower)
         Pt, perm = PT.transpose()
         gb = torch.empty_like(gx)
         gv = torch.empty(PT.nnz, dtype=T.vals.dtype, device=T.vals.device) if need_vals else None
+        if self.tri_mode == "levels":
+            nl, _, lp, lr, _ = PT.levels(lower)
+            capi.csr_batch_trisolve_levels_bwd(PT.desc(T.vals), Pt.desc(dtype=T.vals.dtype), perm,
+                                               nl, lp, lr, x, gx, gb, gv)
+            return gb, gv
+        plan, nl, lr, lv = self._tri_setup(PT, lower)
         capi.csr_batch_trisolve_bwd(PT.desc(T.vals), Pt.desc(dtype=T.vals.dtype), perm, plan.plan,
                                     nl, lr, lv, x, gx, gb, gv)
         return gb, gv
@@ -306,6 +320,26 @@ class Batch:
             self.bwd_times[op] = {"fused_ms": ms[False], "split_ms": ms[True],
                                   "split": self.bwd_split[op]}
         return out
+
+
+    def autotune_trisolve(self, T, lower=True, reps=3, seed=0):
+        """Times the two batched solve modes (forward + adjoint) with the
+        factor T on this batch's blocks and keeps the faster; returns
+        {mode: ms}."""
+        dev = T.vals.device
+        g = torch.Generator(device=dev)
+        g.manual_seed(seed)
+        n = T.pattern.nrows
+        b = torch.randn(n, generator=g, device=dev, dtype=T.vals.dtype)
+        gx = torch.randn(n, generator=g, device=dev, dtype=T.vals.dtype)
+        ms = {}
+        for mode in ("blocks", "levels"):
+            self.tri_mode = mode
+            x = self.trisolve(T, b, lower)
+            ms[mode] = _time(lambda: (self.trisolve(T, b, lower), self.trisolve_bwd(T, x, gx, lower)),
+                             reps)
+        self.tri_mode = min(ms, key=ms.get)
+        return ms
 
 
 def _time(fn, reps):

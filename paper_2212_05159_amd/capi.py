@@ -119,6 +119,8 @@ _SIGS = {
     "csr_batch_sddmv": (C.c_int, [C.c_void_p] * 6),
     "csr_batch_sddmm": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_int64,
                                   C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]),
+    "csr_batch_trisolve_levels_fwd": (C.c_int, [C.c_void_p, C.c_int32] + [C.c_void_p] * 5),
+    "csr_batch_trisolve_levels_bwd": (C.c_int, [C.c_void_p] * 3 + [C.c_int32] + [C.c_void_p] * 7),
     "csr_batch_levels_workspace": (C.c_int, [C.c_int32, C.c_int32, C.POINTER(C.c_size_t)]),
     "csr_batch_levels": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
                                    C.c_size_t, C.c_void_p]),
@@ -518,6 +520,19 @@ def csr_batch_sddmm(A, plan, k, B, ldb, gC, ldgc, gvals):
     _check("csr_batch_sddmm",
            load().csr_batch_sddmm(C.byref(A), C.byref(plan), int(k), _ptr(B), int(ldb), _ptr(gC),
                                   int(ldgc), _ptr(gvals), _stream()))
+
+
+def csr_batch_trisolve_levels_fwd(T, nlevels, level_ptr, level_rows, b, x):
+    _check("csr_batch_trisolve_levels_fwd",
+           load().csr_batch_trisolve_levels_fwd(C.byref(T), int(nlevels), _ptr(level_ptr),
+                                                _ptr(level_rows), _ptr(b), _ptr(x), _stream()))
+
+
+def csr_batch_trisolve_levels_bwd(T, Tt, perm, nlevels, level_ptr, level_rows, x, gx, gb, gvals):
+    _check("csr_batch_trisolve_levels_bwd",
+           load().csr_batch_trisolve_levels_bwd(C.byref(T), C.byref(Tt), _ptr(perm), int(nlevels),
+                                                _ptr(level_ptr), _ptr(level_rows), _ptr(x),
+                                                _ptr(gx), _ptr(gb), _ptr(gvals), _stream()))
 
 
 def csr_batch_spmm_fwd(A, plan, k, B, ldb, Cout, ldc):

@@ -30,6 +30,8 @@
 // own is empty.  The last workgroup to leave resets the counters, so the
 // next launch on the stream starts from zero without a memset node
 // (launches that share a plan must be ordered on one stream).
+#include <hip/hip_cooperative_groups.h>
+
 #include <algorithm>
 #include <vector>
 
@@ -924,6 +926,37 @@ __global__ __launch_bounds__(kTriThreads) void k_batch_tri(
   });
 }
 
+// Level-synchronous variant: ONE cooperative launch over the whole
+// block-diagonal matrix.  Level l of the batch is the union of level l of
+// every block; all resident workgroups share each level's rows (one row
+// per thread, grid-stride), and a grid barrier separates levels.  With ADJ
+// the levels run in reverse over T^T (values through perm) and, after a
+// last barrier, gvals[(i,j)] = -w_i x_j is written row-wise over T.
+template <typename T, bool ADJ>
+__global__ __launch_bounds__(kThreads) void k_batch_tri_coop(
+    int nlevels, const int32_t* __restrict__ level_ptr, const int32_t* __restrict__ rows,
+    const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+    const int32_t* __restrict__ perm, const T* __restrict__ vals, const T* __restrict__ b,
+    T* __restrict__ x, const T* __restrict__ xf, int n, const int32_t* __restrict__ rpA,
+    const int32_t* __restrict__ ciA, T* __restrict__ gv) {
+  cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int nth = gridDim.x * blockDim.x;
+  for (int s = 0; s < nlevels; ++s) {
+    const int l = ADJ ? nlevels - 1 - s : s;
+    const int lo = level_ptr[l], hi = level_ptr[l + 1];
+    for (int q = lo + tid; q < hi; q += nth) tri_row<T, T, ADJ>(rows[q], rp, ci, perm, vals, b, x);
+    if (s + 1 < nlevels) grid.sync();  // uniform over the grid
+  }
+  if (ADJ && gv) {
+    grid.sync();
+    for (int i = tid; i < n; i += nth) {
+      const T wi = x[i];
+      for (int e = rpA[i]; e < rpA[i + 1]; ++e) gv[e] = -wi * xf[ciA[e]];
+    }
+  }
+}
+
 // IC(0) on the lower pattern (diagonal last in every row): for the
 // entries (i, j) of row i in column order,
 //   L_ij = (A_ij - sum_{k<j} L_ik L_jk) / L_jj,   L_ii = sqrt(A_ii - sum_{k<i} L_ik^2),
@@ -1555,4 +1588,79 @@ extern "C" int csr_batch_sddmm(const csrad_csr* A, const csrad_batch_plan* plan,
                        static_cast<const double*>(B), ldb, static_cast<const double*>(gC), ldgc,
                        static_cast<double*>(gvals));
   return launch_status();
+}
+
+namespace {
+// Cooperative launch of k_batch_tri_coop: every workgroup resident at once
+// (as many as the occupancy allows on every CU); the runtime refuses a grid
+// that cannot be co-resident, and the call then returns CSRAD_EHIP.
+template <typename T, bool ADJ>
+int tri_coop_launch(int nlevels, const int32_t* level_ptr, const int32_t* rows,
+                    const int32_t* rp, const int32_t* ci, const int32_t* perm, const T* vals,
+                    const T* b, T* x, const T* xf, int n, const int32_t* rpA, const int32_t* ciA,
+                    T* gv, hipStream_t s) {
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_tri_coop<T, ADJ>, kThreads,
+                                                   0) != hipSuccess ||
+      per_cu < 1)
+    return CSRAD_EHIP;
+  long long want = ((long long)n + kThreads - 1) / kThreads;
+  const long long cap = (long long)cus * per_cu;
+  if (want > cap) want = cap;
+  if (want < 1) want = 1;
+  void* args[] = {&nlevels, &level_ptr, &rows, &rp, &ci, &perm, &vals, &b, &x, &xf, &n, &rpA,
+                  &ciA, &gv};
+  if (hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_batch_tri_coop<T, ADJ>),
+                                 dim3((unsigned)want), dim3(kThreads), args, 0, s) != hipSuccess)
+    return CSRAD_EHIP;
+  return launch_status();
+}
+}  // namespace
+
+extern "C" int csr_batch_trisolve_levels_fwd(const csrad_csr* T, int32_t nlevels,
+                                             const int32_t* level_ptr, const int32_t* level_rows,
+                                             const void* b, void* x, void* stream) {
+  CSRAD_TRY(check_csr(T, true));
+  if (T->nrows != T->ncols || nlevels < 0) return CSRAD_EINVAL;
+  if (T->nrows == 0 || nlevels == 0) return CSRAD_OK;
+  if (!level_ptr || !level_rows || !b || !x) return CSRAD_EINVAL;
+  hipStream_t s = as_stream(stream);
+  if (T->dtype == CSRAD_F32)
+    return tri_coop_launch<float, false>(nlevels, level_ptr, level_rows, T->rowptr, T->colind,
+                                         nullptr, static_cast<const float*>(T->vals),
+                                         static_cast<const float*>(b), static_cast<float*>(x),
+                                         nullptr, T->nrows, nullptr, nullptr, nullptr, s);
+  return tri_coop_launch<double, false>(nlevels, level_ptr, level_rows, T->rowptr, T->colind,
+                                        nullptr, static_cast<const double*>(T->vals),
+                                        static_cast<const double*>(b), static_cast<double*>(x),
+                                        nullptr, T->nrows, nullptr, nullptr, nullptr, s);
+}
+
+extern "C" int csr_batch_trisolve_levels_bwd(const csrad_csr* T, const csrad_csr* Tt,
+                                             const int32_t* perm, int32_t nlevels,
+                                             const int32_t* level_ptr, const int32_t* level_rows,
+                                             const void* x, const void* gx, void* gb, void* gvals,
+                                             void* stream) {
+  CSRAD_TRY(check_csr(T, true));
+  if (!Tt) return CSRAD_EINVAL;
+  CSRAD_TRY(check_csr(Tt, false));
+  if (T->nrows != T->ncols || Tt->nrows != T->nrows || Tt->nnz != T->nnz || nlevels < 0)
+    return CSRAD_EINVAL;
+  if (T->nrows == 0 || nlevels == 0) return CSRAD_OK;
+  if (!level_ptr || !level_rows || !gx || !gb || (gvals && !x) || (T->nnz > 0 && !perm))
+    return CSRAD_EINVAL;
+  hipStream_t s = as_stream(stream);
+  if (T->dtype == CSRAD_F32)
+    return tri_coop_launch<float, true>(nlevels, level_ptr, level_rows, Tt->rowptr, Tt->colind,
+                                        perm, static_cast<const float*>(T->vals),
+                                        static_cast<const float*>(gx), static_cast<float*>(gb),
+                                        static_cast<const float*>(x), T->nrows, T->rowptr,
+                                        T->colind, static_cast<float*>(gvals), s);
+  return tri_coop_launch<double, true>(nlevels, level_ptr, level_rows, Tt->rowptr, Tt->colind,
+                                       perm, static_cast<const double*>(T->vals),
+                                       static_cast<const double*>(gx), static_cast<double*>(gb),
+                                       static_cast<const double*>(x), T->nrows, T->rowptr,
+                                       T->colind, static_cast<double*>(gvals), s);
 }

@@ -625,11 +625,27 @@ void merge_bin(int bin, int rows, const csrad_csr* A, const csrad_csr* B, const 
                const T* vB, const int32_t* rpC, int32_t* ciC, T* vC, const SpgemmWs& w,
                hipStream_t s) {
   if (rows == 0) return;
-  constexpr int R = G <= 8 ? 4 : (G <= 16 ? 2 : 1);  // rows in flight per group
-  const unsigned g = persistent_grid(kThreads / G * R, rows);
-  hipLaunchKernelGGL((k_merge<T, G, NUM, R>), dim3(g), dim3(kThreads), 0, s, bin, w.list,
-                     w.bin_off, A->rowptr, A->colind, vA, B->rowptr, B->colind, vB, rpC, ciC, vC,
-                     w.counts);
+  // Several rows in flight per group hide more memory latency, but run
+  // their merges one after the other: worth it only when every resident
+  // group has many rows to do (short merges, as in A P with one entry per
+  // row of P), not when the rows are few for the chip (P^T (A P)).
+  constexpr int RMAX = G <= 8 ? 4 : (G <= 16 ? 2 : 1);
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    cus = 256;
+  const long long resident_groups = (long long)cus * 8 * (kThreads / G);
+  if (RMAX > 1 && rows >= 8 * resident_groups) {
+    const unsigned g = persistent_grid(kThreads / G * RMAX, rows);
+    hipLaunchKernelGGL((k_merge<T, G, NUM, RMAX>), dim3(g), dim3(kThreads), 0, s, bin, w.list,
+                       w.bin_off, A->rowptr, A->colind, vA, B->rowptr, B->colind, vB, rpC, ciC, vC,
+                       w.counts);
+  } else {
+    const unsigned g = persistent_grid(kThreads / G, rows);
+    hipLaunchKernelGGL((k_merge<T, G, NUM, 1>), dim3(g), dim3(kThreads), 0, s, bin, w.list,
+                       w.bin_off, A->rowptr, A->colind, vA, B->rowptr, B->colind, vB, rpC, ciC, vC,
+                       w.counts);
+  }
 }
 
 // bins: host copy of the class boundaries, or null (every class is then

@@ -176,9 +176,13 @@ def ic0_blocks():
     return Ls
 
 
+@pytest.mark.parametrize("mode", ["blocks", "levels"])
 @pytest.mark.parametrize("dtype", [torch.float32, torch.float64], ids=["f32", "f64"])
-def test_batched_trisolve_ic0_matches_oracle(ic0_blocks, dtype):
+def test_batched_trisolve_ic0_matches_oracle(ic0_blocks, dtype, mode):
+    # both batched solve modes: a workgroup per block ("blocks"), and one
+    # cooperative launch with grid barriers between the batch's levels
     Bt = bt.Batch(ic0_blocks, dtype=dtype)
+    Bt.tri_mode = mode
     n = Bt.pattern.nrows
     T = Bt.A
     b = to_dev(gen.normal(n, 14), dtype)
@@ -200,6 +204,10 @@ def test_batched_trisolve_ic0_matches_oracle(ic0_blocks, dtype):
     # equal to the library's level-by-level solve of the whole matrix
     x1 = sp.trisolve(T.pattern, T.vals, b, True)
     assert rel_err(x, x1.cpu().numpy()) <= TOL[dtype]
+    # the autotuner times both modes and keeps one; results unchanged
+    ms = Bt.autotune_trisolve(T, True, reps=1)
+    assert set(ms) == {"blocks", "levels"} and Bt.tri_mode in ms
+    assert_close(Bt.trisolve(T, b, True), xo, dtype, "x (tuned mode)")
 
 
 def test_batched_autograd_matches_oracle(blocks, ic0_blocks):
