@@ -898,32 +898,110 @@ __device__ __forceinline__ void tri_row(int r, const int32_t* __restrict__ rp,
   x[r] = (b[r] - s) / d;
 }
 
+// Two rows of one level per thread, their loads interleaved (the rows of a
+// level are independent): each row's sum still runs in entry order, so the
+// result is the one-row tri_row's.
+template <typename TX, bool PERM>
+__device__ __forceinline__ void tri_rows2(const int (&r)[2], const bool (&valid)[2],
+                                          const int32_t* __restrict__ rp,
+                                          const int32_t* __restrict__ ci,
+                                          const int32_t* __restrict__ perm,
+                                          const TX* __restrict__ vals, const TX* __restrict__ b,
+                                          TX* __restrict__ x) {
+  constexpr int W = 8;
+  int e0[2], e1[2];
+  TX s[2] = {TX(0), TX(0)}, d[2] = {TX(1), TX(1)};
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    e0[k] = valid[k] ? rp[r[k]] : 0;
+    e1[k] = valid[k] ? rp[r[k] + 1] : 0;
+  }
+  const int nb = max((e1[0] - e0[0] + W - 1) / W, (e1[1] - e0[1] + W - 1) / W);
+  for (int bb = 0; bb < nb; ++bb) {
+    int j[2][W];
+    TX v[2][W], xv[2][W];
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+#pragma unroll
+      for (int u = 0; u < W; ++u) {
+        const int e = e0[k] + bb * W + u;
+        const bool ok = e < e1[k];
+        j[k][u] = ok ? ci[e] : r[k];
+        v[k][u] = ok ? (PERM ? vals[perm[e]] : vals[e]) : TX(0);
+      }
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+#pragma unroll
+      for (int u = 0; u < W; ++u) xv[k][u] = j[k][u] != r[k] ? x[j[k][u]] : TX(0);
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+#pragma unroll
+      for (int u = 0; u < W; ++u) {
+        if (e0[k] + bb * W + u < e1[k]) {
+          if (j[k][u] == r[k]) d[k] = v[k][u];
+          else s[k] += v[k][u] * xv[k][u];
+        }
+      }
+  }
+#pragma unroll
+  for (int k = 0; k < 2; ++k)
+    if (valid[k]) x[r[k]] = (b[r[k]] - s[k]) / d[k];
+}
+
+// A task is a block: its levels in order (ADJ: in reverse, over T^T with
+// values through perm), a barrier between levels, two rows per thread per
+// pass.  The block's level bounds are staged in LDS first.
+constexpr int kLvLds = 1024;
+
 template <typename T, bool ADJ>
 __global__ __launch_bounds__(kTriThreads) void k_batch_tri(
     const BTask* __restrict__ tasks, int ntasks, unsigned* ctr, int nlevels,
     const int32_t* __restrict__ lv_lo, const int32_t* __restrict__ lv_hi,
     const int32_t* __restrict__ rows, const int32_t* __restrict__ rp,
     const int32_t* __restrict__ ci, const int32_t* __restrict__ perm, const T* __restrict__ vals,
-    const T* __restrict__ b, T* __restrict__ x, const T* __restrict__ xf,
-    const int32_t* __restrict__ rpA, const int32_t* __restrict__ ciA, T* __restrict__ gv) {
+    const T* __restrict__ b, T* __restrict__ x) {
+  __shared__ int s_lo[kLvLds], s_hi[kLvLds];
+  const bool staged = nlevels <= kLvLds;
   run_queue(tasks, ntasks, ctr, [&](const BTask& tk) {
     const long long base = (long long)tk.block * nlevels;
-    for (int s = 0; s < nlevels; ++s) {
-      const int l = ADJ ? nlevels - 1 - s : s;
-      const int lo = lv_lo[base + l], hi = lv_hi[base + l];
-      if (hi <= lo) continue;  // uniform over the workgroup
-      for (int q = lo + threadIdx.x; q < hi; q += kTriThreads)
-        tri_row<T, T, ADJ>(rows[q], rp, ci, perm, vals, b, x);
+    if (staged) {
+      for (int l = threadIdx.x; l < nlevels; l += kTriThreads) {
+        s_lo[l] = lv_lo[base + l];
+        s_hi[l] = lv_hi[base + l];
+      }
       __syncthreads();
     }
-    if (ADJ && gv) {
-      // gvals[(i,j)] = -w_i x_j over the block's rows of T (w final now)
-      for (int i = tk.r0 + threadIdx.x; i < tk.r1; i += kTriThreads) {
-        const T wi = x[i];
-        for (int e = rpA[i]; e < rpA[i + 1]; ++e) gv[e] = -wi * xf[ciA[e]];
+    for (int s = 0; s < nlevels; ++s) {
+      const int l = ADJ ? nlevels - 1 - s : s;
+      const int lo = staged ? s_lo[l] : lv_lo[base + l];
+      const int hi = staged ? s_hi[l] : lv_hi[base + l];
+      if (hi <= lo) continue;  // uniform over the workgroup
+      for (int q = lo + threadIdx.x; q < hi; q += 2 * kTriThreads) {
+        const int q1 = q + kTriThreads;
+        const bool valid[2] = {true, q1 < hi};
+        const int r[2] = {rows[q], valid[1] ? rows[q1] : 0};
+        tri_rows2<T, ADJ>(r, valid, rp, ci, perm, vals, b, x);
       }
+      __syncthreads();
     }
   });
+}
+
+// gvals[(i,j)] = -w_i x_j on pat(T), row-wise over T with G lanes per row
+// (the adjoint's value gradient, once w is final).
+template <typename T, int G>
+__global__ __launch_bounds__(kThreads) void k_tri_gvals_rows(int n, const int32_t* __restrict__ rp,
+                                                            const int32_t* __restrict__ ci,
+                                                            const T* __restrict__ w,
+                                                            const T* __restrict__ x,
+                                                            T* __restrict__ gv) {
+  const int sub = threadIdx.x % G;
+  for (long long i = ((long long)blockIdx.x * kThreads + threadIdx.x) / G; i < n;
+       i += (long long)gridDim.x * (kThreads / G)) {
+    const T wi = -w[i];
+    const int e1 = rp[i + 1];
+    for (int e = rp[i] + sub; e < e1; e += G) gv[e] = wi * x[ld_stream(&ci[e])];
+  }
 }
 
 // Level-synchronous variant: ONE cooperative launch over the whole
@@ -1468,12 +1546,12 @@ extern "C" int csr_batch_trisolve_fwd(const csrad_csr* T, const csrad_batch_plan
     hipLaunchKernelGGL((k_batch_tri<float, false>), grid, dim3(kTriThreads), 0, s, tk, plan->ntasks,
                        ctr, nlevels, lo, hi, level_rows, T->rowptr, T->colind, nullptr,
                        static_cast<const float*>(T->vals), static_cast<const float*>(b),
-                       static_cast<float*>(x), nullptr, nullptr, nullptr, nullptr);
+                       static_cast<float*>(x));
   else
     hipLaunchKernelGGL((k_batch_tri<double, false>), grid, dim3(kTriThreads), 0, s, tk, plan->ntasks,
                        ctr, nlevels, lo, hi, level_rows, T->rowptr, T->colind, nullptr,
                        static_cast<const double*>(T->vals), static_cast<const double*>(b),
-                       static_cast<double*>(x), nullptr, nullptr, nullptr, nullptr);
+                       static_cast<double*>(x));
   return launch_status();
 }
 
@@ -1502,14 +1580,38 @@ extern "C" int csr_batch_trisolve_bwd(const csrad_csr* T, const csrad_csr* Tt, c
     hipLaunchKernelGGL((k_batch_tri<float, true>), grid, dim3(kTriThreads), 0, s, tk, plan->ntasks,
                        ctr, nlevels, lo, hi, level_rows, Tt->rowptr, Tt->colind, perm,
                        static_cast<const float*>(T->vals), static_cast<const float*>(gx),
-                       static_cast<float*>(gb), static_cast<const float*>(x), T->rowptr,
-                       T->colind, static_cast<float*>(gvals));
+                       static_cast<float*>(gb));
   else
     hipLaunchKernelGGL((k_batch_tri<double, true>), grid, dim3(kTriThreads), 0, s, tk, plan->ntasks,
                        ctr, nlevels, lo, hi, level_rows, Tt->rowptr, Tt->colind, perm,
                        static_cast<const double*>(T->vals), static_cast<const double*>(gx),
-                       static_cast<double*>(gb), static_cast<const double*>(x), T->rowptr,
-                       T->colind, static_cast<double*>(gvals));
+                       static_cast<double*>(gb));
+  CSRAD_TRY(launch_status());
+  if (gvals) {
+    const int n = T->nrows;
+    const double mean = n > 0 ? (double)T->nnz / n : 0.0;
+    const unsigned g = (unsigned)std::min<long long>(((long long)n * 8 + kThreads - 1) / kThreads,
+                                                     65536);
+    if (mean > 4.0) {
+      if (T->dtype == CSRAD_F32)
+        hipLaunchKernelGGL((k_tri_gvals_rows<float, 8>), dim3(g), dim3(kThreads), 0, s, n,
+                           T->rowptr, T->colind, static_cast<const float*>(gb),
+                           static_cast<const float*>(x), static_cast<float*>(gvals));
+      else
+        hipLaunchKernelGGL((k_tri_gvals_rows<double, 8>), dim3(g), dim3(kThreads), 0, s, n,
+                           T->rowptr, T->colind, static_cast<const double*>(gb),
+                           static_cast<const double*>(x), static_cast<double*>(gvals));
+    } else {
+      if (T->dtype == CSRAD_F32)
+        hipLaunchKernelGGL((k_tri_gvals_rows<float, 4>), dim3(g), dim3(kThreads), 0, s, n,
+                           T->rowptr, T->colind, static_cast<const float*>(gb),
+                           static_cast<const float*>(x), static_cast<float*>(gvals));
+      else
+        hipLaunchKernelGGL((k_tri_gvals_rows<double, 4>), dim3(g), dim3(kThreads), 0, s, n,
+                           T->rowptr, T->colind, static_cast<const double*>(gb),
+                           static_cast<const double*>(x), static_cast<double*>(gvals));
+    }
+  }
   return launch_status();
 }
 
