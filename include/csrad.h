@@ -158,7 +158,10 @@ int csr_transpose_vals(const csrad_csr *A, const int32_t *perm, void *valsT,
  *   non-NULL (CSRAD_SPGEMM_BINS int32 entries) the class boundaries are
  *   returned in the same synchronisation.
  * csr_spgemm_fwd: C_colind[nnz(C)] and C_vals[nnz(C)] given C_rowptr.
- *   Each C_ij sums A_ik B_kj over k in A's row order (deterministic).
+ *   Each C_ij sums A_ik B_kj in a fixed order (deterministic): k in A's
+ *   row order for rows with more than 64 products; for shorter rows the
+ *   products meeting at j are added by a fixed lane tree over A's row
+ *   order (the row merge).
  *   bins_host may be NULL (the rows are classified again); non-NULL, it
  *   must be what csr_spgemm_symbolic returned for the same A and B, with
  *   `work` that symbolic call's workspace, unchanged since: the

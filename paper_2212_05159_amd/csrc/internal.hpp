@@ -23,8 +23,9 @@ int transpose_pattern(int m, int n, int nnz, const int32_t* rowptr, const int32_
 // Stable grouping of n indices by a key in [0, K), K <= 32 (see
 // transpose.hip): ptr[K+1], order[n] (indices ascending within a key).
 size_t group_small_workspace(int n, int K);
+// With skip non-null, nothing is done when *skip (device) is non-zero.
 int group_small_keys(const int32_t* keys, int n, int K, int32_t* ptr, int32_t* order, void* work,
-                     size_t bytes, hipStream_t s);
+                     size_t bytes, hipStream_t s, const int32_t* skip = nullptr);
 
 // Level-scheduled solve with float64 vectors over T's value type (see
 // trisolve.hip); transpose selects T^{-T} over Tt/perm with reversed levels.

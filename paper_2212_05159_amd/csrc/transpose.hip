@@ -14,6 +14,8 @@
 // sorted by length class: <= 32 entries by a few lanes (rank sort), <= 4096 one
 // workgroup (bitonic in LDS), longer ones in 4096-entry LDS-sorted chunks
 // merged by a grid-wide rank computation (binary search in every chunk).
+#include <algorithm>
+
 #include "internal.hpp"
 
 namespace csrad {
@@ -61,14 +63,21 @@ __global__ __launch_bounds__(256) void k_mono_probe(int nnz, const int32_t* __re
   }
 }
 
-// rowptrT for a column-sorted pattern: entry e (0 <= e <= nnz, e = nnz
-// standing for the end) owns the columns j with colind[e-1] < j <= colind[e]
-// (0 <= j and j <= n at the ends) and writes rowptrT[j] = e; every j in
-// [0, n] is owned by exactly one e.
-__global__ __launch_bounds__(256) void k_mono_rowptr(int nnz, int n,
-                                                     const int32_t* __restrict__ colind,
-                                                     int32_t* __restrict__ rowptrT,
-                                                     const int32_t* __restrict__ mono) {
+// Outputs for a column-sorted pattern, one launch:
+//  * rowptrT: entry e (0 <= e <= nnz, e = nnz standing for the end) owns the
+//    columns j with colind[e-1] < j <= colind[e] (0 <= j and j <= n at the
+//    ends) and writes rowptrT[j] = e; every j in [0, n] is owned by exactly
+//    one e;
+//  * colindT and perm: G lanes per row (G from the mean row length) write
+//    the row of each entry and the identity.
+template <int G>
+__global__ __launch_bounds__(256) void k_mono_out(int m, int nnz, int n,
+                                                  const int32_t* __restrict__ rowptr,
+                                                  const int32_t* __restrict__ colind,
+                                                  int32_t* __restrict__ rowptrT,
+                                                  int32_t* __restrict__ colindT,
+                                                  int32_t* __restrict__ perm,
+                                                  const int32_t* __restrict__ mono) {
   if (*mono == 0) return;
   for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e <= nnz;
        e += (long long)gridDim.x * blockDim.x) {
@@ -76,16 +85,6 @@ __global__ __launch_bounds__(256) void k_mono_rowptr(int nnz, int n,
     const int hi = e == nnz ? n : colind[e];
     for (int j = lo; j <= hi; ++j) rowptrT[j] = (int32_t)e;
   }
-}
-
-// colindT and perm for a column-sorted pattern; G lanes per row (G from the
-// mean row length).
-template <int G>
-__global__ __launch_bounds__(256) void k_mono_fill(int m, const int32_t* __restrict__ rowptr,
-                                                   int32_t* __restrict__ colindT,
-                                                   int32_t* __restrict__ perm,
-                                                   const int32_t* __restrict__ mono) {
-  if (*mono == 0) return;
   for (long long i = (long long)blockIdx.x * (256 / G) + threadIdx.x / G; i < m;
        i += (long long)gridDim.x * (256 / G)) {
     for (int e = rowptr[i] + threadIdx.x % G; e < rowptr[i + 1]; e += G) {
@@ -191,29 +190,32 @@ __global__ __launch_bounds__(256) void k_sym_perm(int n, int nnz,
   }
 }
 
-// flags[3] = flags[1] | flags[2]: one of the two fast paths produced the
-// transpose, and the general kernels have nothing to do.
-__global__ void k_fast_flag(int32_t* __restrict__ flags) {
-  if (threadIdx.x == 0) flags[3] = (flags[1] | flags[2]) != 0;
-}
-
 // Column counts, one (wave-aggregated) atomic per entry; nothing when a fast
-// path made the transpose.
+// path made the transpose.  Block 0 records that outcome in flags[3]
+// (flags[1] | flags[2]: symmetric or column-sorted) for the kernels after it.
 __global__ __launch_bounds__(256) void k_count_cols(const int32_t* __restrict__ colind, int nnz,
-                                                    const int32_t* __restrict__ fast,
+                                                    int32_t* __restrict__ flags,
                                                     int32_t* __restrict__ cnt) {
   const long long stride = (long long)gridDim.x * blockDim.x;
-  if (*fast) return;
+  const bool fast = (flags[1] | flags[2]) != 0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) flags[3] = fast;
+  if (fast) return;
   for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += stride)
     wave_agg_count(cnt, colind[e]);
 }
 
-__global__ void k_set4(int32_t* __restrict__ p, int32_t a, int32_t b, int32_t c, int32_t d) {
-  if (threadIdx.x == 0) {
-    p[0] = a;
-    p[1] = b;
-    p[2] = c;
-    p[3] = d;
+// cnt[0 .. len) = 0 and the four path flags, one launch.
+__global__ __launch_bounds__(256) void k_tr_init(int32_t* __restrict__ cnt, long long len,
+                                                 int32_t* __restrict__ flags, int32_t a, int32_t b,
+                                                 int32_t c, int32_t d) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < len;
+       i += (long long)gridDim.x * blockDim.x)
+    cnt[i] = 0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    flags[0] = a;
+    flags[1] = b;
+    flags[2] = c;
+    flags[3] = d;
   }
 }
 
@@ -419,7 +421,9 @@ constexpr int kMsChunks = 8;
 constexpr int kMsTile = 256 * kMsChunks;
 
 __global__ __launch_bounds__(256) void k_ms_hist(const int32_t* __restrict__ keys, int n, int K,
-                                                 int ntiles, int32_t* __restrict__ hist) {
+                                                 int ntiles, int32_t* __restrict__ hist,
+                                                 const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;  // uniform over the grid
   __shared__ int h[kSmallKeys];
   if (threadIdx.x < kSmallKeys) h[threadIdx.x] = 0;
   __syncthreads();
@@ -435,7 +439,9 @@ __global__ __launch_bounds__(256) void k_ms_hist(const int32_t* __restrict__ key
 __global__ __launch_bounds__(256) void k_ms_scatter(const int32_t* __restrict__ keys, int n,
                                                     int K, int ntiles,
                                                     const int32_t* __restrict__ off,
-                                                    int32_t* __restrict__ order) {
+                                                    int32_t* __restrict__ order,
+                                                    const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;  // uniform over the grid
   __shared__ int wcount[4][kSmallKeys];
   __shared__ int running[kSmallKeys];
   const int lane = __lane_id(), w = threadIdx.x / kWave;
@@ -479,7 +485,8 @@ __global__ __launch_bounds__(256) void k_ms_scatter(const int32_t* __restrict__ 
 }
 
 __global__ void k_ms_ptr(const int32_t* __restrict__ off, int K, int ntiles, int n,
-                         int32_t* __restrict__ ptr) {
+                         int32_t* __restrict__ ptr, const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;
   const int l = blockIdx.x * blockDim.x + threadIdx.x;
   if (l < K) ptr[l] = off[(long long)l * ntiles];
   if (l == K) ptr[K] = n;
@@ -549,30 +556,27 @@ int transpose_pattern(int m, int n, int nnz, const int32_t* rowptr, const int32_
   Carver cv(work, bytes);
   TransposeWs w = carve_transpose(cv, n, nnz);
   if (!work || !cv.ok) return CSRAD_EWORKSPACE;
-  CSRAD_TRY(fill_i32(w.cnt, (long long)n + 1, 0, s));
-  hipLaunchKernelGGL(k_set4, dim3(1), dim3(64), 0, s, w.flags, 0, (m == n && nnz > 0) ? 1 : 0,
+  hipLaunchKernelGGL(k_tr_init, dim3(grid_for((long long)n + 1, 256, 2048)), dim3(256), 0, s,
+                     w.cnt, (long long)n + 1, w.flags, 0, (m == n && nnz > 0) ? 1 : 0,
                      nnz > 0 ? 1 : 0, 0);
   if (nnz > 0) {
     hipLaunchKernelGGL(k_mono_probe, dim3(grid_for(nnz, 256, 2048)), dim3(256), 0, s, nnz, colind,
                        w.mono);
-    hipLaunchKernelGGL(k_mono_rowptr, dim3(grid_for((long long)nnz + 1, 256, 2048)), dim3(256), 0,
-                       s, nnz, n, colind, rowptrT, w.mono);
-    if (m > 0) {
-      int g = 1;
-      while (g < 32 && (long long)g * m < nnz) g <<= 1;
-      const unsigned grid = grid_for((long long)m * g, 256, 4096);
-      switch (g) {
-#define CSRAD_MONO_FILL(G)                                                                       \
-  hipLaunchKernelGGL((k_mono_fill<G>), dim3(grid), dim3(256), 0, s, m, rowptr, colindT, perm, \
-                     w.mono)
-        case 1: CSRAD_MONO_FILL(1); break;
-        case 2: CSRAD_MONO_FILL(2); break;
-        case 4: CSRAD_MONO_FILL(4); break;
-        case 8: CSRAD_MONO_FILL(8); break;
-        case 16: CSRAD_MONO_FILL(16); break;
-        default: CSRAD_MONO_FILL(32); break;
-#undef CSRAD_MONO_FILL
-      }
+    int g = 1;
+    while (g < 32 && (long long)g * m < nnz) g <<= 1;
+    const long long work = std::max((long long)nnz + 1, (long long)m * g);
+    const unsigned grid = grid_for(work, 256, 4096);
+    switch (g) {
+#define CSRAD_MONO_OUT(G)                                                                      \
+  hipLaunchKernelGGL((k_mono_out<G>), dim3(grid), dim3(256), 0, s, m, nnz, n, rowptr, colind, \
+                     rowptrT, colindT, perm, w.mono)
+      case 1: CSRAD_MONO_OUT(1); break;
+      case 2: CSRAD_MONO_OUT(2); break;
+      case 4: CSRAD_MONO_OUT(4); break;
+      case 8: CSRAD_MONO_OUT(8); break;
+      case 16: CSRAD_MONO_OUT(16); break;
+      default: CSRAD_MONO_OUT(32); break;
+#undef CSRAD_MONO_OUT
     }
   }
   if (m == n && nnz > 0) {
@@ -580,11 +584,9 @@ int transpose_pattern(int m, int n, int nnz, const int32_t* rowptr, const int32_
     hipLaunchKernelGGL(k_sym_perm, dim3((m + 31) / 32), dim3(256), 0, s, m, nnz, rowptr, colind,
                        rowptrT, colindT, perm, w.sym);
   }
-  if (nnz > 0) {
-    hipLaunchKernelGGL(k_fast_flag, dim3(1), dim3(64), 0, s, w.flags);
+  if (nnz > 0)
     hipLaunchKernelGGL(k_count_cols, dim3(grid_for(nnz, 256, 8192)), dim3(256), 0, s, colind, nnz,
-                       w.fast, w.cnt);
-  }
+                       w.flags, w.cnt);
   CSRAD_TRY(scan_exclusive(w.cnt, rowptrT, n, w.total, w.scan_ws, w.scan_bytes, s, w.fast));
   if (nnz == 0) return launch_status();
   if (n > 0)
@@ -646,7 +648,7 @@ size_t group_small_workspace(int n, int K) {
 }
 
 int group_small_keys(const int32_t* keys, int n, int K, int32_t* ptr, int32_t* order, void* work,
-                     size_t bytes, hipStream_t s) {
+                     size_t bytes, hipStream_t s, const int32_t* skip) {
   if (K < 1 || K > kSmallKeys || n < 1) return CSRAD_EINVAL;
   const int ntiles = (n + kMsTile - 1) / kMsTile;
   const int cells = ntiles * K;
@@ -657,10 +659,11 @@ int group_small_keys(const int32_t* keys, int n, int K, int32_t* ptr, int32_t* o
   void* sws = cv.take<char>(sb);
   long long* total = cv.take<long long>(1);
   if (!work || !cv.ok) return CSRAD_EWORKSPACE;
-  hipLaunchKernelGGL(k_ms_hist, dim3(ntiles), dim3(256), 0, s, keys, n, K, ntiles, hist);
-  CSRAD_TRY(scan_exclusive(hist, off, cells, total, sws, sb, s));
-  hipLaunchKernelGGL(k_ms_scatter, dim3(ntiles), dim3(256), 0, s, keys, n, K, ntiles, off, order);
-  hipLaunchKernelGGL(k_ms_ptr, dim3(1), dim3(64), 0, s, off, K, ntiles, n, ptr);
+  hipLaunchKernelGGL(k_ms_hist, dim3(ntiles), dim3(256), 0, s, keys, n, K, ntiles, hist, skip);
+  CSRAD_TRY(scan_exclusive(hist, off, cells, total, sws, sb, s, skip));
+  hipLaunchKernelGGL(k_ms_scatter, dim3(ntiles), dim3(256), 0, s, keys, n, K, ntiles, off, order,
+                     skip);
+  hipLaunchKernelGGL(k_ms_ptr, dim3(1), dim3(64), 0, s, off, K, ntiles, n, ptr, skip);
   return launch_status();
 }
 

@@ -124,6 +124,7 @@ __global__ void k_tri_compact_cur(int n, const int32_t* __restrict__ flag,
 // rows in the current frontier, [2] its level, [3] which buffer holds it.
 constexpr int kKahnSmall = 8192;
 constexpr int kSpecRounds = 3;
+constexpr int kSpecLevels = kSpecRounds + 1;  // levels the speculative rounds can complete
 
 // Releases the dependents of row j (when valid).  The lanes of a wave walk
 // their rows' dependents in step so that rows made ready together are
@@ -240,6 +241,18 @@ __global__ void k_tri_next_level(int n, const int32_t* __restrict__ part, int np
     state[2] += 1;
     state[4] = t == 0 || state[2] >= n;
   }
+}
+
+// The analysis state, zero but for [1] (the first row without a stored
+// diagonal, none yet).
+__global__ void k_tri_state_init(int32_t* __restrict__ state) {
+  if (threadIdx.x < 8) state[threadIdx.x] = threadIdx.x == 1 ? INT32_MAX : 0;
+}
+
+// state[6] = 0 when the levels are complete (state[4]), else 1: the gate of
+// the speculative grouping by level.
+__global__ void k_tri_spec_flag(int32_t* __restrict__ state) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) state[6] = state[4] ? 0 : 1;
 }
 
 // After the prep pass: state[0] = the level-0 frontier size, [2] = 0,
@@ -538,8 +551,7 @@ extern "C" int csr_trisolve_analyze(const csrad_csr* Tm, int32_t lower, const cs
     CSRAD_TRY(fill_i32(level_ptr, 1, 0, s));
     return hipStreamSynchronize(s) == hipSuccess ? CSRAD_OK : CSRAD_EHIP;
   }
-  CSRAD_TRY(fill_i32(w.counters, 8, 0, s));
-  CSRAD_TRY(fill_i32(w.counters + 1, 1, INT32_MAX, s));
+  hipLaunchKernelGGL(k_tri_state_init, dim3(1), dim3(64), 0, s, w.counters);
   const unsigned gn = (unsigned)((n + kThreads - 1) / kThreads < kMaxPassBlocks
                                      ? (n + kThreads - 1) / kThreads
                                      : kMaxPassBlocks);
@@ -557,16 +569,38 @@ extern "C" int csr_trisolve_analyze(const csrad_csr* Tm, int32_t lower, const cs
   };
   // Coloured orderings have a few wide levels: run kSpecRounds rounds
   // before the first look at the state (each does nothing once the levels
-  // are exhausted), which saves a host round trip per level.
+  // are exhausted), which saves a host round trip per level.  If the
+  // levels end within those rounds (at most kSpecLevels of them), the rows
+  // are grouped by level before that look too (gated on the device), and
+  // the one synchronisation returns both the state and the level pointers.
   for (int r = 0; r < kSpecRounds; ++r) CSRAD_TRY(pull_round());
+  const bool spec_group = n >= kSpecLevels;  // level_ptr holds kSpecLevels + 1 entries
+  if (spec_group) {
+    hipLaunchKernelGGL(k_tri_spec_flag, dim3(1), dim3(64), 0, s, w.counters);
+    CSRAD_TRY(group_small_keys(level_of_row, n, kSpecLevels, level_ptr, level_rows, w.gws,
+                               w.gws_bytes, s, w.counters + 6));
+  }
   int32_t host[8];
+  int32_t spec_ptr[kSpecLevels + 1];
   auto read_state = [&]() -> int {
     if (hipMemcpyAsync(host, w.counters, sizeof(host), hipMemcpyDeviceToHost, s) != hipSuccess)
       return CSRAD_EHIP;
     return hipStreamSynchronize(s) == hipSuccess ? CSRAD_OK : CSRAD_EHIP;
   };
+  if (spec_group &&
+      hipMemcpyAsync(spec_ptr, level_ptr, sizeof(spec_ptr), hipMemcpyDeviceToHost, s) != hipSuccess)
+    return CSRAD_EHIP;
   CSRAD_TRY(read_state());
   if (host[1] != INT32_MAX) return CSRAD_ESINGULAR;
+  if (spec_group && host[4]) {
+    // every row placed within the speculative rounds: nl <= kSpecLevels
+    // and the grouping above is final (level pointers past nl equal n)
+    const int nl = host[2];
+    *nlevels_host = nl;
+    if (level_ptr_host)
+      for (int l = 0; l <= nl; ++l) level_ptr_host[l] = spec_ptr[l];
+    return CSRAD_OK;
+  }
   bool have_front = false;  // the frontier list is in the Kahn buffer
   while (host[0] > 0 && host[2] < n) {
     if (host[0] <= kKahnSmall) {
