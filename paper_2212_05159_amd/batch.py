@@ -335,9 +335,16 @@ class Batch:
         ms = {}
         for mode in ("blocks", "levels"):
             self.tri_mode = mode
-            x = self.trisolve(T, b, lower)
-            ms[mode] = _time(lambda: (self.trisolve(T, b, lower), self.trisolve_bwd(T, x, gx, lower)),
-                             reps)
+            try:
+                x = self.trisolve(T, b, lower)
+                ms[mode] = _time(lambda: (self.trisolve(T, b, lower),
+                                          self.trisolve_bwd(T, x, gx, lower)), reps)
+            except capi.CsradError:
+                # the runtime may refuse a cooperative launch (a grid the
+                # chip cannot hold at once): that mode is then unavailable
+                if mode == "blocks":
+                    raise
+                ms[mode] = float("inf")
         self.tri_mode = min(ms, key=ms.get)
         return ms
 

@@ -235,7 +235,12 @@ __global__ __launch_bounds__(kThreads) void k_num_hash(
 // unless a list runs W entries in a row.  Output entries are kept one per
 // lane and written G at a time.
 // ---------------------------------------------------------------------
-constexpr int kWin = 4;
+// Register window per list: entries a lane holds ahead of its list head
+// (fewer when a group keeps many rows in flight, to keep registers low).
+template <int R>
+constexpr int merge_window() {
+  return R >= 8 ? 2 : 4;
+}
 
 template <int G>
 __device__ __forceinline__ int group_min(int v) {
@@ -275,6 +280,7 @@ __global__ __launch_bounds__(kThreads) void k_merge(
     const int32_t* __restrict__ rpC, int32_t* __restrict__ ciC, T* __restrict__ vC,
     int32_t* __restrict__ counts) {
   constexpr int RPB = kThreads / G;  // groups per block
+  constexpr int kWin = merge_window<R>();
   __shared__ int s_b0[R][kThreads], s_len[R][kThreads], s_a[R][kThreads];
   const int first = bin_off[bin], nrows = bin_off[bin + 1] - first;
   const int lane = __lane_id(), l = threadIdx.x % G, g0 = threadIdx.x - l;
@@ -628,7 +634,8 @@ void merge_bin(int bin, int rows, const csrad_csr* A, const csrad_csr* B, const 
   // Several rows in flight per group hide more memory latency, but run
   // their merges one after the other: worth it only when every resident
   // group has many rows to do (short merges, as in A P with one entry per
-  // row of P), not when the rows are few for the chip (P^T (A P)).
+  // row of P: 4 rows per 8-lane group), not when the rows are few for the
+  // chip (P^T (A P)).
   constexpr int RMAX = G <= 8 ? 4 : (G <= 16 ? 2 : 1);
   int dev = 0, cus = 256;
   if (hipGetDevice(&dev) != hipSuccess ||
