@@ -234,8 +234,7 @@ template <int G>
 __global__ __launch_bounds__(256) void k_scatter(int m, const int32_t* __restrict__ rowptr,
                                                  const int32_t* __restrict__ colind,
                                                  int32_t* __restrict__ cursor,
-                                                 int32_t* __restrict__ tkey,
-                                                 int32_t* __restrict__ tval,
+                                                 int2* __restrict__ tkv,
                                                  const int32_t* __restrict__ fast) {
   if (*fast) return;
   const int sub = threadIdx.x % G;
@@ -243,8 +242,7 @@ __global__ __launch_bounds__(256) void k_scatter(int m, const int32_t* __restric
     const int e1 = rowptr[row + 1];
     for (int e = rowptr[row] + sub; e < e1; e += G) {
       const int slot = wave_agg_add(cursor, colind[e]);
-      tkey[slot] = row;
-      tval[slot] = e;
+      tkv[slot] = make_int2(row, e);  // one 8-byte store: (source row, entry)
     }
   }
 }
@@ -255,8 +253,7 @@ __global__ __launch_bounds__(256) void k_scatter(int m, const int32_t* __restric
 // appended to a list for the workgroup kernels.
 template <int G>
 __global__ __launch_bounds__(256) void k_sort_short(int n, const int32_t* __restrict__ rpT,
-                                                    const int32_t* __restrict__ tkey,
-                                                    const int32_t* __restrict__ tval,
+                                                    const int2* __restrict__ tkv,
                                                     int32_t* __restrict__ okey,
                                                     int32_t* __restrict__ oval,
                                                     int32_t* __restrict__ long_list,
@@ -268,11 +265,11 @@ __global__ __launch_bounds__(256) void k_sort_short(int n, const int32_t* __rest
     const int s = rpT[c], len = rpT[c + 1] - s;
     if (len <= kShort) {
       for (int q = l; q < len; q += G) {
-        const int key = tkey[s + q];
+        const int2 kv = tkv[s + q];
         int r = 0;
-        for (int u = 0; u < len; ++u) r += tkey[s + u] < key;
-        okey[s + r] = key;
-        oval[s + r] = tval[s + q];
+        for (int u = 0; u < len; ++u) r += tkv[s + u].x < kv.x;
+        okey[s + r] = kv.x;
+        oval[s + r] = kv.y;
       }
     } else if (l == 0) {
       long_list[atomicAdd(long_count, 1)] = c;
@@ -309,28 +306,35 @@ __device__ __forceinline__ int pow2_at_least(int x) {
   return p;
 }
 
-// Sorts [s, s+len) of (src_key, src_val) into (dst_key, dst_val); len <= kChunk.
-__device__ void sort_range_lds(const int32_t* src_key, const int32_t* src_val, int32_t* dst_key,
-                               int32_t* dst_val, int s, int len, int32_t* kk, int32_t* vv) {
+// Sorts the (key, value) pairs [s, s+len) of src by key in LDS; len <= kChunk.
+// The sorted keys and values go to (dst_key, dst_val), or back into src as
+// pairs when dst_key is null.
+__device__ void sort_range_lds(int2* src, int32_t* dst_key, int32_t* dst_val, int s, int len,
+                               int32_t* kk, int32_t* vv) {
   const int P = pow2_at_least(len);
   for (int i = threadIdx.x; i < P; i += blockDim.x) {
-    kk[i] = i < len ? src_key[s + i] : INT32_MAX;
-    vv[i] = i < len ? src_val[s + i] : 0;
+    const int2 kv = i < len ? src[s + i] : make_int2(INT32_MAX, 0);
+    kk[i] = kv.x;
+    vv[i] = kv.y;
   }
   __syncthreads();
   lds_bitonic(kk, vv, P);
   for (int i = threadIdx.x; i < len; i += blockDim.x) {
-    dst_key[s + i] = kk[i];
-    dst_val[s + i] = vv[i];
+    if (dst_key) {
+      dst_key[s + i] = kk[i];
+      dst_val[s + i] = vv[i];
+    } else {
+      src[s + i] = make_int2(kk[i], vv[i]);
+    }
   }
   __syncthreads();
 }
 
 // Medium columns (kShort < len <= kChunk): one workgroup each.
 __global__ __launch_bounds__(kSortThreads) void k_sort_medium(
-    const int32_t* __restrict__ rpT, const int32_t* __restrict__ tkey,
-    const int32_t* __restrict__ tval, int32_t* __restrict__ okey, int32_t* __restrict__ oval,
-    const int32_t* __restrict__ long_list, const int32_t* __restrict__ long_count) {
+    const int32_t* __restrict__ rpT, int2* __restrict__ tkv, int32_t* __restrict__ okey,
+    int32_t* __restrict__ oval, const int32_t* __restrict__ long_list,
+    const int32_t* __restrict__ long_count) {
   __shared__ int32_t kk[kChunk];
   __shared__ int32_t vv[kChunk];
   const int nl = *long_count;
@@ -338,7 +342,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_medium(
     const int c = long_list[t];
     const int s = rpT[c], len = rpT[c + 1] - s;
     if (len > kChunk) continue;  // uniform over the block
-    sort_range_lds(tkey, tval, okey, oval, s, len, kk, vv);
+    sort_range_lds(tkv, okey, oval, s, len, kk, vv);
   }
 }
 
@@ -346,7 +350,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_medium(
 // scratch arrays.  Every block walks the whole long list and takes the
 // chunks whose index matches it modulo the grid size.
 __global__ __launch_bounds__(kSortThreads) void k_sort_long_chunks(
-    const int32_t* __restrict__ rpT, int32_t* __restrict__ tkey, int32_t* __restrict__ tval,
+    const int32_t* __restrict__ rpT, int2* __restrict__ tkv,
     const int32_t* __restrict__ long_list, const int32_t* __restrict__ long_count) {
   __shared__ int32_t kk[kChunk];
   __shared__ int32_t vv[kChunk];
@@ -359,17 +363,17 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_long_chunks(
     for (int ch = blockIdx.x; ch < nch; ch += gridDim.x) {
       const int cs = s + ch * kChunk;
       const int cl = min(kChunk, s + len - cs);
-      sort_range_lds(tkey, tval, tkey, tval, cs, cl, kk, vv);
+      sort_range_lds(tkv, nullptr, nullptr, cs, cl, kk, vv);
     }
   }
 }
 
 // Number of keys < key in the sorted range [lo, hi).
-__device__ __forceinline__ int count_less(const int32_t* a, int lo, int hi, int key) {
+__device__ __forceinline__ int count_less(const int2* a, int lo, int hi, int key) {
   int l = lo, h = hi;
   while (l < h) {
     const int mid = (l + h) >> 1;
-    if (a[mid] < key) l = mid + 1;
+    if (a[mid].x < key) l = mid + 1;
     else h = mid;
   }
   return l - lo;
@@ -379,8 +383,7 @@ __device__ __forceinline__ int count_less(const int32_t* a, int lo, int hi, int 
 // in its own sorted chunk plus the number of smaller keys in every other
 // chunk.
 __global__ __launch_bounds__(256) void k_rank_long(const int32_t* __restrict__ rpT,
-                                                   const int32_t* __restrict__ tkey,
-                                                   const int32_t* __restrict__ tval,
+                                                   const int2* __restrict__ tkv,
                                                    int32_t* __restrict__ okey,
                                                    int32_t* __restrict__ oval,
                                                    const int32_t* __restrict__ long_list,
@@ -395,15 +398,15 @@ __global__ __launch_bounds__(256) void k_rank_long(const int32_t* __restrict__ r
     const int nch = (len + kChunk - 1) / kChunk;
     for (long long q = gid; q < len; q += gsz) {
       const int my = (int)(q / kChunk);
-      const int key = tkey[s + q];
+      const int2 kv = tkv[s + q];
       int r = (int)(q - (long long)my * kChunk);
       for (int ch = 0; ch < nch; ++ch) {
         if (ch == my) continue;
         const int lo = s + ch * kChunk, hi = min(s + len, lo + kChunk);
-        r += count_less(tkey, lo, hi, key);
+        r += count_less(tkv, lo, hi, kv.x);
       }
-      okey[s + r] = key;
-      oval[s + r] = tval[s + q];
+      okey[s + r] = kv.x;
+      oval[s + r] = kv.y;
     }
   }
 }
@@ -497,8 +500,7 @@ struct TransposeWs {
   void* scan_ws;
   size_t scan_bytes;
   long long* total;
-  int32_t* tkey;
-  int32_t* tval;
+  int2* tkv;  // scatter slots: (source row, entry)
   int32_t* long_list;
   int32_t* flags;  // [0] long-column count, [1] symmetric path on, [2] column-sorted path on,
                    // [3] either fast path on
@@ -514,8 +516,7 @@ TransposeWs carve_transpose(Carver& cv, int n, int nnz) {
   w.scan_bytes = scan_workspace(n);
   w.scan_ws = cv.take<char>(w.scan_bytes);
   w.total = cv.take<long long>(1);
-  w.tkey = cv.take<int32_t>((size_t)nnz);
-  w.tval = cv.take<int32_t>((size_t)nnz);
+  w.tkv = cv.take<int2>((size_t)nnz);
   w.long_list = cv.take<int32_t>((size_t)n + 1);
   w.flags = cv.take<int32_t>(4);
   w.long_count = w.flags;
@@ -601,7 +602,7 @@ int transpose_pattern(int m, int n, int nnz, const int32_t* rowptr, const int32_
     switch (g) {
 #define CSRAD_SCATTER(G)                                                                     \
   hipLaunchKernelGGL((k_scatter<G>), dim3(grid), dim3(256), 0, s, m, rowptr, colind, w.cnt, \
-                     w.tkey, w.tval, w.fast)
+                     w.tkv, w.fast)
       case 1: CSRAD_SCATTER(1); break;
       case 2: CSRAD_SCATTER(2); break;
       case 4: CSRAD_SCATTER(4); break;
@@ -616,7 +617,7 @@ int transpose_pattern(int m, int n, int nnz, const int32_t* rowptr, const int32_
     const unsigned grid = grid_for((long long)n * g, 256, 8192);
     switch (g) {
 #define CSRAD_SORT_SHORT(G)                                                                  \
-  hipLaunchKernelGGL((k_sort_short<G>), dim3(grid), dim3(256), 0, s, n, rowptrT, w.tkey, w.tval, \
+  hipLaunchKernelGGL((k_sort_short<G>), dim3(grid), dim3(256), 0, s, n, rowptrT, w.tkv,        \
                      colindT, perm, w.long_list, w.long_count, w.fast)
       case 1: CSRAD_SORT_SHORT(1); break;
       case 2: CSRAD_SORT_SHORT(2); break;
@@ -627,11 +628,11 @@ int transpose_pattern(int m, int n, int nnz, const int32_t* rowptr, const int32_
 #undef CSRAD_SORT_SHORT
     }
   }
-  hipLaunchKernelGGL(k_sort_medium, dim3(1024), dim3(kSortThreads), 0, s, rowptrT, w.tkey, w.tval,
+  hipLaunchKernelGGL(k_sort_medium, dim3(1024), dim3(kSortThreads), 0, s, rowptrT, w.tkv,
                      colindT, perm, w.long_list, w.long_count);
-  hipLaunchKernelGGL(k_sort_long_chunks, dim3(256), dim3(kSortThreads), 0, s, rowptrT, w.tkey,
-                     w.tval, w.long_list, w.long_count);
-  hipLaunchKernelGGL(k_rank_long, dim3(1024), dim3(256), 0, s, rowptrT, w.tkey, w.tval, colindT,
+  hipLaunchKernelGGL(k_sort_long_chunks, dim3(256), dim3(kSortThreads), 0, s, rowptrT, w.tkv,
+                     w.long_list, w.long_count);
+  hipLaunchKernelGGL(k_rank_long, dim3(1024), dim3(256), 0, s, rowptrT, w.tkv, colindT,
                      perm, w.long_list, w.long_count);
   return launch_status();
 }
