@@ -1139,8 +1139,9 @@ def main():
                  for kname in bm}
     value = total_bytes / (ms_step * 1e-3) / 1e9
 
-    # Roofline of the dominant kernel: k_spmm_bwd_coop alone, median of 60
-    # launches timed with HIP events on the stream it runs on, against its
+    # Roofline of the dominant kernel: k_spmm_bwd_coop alone, 20 warm-up
+    # launches, then the median of 60 launches timed with HIP events on the
+    # stream it runs on, against its
     # minimum algorithmic bytes ((m+1)I + nnz(I+2V) + 3nkV: pattern, values
     # read and value gradients written once, G read, B read, gB written).
     from paper_2212_05159_amd import sparse as sp
@@ -1156,7 +1157,8 @@ def main():
                            d.plan_bwd)
 
     stream = torch.cuda.current_stream()
-    dom_launch()
+    for _ in range(20):  # warm-up launches
+        dom_launch()
     torch.cuda.synchronize()
     reps_dom = []
     for _ in range(60):
