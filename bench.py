@@ -1130,10 +1130,13 @@ def main():
         products = {"A.P": int(lenP[d.A_ci.long()].sum()), "Pt.AP": int((lenP * lenAP).sum())}
     bm = byte_model(d, nnz_ap, nnz_c, nlev)
     total_bytes = sum(bm.values())
-    op_ms = {}
+    # per op the median over the attribution steps (a one-off host stall in
+    # one step, e.g. an allocation, would otherwise spread over the mean)
+    per_op = {}
     for mk in marks_all:
         for kname, v in mk.durations().items():
-            op_ms[kname] = op_ms.get(kname, 0.0) + v / args.steps
+            per_op.setdefault(kname, []).append(v)
+    op_ms = {kname: float(np.median(v)) for kname, v in per_op.items()}
     breakdown = {kname: {"ms": round(op_ms[kname], 4), "GB": round(bm[kname] / 1e9, 4),
                          "GB/s": round(bm[kname] / (op_ms[kname] * 1e-3) / 1e9, 1)}
                  for kname in bm}

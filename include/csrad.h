@@ -136,7 +136,7 @@ int csr_transpose(const csrad_csr *A, int32_t *rowptrT, int32_t *colindT,
  * (64 MiB), which every GPU the library runs on holds until the process
  * ends; the call allocates nothing.  Returns CSRAD_EWORKSPACE when the
  * transpose of A would need more (csr_transpose_workspace(A) above the
- * limit: roughly 2 nnz + 2 ncols int32 values over 64 MiB), CSRAD_EHIP if
+ * limit: roughly 2.5 nnz + 2 ncols int32 values over 64 MiB), CSRAD_EHIP if
  * the array's device address cannot be obtained.  Outputs as csr_transpose
  * (bit-identical).  Every call on one GPU shares the one array: calls that
  * overlap on one GPU (other streams, other host threads) race; calls

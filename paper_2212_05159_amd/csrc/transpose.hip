@@ -6,14 +6,22 @@
 // mirror, the transpose pattern is the pattern itself and perm maps the
 // mirror positions (a device flag records the outcome, and the general
 // kernels below skip or copy accordingly, so the call stays asynchronous).
-// General case: count per column -> exclusive scan -> scatter with atomic
-// cursors (order within a column is then arbitrary) -> per-column sort by
-// source row.
+// General case, in column blocks of CB = 2^k columns (CB and the block
+// count chosen from n and nnz): the entries are first moved into their
+// column block's range of the output (per-workgroup LDS histograms over the
+// blocks, one device atomic per block a workgroup touches, not one per
+// entry), then one workgroup per column block counts its columns in LDS,
+// writes their row pointers, groups the block's entries by column (in LDS
+// when they fit) and sorts each column by source row.  Patterns with more
+// than 2^25 columns take the per-entry form instead: count per column with
+// device atomics -> exclusive scan -> scatter with atomic cursors -> the
+// same per-column sort.
 // Source rows are unique within a column, so the sorted order is unique
-// and the result is bit-exact and identical between runs.  Columns are
-// sorted by length class: <= 32 entries by a few lanes (rank sort), <= 4096 one
-// workgroup (bitonic in LDS), longer ones in 4096-entry LDS-sorted chunks
-// merged by a grid-wide rank computation (binary search in every chunk).
+// and the result is bit-exact and identical between runs, whichever form
+// made it.  Columns are sorted by length class: <= 32 entries by a few
+// lanes (rank sort), <= 4096 one workgroup (bitonic in LDS), longer ones in
+// 4096-entry LDS-sorted chunks merged by a grid-wide rank computation
+// (binary search in every chunk).
 #include <algorithm>
 
 #include "internal.hpp"
@@ -22,6 +30,10 @@ namespace csrad {
 namespace {
 
 constexpr int kShort = 32;
+// Grid cap of the kernels that a device flag may switch off (grid-stride
+// loops inside): 16 blocks per compute unit keeps the chip full when they
+// run and costs a few microseconds of block dispatch when they do not.
+constexpr unsigned kGatedGrid = 4096;
 constexpr int kChunk = 4096;
 constexpr int kSortThreads = 256;
 
@@ -171,22 +183,23 @@ __global__ __launch_bounds__(256) void k_sym_perm(int n, int nnz,
                                                   int32_t* __restrict__ colindT,
                                                   int32_t* __restrict__ perm,
                                                   int32_t* __restrict__ sym) {
-  const int i = blockIdx.x * (256 / 8) + threadIdx.x / 8;
-  if (i >= n || *sym == 0) return;
-  const int e0 = rowptr[i], e1 = rowptr[i + 1];
-  if (threadIdx.x % 8 == 0) {
-    rowptrT[i] = e0;
-    if (i == n - 1) rowptrT[n] = e1;
-  }
-  for (int e = e0 + threadIdx.x % 8; e < e1; e += 8) {
-    const int c = colind[e];
-    const int pos = mirror_pos_win(rowptr, colind, nnz, c, i);
-    if (pos < 0) {
-      *sym = 0;
-      return;
+  if (*sym == 0) return;  // uniform over the grid: a capped grid costs little when off
+  for (int i = blockIdx.x * (256 / 8) + threadIdx.x / 8; i < n; i += gridDim.x * (256 / 8)) {
+    const int e0 = rowptr[i], e1 = rowptr[i + 1];
+    if (threadIdx.x % 8 == 0) {
+      rowptrT[i] = e0;
+      if (i == n - 1) rowptrT[n] = e1;
     }
-    perm[e] = pos;
-    colindT[e] = c;
+    for (int e = e0 + threadIdx.x % 8; e < e1; e += 8) {
+      const int c = colind[e];
+      const int pos = mirror_pos_win(rowptr, colind, nnz, c, i);
+      if (pos < 0) {
+        *sym = 0;
+        return;
+      }
+      perm[e] = pos;
+      colindT[e] = c;
+    }
   }
 }
 
@@ -412,6 +425,215 @@ __global__ __launch_bounds__(256) void k_rank_long(const int32_t* __restrict__ r
 }
 
 // ---------------------------------------------------------------------
+// Column-block form of the general transpose.
+// ---------------------------------------------------------------------
+constexpr int kBkMaxShift = 12;      // at most 4096 columns per block
+constexpr int kBkMaxBlocks = 8192;   // at most 8192 column blocks (n <= 2^25)
+constexpr int kBkTarget = 2048;      // aimed-for mean entries per column block
+constexpr int kBkTileEntries = 4096; // aimed-for entries per row tile
+constexpr int kBkLdsBytes = 48896;   // dynamic LDS cap of a column-block workgroup
+
+struct BkShape {
+  int shift = 0, nb = 0;
+  bool on = false;
+};
+
+// Column-block size 2^shift (at least 32 columns) with a mean of about
+// kBkTarget entries per block, and at most kBkMaxBlocks blocks.
+BkShape bk_shape(int n, int nnz) {
+  BkShape b;
+  if (n <= 0 || nnz <= 0 || (long long)n > ((long long)kBkMaxBlocks << kBkMaxShift)) return b;
+  int sh = 5;
+  while (sh < kBkMaxShift && (2ll << sh) * nnz <= (long long)kBkTarget * n) ++sh;
+  while (sh < kBkMaxShift && ((n + (1 << sh) - 1) >> sh) > kBkMaxBlocks) ++sh;
+  b.shift = sh;
+  b.nb = (n + (1 << sh) - 1) >> sh;
+  b.on = true;
+  return b;
+}
+
+// Entry capacity of the LDS grouping buffer next to the column counters.
+// (at most 4096 entries: a smaller buffer keeps more workgroups per CU).
+int bk_lds_cap(int shift) {
+  return std::min(4096, (kBkLdsBytes - (2 * (1 << shift) + 2) * 4) / 8);
+}
+int bk_lds_bytes(int shift) { return (2 * (1 << shift) + 2) * 4 + bk_lds_cap(shift) * 8; }
+
+// Pass 1: column-block counts of a tile of rows (G lanes per row) in LDS;
+// the non-zero ones go to the block totals with one atomic each.  Block 0
+// records the fast-path outcome in flags[3] (flags[1] | flags[2]).
+template <int G>
+__global__ __launch_bounds__(256) void k_bk_count(int m, const int32_t* __restrict__ rowptr,
+                                                  const int32_t* __restrict__ colind,
+                                                  int rows_per_tile, int shift, int nb,
+                                                  int32_t* __restrict__ btotal,
+                                                  int32_t* __restrict__ flags) {
+  extern __shared__ int32_t h[];  // nb counters
+  const bool fast = (flags[1] | flags[2]) != 0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) flags[3] = fast;
+  if (fast) return;  // uniform over the grid
+  for (int b = threadIdx.x; b < nb; b += 256) h[b] = 0;
+  __syncthreads();
+  const int r0 = blockIdx.x * rows_per_tile, r1 = min(m, r0 + rows_per_tile);
+  for (int row = r0 + (int)threadIdx.x / G; row < r1; row += 256 / G) {
+    const int e1 = rowptr[row + 1];
+    for (int e = rowptr[row] + (int)threadIdx.x % G; e < e1; e += G)
+      atomicAdd(&h[colind[e] >> shift], 1);
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < nb; b += 256)
+    if (h[b]) atomicAdd(&btotal[b], h[b]);
+}
+
+// Pass 2: the same counts again; one returning atomic per non-zero block
+// reserves this tile's slots in the block's output range (bbase[b] is the
+// range's start), and every entry then takes a slot with an LDS atomic:
+// srow/sent/scol[slot] = (row, entry, column within the block).  srow and
+// sent are the colindT and perm outputs, used as staging until pass 3.
+template <int G>
+__global__ __launch_bounds__(256) void k_bk_place(int m, const int32_t* __restrict__ rowptr,
+                                                  const int32_t* __restrict__ colind,
+                                                  int rows_per_tile, int shift, int nb,
+                                                  const int32_t* __restrict__ bbase,
+                                                  int32_t* __restrict__ brel,
+                                                  int32_t* __restrict__ srow,
+                                                  int32_t* __restrict__ sent,
+                                                  uint16_t* __restrict__ scol,
+                                                  const int32_t* __restrict__ fast) {
+  extern __shared__ int32_t h[];  // nb counters, then the same array as nb cursors
+  if (*fast) return;  // uniform over the grid
+  for (int b = threadIdx.x; b < nb; b += 256) h[b] = 0;
+  __syncthreads();
+  const int r0 = blockIdx.x * rows_per_tile, r1 = min(m, r0 + rows_per_tile);
+  for (int row = r0 + (int)threadIdx.x / G; row < r1; row += 256 / G) {
+    const int e1 = rowptr[row + 1];
+    for (int e = rowptr[row] + (int)threadIdx.x % G; e < e1; e += G)
+      atomicAdd(&h[colind[e] >> shift], 1);
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < nb; b += 256) {
+    const int c = h[b];
+    if (c) h[b] = bbase[b] + atomicAdd(&brel[b], c);
+  }
+  __syncthreads();
+  const int mask = (1 << shift) - 1;
+  for (int row = r0 + (int)threadIdx.x / G; row < r1; row += 256 / G) {
+    const int e1 = rowptr[row + 1];
+    for (int e = rowptr[row] + (int)threadIdx.x % G; e < e1; e += G) {
+      const int col = colind[e];
+      const int slot = atomicAdd(&h[col >> shift], 1);
+      srow[slot] = row;
+      sent[slot] = e;
+      scol[slot] = (uint16_t)(col & mask);
+    }
+  }
+}
+
+// Exclusive scan of a[0 .. len) in LDS by the whole block (256 threads,
+// each a contiguous run); a[len] = the total.  wsum: 4 ints of LDS.
+__device__ void lds_exclusive_scan(int32_t* a, int len, int32_t* wsum) {
+  const int per = (len + 255) / 256;
+  const int lo = min(len, (int)threadIdx.x * per), hi = min(len, lo + per);
+  int sum = 0;
+  for (int i = lo; i < hi; ++i) sum += a[i];
+  const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
+  int v = sum;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const int u = __shfl_up(v, o);
+    if (lane >= o) v += u;
+  }
+  if (lane == kWave - 1) wsum[wid] = v;
+  __syncthreads();
+  int off = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < 256 / kWave; ++w) {
+    if (w < wid) off += wsum[w];
+    tot += wsum[w];
+  }
+  int run = off + v - sum;
+  for (int i = lo; i < hi; ++i) {
+    const int x = a[i];
+    a[i] = run;
+    run += x;
+  }
+  if (threadIdx.x == 0) a[len] = tot;
+  __syncthreads();
+}
+
+// Pass 3: one workgroup per column block b (its entries are the output
+// range [bbase[b], bbase[b+1]), staged by pass 2).  Counts per column in
+// LDS -> exclusive scan -> rowptrT of the block's columns; groups the
+// entries by column (in LDS when at most cap of them, else in tkv at their
+// output positions); then G lanes per column: columns of at most kShort
+// entries are rank-sorted by source row straight into colindT/perm, longer
+// ones are left in tkv and listed for the medium/long sorts.  All staged
+// inputs are read before the first output is written (block barrier), and
+// block ranges are disjoint, so the in-place use of colindT/perm is safe.
+template <int G>
+__global__ __launch_bounds__(256) void k_bk_cols(int n, int shift, int nb, int cap,
+                                                 const int32_t* __restrict__ bbase,
+                                                 const uint16_t* __restrict__ scol,
+                                                 int32_t* __restrict__ colindT,
+                                                 int32_t* __restrict__ perm,
+                                                 int32_t* __restrict__ rowptrT,
+                                                 int2* __restrict__ tkv,
+                                                 int32_t* __restrict__ long_list,
+                                                 int32_t* __restrict__ long_count,
+                                                 const int32_t* __restrict__ fast) {
+  extern __shared__ int32_t lds[];
+  __shared__ int32_t wsum[256 / kWave];
+  if (*fast) return;  // uniform over the grid
+  const int cb = 1 << shift;
+  int32_t* start = lds;                                    // cb + 1
+  int32_t* cur = lds + cb + 1;                             // cb
+  int2* lkv = reinterpret_cast<int2*>(lds + 2 * cb + 2);  // cap pairs (8-byte aligned)
+  const int b = blockIdx.x;
+  const int s0 = bbase[b], s1 = bbase[b + 1], len = s1 - s0;
+  const int c0 = b << shift, ncb = min(cb, n - c0);
+  for (int c = threadIdx.x; c <= ncb; c += 256) start[c] = 0;
+  __syncthreads();
+  for (int i = s0 + threadIdx.x; i < s1; i += 256) atomicAdd(&start[scol[i]], 1);
+  __syncthreads();
+  lds_exclusive_scan(start, ncb, wsum);
+  for (int c = threadIdx.x; c < ncb; c += 256) {
+    cur[c] = start[c];
+    rowptrT[c0 + c] = s0 + start[c];
+  }
+  if (b == nb - 1 && threadIdx.x == 0) rowptrT[n] = s1;
+  __syncthreads();
+  const bool in_lds = len <= cap;
+  for (int i = s0 + threadIdx.x; i < s1; i += 256) {
+    const int p = atomicAdd(&cur[scol[i]], 1);
+    const int2 kv = make_int2(colindT[i], perm[i]);
+    if (in_lds) lkv[p] = kv;
+    else tkv[s0 + p] = kv;
+  }
+  __syncthreads();
+  const int l = threadIdx.x % G;
+  for (int c = threadIdx.x / G; c < ncb; c += 256 / G) {
+    const int st = start[c], lc = start[c + 1] - st;
+    if (lc <= kShort) {
+      for (int q = l; q < lc; q += G) {
+        const int2 kv = in_lds ? lkv[st + q] : tkv[s0 + st + q];
+        int r = 0;
+        if (in_lds) {
+          for (int u = 0; u < lc; ++u) r += lkv[st + u].x < kv.x;
+        } else {
+          for (int u = 0; u < lc; ++u) r += tkv[s0 + st + u].x < kv.x;
+        }
+        colindT[s0 + st + r] = kv.x;
+        perm[s0 + st + r] = kv.y;
+      }
+    } else {
+      if (in_lds)
+        for (int q = l; q < lc; q += G) tkv[s0 + st + q] = lkv[st + q];
+      if (l == 0) long_list[atomicAdd(long_count, 1)] = c0 + c;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------
 // Stable grouping of n elements by a small key (K <= kSmallKeys): the
 // element indices come out ordered by key, ascending index within a key.
 // Per tile of kMsTile elements: a key histogram, then a scan over
@@ -496,6 +718,10 @@ __global__ void k_ms_ptr(const int32_t* __restrict__ off, int K, int ntiles, int
 }
 
 struct TransposeWs {
+  BkShape bk;
+  int32_t* bk_total;  // [nb] block totals, then [nb] reservation counters
+  int32_t* bk_base;   // [nb + 1] block output ranges
+  uint16_t* bk_col;   // [nnz] column within the block, per staged entry
   int32_t* cnt;
   void* scan_ws;
   size_t scan_bytes;
@@ -512,6 +738,11 @@ struct TransposeWs {
 
 TransposeWs carve_transpose(Carver& cv, int n, int nnz) {
   TransposeWs w;
+  w.bk = bk_shape(n, nnz);
+  const size_t nb = w.bk.on ? (size_t)w.bk.nb : 0;
+  w.bk_total = cv.take<int32_t>(2 * nb);
+  w.bk_base = cv.take<int32_t>(nb + 1);
+  w.bk_col = cv.take<uint16_t>(w.bk.on ? (size_t)nnz : 0);
   w.cnt = cv.take<int32_t>((size_t)n + 1);
   w.scan_bytes = scan_workspace(n);
   w.scan_ws = cv.take<char>(w.scan_bytes);
@@ -557,9 +788,12 @@ int transpose_pattern(int m, int n, int nnz, const int32_t* rowptr, const int32_
   Carver cv(work, bytes);
   TransposeWs w = carve_transpose(cv, n, nnz);
   if (!work || !cv.ok) return CSRAD_EWORKSPACE;
-  hipLaunchKernelGGL(k_tr_init, dim3(grid_for((long long)n + 1, 256, 2048)), dim3(256), 0, s,
-                     w.cnt, (long long)n + 1, w.flags, 0, (m == n && nnz > 0) ? 1 : 0,
-                     nnz > 0 ? 1 : 0, 0);
+  // zeroes the counters of the form in use (block totals and reservation
+  // counters, or per-column counts) and sets the path flags
+  int32_t* zero = w.bk.on ? w.bk_total : w.cnt;
+  const long long zlen = w.bk.on ? 2ll * w.bk.nb : (long long)n + 1;
+  hipLaunchKernelGGL(k_tr_init, dim3(grid_for(zlen, 256, 2048)), dim3(256), 0, s, zero, zlen,
+                     w.flags, 0, (m == n && nnz > 0) ? 1 : 0, nnz > 0 ? 1 : 0, 0);
   if (nnz > 0) {
     hipLaunchKernelGGL(k_mono_probe, dim3(grid_for(nnz, 256, 2048)), dim3(256), 0, s, nnz, colind,
                        w.mono);
@@ -582,50 +816,105 @@ int transpose_pattern(int m, int n, int nnz, const int32_t* rowptr, const int32_
   }
   if (m == n && nnz > 0) {
     hipLaunchKernelGGL(k_sym_probe, dim3(1), dim3(256), 0, s, m, rowptr, colind, w.sym, w.mono);
-    hipLaunchKernelGGL(k_sym_perm, dim3((m + 31) / 32), dim3(256), 0, s, m, nnz, rowptr, colind,
-                       rowptrT, colindT, perm, w.sym);
+    hipLaunchKernelGGL(k_sym_perm, dim3(grid_for((long long)m * 8, 256, kGatedGrid)), dim3(256), 0,
+                       s, m, nnz, rowptr, colind, rowptrT, colindT, perm, w.sym);
   }
-  if (nnz > 0)
-    hipLaunchKernelGGL(k_count_cols, dim3(grid_for(nnz, 256, 8192)), dim3(256), 0, s, colind, nnz,
-                       w.flags, w.cnt);
-  CSRAD_TRY(scan_exclusive(w.cnt, rowptrT, n, w.total, w.scan_ws, w.scan_bytes, s, w.fast));
-  if (nnz == 0) return launch_status();
-  if (n > 0)
-    hipLaunchKernelGGL(k_copy_i32, dim3(grid_for(n, 256, 2048)), dim3(256), 0, s, rowptrT, n,
-                       w.cnt, w.fast);
-  // gated kernels take capped grids with grid-stride loops, so that they
-  // cost little when a fast path has made the transpose
-  if (m > 0) {
+  if (w.bk.on) {
+    // column-block form
+    const int nb = w.bk.nb, sh = w.bk.shift;
     int g = 1;
     while (g < 8 && (long long)g * m < nnz) g <<= 1;
-    const unsigned grid = grid_for((long long)m * g, 256, 8192);
+    // row tiles of about kBkTileEntries entries, a whole number of row groups
+    long long rpt = std::max<long long>(256 / g, (long long)kBkTileEntries * m / nnz);
+    rpt = std::min<long long>(rpt, (long long)m) / (256 / g) * (256 / g);
+    if (rpt < 256 / g) rpt = 256 / g;
+    const unsigned tiles = (unsigned)((m + rpt - 1) / rpt);
+    const size_t hb = (size_t)nb * 4;
     switch (g) {
+#define CSRAD_BK_COUNT(G)                                                                     \
+  hipLaunchKernelGGL((k_bk_count<G>), dim3(tiles), dim3(256), hb, s, m, rowptr, colind,        \
+                     (int)rpt, sh, nb, w.bk_total, w.flags)
+      case 1: CSRAD_BK_COUNT(1); break;
+      case 2: CSRAD_BK_COUNT(2); break;
+      case 4: CSRAD_BK_COUNT(4); break;
+      default: CSRAD_BK_COUNT(8); break;
+#undef CSRAD_BK_COUNT
+    }
+    CSRAD_TRY(scan_exclusive(w.bk_total, w.bk_base, nb, w.total, w.scan_ws, w.scan_bytes, s,
+                             w.fast));
+    switch (g) {
+#define CSRAD_BK_PLACE(G)                                                                   \
+  hipLaunchKernelGGL((k_bk_place<G>), dim3(tiles), dim3(256), hb, s, m, rowptr, colind,      \
+                     (int)rpt, sh, nb, w.bk_base, w.bk_total + nb, colindT, perm, w.bk_col, \
+                     w.fast)
+      case 1: CSRAD_BK_PLACE(1); break;
+      case 2: CSRAD_BK_PLACE(2); break;
+      case 4: CSRAD_BK_PLACE(4); break;
+      default: CSRAD_BK_PLACE(8); break;
+#undef CSRAD_BK_PLACE
+    }
+    // lanes per column from the mean column length (at most kShort)
+    int gc = 1;
+    while (gc < kShort && (long long)gc * n < nnz) gc <<= 1;
+    const int cap = bk_lds_cap(sh);
+    const size_t lb = (size_t)bk_lds_bytes(sh);
+    switch (gc) {
+#define CSRAD_BK_COLS(G)                                                                   \
+  hipLaunchKernelGGL((k_bk_cols<G>), dim3(nb), dim3(256), lb, s, n, sh, nb, cap, w.bk_base, \
+                     w.bk_col, colindT, perm, rowptrT, w.tkv, w.long_list, w.long_count,   \
+                     w.fast)
+      case 1: CSRAD_BK_COLS(1); break;
+      case 2: CSRAD_BK_COLS(2); break;
+      case 4: CSRAD_BK_COLS(4); break;
+      case 8: CSRAD_BK_COLS(8); break;
+      case 16: CSRAD_BK_COLS(16); break;
+      default: CSRAD_BK_COLS(32); break;
+#undef CSRAD_BK_COLS
+    }
+  } else {
+    // per-entry form (no entries, or more than 2^25 columns)
+    if (nnz > 0)
+      hipLaunchKernelGGL(k_count_cols, dim3(grid_for(nnz, 256, kGatedGrid)), dim3(256), 0, s,
+                         colind, nnz, w.flags, w.cnt);
+    CSRAD_TRY(scan_exclusive(w.cnt, rowptrT, n, w.total, w.scan_ws, w.scan_bytes, s, w.fast));
+    if (nnz == 0) return launch_status();
+    if (n > 0)
+      hipLaunchKernelGGL(k_copy_i32, dim3(grid_for(n, 256, 2048)), dim3(256), 0, s, rowptrT, n,
+                         w.cnt, w.fast);
+    // gated kernels take capped grids with grid-stride loops, so that they
+    // cost little when a fast path has made the transpose
+    if (m > 0) {
+      int g = 1;
+      while (g < 8 && (long long)g * m < nnz) g <<= 1;
+      const unsigned grid = grid_for((long long)m * g, 256, kGatedGrid);
+      switch (g) {
 #define CSRAD_SCATTER(G)                                                                     \
   hipLaunchKernelGGL((k_scatter<G>), dim3(grid), dim3(256), 0, s, m, rowptr, colind, w.cnt, \
                      w.tkv, w.fast)
-      case 1: CSRAD_SCATTER(1); break;
-      case 2: CSRAD_SCATTER(2); break;
-      case 4: CSRAD_SCATTER(4); break;
-      default: CSRAD_SCATTER(8); break;
+        case 1: CSRAD_SCATTER(1); break;
+        case 2: CSRAD_SCATTER(2); break;
+        case 4: CSRAD_SCATTER(4); break;
+        default: CSRAD_SCATTER(8); break;
 #undef CSRAD_SCATTER
+      }
     }
-  }
-  {
-    // lanes per column from the mean column length (at most kShort)
-    int g = 1;
-    while (g < kShort && (long long)g * n < nnz) g <<= 1;
-    const unsigned grid = grid_for((long long)n * g, 256, 8192);
-    switch (g) {
+    {
+      // lanes per column from the mean column length (at most kShort)
+      int g = 1;
+      while (g < kShort && (long long)g * n < nnz) g <<= 1;
+      const unsigned grid = grid_for((long long)n * g, 256, kGatedGrid);
+      switch (g) {
 #define CSRAD_SORT_SHORT(G)                                                                  \
   hipLaunchKernelGGL((k_sort_short<G>), dim3(grid), dim3(256), 0, s, n, rowptrT, w.tkv,        \
                      colindT, perm, w.long_list, w.long_count, w.fast)
-      case 1: CSRAD_SORT_SHORT(1); break;
-      case 2: CSRAD_SORT_SHORT(2); break;
-      case 4: CSRAD_SORT_SHORT(4); break;
-      case 8: CSRAD_SORT_SHORT(8); break;
-      case 16: CSRAD_SORT_SHORT(16); break;
-      default: CSRAD_SORT_SHORT(32); break;
+        case 1: CSRAD_SORT_SHORT(1); break;
+        case 2: CSRAD_SORT_SHORT(2); break;
+        case 4: CSRAD_SORT_SHORT(4); break;
+        case 8: CSRAD_SORT_SHORT(8); break;
+        case 16: CSRAD_SORT_SHORT(16); break;
+        default: CSRAD_SORT_SHORT(32); break;
 #undef CSRAD_SORT_SHORT
+      }
     }
   }
   hipLaunchKernelGGL(k_sort_medium, dim3(1024), dim3(kSortThreads), 0, s, rowptrT, w.tkv,

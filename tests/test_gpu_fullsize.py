@@ -111,6 +111,11 @@ def test_step128_transpose_levels_trisolve(step128):
     assert np.array_equal(_np(PAt.colind), ciT)
     assert np.array_equal(_np(permA), perm)
     PL = sp.Pattern(d.n, d.n, d.L_rp, d.L_ci)
+    PLt, permL = PL.transpose()  # the general (column-block) form at 8.4M entries
+    rpT, ciT, perm = oracle.transpose(L)
+    assert np.array_equal(_np(PLt.rowptr), rpT)
+    assert np.array_equal(_np(PLt.colind), ciT)
+    assert np.array_equal(_np(permL), perm)
     nl, lph, lptr, lrows, lor = PL.levels(True)
     lor_o, lptr_o, lrows_o = oracle.levels(L, True)
     assert nl == 2
@@ -222,8 +227,7 @@ def test_unfused_scan_in_symbolic_passes():
     rpC, ciC, vCo = oracle.spadd(upcast(A, torch.float32), upcast(B, torch.float32), 1.0, -2.0)
     assert np.array_equal(_np(PC.rowptr), rpC) and np.array_equal(_np(PC.colind), ciC)
     assert np.array_equal(_np(vC), vCo.astype(np.float32))
-    # transpose of a 1 x 5M-column-wide random pattern: column counts over
-    # 5,000,000 columns go through the unfused scan
+    # transpose of a 65536 x 5M random pattern: 2442 column blocks of 2048
     W = gen.random_rows(1 << 16, m, 40, seed=33)
     Wd = sp.Pattern.from_host(W)
     print(f"[fullsize] transpose with {m} columns", flush=True)
@@ -232,3 +236,13 @@ def test_unfused_scan_in_symbolic_passes():
     assert np.array_equal(_np(Wt.rowptr), rpT)
     assert np.array_equal(_np(Wt.colind), ciT)
     assert np.array_equal(_np(perm), permo)
+    # more than 2^25 columns: the per-entry form (device-atomic column
+    # counts, whose 33.6M-item scan takes the unfused path)
+    n2 = (1 << 25) + 12345
+    W2 = gen.random_rows(4096, n2, 8, seed=34)
+    print(f"[fullsize] transpose with {n2} columns", flush=True)
+    W2t, perm2 = sp.Pattern.from_host(W2).transpose()
+    rpT, ciT, permo = oracle.transpose(W2)
+    assert np.array_equal(_np(W2t.rowptr), rpT)
+    assert np.array_equal(_np(W2t.colind), ciT)
+    assert np.array_equal(_np(perm2), permo)

@@ -249,8 +249,21 @@ def _col_sorted_cases():
             ("one_col", one_col), ("identity", eye)]
 
 
+def _skewed_blocks():
+    # every row takes one column in [0, 4096) and two anywhere in [0, 200000):
+    # the column blocks over [0, 4096) hold more entries than fit in LDS
+    # (grouped in the scratch pairs), with columns of about 20 entries
+    rng = np.random.default_rng(35)
+    m, n = 80000, 200000
+    r = np.repeat(np.arange(m), 3)
+    c = np.stack([rng.integers(0, 4096, m), rng.integers(0, n, m), rng.integers(0, n, m)], 1)
+    key = np.unique(r.astype(np.int64) * n + c.reshape(-1))
+    return gen._from_coo(m, n, key // n, key % n, rng.standard_normal(len(key)))
+
+
 TRANSPOSE_CASES = MATS + [("long_cols", _with_long_columns()), ("agg", gen.aggregation(10001, 8)),
-                          ("few_cols", _few_cols())] + _col_sorted_cases()
+                          ("few_cols", _few_cols()), ("skewed_blocks", _skewed_blocks())] \
+    + _col_sorted_cases()
 
 
 @pytest.mark.parametrize("name,A", TRANSPOSE_CASES, ids=[n for n, _ in TRANSPOSE_CASES])
