@@ -37,19 +37,6 @@ constexpr unsigned kGatedGrid = 4096;
 constexpr int kChunk = 4096;
 constexpr int kSortThreads = 256;
 
-// Position of column i in row j (rows sorted), or -1.
-__device__ __forceinline__ int mirror_pos(const int32_t* __restrict__ rowptr,
-                                          const int32_t* __restrict__ colind, int j, int i) {
-  const int hi = rowptr[j + 1];
-  int a = rowptr[j], b = hi;
-  while (a < b) {
-    const int mid = (a + b) >> 1;
-    if (colind[mid] < i) a = mid + 1;
-    else b = mid;
-  }
-  return a < hi && colind[a] == i ? a : -1;
-}
-
 // Column-sorted patterns: when the column indices never decrease over the
 // entry array (across row boundaries too, e.g. an aggregation operator whose
 // aggregates are contiguous, or its transpose), entry order is already
@@ -57,15 +44,19 @@ __device__ __forceinline__ int mirror_pos(const int32_t* __restrict__ rowptr,
 // their own order: perm is the identity, colindT[e] is the row of e, and
 // rowptrT[j] is the first entry with column >= j.  k_mono_probe: each block
 // checks its contiguous share of the entries 256 at a time and stops (after
-// clearing *mono) at the first slice holding a decrease; blocks that start
-// after a clear return at once.  Unsorted patterns therefore cost about one
-// slice per block.
+// clearing *mono) at the first slice holding a decrease; before every slice
+// thread 0 re-reads the flag past the caches, so that blocks whose share is
+// sorted stop once another block has cleared it.  Unsorted patterns
+// therefore cost about one slice per block.  Every exit is block-uniform
+// (decided through a block reduction).
 __global__ __launch_bounds__(256) void k_mono_probe(int nnz, const int32_t* __restrict__ colind,
                                                     int32_t* __restrict__ mono) {
-  if (*mono == 0) return;
   const long long per = ((long long)nnz + gridDim.x - 1) / gridDim.x;
   const long long a = (long long)blockIdx.x * per, b = min((long long)nnz, a + per);
   for (long long base = a; base < b; base += 256) {
+    const bool cleared =
+        threadIdx.x == 0 && __hip_atomic_load(mono, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
+    if (__syncthreads_or(cleared)) return;
     const long long e = base + threadIdx.x;
     const bool down = e >= 1 && e < b && colind[e - 1] > colind[e];
     if (__syncthreads_or(down)) {
@@ -104,23 +95,6 @@ __global__ __launch_bounds__(256) void k_mono_out(int m, int nnz, int n,
       perm[e] = e;
     }
   }
-}
-
-// Cheap first look: one block checks 256 rows spread over the pattern and
-// clears *sym on a missing mirror, so that clearly unsymmetric patterns
-// (e.g. triangular ones) skip the full pass.
-__global__ __launch_bounds__(256) void k_sym_probe(int n, const int32_t* __restrict__ rowptr,
-                                                   const int32_t* __restrict__ colind,
-                                                   int32_t* __restrict__ sym,
-                                                   const int32_t* __restrict__ mono) {
-  if (*mono) {  // the column-sorted path covers it
-    if (threadIdx.x == 0) *sym = 0;
-    return;
-  }
-  const int i = (int)(((long long)threadIdx.x * n) / 256 + (n > 256 ? 128 % (n / 256) : 0));
-  if (i >= n || (n <= 256 && (int)threadIdx.x >= n)) return;
-  for (int e = rowptr[i]; e < rowptr[i + 1]; ++e)
-    if (mirror_pos(rowptr, colind, colind[e], i) < 0) *sym = 0;
 }
 
 // Symmetric try: entry e = (i, j) finds the position of its mirror (j, i)
@@ -174,6 +148,28 @@ __device__ __forceinline__ int mirror_pos_win(const int32_t* __restrict__ rowptr
     if (lo < b && colind[lo] == i) pos = lo;
   }
   return pos;
+}
+
+// Cheap first look: one block checks 256 rows spread over the pattern (the
+// first and the last entry of each, two independent mirror lookups per
+// thread) and clears *sym on a missing mirror, so that clearly unsymmetric
+// patterns (e.g. triangular ones) skip the full pass.
+__global__ __launch_bounds__(256) void k_sym_probe(int n, int nnz,
+                                                   const int32_t* __restrict__ rowptr,
+                                                   const int32_t* __restrict__ colind,
+                                                   int32_t* __restrict__ sym,
+                                                   const int32_t* __restrict__ mono) {
+  if (*mono) {  // the column-sorted path covers it
+    if (threadIdx.x == 0) *sym = 0;
+    return;
+  }
+  const int i = (int)(((long long)threadIdx.x * n) / 256 + (n > 256 ? 128 % (n / 256) : 0));
+  if (i >= n || (n <= 256 && (int)threadIdx.x >= n)) return;
+  const int e0 = rowptr[i], e1 = rowptr[i + 1];
+  if (e1 == e0) return;
+  const int p0 = mirror_pos_win(rowptr, colind, nnz, colind[e0], i);
+  const int p1 = mirror_pos_win(rowptr, colind, nnz, colind[e1 - 1], i);
+  if (p0 < 0 || p1 < 0) *sym = 0;
 }
 
 __global__ __launch_bounds__(256) void k_sym_perm(int n, int nnz,
@@ -432,6 +428,9 @@ constexpr int kBkMaxBlocks = 8192;   // at most 8192 column blocks (n <= 2^25)
 constexpr int kBkTarget = 2048;      // aimed-for mean entries per column block
 constexpr int kBkTileEntries = 4096; // aimed-for entries per row tile
 constexpr int kBkLdsBytes = 48896;   // dynamic LDS cap of a column-block workgroup
+constexpr int kBkMaxTileRows = 4096; // at most 4096 rows per tile
+constexpr int kBkUnroll = 4;         // loads in flight per thread
+constexpr int kBkColsThreads = 512;  // threads of a column-block workgroup
 
 struct BkShape {
   int shift = 0, nb = 0;
@@ -459,10 +458,26 @@ int bk_lds_cap(int shift) {
 }
 int bk_lds_bytes(int shift) { return (2 * (1 << shift) + 2) * 4 + bk_lds_cap(shift) * 8; }
 
-// Pass 1: column-block counts of a tile of rows (G lanes per row) in LDS;
-// the non-zero ones go to the block totals with one atomic each.  Block 0
-// records the fast-path outcome in flags[3] (flags[1] | flags[2]).
-template <int G>
+// Column-block counts of the entries [ea, eb) of a row tile into h (LDS),
+// kBkUnroll coalesced loads in flight per thread.
+__device__ __forceinline__ void bk_tile_counts(const int32_t* __restrict__ colind, int ea, int eb,
+                                               int shift, int32_t* h) {
+  for (long long base = ea; base < eb; base += 256 * kBkUnroll) {
+    int key[kBkUnroll];
+#pragma unroll
+    for (int u = 0; u < kBkUnroll; ++u) {
+      const long long e = base + u * 256 + threadIdx.x;
+      key[u] = e < eb ? colind[e] >> shift : -1;
+    }
+#pragma unroll
+    for (int u = 0; u < kBkUnroll; ++u)
+      if (key[u] >= 0) atomicAdd(&h[key[u]], 1);
+  }
+}
+
+// Pass 1: column-block counts of a tile of rows (its entries read flat) in
+// LDS; the non-zero ones go to the block totals with one atomic each.
+// Block 0 records the fast-path outcome in flags[3] (flags[1] | flags[2]).
 __global__ __launch_bounds__(256) void k_bk_count(int m, const int32_t* __restrict__ rowptr,
                                                   const int32_t* __restrict__ colind,
                                                   int rows_per_tile, int shift, int nb,
@@ -475,21 +490,19 @@ __global__ __launch_bounds__(256) void k_bk_count(int m, const int32_t* __restri
   for (int b = threadIdx.x; b < nb; b += 256) h[b] = 0;
   __syncthreads();
   const int r0 = blockIdx.x * rows_per_tile, r1 = min(m, r0 + rows_per_tile);
-  for (int row = r0 + (int)threadIdx.x / G; row < r1; row += 256 / G) {
-    const int e1 = rowptr[row + 1];
-    for (int e = rowptr[row] + (int)threadIdx.x % G; e < e1; e += G)
-      atomicAdd(&h[colind[e] >> shift], 1);
-  }
+  bk_tile_counts(colind, rowptr[r0], rowptr[r1], shift, h);
   __syncthreads();
   for (int b = threadIdx.x; b < nb; b += 256)
     if (h[b]) atomicAdd(&btotal[b], h[b]);
 }
 
-// Pass 2: the same counts again; one returning atomic per non-zero block
-// reserves this tile's slots in the block's output range (bbase[b] is the
-// range's start), and every entry then takes a slot with an LDS atomic:
-// srow/sent/scol[slot] = (row, entry, column within the block).  srow and
-// sent are the colindT and perm outputs, used as staging until pass 3.
+// Pass 2: the same counts again (G lanes per row); one returning atomic per
+// non-zero block reserves this tile's slots in the block's output range
+// (bbase[b] is the range's start), and every entry then takes a slot with
+// an LDS atomic: srow/sent/scol[slot] = (row, entry, column within the
+// block).  srow and sent are the colindT and perm outputs, used as staging
+// until pass 3.  (Reading the tile's entries flat and finding their rows by
+// a search in LDS measured slower than lanes per row here.)
 template <int G>
 __global__ __launch_bounds__(256) void k_bk_place(int m, const int32_t* __restrict__ rowptr,
                                                   const int32_t* __restrict__ colind,
@@ -501,7 +514,7 @@ __global__ __launch_bounds__(256) void k_bk_place(int m, const int32_t* __restri
                                                   uint16_t* __restrict__ scol,
                                                   const int32_t* __restrict__ fast) {
   extern __shared__ int32_t h[];  // nb counters, then the same array as nb cursors
-  if (*fast) return;  // uniform over the grid
+  if (*fast) return;              // uniform over the grid
   for (int b = threadIdx.x; b < nb; b += 256) h[b] = 0;
   __syncthreads();
   const int r0 = blockIdx.x * rows_per_tile, r1 = min(m, r0 + rows_per_tile);
@@ -529,10 +542,11 @@ __global__ __launch_bounds__(256) void k_bk_place(int m, const int32_t* __restri
   }
 }
 
-// Exclusive scan of a[0 .. len) in LDS by the whole block (256 threads,
-// each a contiguous run); a[len] = the total.  wsum: 4 ints of LDS.
+// Exclusive scan of a[0 .. len) in LDS by the whole block (BT threads,
+// each a contiguous run); a[len] = the total.  wsum: BT / 64 ints of LDS.
+template <int BT>
 __device__ void lds_exclusive_scan(int32_t* a, int len, int32_t* wsum) {
-  const int per = (len + 255) / 256;
+  const int per = (len + BT - 1) / BT;
   const int lo = min(len, (int)threadIdx.x * per), hi = min(len, lo + per);
   int sum = 0;
   for (int i = lo; i < hi; ++i) sum += a[i];
@@ -547,7 +561,7 @@ __device__ void lds_exclusive_scan(int32_t* a, int len, int32_t* wsum) {
   __syncthreads();
   int off = 0, tot = 0;
 #pragma unroll
-  for (int w = 0; w < 256 / kWave; ++w) {
+  for (int w = 0; w < BT / kWave; ++w) {
     if (w < wid) off += wsum[w];
     tot += wsum[w];
   }
@@ -570,8 +584,8 @@ __device__ void lds_exclusive_scan(int32_t* a, int len, int32_t* wsum) {
 // ones are left in tkv and listed for the medium/long sorts.  All staged
 // inputs are read before the first output is written (block barrier), and
 // block ranges are disjoint, so the in-place use of colindT/perm is safe.
-template <int G>
-__global__ __launch_bounds__(256) void k_bk_cols(int n, int shift, int nb, int cap,
+template <int G, int BT>
+__global__ __launch_bounds__(BT) void k_bk_cols(int n, int shift, int nb, int cap,
                                                  const int32_t* __restrict__ bbase,
                                                  const uint16_t* __restrict__ scol,
                                                  int32_t* __restrict__ colindT,
@@ -581,8 +595,8 @@ __global__ __launch_bounds__(256) void k_bk_cols(int n, int shift, int nb, int c
                                                  int32_t* __restrict__ long_list,
                                                  int32_t* __restrict__ long_count,
                                                  const int32_t* __restrict__ fast) {
-  extern __shared__ int32_t lds[];
-  __shared__ int32_t wsum[256 / kWave];
+  extern __shared__ __align__(16) int32_t lds[];
+  __shared__ int32_t wsum[BT / kWave];
   if (*fast) return;  // uniform over the grid
   const int cb = 1 << shift;
   int32_t* start = lds;                                    // cb + 1
@@ -591,27 +605,48 @@ __global__ __launch_bounds__(256) void k_bk_cols(int n, int shift, int nb, int c
   const int b = blockIdx.x;
   const int s0 = bbase[b], s1 = bbase[b + 1], len = s1 - s0;
   const int c0 = b << shift, ncb = min(cb, n - c0);
-  for (int c = threadIdx.x; c <= ncb; c += 256) start[c] = 0;
+  for (int c = threadIdx.x; c <= ncb; c += BT) start[c] = 0;
   __syncthreads();
-  for (int i = s0 + threadIdx.x; i < s1; i += 256) atomicAdd(&start[scol[i]], 1);
+  for (long long base = s0; base < s1; base += BT * kBkUnroll) {
+    int c[kBkUnroll];
+#pragma unroll
+    for (int u = 0; u < kBkUnroll; ++u) {
+      const long long i = base + u * BT + threadIdx.x;
+      c[u] = i < s1 ? scol[i] : -1;
+    }
+#pragma unroll
+    for (int u = 0; u < kBkUnroll; ++u)
+      if (c[u] >= 0) atomicAdd(&start[c[u]], 1);
+  }
   __syncthreads();
-  lds_exclusive_scan(start, ncb, wsum);
-  for (int c = threadIdx.x; c < ncb; c += 256) {
+  lds_exclusive_scan<BT>(start, ncb, wsum);
+  for (int c = threadIdx.x; c < ncb; c += BT) {
     cur[c] = start[c];
     rowptrT[c0 + c] = s0 + start[c];
   }
   if (b == nb - 1 && threadIdx.x == 0) rowptrT[n] = s1;
   __syncthreads();
   const bool in_lds = len <= cap;
-  for (int i = s0 + threadIdx.x; i < s1; i += 256) {
-    const int p = atomicAdd(&cur[scol[i]], 1);
-    const int2 kv = make_int2(colindT[i], perm[i]);
-    if (in_lds) lkv[p] = kv;
-    else tkv[s0 + p] = kv;
+  for (long long base = s0; base < s1; base += BT * kBkUnroll) {
+    int c[kBkUnroll];
+    int2 kv[kBkUnroll];
+#pragma unroll
+    for (int u = 0; u < kBkUnroll; ++u) {
+      const long long i = base + u * BT + threadIdx.x;
+      c[u] = i < s1 ? scol[i] : -1;
+      kv[u] = i < s1 ? make_int2(colindT[i], perm[i]) : make_int2(0, 0);
+    }
+#pragma unroll
+    for (int u = 0; u < kBkUnroll; ++u) {
+      if (c[u] < 0) continue;
+      const int p = atomicAdd(&cur[c[u]], 1);
+      if (in_lds) lkv[p] = kv[u];
+      else tkv[s0 + p] = kv[u];
+    }
   }
   __syncthreads();
   const int l = threadIdx.x % G;
-  for (int c = threadIdx.x / G; c < ncb; c += 256 / G) {
+  for (int c = threadIdx.x / G; c < ncb; c += BT / G) {
     const int st = start[c], lc = start[c + 1] - st;
     if (lc <= kShort) {
       for (int q = l; q < lc; q += G) {
@@ -815,38 +850,29 @@ int transpose_pattern(int m, int n, int nnz, const int32_t* rowptr, const int32_
     }
   }
   if (m == n && nnz > 0) {
-    hipLaunchKernelGGL(k_sym_probe, dim3(1), dim3(256), 0, s, m, rowptr, colind, w.sym, w.mono);
+    hipLaunchKernelGGL(k_sym_probe, dim3(1), dim3(256), 0, s, m, nnz, rowptr, colind, w.sym,
+                       w.mono);
     hipLaunchKernelGGL(k_sym_perm, dim3(grid_for((long long)m * 8, 256, kGatedGrid)), dim3(256), 0,
                        s, m, nnz, rowptr, colind, rowptrT, colindT, perm, w.sym);
   }
   if (w.bk.on) {
     // column-block form
     const int nb = w.bk.nb, sh = w.bk.shift;
-    int g = 1;
-    while (g < 8 && (long long)g * m < nnz) g <<= 1;
-    // row tiles of about kBkTileEntries entries, a whole number of row groups
-    long long rpt = std::max<long long>(256 / g, (long long)kBkTileEntries * m / nnz);
-    rpt = std::min<long long>(rpt, (long long)m) / (256 / g) * (256 / g);
-    if (rpt < 256 / g) rpt = 256 / g;
+    // row tiles of about kBkTileEntries entries (64 to kBkMaxTileRows rows)
+    const long long rpt = std::min<long long>(
+        kBkMaxTileRows, std::max<long long>(64, (long long)kBkTileEntries * m / nnz));
     const unsigned tiles = (unsigned)((m + rpt - 1) / rpt);
-    const size_t hb = (size_t)nb * 4;
-    switch (g) {
-#define CSRAD_BK_COUNT(G)                                                                     \
-  hipLaunchKernelGGL((k_bk_count<G>), dim3(tiles), dim3(256), hb, s, m, rowptr, colind,        \
-                     (int)rpt, sh, nb, w.bk_total, w.flags)
-      case 1: CSRAD_BK_COUNT(1); break;
-      case 2: CSRAD_BK_COUNT(2); break;
-      case 4: CSRAD_BK_COUNT(4); break;
-      default: CSRAD_BK_COUNT(8); break;
-#undef CSRAD_BK_COUNT
-    }
+    hipLaunchKernelGGL(k_bk_count, dim3(tiles), dim3(256), (size_t)nb * 4, s, m, rowptr, colind,
+                       (int)rpt, sh, nb, w.bk_total, w.flags);
     CSRAD_TRY(scan_exclusive(w.bk_total, w.bk_base, nb, w.total, w.scan_ws, w.scan_bytes, s,
                              w.fast));
+    int g = 1;
+    while (g < 8 && (long long)g * m < nnz) g <<= 1;
     switch (g) {
-#define CSRAD_BK_PLACE(G)                                                                   \
-  hipLaunchKernelGGL((k_bk_place<G>), dim3(tiles), dim3(256), hb, s, m, rowptr, colind,      \
-                     (int)rpt, sh, nb, w.bk_base, w.bk_total + nb, colindT, perm, w.bk_col, \
-                     w.fast)
+#define CSRAD_BK_PLACE(G)                                                                    \
+  hipLaunchKernelGGL((k_bk_place<G>), dim3(tiles), dim3(256), (size_t)nb * 4, s, m, rowptr, \
+                     colind, (int)rpt, sh, nb, w.bk_base, w.bk_total + nb, colindT, perm,   \
+                     w.bk_col, w.fast)
       case 1: CSRAD_BK_PLACE(1); break;
       case 2: CSRAD_BK_PLACE(2); break;
       case 4: CSRAD_BK_PLACE(4); break;
@@ -859,10 +885,10 @@ int transpose_pattern(int m, int n, int nnz, const int32_t* rowptr, const int32_
     const int cap = bk_lds_cap(sh);
     const size_t lb = (size_t)bk_lds_bytes(sh);
     switch (gc) {
-#define CSRAD_BK_COLS(G)                                                                   \
-  hipLaunchKernelGGL((k_bk_cols<G>), dim3(nb), dim3(256), lb, s, n, sh, nb, cap, w.bk_base, \
-                     w.bk_col, colindT, perm, rowptrT, w.tkv, w.long_list, w.long_count,   \
-                     w.fast)
+#define CSRAD_BK_COLS(G)                                                                    \
+  hipLaunchKernelGGL((k_bk_cols<G, kBkColsThreads>), dim3(nb), dim3(kBkColsThreads), lb, s, n, \
+                     sh, nb, cap, w.bk_base, w.bk_col, colindT, perm, rowptrT, w.tkv,         \
+                     w.long_list, w.long_count, w.fast)
       case 1: CSRAD_BK_COLS(1); break;
       case 2: CSRAD_BK_COLS(2); break;
       case 4: CSRAD_BK_COLS(4); break;
