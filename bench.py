@@ -36,6 +36,7 @@ from __future__ import annotations
 
 import argparse
 import concurrent.futures as cf
+import gc
 import json
 import os
 import sys
@@ -1087,9 +1088,14 @@ def main():
     torch.cuda.synchronize()
 
     # Timed region: exactly `steps` steps (three concurrent chains unless
-    # --serial), bracketed by synchronisations.
+    # --serial), bracketed by synchronisations.  Python's cyclic garbage
+    # collector is paused over the timed and attribution passes (collected
+    # just before), as timeit does: a collection pass is host-side noise of
+    # tens of milliseconds that would otherwise land inside one step.
     t_start = torch.cuda.Event(enable_timing=True)
     t_end = torch.cuda.Event(enable_timing=True)
+    gc.collect()
+    gc.disable()
     torch.cuda.synchronize()
     t_start.record()
     w0 = time.perf_counter()
@@ -1122,6 +1128,7 @@ def main():
     a_end.record()
     torch.cuda.synchronize()
     serial_ms = a_start.elapsed_time(a_end) / args.steps
+    gc.enable()
     log(f"attribution pass (one stream): {serial_ms:.3f} ms/step")
 
     # intermediate products of the two SpGEMMs, from the last attribution

@@ -261,9 +261,24 @@ def _skewed_blocks():
     return gen._from_coo(m, n, key // n, key % n, rng.standard_normal(len(key)))
 
 
+def _nearly_symmetric():
+    # a structurally symmetric pattern with one extra entry below the
+    # diagonal (every entry above still finds its mirror: only the
+    # above/below count tells), and the same with one extra entry above
+    s = gen.poisson2d(60, 50)
+    r, c = s.row_of_entry(), s.colind
+    rng = np.random.default_rng(36)
+    out = []
+    for name, (i, j) in (("sym_extra_lower", (2000, 3)), ("sym_extra_upper", (3, 2000))):
+        key = np.unique(np.concatenate([r.astype(np.int64) * s.ncols + c, [i * s.ncols + j]]))
+        out.append((name, gen._from_coo(s.nrows, s.ncols, key // s.ncols, key % s.ncols,
+                                        rng.standard_normal(len(key)))))
+    return out
+
+
 TRANSPOSE_CASES = MATS + [("long_cols", _with_long_columns()), ("agg", gen.aggregation(10001, 8)),
                           ("few_cols", _few_cols()), ("skewed_blocks", _skewed_blocks())] \
-    + _col_sorted_cases()
+    + _col_sorted_cases() + _nearly_symmetric() + [("poisson2d_sym", gen.poisson2d(60, 50))]
 
 
 @pytest.mark.parametrize("name,A", TRANSPOSE_CASES, ids=[n for n, _ in TRANSPOSE_CASES])
