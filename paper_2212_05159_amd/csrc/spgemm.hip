@@ -49,20 +49,34 @@ __host__ __device__ inline int bin_of(long long u, int lists) {
   return kDenseBin;
 }
 
-// Per row: U_i and its bin.  The rows are then grouped by bin with the
-// stable multi-split (ascending row order within a bin, no atomics).
+// Per row: U_i and its bin, one thread per row.  The row's entries are
+// taken kBinBatch at a time with all their loads issued together (A's
+// columns, then the B row bounds they select), so a row costs about two
+// rounds of memory latency, not two per entry.  The rows are then grouped
+// by bin with the stable multi-split (ascending row order within a bin, no
+// atomics).
+constexpr int kBinBatch = 8;
 __global__ __launch_bounds__(kThreads) void k_bin_of(int m, const int32_t* __restrict__ rpA,
                                                      const int32_t* __restrict__ ciA,
                                                      const int32_t* __restrict__ rpB,
                                                      int32_t* __restrict__ binid) {
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < m;
+       i += (long long)gridDim.x * blockDim.x) {
     long long u = 0;
     int lists = 0;
-    for (int a = rpA[i]; a < rpA[i + 1]; ++a) {
-      const int k = ciA[a];
-      const int len = rpB[k + 1] - rpB[k];
-      u += len;
-      lists += len > 0;
+    const int a1 = rpA[i + 1];
+    for (int a0 = rpA[i]; a0 < a1; a0 += kBinBatch) {
+      int k[kBinBatch];
+#pragma unroll
+      for (int t = 0; t < kBinBatch; ++t) k[t] = a0 + t < a1 ? ciA[a0 + t] : -1;
+      int len[kBinBatch];
+#pragma unroll
+      for (int t = 0; t < kBinBatch; ++t) len[t] = k[t] >= 0 ? rpB[k[t] + 1] - rpB[k[t]] : 0;
+#pragma unroll
+      for (int t = 0; t < kBinBatch; ++t) {
+        u += len[t];
+        lists += len[t] > 0;
+      }
     }
     binid[i] = bin_of(u, lists);
   }
@@ -114,6 +128,42 @@ __device__ __forceinline__ int find_sorted(const int32_t* __restrict__ ci, int l
     else hi = mid;
   }
   return -1;
+}
+
+// Windowed lookup in short sorted rows: the first kCWin columns of
+// ci[lo, hi) come from two unaligned 16-byte loads (one round of memory
+// latency; global loads need only 4-byte alignment on this target), so a
+// row of at most kCWin entries needs no search; longer rows search the
+// rest.  len: the array's length (the vector loads stay inside it).
+constexpr int kCWin = 8;
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+typedef i32x4 i32x4_u __attribute__((aligned(4)));
+
+__device__ __forceinline__ void load_win(const int32_t* __restrict__ ci, int len, int lo, int hi,
+                                         int (&v)[kCWin]) {
+  if (lo + kCWin <= len) {
+    const i32x4 a = *reinterpret_cast<const i32x4_u*>(ci + lo);
+    const i32x4 b = *reinterpret_cast<const i32x4_u*>(ci + lo + 4);
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+    v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+#pragma unroll
+    for (int u = 0; u < kCWin; ++u) v[u] = lo + u < hi ? v[u] : INT32_MAX;
+  } else {
+#pragma unroll
+    for (int u = 0; u < kCWin; ++u) v[u] = lo + u < hi ? ci[lo + u] : INT32_MAX;
+  }
+}
+
+// Index of key in the sorted range ci[lo, hi) whose first kCWin columns
+// are v, or -1.
+__device__ __forceinline__ int find_in_win(const int32_t* __restrict__ ci, int lo, int hi,
+                                           const int (&v)[kCWin], int key) {
+  int pos = -1;
+#pragma unroll
+  for (int u = 0; u < kCWin; ++u)
+    if (v[u] == key) pos = lo + u;
+  if (pos < 0 && hi - lo > kCWin && v[kCWin - 1] < key) pos = find_sorted(ci, lo + kCWin, hi, key);
+  return pos;
 }
 
 // C_ij = sum over A's row i (in order) of A_ik B_kj.
@@ -494,43 +544,83 @@ __global__ __launch_bounds__(kThreads) void k_num_dense(
 // ---------------------------------------------------------------------
 // Backward.
 // ---------------------------------------------------------------------
-// gA: G lanes per row of A, lanes over A's entries.
-template <typename T, int G>
+// Both backward kernels are bound by chains of dependent gathers (A's
+// columns -> B's row bounds -> B's columns and values -> C's row -> gC),
+// and the chains a CU keeps in flight are capped by its resident threads,
+// not by the lanes given to a row.  So each lane takes U entries and issues
+// the loads of all U together, stage by stage: U chains in flight per
+// thread.
+
+// gA: G lanes per row of A, each lane U of A's entries at a time (entries
+// l, l + G, l + 2G, ... of the row, so a lane sums in row order); the B
+// rows they select are walked in lock step, one entry of each per round.
+// Every lane of the row's group holds the first kCWin columns of C's row i.
+template <typename T, int G, int U>
 __global__ __launch_bounds__(kThreads) void k_bwd_a(int m, const int32_t* __restrict__ rpA,
                                                     const int32_t* __restrict__ ciA,
                                                     const int32_t* __restrict__ rpB,
                                                     const int32_t* __restrict__ ciB,
                                                     const T* __restrict__ vB,
                                                     const int32_t* __restrict__ rpC,
-                                                    const int32_t* __restrict__ ciC,
+                                                    const int32_t* __restrict__ ciC, int nnzC,
                                                     const T* __restrict__ gC, T* __restrict__ gA) {
   const int b = xcd_block(blockIdx.x, gridDim.x);
   const int i = b * (kThreads / G) + threadIdx.x / G;
   const int l = threadIdx.x % G;
   if (i >= m) return;
   const int c0 = rpC[i], c1 = rpC[i + 1];
+  int win[kCWin];
+  load_win(ciC, nnzC, c0, c1, win);
   const int a1 = rpA[i + 1];
-  for (int a = rpA[i] + l; a < a1; a += G) {
-    const int k = ciA[a];
-    T s = 0;
-    for (int q = rpB[k]; q < rpB[k + 1]; ++q) {
-      const int p = find_sorted(ciC, c0, c1, ciB[q]);
-      if (p >= 0) s += gC[p] * vB[q];
+  for (int a0 = rpA[i] + l; a0 < a1; a0 += G * U) {
+    int k[U], q[U], qe[U];
+    T sum[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) k[u] = a0 + u * G < a1 ? ciA[a0 + u * G] : -1;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      q[u] = k[u] >= 0 ? rpB[k[u]] : 0;
+      qe[u] = k[u] >= 0 ? rpB[k[u] + 1] : 0;
+      sum[u] = 0;
     }
-    gA[a] = s;
+    bool more = true;
+    while (more) {
+      int j[U], p[U];
+      T bv[U], g[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        j[u] = q[u] < qe[u] ? ciB[q[u]] : -1;
+        bv[u] = q[u] < qe[u] ? vB[q[u]] : T(0);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) p[u] = j[u] >= 0 ? find_in_win(ciC, c0, c1, win, j[u]) : -1;
+#pragma unroll
+      for (int u = 0; u < U; ++u) g[u] = p[u] >= 0 ? gC[p[u]] : T(0);
+      more = false;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (p[u] >= 0) sum[u] += g[u] * bv[u];
+        q[u] += q[u] < qe[u];
+        more |= q[u] < qe[u];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (a0 + u * G < a1) gA[a0 + u * G] = sum[u];
   }
 }
 
 // gB: G lanes per row k of B; the entries of the row in turn, the lanes
 // splitting column k of A (A^T's row k, rows ascending, values through
-// permA) and summing with a group reduction.  The entry loop runs the
-// same number of times across the wave (the reduction needs whole groups).
-template <typename T, int G>
+// permA), U of its entries per lane at a time, and summing with a group
+// reduction.  The entry loop runs the same number of times across the wave
+// (the reduction needs whole groups).
+template <typename T, int G, int U>
 __global__ __launch_bounds__(kThreads) void k_bwd_b(
     int n, const int32_t* __restrict__ rpB, const int32_t* __restrict__ ciB,
     const int32_t* __restrict__ rpAT, const int32_t* __restrict__ ciAT,
     const int32_t* __restrict__ permA, const T* __restrict__ vA, const int32_t* __restrict__ rpC,
-    const int32_t* __restrict__ ciC, const T* __restrict__ gC, T* __restrict__ gB) {
+    const int32_t* __restrict__ ciC, int nnzC, const T* __restrict__ gC, T* __restrict__ gB) {
   const int b = xcd_block(blockIdx.x, gridDim.x);
   const int k = b * (kThreads / G) + threadIdx.x / G;
   const int l = threadIdx.x % G;
@@ -543,15 +633,37 @@ __global__ __launch_bounds__(kThreads) void k_bwd_b(
     q1 = rpB[k + 1];
   }
   const int steps = wave_max(q1 - q0);
-  for (int u = 0; u < steps; ++u) {
-    const int q = q0 + u;
+  for (int st = 0; st < steps; ++st) {
+    const int q = q0 + st;
     T s = 0;
     if (q < q1) {
       const int j = ciB[q];
-      for (int t = t0 + l; t < t1; t += G) {
-        const int i = ciAT[t];
-        const int p = find_sorted(ciC, rpC[i], rpC[i + 1], j);
-        if (p >= 0) s += vA[permA[t]] * gC[p];
+      for (int tb = t0 + l; tb < t1; tb += G * U) {
+        int i[U], e[U], lo[U], hi[U], p[U];
+        T av[U], g[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int t = tb + u * G;
+          i[u] = t < t1 ? ciAT[t] : -1;
+          e[u] = t < t1 ? permA[t] : -1;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          lo[u] = i[u] >= 0 ? rpC[i[u]] : 0;
+          hi[u] = i[u] >= 0 ? rpC[i[u] + 1] : 0;
+          av[u] = e[u] >= 0 ? vA[e[u]] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          int win[kCWin];
+          load_win(ciC, nnzC, lo[u], hi[u], win);
+          p[u] = i[u] >= 0 ? find_in_win(ciC, lo[u], hi[u], win, j) : -1;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) g[u] = p[u] >= 0 ? gC[p[u]] : T(0);
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+          if (p[u] >= 0) s += av[u] * g[u];
       }
     }
     s = group_sum<G>(s);
@@ -610,8 +722,7 @@ unsigned persistent_grid(int rows_per_block, int m) {
 int classify(const csrad_csr* A, const csrad_csr* B, const SpgemmWs& w, hipStream_t s) {
   const int m = A->nrows;
   if (m == 0) return fill_i32(w.bin_off, kNumBins + 1, 0, s);
-  unsigned g = (unsigned)((m + kThreads - 1) / kThreads);
-  if (g > 8192) g = 8192;
+  const unsigned g = (unsigned)std::min<long long>(65536, ((long long)m + kThreads - 1) / kThreads);
   hipLaunchKernelGGL(k_bin_of, dim3(g), dim3(kThreads), 0, s, m, A->rowptr, A->colind, B->rowptr,
                      w.binid);
   return group_small_keys(w.binid, m, kNumBins, w.bin_off, w.list, w.group_ws, w.group_bytes, s);
@@ -691,16 +802,40 @@ int lanes_for(long long nnz, int rows) {
   return g;
 }
 
-#define CSRAD_G_SWITCH(g, ...)                            \
-  switch (g) {                                            \
-    case 1: { constexpr int G = 1; __VA_ARGS__; } break;   \
-    case 2: { constexpr int G = 2; __VA_ARGS__; } break;   \
-    case 4: { constexpr int G = 4; __VA_ARGS__; } break;   \
-    case 8: { constexpr int G = 8; __VA_ARGS__; } break;   \
-    case 16: { constexpr int G = 16; __VA_ARGS__; } break; \
-    case 32: { constexpr int G = 32; __VA_ARGS__; } break; \
-    default: { constexpr int G = 64; __VA_ARGS__; } break; \
+// Lanes per row G and entries per lane U from the lanes_for count L of a
+// mean inner length.  Batching U = 4 entries per lane pays when the rows
+// are many for the chip (rows x L at least 8 times the resident threads:
+// each lane then carries four gather chains and there are still threads
+// to spare); with fewer rows, one entry per lane keeps more threads busy
+// (A P's backward, 2.1 M rows: 136 -> 74 us and 149 -> 99 us batched; the
+// backward of P^T (A P), 262 k rows: 37 us unbatched, 71 us batched).
+#define CSRAD_GU_SWITCH(L, BATCH, ...)                                        \
+  if (BATCH) {                                                                \
+    switch (L) {                                                              \
+      case 8: { constexpr int G = 2, U = 4; __VA_ARGS__; } break;              \
+      case 16: { constexpr int G = 4, U = 4; __VA_ARGS__; } break;             \
+      case 32: { constexpr int G = 8, U = 4; __VA_ARGS__; } break;             \
+      default: { constexpr int G = 16, U = 4; __VA_ARGS__; } break;            \
+    }                                                                         \
+  } else {                                                                    \
+    switch (L) {                                                              \
+      case 1: { constexpr int G = 1, U = 1; __VA_ARGS__; } break;              \
+      case 2: { constexpr int G = 2, U = 1; __VA_ARGS__; } break;              \
+      case 4: { constexpr int G = 4, U = 1; __VA_ARGS__; } break;              \
+      case 8: { constexpr int G = 8, U = 1; __VA_ARGS__; } break;              \
+      case 16: { constexpr int G = 16, U = 1; __VA_ARGS__; } break;            \
+      case 32: { constexpr int G = 32, U = 1; __VA_ARGS__; } break;            \
+      default: { constexpr int G = 64, U = 1; __VA_ARGS__; } break;            \
+    }                                                                         \
   }
+
+bool batch_entries(long long rows, int lanes) {
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    cus = 256;
+  return lanes >= 8 && rows * lanes >= 8ll * cus * 2048;
+}
 
 template <typename T>
 int spgemm_bwd_t(const csrad_csr* A, const csrad_csr* B, const csrad_csr* At,
@@ -708,20 +843,24 @@ int spgemm_bwd_t(const csrad_csr* A, const csrad_csr* B, const csrad_csr* At,
                  hipStream_t s) {
   if (gA && A->nrows > 0) {
     const int m = A->nrows;
-    CSRAD_G_SWITCH(lanes_for(A->nnz, m),
-                   hipLaunchKernelGGL((k_bwd_a<T, G>), dim3((m + kThreads / G - 1) / (kThreads / G)),
-                                      dim3(kThreads), 0, s, m, A->rowptr, A->colind, B->rowptr,
-                                      B->colind, static_cast<const T*>(B->vals), C->rowptr,
-                                      C->colind, gC, gA));
+    const int L = lanes_for(A->nnz, m);
+    CSRAD_GU_SWITCH(L, batch_entries(m, L),
+                    hipLaunchKernelGGL((k_bwd_a<T, G, U>),
+                                       dim3((m + kThreads / G - 1) / (kThreads / G)),
+                                       dim3(kThreads), 0, s, m, A->rowptr, A->colind, B->rowptr,
+                                       B->colind, static_cast<const T*>(B->vals), C->rowptr,
+                                       C->colind, C->nnz, gC, gA));
   }
   if (gB && B->nrows > 0) {
     const int n = B->nrows;
-    // lanes from the mean column length of A (the inner loop)
-    CSRAD_G_SWITCH(lanes_for(A->nnz, A->ncols),
-                   hipLaunchKernelGGL((k_bwd_b<T, G>), dim3((n + kThreads / G - 1) / (kThreads / G)),
-                                      dim3(kThreads), 0, s, n, B->rowptr, B->colind, At->rowptr,
-                                      At->colind, permA, static_cast<const T*>(A->vals), C->rowptr,
-                                      C->colind, gC, gB));
+    // from the mean column length of A (the inner loop)
+    const int L = lanes_for(A->nnz, A->ncols);
+    CSRAD_GU_SWITCH(L, batch_entries(n, L),
+                    hipLaunchKernelGGL((k_bwd_b<T, G, U>),
+                                       dim3((n + kThreads / G - 1) / (kThreads / G)),
+                                       dim3(kThreads), 0, s, n, B->rowptr, B->colind, At->rowptr,
+                                       At->colind, permA, static_cast<const T*>(A->vals),
+                                       C->rowptr, C->colind, C->nnz, gC, gB));
   }
   return launch_status();
 }

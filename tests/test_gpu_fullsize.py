@@ -246,3 +246,24 @@ def test_unfused_scan_in_symbolic_passes():
     assert np.array_equal(_np(W2t.rowptr), rpT)
     assert np.array_equal(_np(W2t.colind), ciT)
     assert np.array_equal(_np(perm2), permo)
+
+
+def test_spgemm_bwd_batched_float64():
+    # 600,000 rows of 7 entries (lanes_for 8): rows x lanes reach 8 times
+    # the chip's resident threads, so both backward kernels take U = 4
+    # entries per lane; float64 values against the oracle (the float32 form
+    # at this size runs inside the 128^3 step above)
+    m, n, p = 600_000, 600_000, 80_000
+    A = gen.random_rows(m, n, 7, seed=41)
+    B = gen.random_rows(n, p, 2, seed=42)
+    print(f"[fullsize] SpGEMM VJP, batched entries, {m} rows, float64", flush=True)
+    Ad = sp.CsrTensor.from_host(A, dtype=torch.float64)
+    Bd = sp.CsrTensor.from_host(B, dtype=torch.float64)
+    PC, vC = sp.spgemm(Ad.pattern, Ad.vals, Bd.pattern, Bd.vals)
+    rng = np.random.default_rng(43)
+    gC = rng.standard_normal(PC.nnz)
+    gA, gB = sp.spgemm_bwd(Ad.pattern, Ad.vals, Bd.pattern, Bd.vals, PC,
+                           torch.as_tensor(gC, device="cuda"))
+    gAo, gBo = oracle.spgemm_bwd(A, B, _np(PC.rowptr), _np(PC.colind), gC)
+    assert rel_err(_np(gA), gAo) <= 1e-12
+    assert rel_err(_np(gB), gBo) <= 1e-12
