@@ -102,10 +102,10 @@ __global__ __launch_bounds__(256) void k_mono_out(int m, int nnz, int n,
 // an involution, so perm[e] = mirror position is the same permutation,
 // written in order.  The transpose's pattern is the pattern itself, so
 // rowptrT and colindT are copied on the way.  Clears *sym when some entry
-// has no mirror (the general path then rewrites all three outputs).  8
-// lanes per row.  The lookup reads the first kMirrorWin columns of row j
-// with independent loads (one round of memory latency instead of a chain of
-// binary-search steps) and searches the rest of longer rows.
+// has no mirror (the general path then rewrites all three outputs).  The
+// lookup reads the first kMirrorWin columns of row j with independent loads
+// (one round of memory latency instead of a chain of binary-search steps)
+// and searches the rest of longer rows.
 constexpr int kMirrorWin = 8;
 
 // Unaligned 16- and 8-byte vectors of int32 (global loads need only 4-byte
@@ -115,14 +115,14 @@ typedef int i32x2 __attribute__((ext_vector_type(2)));
 typedef i32x4 i32x4_u __attribute__((aligned(4)));
 typedef i32x2 i32x2_u __attribute__((aligned(4)));
 
-__device__ __forceinline__ int mirror_pos_win(const int32_t* __restrict__ rowptr,
-                                              const int32_t* __restrict__ colind, int nnz, int j,
-                                              int i) {
-  const i32x2 ab = *reinterpret_cast<const i32x2_u*>(rowptr + j);  // rowptr[j], rowptr[j+1]
-  const int a = ab.x, b = ab.y;
+// Position of column i in the sorted row [a, b) of colind, or -1: the first
+// kMirrorWin columns with two 16-byte loads, the rest of a longer row by
+// binary search.
+__device__ __forceinline__ int mirror_in_row(const int32_t* __restrict__ colind, int nnz, int a,
+                                             int b, int i) {
   int v[kMirrorWin];
   if (a + kMirrorWin <= nnz) {
-    // two 16-byte loads cover the first 8 columns of row j (entries past
+    // two 16-byte loads cover the first 8 columns of the row (entries past
     // the row's end are masked)
     const i32x4 lo = *reinterpret_cast<const i32x4_u*>(colind + a);
     const i32x4 hi = *reinterpret_cast<const i32x4_u*>(colind + a + 4);
@@ -150,6 +150,14 @@ __device__ __forceinline__ int mirror_pos_win(const int32_t* __restrict__ rowptr
   return pos;
 }
 
+// Position of column i in row j, or -1.
+__device__ __forceinline__ int mirror_pos_win(const int32_t* __restrict__ rowptr,
+                                              const int32_t* __restrict__ colind, int nnz, int j,
+                                              int i) {
+  const i32x2 ab = *reinterpret_cast<const i32x2_u*>(rowptr + j);  // rowptr[j], rowptr[j+1]
+  return mirror_in_row(colind, nnz, ab.x, ab.y, i);
+}
+
 // Cheap first look: one block checks 256 rows spread over the pattern (the
 // first and the last entry of each, two independent mirror lookups per
 // thread) and clears *sym on a missing mirror, so that clearly unsymmetric
@@ -172,6 +180,12 @@ __global__ __launch_bounds__(256) void k_sym_probe(int n, int nnz,
   if (p0 < 0 || p1 < 0) *sym = 0;
 }
 
+// G lanes per row, each lane U of the row's entries at a time (entries l,
+// l + G, ...) with the loads of all U mirror lookups issued stage by stage
+// (columns, mirror row bounds, mirror windows): the lookups are chains of
+// dependent gathers, and U chains per thread keep more of them in flight
+// than more lanes would (the resident threads are the cap).
+template <int G, int U>
 __global__ __launch_bounds__(256) void k_sym_perm(int n, int nnz,
                                                   const int32_t* __restrict__ rowptr,
                                                   const int32_t* __restrict__ colind,
@@ -180,21 +194,39 @@ __global__ __launch_bounds__(256) void k_sym_perm(int n, int nnz,
                                                   int32_t* __restrict__ perm,
                                                   int32_t* __restrict__ sym) {
   if (*sym == 0) return;  // uniform over the grid: a capped grid costs little when off
-  for (int i = blockIdx.x * (256 / 8) + threadIdx.x / 8; i < n; i += gridDim.x * (256 / 8)) {
+  for (int i = blockIdx.x * (256 / G) + threadIdx.x / G; i < n; i += gridDim.x * (256 / G)) {
     const int e0 = rowptr[i], e1 = rowptr[i + 1];
-    if (threadIdx.x % 8 == 0) {
+    if (threadIdx.x % G == 0) {
       rowptrT[i] = e0;
       if (i == n - 1) rowptrT[n] = e1;
     }
-    for (int e = e0 + threadIdx.x % 8; e < e1; e += 8) {
-      const int c = colind[e];
-      const int pos = mirror_pos_win(rowptr, colind, nnz, c, i);
-      if (pos < 0) {
-        *sym = 0;
-        return;
+    for (int eb = e0 + threadIdx.x % G; eb < e1; eb += G * U) {
+      int c[U], a[U], b[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) c[u] = eb + u * G < e1 ? colind[eb + u * G] : -1;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        a[u] = 0;
+        b[u] = 0;
+        if (c[u] >= 0) {
+          const i32x2 ab = *reinterpret_cast<const i32x2_u*>(rowptr + c[u]);
+          a[u] = ab.x;
+          b[u] = ab.y;
+        }
       }
-      perm[e] = pos;
-      colindT[e] = c;
+      int pos[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) pos[u] = c[u] >= 0 ? mirror_in_row(colind, nnz, a[u], b[u], i) : 0;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (c[u] < 0) continue;
+        if (pos[u] < 0) {
+          *sym = 0;
+          return;
+        }
+        perm[eb + u * G] = pos[u];
+        colindT[eb + u * G] = c[u];
+      }
     }
   }
 }
@@ -852,8 +884,37 @@ int transpose_pattern(int m, int n, int nnz, const int32_t* rowptr, const int32_
   if (m == n && nnz > 0) {
     hipLaunchKernelGGL(k_sym_probe, dim3(1), dim3(256), 0, s, m, nnz, rowptr, colind, w.sym,
                        w.mono);
-    hipLaunchKernelGGL(k_sym_perm, dim3(grid_for((long long)m * 8, 256, kGatedGrid)), dim3(256), 0,
-                       s, m, nnz, rowptr, colind, rowptrT, colindT, perm, w.sym);
+    // lanes from the mean row length; U = 4 entries per lane when the rows
+    // are many for the chip (the lookups are latency chains)
+    int L = 1;
+    while (L < 32 && (long long)L * m < nnz) L <<= 1;
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      cus = 256;
+    const bool batch = L >= 8 && (long long)m * L >= 8ll * cus * 2048;
+    const int gl = batch ? L / 4 : L;
+    const unsigned grid = grid_for((long long)m * gl, 256, kGatedGrid);
+#define CSRAD_SYM_PERM(G, U)                                                                 \
+  hipLaunchKernelGGL((k_sym_perm<G, U>), dim3(grid), dim3(256), 0, s, m, nnz, rowptr, colind, \
+                     rowptrT, colindT, perm, w.sym)
+    if (batch) {
+      switch (gl) {
+        case 2: CSRAD_SYM_PERM(2, 4); break;
+        case 4: CSRAD_SYM_PERM(4, 4); break;
+        default: CSRAD_SYM_PERM(8, 4); break;
+      }
+    } else {
+      switch (gl) {
+        case 1: CSRAD_SYM_PERM(1, 1); break;
+        case 2: CSRAD_SYM_PERM(2, 1); break;
+        case 4: CSRAD_SYM_PERM(4, 1); break;
+        case 8: CSRAD_SYM_PERM(8, 1); break;
+        case 16: CSRAD_SYM_PERM(16, 1); break;
+        default: CSRAD_SYM_PERM(32, 1); break;
+      }
+    }
+#undef CSRAD_SYM_PERM
   }
   if (w.bk.on) {
     // column-block form
