@@ -98,6 +98,15 @@ int csr_spmv_fwd(const csrad_csr *A, const void *x, void *y, void *stream);
 int csr_spmv_bwd(const csrad_csr *A, const csrad_csr *At, const int32_t *perm,
                  const void *x, const void *gy, void *gx, void *gvals,
                  void *stream);
+/* csr_spmv_bwd_split: the same VJP (Section 3.1.1) with both gradients
+ * requested and At/perm given, formed as g_x by the gather over A^T and
+ * g_vals row-wise over A (coalesced writes), the two passes sharing one
+ * launch.  Results are bit-identical to csr_spmv_bwd with At.  Returns
+ * CSRAD_EINVAL when At, perm (nnz > 0), gx or gvals is missing or At does
+ * not match A's shape. */
+int csr_spmv_bwd_split(const csrad_csr *A, const csrad_csr *At,
+                       const int32_t *perm, const void *x, const void *gy,
+                       void *gx, void *gvals, void *stream);
 
 /* ---------------------------------------------------------------------
  * SpDMM, sparse times dense (Section 3.1.3; Table 1, SpDMM row).

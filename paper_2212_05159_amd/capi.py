@@ -44,6 +44,7 @@ _SIGS = {
     "csr_status_string": (C.c_char_p, [C.c_int]),
     "csr_spmv_fwd": (C.c_int, [C.c_void_p] * 4),
     "csr_spmv_bwd": (C.c_int, [C.c_void_p] * 8),
+    "csr_spmv_bwd_split": (C.c_int, [C.c_void_p] * 8),
     "csr_spmm_fwd": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int64, C.c_void_p,
                                C.c_int64, C.c_void_p, C.c_void_p]),
     "csr_spmm_bwd": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p,
@@ -212,6 +213,12 @@ def csr_spmv_bwd(A, At, perm, x, gy, gx, gvals):
     _check("csr_spmv_bwd", load().csr_spmv_bwd(C.byref(A), C.byref(At) if At is not None else None,
                                                _ptr(perm), _ptr(x), _ptr(gy), _ptr(gx),
                                                _ptr(gvals), _stream()))
+
+
+def csr_spmv_bwd_split(A, At, perm, x, gy, gx, gvals):
+    _check("csr_spmv_bwd_split", load().csr_spmv_bwd_split(C.byref(A), C.byref(At), _ptr(perm),
+                                                           _ptr(x), _ptr(gy), _ptr(gx),
+                                                           _ptr(gvals), _stream()))
 
 
 def _plan(plan):

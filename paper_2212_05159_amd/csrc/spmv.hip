@@ -79,7 +79,7 @@ __global__ __launch_bounds__(ROWS) void k_spmv_stream(int m, const int32_t* __re
 }
 
 // Gather over A^T: output row j of A^T is column j of A.
-template <typename T, int G, bool WANT_GX, bool WANT_GV>
+template <typename T, int G, int U, bool WANT_GX, bool WANT_GV>
 __global__ __launch_bounds__(kThreads) void k_spmv_bwd_gather(
     int n, const int32_t* __restrict__ rpT, const int32_t* __restrict__ ciT,
     const int32_t* __restrict__ perm, const T* __restrict__ vals, const T* __restrict__ x,
@@ -91,12 +91,28 @@ __global__ __launch_bounds__(kThreads) void k_spmv_bwd_gather(
   if (j < n) {
     const T xj = WANT_GV ? x[j] : T(0);
     const int t1 = rpT[j + 1];
-    for (int t = rpT[j] + sub; t < t1; t += G) {
-      const int i = ld_stream(&ciT[t]);
-      const int e = ld_stream(&perm[t]);
-      const T g = gy[i];
-      if (WANT_GX) s += vals[e] * g;
-      if (WANT_GV) gv[e] = g * xj;
+    // U entries per lane per round (t = sub, sub + G, ...: the lane sums in
+    // row order), loads issued stage by stage
+    for (int tb = rpT[j] + sub; tb < t1; tb += G * U) {
+      int i[U], e[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int t = tb + u * G;
+        i[u] = t < t1 ? ld_stream(&ciT[t]) : -1;
+        e[u] = t < t1 ? ld_stream(&perm[t]) : -1;
+      }
+      T g[U], v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        g[u] = i[u] >= 0 ? gy[i[u]] : T(0);
+        v[u] = (WANT_GX && i[u] >= 0) ? vals[e[u]] : T(0);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (i[u] < 0) continue;
+        if (WANT_GX) s += v[u] * g[u];
+        if (WANT_GV) gv[e[u]] = g[u] * xj;
+      }
     }
   }
   if (WANT_GX) {
@@ -106,8 +122,9 @@ __global__ __launch_bounds__(kThreads) void k_spmv_bwd_gather(
 }
 
 // Row-wise pass over A: gvals (always) and, with ATOMIC, gx += vals*gy
-// scattered with atomics (gx must be zeroed first).
-template <typename T, int G, bool WANT_GV, bool ATOMIC>
+// scattered with atomics (gx must be zeroed first).  U entries per lane per
+// round, loads issued together.
+template <typename T, int G, int U, bool WANT_GV, bool ATOMIC>
 __global__ __launch_bounds__(kThreads) void k_spmv_bwd_rows(
     int m, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colind,
     const T* __restrict__ vals, const T* __restrict__ x, const T* __restrict__ gy,
@@ -118,10 +135,79 @@ __global__ __launch_bounds__(kThreads) void k_spmv_bwd_rows(
   if (row >= m) return;
   const T g = gy[row];
   const int e1 = rowptr[row + 1];
-  for (int e = rowptr[row] + sub; e < e1; e += G) {
-    const int c = colind[e];
-    if (WANT_GV) gv[e] = g * x[c];
-    if (ATOMIC) atomicAdd(&gx[c], vals[e] * g);
+  for (int eb = rowptr[row] + sub; eb < e1; eb += G * U) {
+    int c[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) c[u] = eb + u * G < e1 ? colind[eb + u * G] : -1;
+    T xv[U], va[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      xv[u] = (WANT_GV && c[u] >= 0) ? x[c[u]] : T(0);
+      va[u] = (ATOMIC && c[u] >= 0) ? vals[eb + u * G] : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (c[u] < 0) continue;
+      if (WANT_GV) gv[eb + u * G] = g * xv[u];
+      if (ATOMIC) atomicAdd(&gx[c[u]], va[u] * g);
+    }
+  }
+}
+
+// The two passes of the split backward in one launch: while both have
+// blocks left, even blocks run the gather over A^T for g_x (GG lanes per
+// row, one entry per lane) and odd blocks the row-wise value gradient over
+// A (GR lanes per row, UR entries per lane), so the scattered gather and
+// the latency-bound row pass overlap on the CUs instead of running one
+// after the other.  Same arithmetic as the two passes alone.
+template <typename T, int GG, int GR, int UR>
+__global__ __launch_bounds__(kThreads) void k_spmv_bwd_pair(
+    int n, int m, int nbg, int nbr, const int32_t* __restrict__ rpT,
+    const int32_t* __restrict__ ciT, const int32_t* __restrict__ perm,
+    const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colind,
+    const T* __restrict__ vals, const T* __restrict__ x, const T* __restrict__ gy,
+    T* __restrict__ gx, T* __restrict__ gv) {
+  const int common = min(nbg, nbr);
+  const int b = blockIdx.x;
+  int kind, idx;
+  if (b < 2 * common) {
+    kind = b & 1;
+    idx = b >> 1;
+  } else {
+    kind = nbg > nbr ? 0 : 1;
+    idx = common + (b - 2 * common);
+  }
+  if (kind == 0) {
+    const int j = idx * (kThreads / GG) + threadIdx.x / GG;
+    const int sub = threadIdx.x % GG;
+    T s = 0;
+    if (j < n) {
+      const int t1 = rpT[j + 1];
+      for (int t = rpT[j] + sub; t < t1; t += GG) {
+        const int i = ld_stream(&ciT[t]);
+        const int e = ld_stream(&perm[t]);
+        s += vals[e] * gy[i];
+      }
+    }
+    s = group_sum<GG>(s);
+    if (j < n && sub == 0) gx[j] = s;
+  } else {
+    const int row = idx * (kThreads / GR) + threadIdx.x / GR;
+    const int sub = threadIdx.x % GR;
+    if (row >= m) return;
+    const T g = gy[row];
+    const int e1 = rowptr[row + 1];
+    for (int eb = rowptr[row] + sub; eb < e1; eb += GR * UR) {
+      int c[UR];
+#pragma unroll
+      for (int u = 0; u < UR; ++u) c[u] = eb + u * GR < e1 ? colind[eb + u * GR] : -1;
+      T xv[UR];
+#pragma unroll
+      for (int u = 0; u < UR; ++u) xv[u] = c[u] >= 0 ? x[c[u]] : T(0);
+#pragma unroll
+      for (int u = 0; u < UR; ++u)
+        if (c[u] >= 0) gv[eb + u * GR] = g * xv[u];
+    }
   }
 }
 
@@ -173,39 +259,73 @@ int spmv_fwd_t(const csrad_csr* A, const void* x, void* y, hipStream_t s) {
   return launch_status();
 }
 
-template <typename T, int G, bool GX, bool GV>
+template <typename T, int G, int U, bool GX, bool GV>
 void launch_gather(const csrad_csr* A, const csrad_csr* At, const int32_t* perm, const T* x,
                    const T* gy, T* gx, T* gv, hipStream_t s) {
   const int n = A->ncols;
   const int blocks = (n + kThreads / G - 1) / (kThreads / G);
-  hipLaunchKernelGGL((k_spmv_bwd_gather<T, G, GX, GV>), dim3(blocks), dim3(kThreads), 0, s, n,
+  hipLaunchKernelGGL((k_spmv_bwd_gather<T, G, U, GX, GV>), dim3(blocks), dim3(kThreads), 0, s, n,
                      At->rowptr, At->colind, perm, static_cast<const T*>(A->vals), x, gy, gx, gv);
 }
 
-template <typename T, int G>
+template <typename T, int G, int U>
 void gather_g(const csrad_csr* A, const csrad_csr* At, const int32_t* perm, const T* x,
               const T* gy, T* gx, T* gv, hipStream_t s) {
-  if (gx && gv) launch_gather<T, G, true, true>(A, At, perm, x, gy, gx, gv, s);
-  else if (gx) launch_gather<T, G, true, false>(A, At, perm, x, gy, gx, gv, s);
-  else launch_gather<T, G, false, true>(A, At, perm, x, gy, gx, gv, s);
+  if (gx && gv) launch_gather<T, G, U, true, true>(A, At, perm, x, gy, gx, gv, s);
+  else if (gx) launch_gather<T, G, U, true, false>(A, At, perm, x, gy, gx, gv, s);
+  else launch_gather<T, G, U, false, true>(A, At, perm, x, gy, gx, gv, s);
 }
 
-template <typename T, int G>
+template <typename T, int G, int U>
 void rows_g(const csrad_csr* A, const T* x, const T* gy, T* gx, T* gv, bool atomic,
             hipStream_t s) {
   const int m = A->nrows;
   const int blocks = (m + kThreads / G - 1) / (kThreads / G);
   const T* v = static_cast<const T*>(A->vals);
   if (atomic && gv)
-    hipLaunchKernelGGL((k_spmv_bwd_rows<T, G, true, true>), dim3(blocks), dim3(kThreads), 0, s, m,
-                       A->rowptr, A->colind, v, x, gy, gx, gv);
+    hipLaunchKernelGGL((k_spmv_bwd_rows<T, G, U, true, true>), dim3(blocks), dim3(kThreads), 0, s,
+                       m, A->rowptr, A->colind, v, x, gy, gx, gv);
   else if (atomic)
-    hipLaunchKernelGGL((k_spmv_bwd_rows<T, G, false, true>), dim3(blocks), dim3(kThreads), 0, s, m,
-                       A->rowptr, A->colind, v, x, gy, gx, gv);
+    hipLaunchKernelGGL((k_spmv_bwd_rows<T, G, U, false, true>), dim3(blocks), dim3(kThreads), 0, s,
+                       m, A->rowptr, A->colind, v, x, gy, gx, gv);
   else
-    hipLaunchKernelGGL((k_spmv_bwd_rows<T, G, true, false>), dim3(blocks), dim3(kThreads), 0, s, m,
-                       A->rowptr, A->colind, v, x, gy, gx, gv);
+    hipLaunchKernelGGL((k_spmv_bwd_rows<T, G, U, true, false>), dim3(blocks), dim3(kThreads), 0, s,
+                       m, A->rowptr, A->colind, v, x, gy, gx, gv);
 }
+
+// Lanes per row G and entries per lane U from the lanes_for count L: the
+// row-wise pass is a chain of dependent gathers per entry, and a CU's
+// resident threads cap the chains in flight, so when the rows are many for
+// the chip (rows x L at least 8 times the resident threads) a lane takes
+// U = 4 entries with their loads issued together (128^3 Poisson: 63 ->
+// 41 us); otherwise one entry per lane.
+bool batch_entries(long long rows, int lanes) {
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    cus = 256;
+  return lanes >= 8 && rows * lanes >= 8ll * cus * 2048;
+}
+
+#define CSRAD_GU_SWITCH(L, BATCH, ...)                                \
+  if (BATCH) {                                                        \
+    switch (L) {                                                      \
+      case 8: { constexpr int G = 2, U = 4; __VA_ARGS__; } break;      \
+      case 16: { constexpr int G = 4, U = 4; __VA_ARGS__; } break;     \
+      case 32: { constexpr int G = 8, U = 4; __VA_ARGS__; } break;     \
+      default: { constexpr int G = 16, U = 4; __VA_ARGS__; } break;    \
+    }                                                                 \
+  } else {                                                            \
+    switch (L) {                                                      \
+      case 1: { constexpr int G = 1, U = 1; __VA_ARGS__; } break;      \
+      case 2: { constexpr int G = 2, U = 1; __VA_ARGS__; } break;      \
+      case 4: { constexpr int G = 4, U = 1; __VA_ARGS__; } break;      \
+      case 8: { constexpr int G = 8, U = 1; __VA_ARGS__; } break;      \
+      case 16: { constexpr int G = 16, U = 1; __VA_ARGS__; } break;    \
+      case 32: { constexpr int G = 32, U = 1; __VA_ARGS__; } break;    \
+      default: { constexpr int G = 64, U = 1; __VA_ARGS__; } break;    \
+    }                                                                 \
+  }
 
 template <typename T>
 int spmv_bwd_t(const csrad_csr* A, const csrad_csr* At, const int32_t* perm, const void* x,
@@ -216,15 +336,11 @@ int spmv_bwd_t(const csrad_csr* A, const csrad_csr* At, const int32_t* perm, con
   T* gvv = static_cast<T*>(gv);
   if (At) {
     if (A->ncols == 0) return CSRAD_OK;
-    switch (lanes_for(A->nnz, A->ncols)) {
-      case 1: gather_g<T, 1>(A, At, perm, xx, gg, gxx, gvv, s); break;
-      case 2: gather_g<T, 2>(A, At, perm, xx, gg, gxx, gvv, s); break;
-      case 4: gather_g<T, 4>(A, At, perm, xx, gg, gxx, gvv, s); break;
-      case 8: gather_g<T, 8>(A, At, perm, xx, gg, gxx, gvv, s); break;
-      case 16: gather_g<T, 16>(A, At, perm, xx, gg, gxx, gvv, s); break;
-      case 32: gather_g<T, 32>(A, At, perm, xx, gg, gxx, gvv, s); break;
-      default: gather_g<T, 64>(A, At, perm, xx, gg, gxx, gvv, s); break;
-    }
+    // one entry per lane: the gather over A^T is bound by its scattered
+    // value reads and gradient writes, not by latency chains (batching
+    // measured no faster for g_x alone and slower fused)
+    const int L = lanes_for(A->nnz, A->ncols);
+    CSRAD_GU_SWITCH(L, false, (gather_g<T, G, U>(A, At, perm, xx, gg, gxx, gvv, s)));
     return launch_status();
   }
   // No transpose: row-wise pass, atomics for A^T gy.
@@ -233,14 +349,47 @@ int spmv_bwd_t(const csrad_csr* A, const csrad_csr* At, const int32_t* perm, con
   }
   if (A->nrows == 0) return launch_status();
   const bool atomic = gxx != nullptr;
-  switch (lanes_for(A->nnz, A->nrows)) {
-    case 1: rows_g<T, 1>(A, xx, gg, gxx, gvv, atomic, s); break;
-    case 2: rows_g<T, 2>(A, xx, gg, gxx, gvv, atomic, s); break;
-    case 4: rows_g<T, 4>(A, xx, gg, gxx, gvv, atomic, s); break;
-    case 8: rows_g<T, 8>(A, xx, gg, gxx, gvv, atomic, s); break;
-    case 16: rows_g<T, 16>(A, xx, gg, gxx, gvv, atomic, s); break;
-    case 32: rows_g<T, 32>(A, xx, gg, gxx, gvv, atomic, s); break;
-    default: rows_g<T, 64>(A, xx, gg, gxx, gvv, atomic, s); break;
+  const int L = lanes_for(A->nnz, A->nrows);
+  CSRAD_GU_SWITCH(L, batch_entries(A->nrows, L),
+                  (rows_g<T, G, U>(A, xx, gg, gxx, gvv, atomic, s)));
+  return launch_status();
+}
+
+template <typename T, int GG, int GR, int UR>
+void launch_pair(const csrad_csr* A, const csrad_csr* At, const int32_t* perm, const T* x,
+                 const T* gy, T* gx, T* gv, hipStream_t s) {
+  const int n = A->ncols, m = A->nrows;
+  const int nbg = (n + kThreads / GG - 1) / (kThreads / GG);
+  const int nbr = (m + kThreads / GR - 1) / (kThreads / GR);
+  if (nbg + nbr == 0) return;
+  hipLaunchKernelGGL((k_spmv_bwd_pair<T, GG, GR, UR>), dim3(nbg + nbr), dim3(kThreads), 0, s, n,
+                     m, nbg, nbr, At->rowptr, At->colind, perm, A->rowptr, A->colind,
+                     static_cast<const T*>(A->vals), x, gy, gx, gv);
+}
+
+template <typename T, int GG>
+void pair_g(const csrad_csr* A, const csrad_csr* At, const int32_t* perm, const T* x, const T* gy,
+            T* gx, T* gv, hipStream_t s) {
+  const int L = lanes_for(A->nnz, A->nrows);
+  CSRAD_GU_SWITCH(L, batch_entries(A->nrows, L),
+                  (launch_pair<T, GG, G, U>(A, At, perm, x, gy, gx, gv, s)));
+}
+
+template <typename T>
+int spmv_bwd_split_t(const csrad_csr* A, const csrad_csr* At, const int32_t* perm, const void* x,
+                     const void* gy, void* gx, void* gv, hipStream_t s) {
+  const T* xx = static_cast<const T*>(x);
+  const T* gg = static_cast<const T*>(gy);
+  T* gxx = static_cast<T*>(gx);
+  T* gvv = static_cast<T*>(gv);
+  switch (lanes_for(A->nnz, A->ncols)) {
+    case 1: pair_g<T, 1>(A, At, perm, xx, gg, gxx, gvv, s); break;
+    case 2: pair_g<T, 2>(A, At, perm, xx, gg, gxx, gvv, s); break;
+    case 4: pair_g<T, 4>(A, At, perm, xx, gg, gxx, gvv, s); break;
+    case 8: pair_g<T, 8>(A, At, perm, xx, gg, gxx, gvv, s); break;
+    case 16: pair_g<T, 16>(A, At, perm, xx, gg, gxx, gvv, s); break;
+    case 32: pair_g<T, 32>(A, At, perm, xx, gg, gxx, gvv, s); break;
+    default: pair_g<T, 64>(A, At, perm, xx, gg, gxx, gvv, s); break;
   }
   return launch_status();
 }
@@ -271,4 +420,19 @@ extern "C" int csr_spmv_bwd(const csrad_csr* A, const csrad_csr* At, const int32
   hipStream_t s = as_stream(stream);
   return A->dtype == CSRAD_F32 ? spmv_bwd_t<float>(A, At, perm, x, gy, gx, gvals, s)
                                : spmv_bwd_t<double>(A, At, perm, x, gy, gx, gvals, s);
+}
+
+extern "C" int csr_spmv_bwd_split(const csrad_csr* A, const csrad_csr* At, const int32_t* perm,
+                                  const void* x, const void* gy, void* gx, void* gvals,
+                                  void* stream) {
+  CSRAD_TRY(check_csr(A, true));
+  if (!At || !gx || !gvals) return CSRAD_EINVAL;
+  if (A->nrows > 0 && !gy) return CSRAD_EINVAL;
+  if (A->ncols > 0 && !x) return CSRAD_EINVAL;
+  CSRAD_TRY(check_csr(At, false));
+  if (At->nrows != A->ncols || At->ncols != A->nrows || At->nnz != A->nnz) return CSRAD_EINVAL;
+  if (A->nnz > 0 && !perm) return CSRAD_EINVAL;
+  hipStream_t s = as_stream(stream);
+  return A->dtype == CSRAD_F32 ? spmv_bwd_split_t<float>(A, At, perm, x, gy, gx, gvals, s)
+                               : spmv_bwd_split_t<double>(A, At, perm, x, gy, gx, gvals, s);
 }

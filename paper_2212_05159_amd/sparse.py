@@ -162,10 +162,10 @@ def spmv_bwd(P, vals, x, gy, need_x=True, need_vals=True, use_transpose=True, mo
     if use_transpose:
         Pt, perm = P.transpose()
         if need_x and need_vals and mode == "split":
-            # A^T gy over A^T, then the value gradient row-wise over A (the
-            # autotuner's choice for patterns with a scattered transpose)
-            capi.csr_spmv_bwd(P.desc(vals), Pt.desc(dtype=vals.dtype), perm, x, gy, gx, None)
-            capi.csr_spmv_bwd(P.desc(vals), None, None, x, gy, None, gv)
+            # A^T gy over A^T and the value gradient row-wise over A, the two
+            # passes in one launch (the autotuner's choice for patterns with
+            # a scattered transpose)
+            capi.csr_spmv_bwd_split(P.desc(vals), Pt.desc(dtype=vals.dtype), perm, x, gy, gx, gv)
         else:
             capi.csr_spmv_bwd(P.desc(vals), Pt.desc(dtype=vals.dtype), perm, x, gy, gx, gv)
     else:
