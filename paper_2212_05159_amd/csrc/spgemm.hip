@@ -553,9 +553,11 @@ __global__ __launch_bounds__(kThreads) void k_num_dense(
 
 // gA: G lanes per row of A, each lane U of A's entries at a time (entries
 // l, l + G, l + 2G, ... of the row, so a lane sums in row order); the B
-// rows they select are walked in lock step, one entry of each per round.
-// Every lane of the row's group holds the first kCWin columns of C's row i.
-template <typename T, int G, int U>
+// rows they select are walked in lock step, Q entries of each per round
+// (U = 4, Q = 1 for many short B rows; U = 1, Q = 4 for few rows with
+// longer B rows).  Every lane of the row's group holds the first kCWin
+// columns of C's row i.
+template <typename T, int G, int U, int Q>
 __global__ __launch_bounds__(kThreads) void k_bwd_a(int m, const int32_t* __restrict__ rpA,
                                                     const int32_t* __restrict__ ciA,
                                                     const int32_t* __restrict__ rpB,
@@ -585,22 +587,32 @@ __global__ __launch_bounds__(kThreads) void k_bwd_a(int m, const int32_t* __rest
     }
     bool more = true;
     while (more) {
-      int j[U], p[U];
-      T bv[U], g[U];
+      int j[U][Q], p[U][Q];
+      T bv[U][Q], g[U][Q];
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        j[u] = q[u] < qe[u] ? ciB[q[u]] : -1;
-        bv[u] = q[u] < qe[u] ? vB[q[u]] : T(0);
-      }
+      for (int u = 0; u < U; ++u)
 #pragma unroll
-      for (int u = 0; u < U; ++u) p[u] = j[u] >= 0 ? find_in_win(ciC, c0, c1, win, j[u]) : -1;
+        for (int w = 0; w < Q; ++w) {
+          const bool in = q[u] + w < qe[u];
+          j[u][w] = in ? ciB[q[u] + w] : -1;
+          bv[u][w] = in ? vB[q[u] + w] : T(0);
+        }
 #pragma unroll
-      for (int u = 0; u < U; ++u) g[u] = p[u] >= 0 ? gC[p[u]] : T(0);
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int w = 0; w < Q; ++w)
+          p[u][w] = j[u][w] >= 0 ? find_in_win(ciC, c0, c1, win, j[u][w]) : -1;
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int w = 0; w < Q; ++w) g[u][w] = p[u][w] >= 0 ? gC[p[u][w]] : T(0);
       more = false;
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        if (p[u] >= 0) sum[u] += g[u] * bv[u];
-        q[u] += q[u] < qe[u];
+#pragma unroll
+        for (int w = 0; w < Q; ++w)
+          if (p[u][w] >= 0) sum[u] += g[u][w] * bv[u][w];
+        q[u] = min(q[u] + Q, qe[u]);
         more |= q[u] < qe[u];
       }
     }
@@ -668,6 +680,79 @@ __global__ __launch_bounds__(kThreads) void k_bwd_b(
     }
     s = group_sum<G>(s);
     if (q < q1 && l == 0) gB[q] = s;
+  }
+}
+
+// gB for short columns of A (at most kColShort entries, e.g. A = P^T with
+// one entry per column): one thread per row k of B holds column k of A in
+// registers (rows, values, and the first kCWin columns of each C row they
+// select) and walks row k of B kQ entries per round, its gathers issued
+// together; a column with more entries takes the plain loop.  Sums over the
+// column in order, as the general kernel does with one lane.
+constexpr int kColShort = 2;
+constexpr int kQ = 4;
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_bwd_b_short(
+    int n, const int32_t* __restrict__ rpB, const int32_t* __restrict__ ciB,
+    const int32_t* __restrict__ rpAT, const int32_t* __restrict__ ciAT,
+    const int32_t* __restrict__ permA, const T* __restrict__ vA, const int32_t* __restrict__ rpC,
+    const int32_t* __restrict__ ciC, int nnzC, const T* __restrict__ gC, T* __restrict__ gB) {
+  const int k = xcd_block(blockIdx.x, gridDim.x) * kThreads + threadIdx.x;
+  if (k >= n) return;
+  const int t0 = rpAT[k], t1 = rpAT[k + 1], q0 = rpB[k], q1 = rpB[k + 1];
+  const int cnt = t1 - t0;
+  if (cnt > kColShort) {
+    for (int q = q0; q < q1; ++q) {
+      const int j = ciB[q];
+      T s = 0;
+      for (int t = t0; t < t1; ++t) {
+        const int i = ciAT[t];
+        const int lo = rpC[i], hi = rpC[i + 1];
+        int win[kCWin];
+        load_win(ciC, nnzC, lo, hi, win);
+        const int p = find_in_win(ciC, lo, hi, win, j);
+        if (p >= 0) s += vA[permA[t]] * gC[p];
+      }
+      gB[q] = s;
+    }
+    return;
+  }
+  int lo[kColShort], hi[kColShort], win[kColShort][kCWin];
+  T av[kColShort];
+#pragma unroll
+  for (int u = 0; u < kColShort; ++u) {
+    const int i = u < cnt ? ciAT[t0 + u] : -1;
+    const int e = u < cnt ? permA[t0 + u] : -1;
+    lo[u] = i >= 0 ? rpC[i] : 0;
+    hi[u] = i >= 0 ? rpC[i + 1] : 0;
+    av[u] = e >= 0 ? vA[e] : T(0);
+  }
+#pragma unroll
+  for (int u = 0; u < kColShort; ++u) load_win(ciC, nnzC, lo[u], hi[u], win[u]);
+  for (int qb = q0; qb < q1; qb += kQ) {
+    int j[kQ];
+#pragma unroll
+    for (int w = 0; w < kQ; ++w) j[w] = qb + w < q1 ? ciB[qb + w] : -1;
+    int p[kQ][kColShort];
+    T g[kQ][kColShort];
+#pragma unroll
+    for (int w = 0; w < kQ; ++w)
+#pragma unroll
+      for (int u = 0; u < kColShort; ++u)
+        p[w][u] = (j[w] >= 0 && u < cnt) ? find_in_win(ciC, lo[u], hi[u], win[u], j[w]) : -1;
+#pragma unroll
+    for (int w = 0; w < kQ; ++w)
+#pragma unroll
+      for (int u = 0; u < kColShort; ++u) g[w][u] = p[w][u] >= 0 ? gC[p[w][u]] : T(0);
+#pragma unroll
+    for (int w = 0; w < kQ; ++w) {
+      if (j[w] < 0) continue;
+      T s = 0;
+#pragma unroll
+      for (int u = 0; u < kColShort; ++u)
+        if (p[w][u] >= 0) s += av[u] * g[w][u];
+      gB[qb + w] = s;
+    }
   }
 }
 
@@ -844,8 +929,10 @@ int spgemm_bwd_t(const csrad_csr* A, const csrad_csr* B, const csrad_csr* At,
   if (gA && A->nrows > 0) {
     const int m = A->nrows;
     const int L = lanes_for(A->nnz, m);
+    // entries of A per lane when A's rows are many, else entries of the B
+    // rows per round
     CSRAD_GU_SWITCH(L, batch_entries(m, L),
-                    hipLaunchKernelGGL((k_bwd_a<T, G, U>),
+                    hipLaunchKernelGGL((k_bwd_a<T, G, U, (U == 1 ? 4 : 1)>),
                                        dim3((m + kThreads / G - 1) / (kThreads / G)),
                                        dim3(kThreads), 0, s, m, A->rowptr, A->colind, B->rowptr,
                                        B->colind, static_cast<const T*>(B->vals), C->rowptr,
@@ -855,6 +942,13 @@ int spgemm_bwd_t(const csrad_csr* A, const csrad_csr* B, const csrad_csr* At,
     const int n = B->nrows;
     // from the mean column length of A (the inner loop)
     const int L = lanes_for(A->nnz, A->ncols);
+    if (L <= kColShort) {
+      // short columns of A: one thread per row of B, the column in registers
+      hipLaunchKernelGGL((k_bwd_b_short<T>), dim3((n + kThreads - 1) / kThreads), dim3(kThreads),
+                         0, s, n, B->rowptr, B->colind, At->rowptr, At->colind, permA,
+                         static_cast<const T*>(A->vals), C->rowptr, C->colind, C->nnz, gC, gB);
+      return launch_status();
+    }
     CSRAD_GU_SWITCH(L, batch_entries(n, L),
                     hipLaunchKernelGGL((k_bwd_b<T, G, U>),
                                        dim3((n + kThreads / G - 1) / (kThreads / G)),
