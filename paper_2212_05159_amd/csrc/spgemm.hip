@@ -324,7 +324,7 @@ __device__ __forceinline__ void wave_sync_lds() {
 // memory latency of one row.
 template <typename T, int G, bool NUM, int R>
 __global__ __launch_bounds__(kThreads) void k_merge(
-    int bin, const int32_t* __restrict__ list, const int32_t* __restrict__ bin_off,
+    int m, int bin, const int32_t* __restrict__ list, const int32_t* __restrict__ bin_off,
     const int32_t* __restrict__ rpA, const int32_t* __restrict__ ciA, const T* __restrict__ vA,
     const int32_t* __restrict__ rpB, const int32_t* __restrict__ ciB, const T* __restrict__ vB,
     const int32_t* __restrict__ rpC, int32_t* __restrict__ ciC, T* __restrict__ vC,
@@ -333,6 +333,9 @@ __global__ __launch_bounds__(kThreads) void k_merge(
   constexpr int kWin = merge_window<R>();
   __shared__ int s_b0[R][kThreads], s_len[R][kThreads], s_a[R][kThreads];
   const int first = bin_off[bin], nrows = bin_off[bin + 1] - first;
+  // a class holding all m rows lists them in order (the grouping is
+  // stable): the row is its index, one dependent load fewer
+  const bool all_rows = nrows == m;
   const int lane = __lane_id(), l = threadIdx.x % G, g0 = threadIdx.x - l;
   const unsigned long long gm = group_mask<G>(lane);
   const unsigned long long below = gm & ((1ull << lane) - 1ull);
@@ -344,7 +347,7 @@ __global__ __launch_bounds__(kThreads) void k_merge(
     for (int t = 0; t < R; ++t) {
       const int idx = base + (threadIdx.x / G) * R + t;
       valid[t] = idx < nrows;
-      i[t] = valid[t] ? list[first + idx] : 0;
+      i[t] = valid[t] ? (all_rows ? idx : list[first + idx]) : 0;
     }
 #pragma unroll
     for (int t = 0; t < R; ++t) {
@@ -840,14 +843,14 @@ void merge_bin(int bin, int rows, const csrad_csr* A, const csrad_csr* B, const 
   const long long resident_groups = (long long)cus * 8 * (kThreads / G);
   if (RMAX > 1 && rows >= 8 * resident_groups) {
     const unsigned g = persistent_grid(kThreads / G * RMAX, rows);
-    hipLaunchKernelGGL((k_merge<T, G, NUM, RMAX>), dim3(g), dim3(kThreads), 0, s, bin, w.list,
-                       w.bin_off, A->rowptr, A->colind, vA, B->rowptr, B->colind, vB, rpC, ciC, vC,
-                       w.counts);
+    hipLaunchKernelGGL((k_merge<T, G, NUM, RMAX>), dim3(g), dim3(kThreads), 0, s, A->nrows, bin,
+                       w.list, w.bin_off, A->rowptr, A->colind, vA, B->rowptr, B->colind, vB, rpC,
+                       ciC, vC, w.counts);
   } else {
     const unsigned g = persistent_grid(kThreads / G, rows);
-    hipLaunchKernelGGL((k_merge<T, G, NUM, 1>), dim3(g), dim3(kThreads), 0, s, bin, w.list,
-                       w.bin_off, A->rowptr, A->colind, vA, B->rowptr, B->colind, vB, rpC, ciC, vC,
-                       w.counts);
+    hipLaunchKernelGGL((k_merge<T, G, NUM, 1>), dim3(g), dim3(kThreads), 0, s, A->nrows, bin,
+                       w.list, w.bin_off, A->rowptr, A->colind, vA, B->rowptr, B->colind, vB, rpC,
+                       ciC, vC, w.counts);
   }
 }
 
