@@ -67,6 +67,10 @@ __device__ __forceinline__ int sum_parts(const int32_t* __restrict__ part, int n
   return s_sum;
 }
 
+// Columns of a row read per round (loads issued together) by the
+// analysis passes, which walk one row per thread.
+constexpr int kRowBatch = 8;
+
 __global__ __launch_bounds__(kThreads) void k_tri_prep(int n, int lower,
                                                        const int32_t* __restrict__ rp,
                                                        const int32_t* __restrict__ ci,
@@ -82,10 +86,18 @@ __global__ __launch_bounds__(kThreads) void k_tri_prep(int n, int lower,
     if (i < n) {
       int deps = 0;
       bool diag = false;
-      for (int e = rp[i]; e < rp[i + 1]; ++e) {
-        const int j = ci[e];
-        deps += dep_side(lower, i, j);
-        diag |= (j == i);
+      const int e1 = rp[i + 1];
+      // kRowBatch columns per round with their loads issued together
+      for (int eb = rp[i]; eb < e1; eb += kRowBatch) {
+        int j[kRowBatch];
+#pragma unroll
+        for (int u = 0; u < kRowBatch; ++u) j[u] = eb + u < e1 ? ci[eb + u] : -1;
+#pragma unroll
+        for (int u = 0; u < kRowBatch; ++u) {
+          if (j[u] < 0) continue;
+          deps += dep_side(lower, i, j[u]);
+          diag |= (j[u] == i);
+        }
       }
       indeg[i] = deps;
       level_of_row[i] = deps == 0 ? 0 : kUnset;
@@ -213,9 +225,18 @@ __global__ __launch_bounds__(kThreads) void k_tri_pull(int n, int lower,
     bool placed = false;
     if (i < n && level_of_row[i] == kUnset) {
       int cnt = 0;
-      for (int e = rp[i]; e < rp[i + 1]; ++e) {
-        const int j = ci[e];
-        if (dep_side(lower, i, j) && level_of_row[j] > L) ++cnt;
+      const int e1 = rp[i + 1];
+      // kRowBatch columns per round, then their levels, loads issued together
+      for (int eb = rp[i]; eb < e1; eb += kRowBatch) {
+        int j[kRowBatch];
+#pragma unroll
+        for (int u = 0; u < kRowBatch; ++u) j[u] = eb + u < e1 ? ci[eb + u] : -1;
+        int lv[kRowBatch];
+#pragma unroll
+        for (int u = 0; u < kRowBatch; ++u)
+          lv[u] = (j[u] >= 0 && dep_side(lower, i, j[u])) ? level_of_row[j[u]] : L;
+#pragma unroll
+        for (int u = 0; u < kRowBatch; ++u) cnt += lv[u] > L;
       }
       if (cnt == 0) {
         level_of_row[i] = L + 1;
