@@ -110,3 +110,18 @@ def test_sparse_add_and_inverse_factor_argument_errors(lib):
     Lt = capi.csrad_csr(4, 4, 3, 0, 1, 1, None)  # nnz differs from L's
     assert lib.csr_pcg_step(C.byref(d), 3, None, C.byref(d), C.byref(Lt), 1, 0, None, None,
                             None, 1, 1, 1, 1, 1, 1, None, 0, 1, 1 << 30, None) == -1
+
+
+def test_split_spmv_bwd_argument_errors(lib):
+    # the paired split backward needs A^T (of A's transposed shape), perm and
+    # both outputs; every refusal comes back before any launch
+    d = capi.csrad_csr(4, 5, 4, 0, 1, 1, 1)
+    t = capi.csrad_csr(5, 4, 4, 0, 1, 1, None)
+    assert lib.csr_spmv_bwd_split(C.byref(d), None, 1, 1, 1, 1, 1, None) == -1
+    assert lib.csr_spmv_bwd_split(C.byref(d), C.byref(t), None, 1, 1, 1, 1, None) == -1
+    assert lib.csr_spmv_bwd_split(C.byref(d), C.byref(t), 1, 1, 1, None, 1, None) == -1
+    assert lib.csr_spmv_bwd_split(C.byref(d), C.byref(t), 1, 1, 1, 1, None, None) == -1
+    same = capi.csrad_csr(4, 5, 4, 0, 1, 1, None)  # A's own shape, not A^T's
+    assert lib.csr_spmv_bwd_split(C.byref(d), C.byref(same), 1, 1, 1, 1, 1, None) == -1
+    bad = capi.csrad_csr(4, 5, 4, 7, 1, 1, 1)  # unknown value type
+    assert lib.csr_spmv_bwd_split(C.byref(bad), C.byref(t), 1, 1, 1, 1, 1, None) == -2
