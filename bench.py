@@ -216,7 +216,14 @@ def batched_section(blocks, gen_s, reps=5, skew=None):
         "whole_matrix_ms": round(tot(whole), 4),
         "per_block_ms": round(per_ms, 4),
         "speedup_vs_per_block": round(per_ms / tot(tuned), 2),
-        "launches_per_step": 6 + sum(int(v["split"]) for v in B.bwd_times.values()),
+        # launches: one per SpMV/SpMM op (two for a split backward through
+        # the queue); the solves 3 (per-block: forward, adjoint, value
+        # gradients) or 2 (cooperative), or one per wide level (grid: None)
+        "launches_per_step": None if LB.tri_mode == "grid" else (
+            4 + sum(int(v["split"]) for op, v in B.bwd_times.items()
+                    if B.impl[op + "_bwd"] == "queue") + (3 if LB.tri_mode == "blocks" else 2)),
+        "op_impl": {op: {k2: (round(v2, 4) if isinstance(v2, float) else v2)
+                         for k2, v2 in v.items()} for op, v in B.impl_times.items()},
         "trisolve_modes_ms": {m: round(v, 4) for m, v in tri_modes.items()},
         "trisolve_mode": LB.tri_mode,
         "backward_split": {op: {k2: (round(v2, 4) if isinstance(v2, float) else v2)
@@ -240,7 +247,8 @@ def batched_section(blocks, gen_s, reps=5, skew=None):
 def skew_section(blocks, reps):
     """SpMV and SpMM (64 columns) forward and backward over blocks with
     heavy-tailed row lengths, with every block row-split, every block
-    merge-path, and the autotuner's choice."""
+    merge-path, the plain per-matrix kernels over the concatenation, and the
+    autotuner's choice."""
     import torch
     from paper_2212_05159_amd import batch as bt
 
@@ -285,10 +293,15 @@ def skew_section(blocks, reps):
             v = var if fam.startswith("spmv") else (bt.rows_variant(16) if var != bt.MERGE else var)
             B.set_variants(fam, np.full(B.nblocks, v, np.int32))
         res[label] = run(label)
+    # the library's per-matrix kernels over the whole concatenation
+    B.impl = {op: "plain" for op in B.impl}
+    res["plain"] = run("plain")
     B.autotune(k=k, reps=3)
     res["tuned"] = run("tuned")
+    res["op_impl"] = {op: v["impl"] for op, v in B.impl_times.items()}
     log("uneven rows: " + ", ".join(f"{lab} spmm fwd {res[lab]['spmm fwd']['ms']} ms"
-                                     for lab in ("row_split", "merge_path", "tuned")))
+                                     for lab in ("row_split", "merge_path", "plain", "tuned"))
+        + f"; kept {res['op_impl']}")
     return res
 
 

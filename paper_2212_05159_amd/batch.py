@@ -1,7 +1,10 @@
 """Batches of independent CSR matrices of uneven sizes as one block-diagonal
 matrix, with every op (SpMV and SpMM forward and backward, the triangular
 solve and its adjoint) run as ONE persistent launch over a work queue
-(``csr_batch_*`` in the library).
+(``csr_batch_*`` in the library), or, where the autotuner measures it
+faster, as the library's per-matrix kernel over the whole concatenation
+(one launch as well, one traversal for every block; for the solve, one
+grid launch per wide level of the batch).
 
 A plan cuts the blocks into row-aligned tasks of about equal cost (rows +
 stored entries), ordered by block cost, largest first; each task carries
@@ -71,10 +74,17 @@ class Batch:
         # pass over A^T); set by autotune
         self.bwd_split = {"spmv": False, "spmm": False}
         # triangular solves: "blocks" (a workgroup per block, levels in
-        # order inside it) or "levels" (one cooperative launch, all
-        # workgroups on each level of the batch, grid barriers between);
-        # set by autotune_trisolve
+        # order inside it), "levels" (one cooperative launch, all
+        # workgroups on each level of the batch, grid barriers between) or
+        # "grid" (the library's level-scheduled solve of the whole
+        # block-diagonal matrix: one grid launch per wide level of the
+        # batch); set by autotune_trisolve
         self.tri_mode = "blocks"
+        # per op: "queue" (the persistent launch over the plan's work queue,
+        # per-block variants) or "plain" (the library's per-matrix kernel
+        # over the whole concatenation: also one launch, one traversal for
+        # every block); set by autotune, which keeps the faster
+        self.impl = {"spmv": "queue", "spmv_bwd": "queue", "spmm": "queue", "spmm_bwd": "queue"}
         self._plans = {}
         self._tri = {}
         rows = np.diff(self.block_rowptr).astype(np.int64)
@@ -131,6 +141,8 @@ class Batch:
         vals = self.A.vals if vals is None else vals
         sp._check_vals(self.pattern, vals)
         sp._check_dense(x, vals, (self.pattern.ncols,), "x")
+        if self.impl["spmv"] == "plain":
+            return sp.spmv(self.pattern, vals, x)
         y = torch.empty(self.pattern.nrows, dtype=vals.dtype, device=vals.device)
         capi.csr_batch_spmv_fwd(self.pattern.desc(vals), self.plan("spmv").plan, x, y)
         return y
@@ -142,6 +154,8 @@ class Batch:
         sp._check_dense(gy, vals, (P.nrows,), "gy")
         if need_vals:
             sp._check_dense(x, vals, (P.ncols,), "x")
+        if self.impl["spmv_bwd"] == "plain":
+            return sp.spmv_bwd(P, vals, x, gy, need_x=need_x, need_vals=need_vals)
         Pt, perm = P.transpose()
         gx = torch.empty(P.ncols, dtype=vals.dtype, device=vals.device) if need_x else None
         gv = torch.empty(P.nnz, dtype=vals.dtype, device=vals.device) if need_vals else None
@@ -158,6 +172,8 @@ class Batch:
         sp._check_vals(self.pattern, vals)
         k = sp._cols(B, "B")
         sp._check_dense(B, vals, (self.pattern.ncols, k), "B")
+        if self.impl["spmm"] == "plain":
+            return sp.spmm(self.pattern, vals, B)
         out = torch.empty(self.pattern.nrows, k, dtype=vals.dtype, device=vals.device)
         capi.csr_batch_spmm_fwd(self.pattern.desc(vals), self.plan("spmm").plan, k, B,
                                 B.stride(0), out, out.stride(0))
@@ -171,6 +187,8 @@ class Batch:
         sp._check_dense(gC, vals, (P.nrows, k), "gC")
         if need_vals:
             sp._check_dense(B, vals, (P.ncols, k), "B")
+        if self.impl["spmm_bwd"] == "plain":
+            return sp.spmm_bwd(P, vals, B, gC, need_B=need_B, need_vals=need_vals)
         Pt, perm = P.transpose()
         gB = torch.empty(P.ncols, k, dtype=vals.dtype, device=vals.device) if need_B else None
         gv = torch.empty(P.nnz, dtype=vals.dtype, device=vals.device) if need_vals else None
@@ -207,6 +225,8 @@ class Batch:
         sp._check_square(PT, "batch trisolve")
         sp._check_vals(PT, T.vals)
         sp._check_dense(b, T.vals, (PT.nrows,), "b")
+        if self.tri_mode == "grid":
+            return sp.trisolve(PT, T.vals, b, lower)
         x = torch.empty_like(b)
         if self.tri_mode == "levels":
             nl, _, lp, lr, _ = PT.levels(lower)
@@ -222,6 +242,8 @@ class Batch:
         sp._check_vals(PT, T.vals)
         sp._check_dense(x, T.vals, (PT.nrows,), "x")
         sp._check_dense(gx, T.vals, (PT.nrows,), "gx")
+        if self.tri_mode == "grid":
+            return sp.trisolve_bwd(PT, T.vals, x, gx, lower, need_vals)
         Pt, perm = PT.transpose()
         gb = torch.empty_like(gx)
         gv = torch.empty(PT.nnz, dtype=T.vals.dtype, device=T.vals.device) if need_vals else None
@@ -253,8 +275,11 @@ class Batch:
     def autotune(self, families=("spmv", "spmv_t", "spmm", "spmm_t"), k=64, reps=3, seed=0):
         """Per class of blocks (block_classes), times every candidate
         variant of each op family on a plan holding only that class's
-        blocks and keeps the fastest.  Returns {family: {class: (variant,
-        ms)}}."""
+        blocks and keeps the fastest; then the fused or split backward, and
+        per op the persistent launch or the plain whole-batch kernel
+        (impl_times).  Returns {family: {class: (variant, ms)}}."""
+        for op in self.impl:  # the queue's own timings below run through the queue
+            self.impl[op] = "queue"
         classes = self.block_classes()
         keys = sorted(set(classes))
         dev = self.A.vals.device
@@ -319,13 +344,30 @@ class Batch:
             self.bwd_split[op] = ms[True] < ms[False]
             self.bwd_times[op] = {"fused_ms": ms[False], "split_ms": ms[True],
                                   "split": self.bwd_split[op]}
+        # per op, the tuned persistent launch against the plain kernel over
+        # the whole concatenation: keep the faster
+        self.impl_times = {}
+        runs = {"spmv": ("spmv", lambda: self.spmv(x)),
+                "spmv_bwd": ("spmv_t", lambda: self.spmv_bwd(x, gy)),
+                "spmm": ("spmm", lambda: self.spmm(B)),
+                "spmm_bwd": ("spmm_t", lambda: self.spmm_bwd(B, G))}
+        for op, (fam, fn) in runs.items():
+            if fam not in families:
+                continue
+            ms = {}
+            for impl in ("queue", "plain"):
+                self.impl[op] = impl
+                ms[impl] = _time(fn, reps)
+            self.impl[op] = min(ms, key=ms.get)
+            self.impl_times[op] = {"queue_ms": ms["queue"], "plain_ms": ms["plain"],
+                                   "impl": self.impl[op]}
         return out
 
 
     def autotune_trisolve(self, T, lower=True, reps=3, seed=0):
-        """Times the two batched solve modes (forward + adjoint) with the
-        factor T on this batch's blocks and keeps the faster; returns
-        {mode: ms}."""
+        """Times the batched solve modes (forward + adjoint) with the factor
+        T on this batch's blocks and keeps the fastest; returns {mode:
+        ms}."""
         dev = T.vals.device
         g = torch.Generator(device=dev)
         g.manual_seed(seed)
@@ -333,7 +375,7 @@ class Batch:
         b = torch.randn(n, generator=g, device=dev, dtype=T.vals.dtype)
         gx = torch.randn(n, generator=g, device=dev, dtype=T.vals.dtype)
         ms = {}
-        for mode in ("blocks", "levels"):
+        for mode in ("blocks", "levels", "grid"):
             self.tri_mode = mode
             try:
                 x = self.trisolve(T, b, lower)

@@ -106,6 +106,17 @@ def test_batched_ops_match_oracle(blocks, dtype, k, vname):
     _, gvm1 = Bt.spmm_bwd(X, G, need_B=False)
     assert torch.equal(gx1, gx) and torch.equal(gv1, gv)
     assert torch.equal(gX1, gX) and torch.equal(gvm1, gvm)
+    # the plain whole-batch kernels (the autotuner's other choice per op)
+    Bt.impl = {op: "plain" for op in Bt.impl}
+    assert_close(Bt.spmv(x), oracle.spmv(Ao, f(x)), dtype, f"{vname} y (plain)")
+    gxp, gvp = Bt.spmv_bwd(x, gy)
+    assert_close(gxp, gxo, dtype, f"{vname} gx (plain)")
+    assert_close(gvp, gvo, dtype, f"{vname} gvals (plain)")
+    assert_close(Bt.spmm(X), oracle.spmm(Ao, f(X)), dtype, f"{vname} C (plain)")
+    gXp, gvmp = Bt.spmm_bwd(X, G)
+    assert_close(gXp, gXo, dtype, f"{vname} gB (plain)")
+    assert_close(gvmp, gvmo, dtype, f"{vname} gvals(SpMM) (plain)")
+    Bt.impl = {op: "queue" for op in Bt.impl}
     # split backward (A^T products over A^T's plan, value gradients row-wise
     # over A's plan): the same products and sums, so the same bits
     Bt.bwd_split = {"spmv": True, "spmm": True}
@@ -176,7 +187,7 @@ def ic0_blocks():
     return Ls
 
 
-@pytest.mark.parametrize("mode", ["blocks", "levels"])
+@pytest.mark.parametrize("mode", ["blocks", "levels", "grid"])
 @pytest.mark.parametrize("dtype", [torch.float32, torch.float64], ids=["f32", "f64"])
 def test_batched_trisolve_ic0_matches_oracle(ic0_blocks, dtype, mode):
     # both batched solve modes: a workgroup per block ("blocks"), and one
@@ -204,9 +215,9 @@ def test_batched_trisolve_ic0_matches_oracle(ic0_blocks, dtype, mode):
     # equal to the library's level-by-level solve of the whole matrix
     x1 = sp.trisolve(T.pattern, T.vals, b, True)
     assert rel_err(x, x1.cpu().numpy()) <= TOL[dtype]
-    # the autotuner times both modes and keeps one; results unchanged
+    # the autotuner times the three modes and keeps one; results unchanged
     ms = Bt.autotune_trisolve(T, True, reps=1)
-    assert set(ms) == {"blocks", "levels"} and Bt.tri_mode in ms
+    assert set(ms) == {"blocks", "levels", "grid"} and Bt.tri_mode in ms
     assert_close(Bt.trisolve(T, b, True), xo, dtype, "x (tuned mode)")
 
 
@@ -243,6 +254,8 @@ def test_autotuned_variants_match_oracle(blocks):
     res = Bt.autotune(k=64, reps=1)
     assert set(res) == {"spmv", "spmv_t", "spmm", "spmm_t"}
     assert set(Bt.bwd_times) == {"spmv", "spmm"}
+    assert set(Bt.impl_times) == {"spmv", "spmv_bwd", "spmm", "spmm_bwd"}
+    assert all(Bt.impl[op] == v["impl"] in ("queue", "plain") for op, v in Bt.impl_times.items())
     classes = set(Bt.block_classes())
     for fam, per in res.items():
         assert set(per) == classes
