@@ -64,7 +64,32 @@ __device__ __forceinline__ int sum_parts(const int32_t* __restrict__ part, int n
   for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
   if (__lane_id() == 0 && c) atomicAdd(&s_sum, c);
   __syncthreads();
-  return s_sum;
+  const int r = s_sum;
+  __syncthreads();  // every thread has read it before a next call resets it
+  return r;
+}
+
+// Sums of part[0 .. np) and part[kMaxPassBlocks .. kMaxPassBlocks + np) in
+// one pass (both loads in flight together).
+__device__ __forceinline__ int2 sum_parts2(const int32_t* __restrict__ part, int np) {
+  __shared__ int s_a, s_b;
+  if (threadIdx.x == 0) s_a = s_b = 0;
+  __syncthreads();
+  int a = 0, b = 0;
+  for (int i = threadIdx.x; i < np; i += blockDim.x) {
+    a += part[i];
+    b += part[kMaxPassBlocks + i];
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    a += __shfl_xor(a, o);
+    b += __shfl_xor(b, o);
+  }
+  if (__lane_id() == 0) {
+    if (a) atomicAdd(&s_a, a);
+    if (b) atomicAdd(&s_b, b);
+  }
+  __syncthreads();
+  return make_int2(s_a, s_b);
 }
 
 // Columns of a row read per round (loads issued together) by the
@@ -79,7 +104,7 @@ __global__ __launch_bounds__(kThreads) void k_tri_prep(int n, int lower,
                                                        int32_t* __restrict__ state,
                                                        int32_t* __restrict__ part) {
   const long long stride = (long long)gridDim.x * blockDim.x;
-  int cnt = 0;
+  int cnt = 0, left = 0;
   for (long long base = (long long)blockIdx.x * blockDim.x; base < n; base += stride) {
     const int i = (int)(base + threadIdx.x);
     bool zero = false;
@@ -105,8 +130,10 @@ __global__ __launch_bounds__(kThreads) void k_tri_prep(int n, int lower,
       if (!diag) atomicMin(&state[1], i);
     }
     cnt += zero;
+    left += i < n && !zero;
   }
   block_count_to(cnt, part);
+  block_count_to(left, part + kMaxPassBlocks);
 }
 
 // The frontier (the rows on level state[2]) into the buffer Kahn's
@@ -219,7 +246,7 @@ __global__ __launch_bounds__(kThreads) void k_tri_pull(int n, int lower,
   if (state[4]) return;  // uniform over the grid
   const int L = state[2];
   const long long stride = (long long)gridDim.x * blockDim.x;
-  int cnt = 0;
+  int cnt = 0, left = 0;
   for (long long base = (long long)blockIdx.x * blockDim.x; base < n; base += stride) {
     const int i = (int)(base + threadIdx.x);
     bool placed = false;
@@ -243,24 +270,36 @@ __global__ __launch_bounds__(kThreads) void k_tri_pull(int n, int lower,
         placed = true;
       } else {
         indeg[i] = cnt;
+        ++left;
       }
     }
     cnt += placed;
   }
   block_count_to(cnt, part);
+  block_count_to(left, part + kMaxPassBlocks);
 }
 
 // After a pull pass: state[0] = rows placed (the sum of the np block
 // counts), [2] += 1, [4] = no further level (nothing placed, or n
-// levels).  Nothing once [4] is set.
+// levels); when the pass placed rows and left none unplaced, the levels
+// are complete at once: [2] = the level count, [0] = 0, [4] = 1 (no
+// further pass needed to find that nothing is left).  Nothing once [4]
+// is set.
 __global__ void k_tri_next_level(int n, const int32_t* __restrict__ part, int np,
                                  int32_t* __restrict__ state) {
   if (state[4]) return;
-  const int t = sum_parts(part, np);
+  const int2 tl = sum_parts2(part, np);
+  const int t = tl.x, left = tl.y;
   if (threadIdx.x == 0) {
-    state[0] = t;
-    state[2] += 1;
-    state[4] = t == 0 || state[2] >= n;
+    if (t > 0 && left == 0) {
+      state[0] = 0;
+      state[2] += 2;
+      state[4] = 1;
+    } else {
+      state[0] = t;
+      state[2] += 1;
+      state[4] = t == 0 || state[2] >= n;
+    }
   }
 }
 
@@ -277,15 +316,18 @@ __global__ void k_tri_spec_flag(int32_t* __restrict__ state) {
 }
 
 // After the prep pass: state[0] = the level-0 frontier size, [2] = 0,
-// [3] = 0, [4] = no level.
+// [3] = 0, [4] = no level; with every row on level 0 (no dependencies
+// anywhere) the levels are complete: [0] = 0, [2] = 1, [4] = 1.
 __global__ void k_tri_first_level(const int32_t* __restrict__ part, int np,
                                   int32_t* __restrict__ state) {
-  const int t = sum_parts(part, np);
+  const int2 tl = sum_parts2(part, np);
+  const int t = tl.x, left = tl.y;
   if (threadIdx.x == 0) {
-    state[0] = t;
-    state[2] = 0;
+    const bool all = t > 0 && left == 0;
+    state[0] = all ? 0 : t;
+    state[2] = all ? 1 : 0;
     state[3] = 0;
-    state[4] = t == 0;
+    state[4] = t == 0 || all;
   }
 }
 
@@ -484,7 +526,8 @@ struct TriWs {
   int32_t* fa;
   int32_t* fb;
   int32_t* counters;  // [0] frontier size, [1] bad row, [2] level, [3] buffer, [4] done
-  int32_t* part;      // per-block row counts of the prep and pull passes
+  int32_t* part;      // per-block row counts of the prep and pull passes: [0, kMaxPassBlocks)
+                      // rows placed, [kMaxPassBlocks, 2 kMaxPassBlocks) rows left unplaced
   int32_t* flag;
   int32_t* pos;
   void* sws;
@@ -504,7 +547,7 @@ TriWs carve_tri(Carver& cv, int n) {
   w.fa = cv.take<int32_t>((size_t)n);
   w.fb = cv.take<int32_t>((size_t)n);
   w.counters = cv.take<int32_t>(8);
-  w.part = cv.take<int32_t>(kMaxPassBlocks);
+  w.part = cv.take<int32_t>(2 * kMaxPassBlocks);
   w.flag = cv.take<int32_t>((size_t)n + 1);
   w.pos = cv.take<int32_t>((size_t)n + 1);
   w.sws_bytes = scan_workspace(n);
@@ -579,13 +622,13 @@ extern "C" int csr_trisolve_analyze(const csrad_csr* Tm, int32_t lower, const cs
   const int lw = lower ? 1 : 0;
   hipLaunchKernelGGL(k_tri_prep, dim3(gn), dim3(kThreads), 0, s, n, lw, Tm->rowptr, Tm->colind,
                      w.indeg, level_of_row, w.counters, w.part);
-  hipLaunchKernelGGL(k_tri_first_level, dim3(1), dim3(256), 0, s, w.part, (int)gn, w.counters);
+  hipLaunchKernelGGL(k_tri_first_level, dim3(1), dim3(1024), 0, s, w.part, (int)gn, w.counters);
   // One wide-level round: a pull pass and the level step (no compaction:
   // the frontier is materialised only when Kahn's algorithm takes over).
   auto pull_round = [&]() -> int {
     hipLaunchKernelGGL(k_tri_pull, dim3(gn), dim3(kThreads), 0, s, n, lw, w.counters, Tm->rowptr,
                        Tm->colind, level_of_row, w.indeg, w.part);
-    hipLaunchKernelGGL(k_tri_next_level, dim3(1), dim3(256), 0, s, n, w.part, (int)gn, w.counters);
+    hipLaunchKernelGGL(k_tri_next_level, dim3(1), dim3(1024), 0, s, n, w.part, (int)gn, w.counters);
     return launch_status();
   };
   // Coloured orderings have a few wide levels: run kSpecRounds rounds
