@@ -300,19 +300,16 @@ __global__ void k_tri_next_level(int n, const int32_t* __restrict__ part, int np
       state[2] += 1;
       state[4] = t == 0 || state[2] >= n;
     }
+    state[6] = state[4] ? 0 : 1;
   }
 }
 
 // The analysis state, zero but for [1] (the first row without a stored
-// diagonal, none yet).
+// diagonal, none yet) and [6] (the gate of the speculative grouping by
+// level: 0 once the levels are complete, kept by the level steps).
 __global__ void k_tri_state_init(int32_t* __restrict__ state) {
-  if (threadIdx.x < 8) state[threadIdx.x] = threadIdx.x == 1 ? INT32_MAX : 0;
-}
-
-// state[6] = 0 when the levels are complete (state[4]), else 1: the gate of
-// the speculative grouping by level.
-__global__ void k_tri_spec_flag(int32_t* __restrict__ state) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) state[6] = state[4] ? 0 : 1;
+  if (threadIdx.x < 8)
+    state[threadIdx.x] = threadIdx.x == 1 ? INT32_MAX : (threadIdx.x == 6 ? 1 : 0);
 }
 
 // After the prep pass: state[0] = the level-0 frontier size, [2] = 0,
@@ -328,6 +325,7 @@ __global__ void k_tri_first_level(const int32_t* __restrict__ part, int np,
     state[2] = all ? 1 : 0;
     state[3] = 0;
     state[4] = t == 0 || all;
+    state[6] = state[4] ? 0 : 1;
   }
 }
 
@@ -640,7 +638,6 @@ extern "C" int csr_trisolve_analyze(const csrad_csr* Tm, int32_t lower, const cs
   for (int r = 0; r < kSpecRounds; ++r) CSRAD_TRY(pull_round());
   const bool spec_group = n >= kSpecLevels;  // level_ptr holds kSpecLevels + 1 entries
   if (spec_group) {
-    hipLaunchKernelGGL(k_tri_spec_flag, dim3(1), dim3(64), 0, s, w.counters);
     CSRAD_TRY(group_small_keys(level_of_row, n, kSpecLevels, level_ptr, level_rows, w.gws,
                                w.gws_bytes, s, w.counters + 6));
   }
