@@ -728,12 +728,17 @@ __global__ __launch_bounds__(256) void k_ms_hist(const int32_t* __restrict__ key
   if (threadIdx.x < K) hist[(long long)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
 }
 
+// Block 0 also writes the key pointers ptr[0 .. K] (ptr[l] = the first
+// slot of key l, ptr[K] = n).
 __global__ __launch_bounds__(256) void k_ms_scatter(const int32_t* __restrict__ keys, int n,
                                                     int K, int ntiles,
                                                     const int32_t* __restrict__ off,
                                                     int32_t* __restrict__ order,
+                                                    int32_t* __restrict__ ptr,
                                                     const int32_t* __restrict__ skip) {
   if (skip && *skip) return;  // uniform over the grid
+  if (blockIdx.x == 0 && (int)threadIdx.x <= K)
+    ptr[threadIdx.x] = (int)threadIdx.x < K ? off[(long long)threadIdx.x * ntiles] : n;
   __shared__ int wcount[4][kSmallKeys];
   __shared__ int running[kSmallKeys];
   const int lane = __lane_id(), w = threadIdx.x / kWave;
@@ -774,14 +779,6 @@ __global__ __launch_bounds__(256) void k_ms_scatter(const int32_t* __restrict__ 
     for (int q = threadIdx.x; q < 4 * kSmallKeys; q += 256) (&wcount[0][0])[q] = 0;
     __syncthreads();
   }
-}
-
-__global__ void k_ms_ptr(const int32_t* __restrict__ off, int K, int ntiles, int n,
-                         int32_t* __restrict__ ptr, const int32_t* __restrict__ skip) {
-  if (skip && *skip) return;
-  const int l = blockIdx.x * blockDim.x + threadIdx.x;
-  if (l < K) ptr[l] = off[(long long)l * ntiles];
-  if (l == K) ptr[K] = n;
 }
 
 struct TransposeWs {
@@ -1039,8 +1036,7 @@ int group_small_keys(const int32_t* keys, int n, int K, int32_t* ptr, int32_t* o
   hipLaunchKernelGGL(k_ms_hist, dim3(ntiles), dim3(256), 0, s, keys, n, K, ntiles, hist, skip);
   CSRAD_TRY(scan_exclusive(hist, off, cells, total, sws, sb, s, skip));
   hipLaunchKernelGGL(k_ms_scatter, dim3(ntiles), dim3(256), 0, s, keys, n, K, ntiles, off, order,
-                     skip);
-  hipLaunchKernelGGL(k_ms_ptr, dim3(1), dim3(64), 0, s, off, K, ntiles, n, ptr, skip);
+                     ptr, skip);
   return launch_status();
 }
 
