@@ -431,7 +431,10 @@ int lanes_for(long long nnz, int rows) {
   }
 
 // Runs the levels: big ones as grid launches, runs of small ones in one
-// workgroup.  REVERSE visits levels from last to first.
+// workgroup.  REVERSE visits levels from last to first.  The first level
+// visited reads no other row, so (with nothing stored on the other side of
+// the diagonal) its rows hold the diagonal alone: as a grid launch it takes
+// one lane per row.
 template <typename TV, typename TX, int G, bool PERM, bool REVERSE>
 void run_levels(int nlevels, const int32_t* lp_host, const int32_t* lp_dev, const int32_t* rows,
                 int lower, const int32_t* rp, const int32_t* ci, const int32_t* perm,
@@ -446,9 +449,15 @@ void run_levels(int nlevels, const int32_t* lp_host, const int32_t* lp_dev, cons
     const int l = REVERSE ? nlevels - 1 - t : t;
     if (big(l)) {
       const int lo = lp_host[l], hi = lp_host[l + 1];
-      const int rpb = kThreads / G;
-      hipLaunchKernelGGL((k_tri_level<TV, TX, G, PERM>), dim3((hi - lo + rpb - 1) / rpb),
-                         dim3(kThreads), 0, s, lo, hi, lower, rows, rp, ci, perm, vals, b, x);
+      if (t == 0 && G > 1) {
+        const unsigned blocks = (unsigned)((hi - lo + kThreads - 1) / kThreads);
+        hipLaunchKernelGGL((k_tri_level<TV, TX, 1, PERM>), dim3(blocks), dim3(kThreads), 0, s, lo,
+                           hi, lower, rows, rp, ci, perm, vals, b, x);
+      } else {
+        const int rpb = kThreads / G;
+        hipLaunchKernelGGL((k_tri_level<TV, TX, G, PERM>), dim3((hi - lo + rpb - 1) / rpb),
+                           dim3(kThreads), 0, s, lo, hi, lower, rows, rp, ci, perm, vals, b, x);
+      }
       ++t;
       continue;
     }
