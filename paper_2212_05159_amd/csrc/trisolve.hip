@@ -335,7 +335,7 @@ __global__ void k_iota(int32_t* p, int n) {
 
 // Solve one row of T x = b on G lanes (also the adjoint solve over T^T
 // when PERM is set: values then come through perm).
-template <typename TV, typename TX, int G, bool PERM>
+template <typename TV, typename TX, int G, int U, bool PERM>
 __device__ __forceinline__ void solve_row(int r, int sub, int lower, const int32_t* __restrict__ rp,
                                           const int32_t* __restrict__ ci,
                                           const int32_t* __restrict__ perm,
@@ -344,11 +344,27 @@ __device__ __forceinline__ void solve_row(int r, int sub, int lower, const int32
   TX s = 0, d = 0;
   if (valid) {
     const int e1 = rp[r + 1];
-    for (int e = rp[r] + sub; e < e1; e += G) {
-      const int j = ci[e];
-      const TX v = (TX)(PERM ? vals[perm[e]] : vals[e]);
-      if (j == r) d = v;
-      else if (dep_side(lower, r, j)) s += v * x[j];
+    // U entries per lane per round (e = sub, sub + G, ...: the lane sums in
+    // row order), their loads issued stage by stage
+    for (int eb = rp[r] + sub; eb < e1; eb += G * U) {
+      int j[U], pe[U];
+      TX v[U], xv[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = eb + u * G;
+        j[u] = e < e1 ? ci[e] : -1;
+        pe[u] = e < e1 ? (PERM ? perm[e] : e) : 0;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        v[u] = j[u] >= 0 ? (TX)vals[pe[u]] : TX(0);
+        xv[u] = (j[u] >= 0 && j[u] != r && dep_side(lower, r, j[u])) ? x[j[u]] : TX(0);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (j[u] == r) d = v[u];
+        else if (j[u] >= 0 && dep_side(lower, r, j[u])) s += v[u] * xv[u];
+      }
     }
   }
   s = group_sum<G>(s);
@@ -356,7 +372,7 @@ __device__ __forceinline__ void solve_row(int r, int sub, int lower, const int32
   if (valid && sub == 0) x[r] = (b[r] - s) / d;
 }
 
-template <typename TV, typename TX, int G, bool PERM>
+template <typename TV, typename TX, int G, int U, bool PERM>
 __global__ __launch_bounds__(kThreads) void k_tri_level(int lo, int hi, int lower,
                                                        const int32_t* __restrict__ rows,
                                                        const int32_t* __restrict__ rp,
@@ -368,12 +384,12 @@ __global__ __launch_bounds__(kThreads) void k_tri_level(int lo, int hi, int lowe
   const int q = lo + blockIdx.x * (kThreads / G) + threadIdx.x / G;
   const bool valid = q < hi;
   const int r = valid ? rows[q] : 0;
-  solve_row<TV, TX, G, PERM>(r, threadIdx.x % G, lower, rp, ci, perm, vals, b, x, valid);
+  solve_row<TV, TX, G, U, PERM>(r, threadIdx.x % G, lower, rp, ci, perm, vals, b, x, valid);
 }
 
 // A run of consecutive small levels [l0, l1) in one workgroup.  With
 // REVERSE the levels run from l1-1 down to l0.
-template <typename TV, typename TX, int G, bool PERM, bool REVERSE>
+template <typename TV, typename TX, int G, int U, bool PERM, bool REVERSE>
 __global__ __launch_bounds__(kOneBlockThreads) void k_tri_levels_block(
     int l0, int l1, int lower, const int32_t* __restrict__ level_ptr,
     const int32_t* __restrict__ rows, const int32_t* __restrict__ rp,
@@ -387,7 +403,7 @@ __global__ __launch_bounds__(kOneBlockThreads) void k_tri_levels_block(
       const int q = base + threadIdx.x / G;
       const bool valid = q < hi;
       const int r = valid ? rows[q] : 0;
-      solve_row<TV, TX, G, PERM>(r, threadIdx.x % G, lower, rp, ci, perm, vals, b, x, valid);
+      solve_row<TV, TX, G, U, PERM>(r, threadIdx.x % G, lower, rp, ci, perm, vals, b, x, valid);
     }
     __syncthreads();
   }
@@ -435,10 +451,18 @@ int lanes_for(long long nnz, int rows) {
 // visited reads no other row, so (with nothing stored on the other side of
 // the diagonal) its rows hold the diagonal alone: as a grid launch it takes
 // one lane per row.
-template <typename TV, typename TX, int G, bool PERM, bool REVERSE>
+// Past the first level, a row takes half the lanes that its mean length
+// asks for (GL), each lane kLevelU entries per round with their loads
+// issued together: the solve is a chain of dependent gathers per entry and
+// a CU's resident threads cap the chains in flight (128^3 red-black L:
+// forward 0.045 -> 0.036 ms, adjoint 0.105 -> 0.095 ms).
+constexpr int kLevelSplit = 2, kLevelU = 4;
+
+template <typename TV, typename TX, int GL, bool PERM, bool REVERSE>
 void run_levels(int nlevels, const int32_t* lp_host, const int32_t* lp_dev, const int32_t* rows,
                 int lower, const int32_t* rp, const int32_t* ci, const int32_t* perm,
                 const TV* vals, const TX* b, TX* x, hipStream_t s) {
+  constexpr int G = GL >= kLevelSplit ? GL / kLevelSplit : 1, U = kLevelU;
   // A level is worth a grid launch once the single workgroup would need
   // more than kOneBlockPasses passes over it (a pass costs a dependent
   // memory round trip; a launch a few of them).
@@ -449,13 +473,13 @@ void run_levels(int nlevels, const int32_t* lp_host, const int32_t* lp_dev, cons
     const int l = REVERSE ? nlevels - 1 - t : t;
     if (big(l)) {
       const int lo = lp_host[l], hi = lp_host[l + 1];
-      if (t == 0 && G > 1) {
+      if (t == 0 && (G > 1 || U > 1)) {
         const unsigned blocks = (unsigned)((hi - lo + kThreads - 1) / kThreads);
-        hipLaunchKernelGGL((k_tri_level<TV, TX, 1, PERM>), dim3(blocks), dim3(kThreads), 0, s, lo,
-                           hi, lower, rows, rp, ci, perm, vals, b, x);
+        hipLaunchKernelGGL((k_tri_level<TV, TX, 1, 1, PERM>), dim3(blocks), dim3(kThreads), 0, s,
+                           lo, hi, lower, rows, rp, ci, perm, vals, b, x);
       } else {
         const int rpb = kThreads / G;
-        hipLaunchKernelGGL((k_tri_level<TV, TX, G, PERM>), dim3((hi - lo + rpb - 1) / rpb),
+        hipLaunchKernelGGL((k_tri_level<TV, TX, G, U, PERM>), dim3((hi - lo + rpb - 1) / rpb),
                            dim3(kThreads), 0, s, lo, hi, lower, rows, rp, ci, perm, vals, b, x);
       }
       ++t;
@@ -466,7 +490,7 @@ void run_levels(int nlevels, const int32_t* lp_host, const int32_t* lp_dev, cons
     // levels t..u-1 in visiting order
     const int l0 = REVERSE ? nlevels - u : t;
     const int l1 = REVERSE ? nlevels - t : u;
-    hipLaunchKernelGGL((k_tri_levels_block<TV, TX, G, PERM, REVERSE>), dim3(1),
+    hipLaunchKernelGGL((k_tri_levels_block<TV, TX, G, U, PERM, REVERSE>), dim3(1),
                        dim3(kOneBlockThreads), 0, s, l0, l1, lower, lp_dev, rows, rp, ci, perm,
                        vals, b, x);
     t = u;
