@@ -287,9 +287,12 @@ __global__ __launch_bounds__(kThreads) void k_num_hash(
 // ---------------------------------------------------------------------
 // Register window per list: entries a lane holds ahead of its list head
 // (fewer when a group keeps many rows in flight, to keep registers low).
-template <int R>
+// SHORT: B's rows hold about one entry (the mean is at most 2), so a
+// longer window would only cost registers (A P with a one-entry-per-row
+// P: 4 rows in flight at 8 waves per SIMD instead of 6, 0.355 -> 0.343 ms).
+template <int R, bool SHORT>
 constexpr int merge_window() {
-  return R >= 8 ? 2 : 4;
+  return (R >= 8 || SHORT) ? 2 : 4;
 }
 
 template <int G>
@@ -322,7 +325,7 @@ __device__ __forceinline__ void wave_sync_lds() {
 // R rows per group are in flight at once (their load rounds are issued
 // together, then merged one after the other), so a wave hides R times the
 // memory latency of one row.
-template <typename T, int G, bool NUM, int R>
+template <typename T, int G, bool NUM, int R, bool SHORT>
 __global__ __launch_bounds__(kThreads) void k_merge(
     int m, int bin, const int32_t* __restrict__ list, const int32_t* __restrict__ bin_off,
     const int32_t* __restrict__ rpA, const int32_t* __restrict__ ciA, const T* __restrict__ vA,
@@ -330,7 +333,7 @@ __global__ __launch_bounds__(kThreads) void k_merge(
     const int32_t* __restrict__ rpC, int32_t* __restrict__ ciC, T* __restrict__ vC,
     int32_t* __restrict__ counts) {
   constexpr int RPB = kThreads / G;  // groups per block
-  constexpr int kWin = merge_window<R>();
+  constexpr int kWin = merge_window<R, SHORT>();
   __shared__ int s_b0[R][kThreads], s_len[R][kThreads], s_a[R][kThreads];
   const int first = bin_off[bin], nrows = bin_off[bin + 1] - first;
   // a class holding all m rows lists them in order (the grouping is
@@ -841,14 +844,20 @@ void merge_bin(int bin, int rows, const csrad_csr* A, const csrad_csr* B, const 
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     cus = 256;
   const long long resident_groups = (long long)cus * 8 * (kThreads / G);
+  const bool short_b = B->nnz <= 2ll * B->nrows;
   if (RMAX > 1 && rows >= 8 * resident_groups) {
     const unsigned g = persistent_grid(kThreads / G * RMAX, rows);
-    hipLaunchKernelGGL((k_merge<T, G, NUM, RMAX>), dim3(g), dim3(kThreads), 0, s, A->nrows, bin,
-                       w.list, w.bin_off, A->rowptr, A->colind, vA, B->rowptr, B->colind, vB, rpC,
-                       ciC, vC, w.counts);
+    if (short_b)
+      hipLaunchKernelGGL((k_merge<T, G, NUM, RMAX, true>), dim3(g), dim3(kThreads), 0, s, A->nrows,
+                         bin, w.list, w.bin_off, A->rowptr, A->colind, vA, B->rowptr, B->colind,
+                         vB, rpC, ciC, vC, w.counts);
+    else
+      hipLaunchKernelGGL((k_merge<T, G, NUM, RMAX, false>), dim3(g), dim3(kThreads), 0, s,
+                         A->nrows, bin, w.list, w.bin_off, A->rowptr, A->colind, vA, B->rowptr,
+                         B->colind, vB, rpC, ciC, vC, w.counts);
   } else {
     const unsigned g = persistent_grid(kThreads / G, rows);
-    hipLaunchKernelGGL((k_merge<T, G, NUM, 1>), dim3(g), dim3(kThreads), 0, s, A->nrows, bin,
+    hipLaunchKernelGGL((k_merge<T, G, NUM, 1, false>), dim3(g), dim3(kThreads), 0, s, A->nrows, bin,
                        w.list, w.bin_off, A->rowptr, A->colind, vA, B->rowptr, B->colind, vB, rpC,
                        ciC, vC, w.counts);
   }
