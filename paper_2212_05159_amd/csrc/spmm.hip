@@ -166,12 +166,43 @@ __device__ __forceinline__ double bcast16(double v) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-template <typename V, int N, int U = 0>
+// out[u] = the value of lane S*u of the DPP row, u < N.
+template <typename V, int N, int S = 1, int U = 0>
 __device__ __forceinline__ void bcast_all(V mine, V (&out)[N]) {
   if constexpr (U < N) {
-    out[U] = bcast16<U>(mine);
-    bcast_all<V, N, U + 1>(mine, out);
+    out[U] = bcast16<S * U>(mine);
+    bcast_all<V, N, S, U + 1>(mine, out);
   }
+}
+
+// Eight sums over one 16-lane DPP row, scattered: every lane holds d[0..7];
+// lanes 2u and 2u+1 return the row's sum of d[u].  Each level pairs lanes
+// that differ in one bit of u (row mirror: lane bit 3, half-row mirror:
+// bit 2, quad swap: bit 1), keeps the half of its values that its bit
+// selects and adds the partner's copies of them; a swap of neighbours
+// completes the sums.  8 cross-lane moves instead of 32, and the partial
+// sums die as they are combined.
+template <int CTRL>
+__device__ __forceinline__ float dpp_any(float v) {
+  return dpp_f32<CTRL>(v);
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_any(double v) {
+  return dpp_f64<CTRL>(v);
+}
+template <typename T>
+__device__ __forceinline__ T row_sum_scatter8(const T (&d)[8], int lr) {
+  const bool b3 = lr & 8, b2 = lr & 4, b1 = lr & 2;
+  T e[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    e[q] = (b3 ? d[4 + q] : d[q]) + dpp_any<kDppMirror>(b3 ? d[q] : d[4 + q]);
+  T f[2];
+#pragma unroll
+  for (int q = 0; q < 2; ++q)
+    f[q] = (b2 ? e[2 + q] : e[q]) + dpp_any<kDppHalfMirror>(b2 ? e[q] : e[2 + q]);
+  const T h = (b1 ? f[1] : f[0]) + dpp_any<kDppXor2>(b1 ? f[0] : f[1]);
+  return h + dpp_any<kDppXor1>(h);
 }
 
 constexpr int kCoop = 8;
@@ -246,40 +277,60 @@ __global__ __launch_bounds__(kThreads) void k_spmm_bwd_coop(
     T acc[VW];
 #pragma unroll
     for (int w = 0; w < VW; ++w) acc[w] = T(0);
+    // a 16-lane group takes entry u of the batch in lanes 2u and 2u+1 (the
+    // layout the scattered row sums leave); wider groups in lane u
+    constexpr int S = LPR == 16 ? 2 : 1;
     for (int tb = t0; tb < t1; tb += kCoop) {
       const int cnt = min(kCoop, t1 - tb);
+      const int me = lr / S;
       int myi = 0, mye = 0;
       T mya = 0;
-      if (lr < cnt) {
-        myi = ld_stream(&ciT[tb + lr]);
-        mye = ld_stream(&perm[tb + lr]);
+      if (me < cnt) {
+        myi = ld_stream(&ciT[tb + me]);
+        mye = ld_stream(&perm[tb + me]);
         if (GB) mya = vals[mye];
       }
       int i[kCoop];
-      bcast_all<int, kCoop>(myi, i);
+      bcast_all<int, kCoop, S>(myi, i);
       Vec<T, VW> g[kCoop];
 #pragma unroll
       for (int u = 0; u < kCoop; ++u) g[u] = load_or_zero<T, VW>(G + (long long)i[u] * ldg + col, act && u < cnt);
       if (GB) {
         T a[kCoop];
-        bcast_all<T, kCoop>(mya, a);
+        bcast_all<T, kCoop, S>(mya, a);
 #pragma unroll
         for (int u = 0; u < kCoop; ++u)
 #pragma unroll
           for (int w = 0; w < VW; ++w) acc[w] += a[u] * g[u].v[w];
+        // an empty statement that reads and rewrites acc keeps the
+        // multiply-adds here, ahead of the dot products: sunk past them,
+        // they would keep the batch's broadcast values live through the
+        // reductions and cost occupancy
+#pragma unroll
+        for (int w = 0; w < VW; ++w) asm volatile("" : "+v"(acc[w]));
       }
       if (GV) {
-        T mine = 0;
+        T d[kCoop];
 #pragma unroll
         for (int u = 0; u < kCoop; ++u) {
-          T d = 0;
+          d[u] = 0;
 #pragma unroll
-          for (int w = 0; w < VW; ++w) d += g[u].v[w] * bj.v[w];
-          d = group_sum<LPR>(d);
-          if (lr == u) mine = d;
+          for (int w = 0; w < VW; ++w) d[u] += g[u].v[w] * bj.v[w];
         }
-        // lane u of the group's first DPP row owns entry u of the batch
-        if (l < cnt) gv[mye] = c0 == 0 ? mine : gv[mye] + mine;
+        if constexpr (LPR == 16) {
+          static_assert(kCoop == 8, "the scattered row sums take 8 values");
+          const T mine = row_sum_scatter8<T>(d, lr);
+          if ((lr & 1) == 0 && me < cnt) gv[mye] = c0 == 0 ? mine : gv[mye] + mine;
+        } else {
+          T mine = 0;
+#pragma unroll
+          for (int u = 0; u < kCoop; ++u) {
+            const T su = group_sum<LPR>(d[u]);
+            if (lr == u) mine = su;
+          }
+          // lane u of the group's first DPP row owns entry u of the batch
+          if (l < cnt) gv[mye] = c0 == 0 ? mine : gv[mye] + mine;
+        }
       }
     }
     if (GB && act) {
