@@ -345,25 +345,29 @@ __device__ __forceinline__ void solve_row(int r, int sub, int lower, const int32
   if (valid) {
     const int e1 = rp[r + 1];
     // U entries per lane per round (e = sub, sub + G, ...: the lane sums in
-    // row order), their loads issued stage by stage
+    // row order), their loads issued stage by stage without branches:
+    // positions past the row's end read its last entry and are masked out,
+    // and entries that read no other row (the diagonal) load x at the row
+    // itself, whose value is not used
     for (int eb = rp[r] + sub; eb < e1; eb += G * U) {
       int j[U], pe[U];
       TX v[U], xv[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int e = eb + u * G;
-        j[u] = e < e1 ? ci[e] : -1;
-        pe[u] = e < e1 ? (PERM ? perm[e] : e) : 0;
+        const int e = min(eb + u * G, e1 - 1);
+        j[u] = ci[e];
+        pe[u] = PERM ? perm[e] : e;
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        v[u] = j[u] >= 0 ? (TX)vals[pe[u]] : TX(0);
-        xv[u] = (j[u] >= 0 && j[u] != r && dep_side(lower, r, j[u])) ? x[j[u]] : TX(0);
+        v[u] = (TX)vals[pe[u]];
+        xv[u] = x[(j[u] != r && dep_side(lower, r, j[u])) ? j[u] : r];
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
+        if (eb + u * G >= e1) continue;
         if (j[u] == r) d = v[u];
-        else if (j[u] >= 0 && dep_side(lower, r, j[u])) s += v[u] * xv[u];
+        else if (dep_side(lower, r, j[u])) s += v[u] * xv[u];
       }
     }
   }
@@ -464,9 +468,9 @@ void run_levels(int nlevels, const int32_t* lp_host, const int32_t* lp_dev, cons
                 const TV* vals, const TX* b, TX* x, hipStream_t s) {
   constexpr int G = GL >= kLevelSplit ? GL / kLevelSplit : 1, U = kLevelU;
   // A level is worth a grid launch once the single workgroup would need
-  // more than kOneBlockPasses passes over it (a pass costs a dependent
-  // memory round trip; a launch a few of them).
-  constexpr int kBig = kOneBlockPasses * (kOneBlockThreads / G);
+  // more than kOneBlockPasses passes over it at GL lanes per row (a pass
+  // costs a dependent memory round trip; a launch a few of them).
+  constexpr int kBig = kOneBlockPasses * (kOneBlockThreads / GL);
   auto big = [&](int l) { return lp_host[l + 1] - lp_host[l] > kBig; };
   int t = 0;
   while (t < nlevels) {
