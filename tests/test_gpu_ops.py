@@ -90,7 +90,9 @@ def test_spmv_fwd_bwd(dtype, name, A, use_t):
 
 # ---------------------------------------------------------------- SpMM
 @pytest.mark.parametrize("dtype", DTYPES)
-@pytest.mark.parametrize("k", [1, 3, 8, 64, 100])
+# 16-lane cooperative kernels: k = 32 in float64 (16 lanes of 2 values), 48 in
+# float32 (12 of the 16 lanes active) and 64 in float32 (all 16)
+@pytest.mark.parametrize("k", [1, 3, 8, 32, 48, 64, 100])
 @pytest.mark.parametrize("name", ["poisson32", "rand_ragged", "rand_long_rows", "empty"])
 def test_spmm_fwd_bwd(dtype, k, name):
     A = dict(MATS)[name]
