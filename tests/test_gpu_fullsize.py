@@ -260,6 +260,12 @@ def test_spgemm_bwd_batched_float64():
     Ad = sp.CsrTensor.from_host(A, dtype=torch.float64)
     Bd = sp.CsrTensor.from_host(B, dtype=torch.float64)
     PC, vC = sp.spgemm(Ad.pattern, Ad.vals, Bd.pattern, Bd.vals)
+    # the product itself: B's rows hold 2 entries, so the row merge keeps 4
+    # rows in flight per group with a 2-entry list window
+    rpo, cio, vo = oracle.spgemm(A, B)
+    assert np.array_equal(_np(PC.rowptr), rpo)
+    assert np.array_equal(_np(PC.colind), cio)
+    assert rel_err(_np(vC), vo) <= 1e-12
     rng = np.random.default_rng(43)
     gC = rng.standard_normal(PC.nnz)
     gA, gB = sp.spgemm_bwd(Ad.pattern, Ad.vals, Bd.pattern, Bd.vals, PC,
