@@ -440,11 +440,12 @@ __device__ __forceinline__ double bc16(double v) {
   const int hi = bc16<U>((int)(b >> 32));
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
-template <typename V, int U = 0>
+// out[u] = the value of lane S*u of the DPP row, u < kEb.
+template <typename V, int S = 1, int U = 0>
 __device__ __forceinline__ void bc_all(V mine, V (&out)[kEb]) {
   if constexpr (U < kEb) {
-    out[U] = bc16<U>(mine);
-    bc_all<V, U + 1>(mine, out);
+    out[U] = bc16<S * U>(mine);
+    bc_all<V, S, U + 1>(mine, out);
   }
 }
 
@@ -622,39 +623,47 @@ __device__ __forceinline__ void spmmb_seg(int ta, int tb, int col, bool act, int
                                           const T* __restrict__ v, const T* __restrict__ G,
                                           long long ldg, const Vec<T, VW>& bj, int c0,
                                           T* __restrict__ gv, T (&acc)[VW]) {
+  // entry u of a batch sits in lanes 2u and 2u+1 of the 16-lane group (the
+  // layout the scattered row sums leave), as in the per-matrix kernel: the
+  // two give the same bits
+  static_assert(kGrp == 16 && kEb == 8, "the scattered row sums take 8 values over 16 lanes");
   for (int t = ta; t < tb; t += kEb) {
     const int cnt = min(kEb, tb - t);
+    const int me = lr >> 1;
     int myi = 0, mye = 0;
     T mya = 0;
-    if (lr < cnt) {
-      myi = ld_stream(&ciT[t + lr]);
-      mye = ld_stream(&perm[t + lr]);
+    if (me < cnt) {
+      myi = ld_stream(&ciT[t + me]);
+      mye = ld_stream(&perm[t + me]);
       if (GB) mya = v[mye];
     }
     int i[kEb];
-    bc_all<int>(myi, i);
+    bc_all<int, 2>(myi, i);
     Vec<T, VW> g[kEb];
 #pragma unroll
     for (int u = 0; u < kEb; ++u) g[u] = ld_or_zero<T, VW>(G + (long long)i[u] * ldg + col, act && u < cnt);
     if (GB) {
       T a[kEb];
-      bc_all<T>(mya, a);
+      bc_all<T, 2>(mya, a);
 #pragma unroll
       for (int u = 0; u < kEb; ++u)
 #pragma unroll
         for (int w = 0; w < VW; ++w) acc[w] += a[u] * g[u].v[w];
+      // keeps the multiply-adds ahead of the dot products (sunk past them,
+      // they would keep the broadcast values live through the reductions)
+#pragma unroll
+      for (int w = 0; w < VW; ++w) asm volatile("" : "+v"(acc[w]));
     }
     if (GV) {
-      T mine = 0;
+      T d[kEb];
 #pragma unroll
       for (int u = 0; u < kEb; ++u) {
-        T d = 0;
+        d[u] = 0;
 #pragma unroll
-        for (int w = 0; w < VW; ++w) d += g[u].v[w] * bj.v[w];
-        d = group_sum<kGrp>(d);
-        if (lr == u) mine = d;
+        for (int w = 0; w < VW; ++w) d[u] += g[u].v[w] * bj.v[w];
       }
-      if (lr < cnt) gv[mye] = c0 == 0 ? mine : gv[mye] + mine;
+      const T mine = row_sum_scatter8<T>(d, lr);
+      if ((lr & 1) == 0 && me < cnt) gv[mye] = c0 == 0 ? mine : gv[mye] + mine;
     }
   }
 }
@@ -843,16 +852,18 @@ __global__ __launch_bounds__(kThreads) void k_batch_sddmm(
 #pragma unroll
           for (int u = 0; u < kEb; ++u)
             bv[u] = ld_or_zero<T, VW>(B + (long long)c[u] * ldb + col, act && u < cnt);
-          T mine = 0;
+          // the same dots and scattered row sums as the fused backward (the
+          // split and fused forms give the same bits): entry u ends in lane 2u
+          T d[kEb];
 #pragma unroll
           for (int u = 0; u < kEb; ++u) {
-            T d = 0;
+            d[u] = 0;
 #pragma unroll
-            for (int w = 0; w < VW; ++w) d += gi.v[w] * bv[u].v[w];
-            d = group_sum<kGrp>(d);
-            if (l == u) mine = d;
+            for (int w = 0; w < VW; ++w) d[u] += gi.v[w] * bv[u].v[w];
           }
-          if (l < cnt) gv[eb + l] = c0 == 0 ? mine : gv[eb + l] + mine;
+          const T mine = row_sum_scatter8<T>(d, l);
+          const int me = l >> 1;
+          if ((l & 1) == 0 && me < cnt) gv[eb + me] = c0 == 0 ? mine : gv[eb + me] + mine;
         }
       }
     }

@@ -175,35 +175,6 @@ __device__ __forceinline__ void bcast_all(V mine, V (&out)[N]) {
   }
 }
 
-// Eight sums over one 16-lane DPP row, scattered: every lane holds d[0..7];
-// lanes 2u and 2u+1 return the row's sum of d[u].  Each level pairs lanes
-// that differ in one bit of u (row mirror: lane bit 3, half-row mirror:
-// bit 2, quad swap: bit 1), keeps the half of its values that its bit
-// selects and adds the partner's copies of them; a swap of neighbours
-// completes the sums.  8 cross-lane moves instead of 32, and the partial
-// sums die as they are combined.
-template <int CTRL>
-__device__ __forceinline__ float dpp_any(float v) {
-  return dpp_f32<CTRL>(v);
-}
-template <int CTRL>
-__device__ __forceinline__ double dpp_any(double v) {
-  return dpp_f64<CTRL>(v);
-}
-template <typename T>
-__device__ __forceinline__ T row_sum_scatter8(const T (&d)[8], int lr) {
-  const bool b3 = lr & 8, b2 = lr & 4, b1 = lr & 2;
-  T e[4];
-#pragma unroll
-  for (int q = 0; q < 4; ++q)
-    e[q] = (b3 ? d[4 + q] : d[q]) + dpp_any<kDppMirror>(b3 ? d[q] : d[4 + q]);
-  T f[2];
-#pragma unroll
-  for (int q = 0; q < 2; ++q)
-    f[q] = (b2 ? e[2 + q] : e[q]) + dpp_any<kDppHalfMirror>(b2 ? e[q] : e[2 + q]);
-  const T h = (b1 ? f[1] : f[0]) + dpp_any<kDppXor2>(b1 ? f[0] : f[1]);
-  return h + dpp_any<kDppXor1>(h);
-}
 
 constexpr int kCoop = 8;
 
@@ -366,13 +337,30 @@ __global__ __launch_bounds__(kThreads) void k_sddmm_rows(
         const int c = ld_stream(&colind[min(eb + u, e1 - 1)]);
         bv[u] = load_or_zero<T, VW>(B + (long long)c * ldb + col, act);
       }
+      if constexpr (LPR == 16) {
+        // the same dots and scattered row sums as the fused backward's
+        // 16-lane groups (the two give the same bits): entry u ends in
+        // lanes 2u and 2u+1
+        static_assert(kBatch == 8, "the scattered row sums take 8 values");
+        T d[kBatch];
 #pragma unroll
-      for (int u = 0; u < kBatch; ++u) {
-        T d = 0;
+        for (int u = 0; u < kBatch; ++u) {
+          d[u] = 0;
 #pragma unroll
-        for (int w = 0; w < VW; ++w) d += gi.v[w] * bv[u].v[w];
-        d = group_sum<LPR>(d);
-        if (l == 0 && eb + u < e1) gv[eb + u] = c0 == 0 ? d : gv[eb + u] + d;
+          for (int w = 0; w < VW; ++w) d[u] += gi.v[w] * bv[u].v[w];
+        }
+        const T mine = row_sum_scatter8<T>(d, l);
+        const int e = eb + (l >> 1);
+        if ((l & 1) == 0 && e < e1) gv[e] = c0 == 0 ? mine : gv[e] + mine;
+      } else {
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+          T d = 0;
+#pragma unroll
+          for (int w = 0; w < VW; ++w) d += gi.v[w] * bv[u].v[w];
+          d = group_sum<LPR>(d);
+          if (l == 0 && eb + u < e1) gv[eb + u] = c0 == 0 ? d : gv[eb + u] + d;
+        }
       }
     }
   }

@@ -111,6 +111,9 @@ def test_spmm_fwd_bwd(dtype, k, name):
     assert_close(gv, gvo, dtype, "gvals")
     assert_close(gv_only, gvo, dtype, "gvals only")
     assert_close(gB_only, gBo, dtype, "gB only")
+    # the row-wise value-gradient pass and the fused pass over A^T form the
+    # same dots with the same reduction: the same bits
+    assert torch.equal(gv_only, gv)
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
